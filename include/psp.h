@@ -1,0 +1,188 @@
+/*
+ * psp.h -- C ABI of libpsp: perturbation-induced static pivoting on MI355X
+ * (gfx950), FP64 throughout.
+ *
+ * Method (arXiv 2311.11833, Alg. 1): instead of pivoting, factor K perturbed
+ * systems A + eps_k D without row exchanges, solve each, and combine the
+ * perturbed solutions x_k with weights c_k so that the A^{-1} b term is kept
+ * and the first K-1 powers of eps cancel (Sec. III-A, Theorem 1, Remark 2):
+ *     x_hat = sum_k c_k x_k,    sum_k c_k eps_k^j = delta_{j0}, j < K.
+ *
+ * Conventions shared by every call:
+ *   - Every call returns psp_status; no C++ exception crosses the ABI.  The
+ *     text of the last failure on the calling thread is psp_last_error().
+ *   - All reals are IEEE binary64, all indices int32.  Matrices arrive in
+ *     CSR form for one sparsity pattern; "values" are the nnz entries in that
+ *     CSR order.  Dense vectors with nrhs right-hand sides are row-major
+ *     n x nrhs (entry (i, r) at i*nrhs + r).
+ *   - Pointers documented "device" are device memory owned by the caller;
+ *     the library never frees them.  Pointers documented "host" are read
+ *     during the call only.  "stream" is a hipStream_t (NULL = the null
+ *     stream); device work is enqueued on it and the call returns without
+ *     waiting, so device outputs are valid after the caller synchronises
+ *     the stream.
+ *   - Numerical breakdown is not a call error: it is reported per system in
+ *     the device array "info" (0 = ok, j+1 = pivot j was exactly zero or not
+ *     finite; the LAPACK getrf convention), written by the kernels.  The
+ *     outputs of a system with info != 0 are NaN.
+ *   - Handles (psp_plan, psp_factors) are host objects owned by the library
+ *     and freed by the matching destroy/release call.
+ */
+#ifndef PSP_H
+#define PSP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PSP_API __attribute__((visibility("default")))
+
+typedef enum {
+    PSP_OK = 0,
+    PSP_E_INVALID = 1,      /* bad size, NULL pointer or malformed CSR pattern          */
+    PSP_E_EPS = 2,          /* perturbation nodes not distinct, zero or not finite      */
+    PSP_E_NOMEM = 3,        /* caller workspace too small, or host allocation failed    */
+    PSP_E_HIP = 4,          /* HIP runtime error (including one left by earlier work)   */
+    PSP_E_STATE = 5,        /* handle used in the wrong order or with a mismatched plan */
+    PSP_E_UNSUPPORTED = 6   /* device is not gfx950, or size beyond the chosen path     */
+} psp_status;
+
+/* Message describing the last non-OK status returned on this thread. */
+PSP_API const char* psp_last_error(void);
+
+/* ABI version (major*100 + minor). */
+PSP_API int32_t psp_version(void);
+
+/* ------------------------------------------------------------------------
+ * Plan: symbolic analysis of one sparsity pattern, host CPU, once per
+ * pattern.  This is the static pivot sequence of Sec. II-C, computed once and
+ * reused by every perturbed system, every Newton step and every scenario.
+ *   S      = pat(A) | pat(A^T) | diagonal (the diagonal is always present
+ *            because D is diagonal).
+ *   order  PSP_ORDER_MD: minimum degree on the elimination graph of S with
+ *            exact degrees; ties go to the smallest index; a vertex whose
+ *            degree d in S satisfies d > 16 and d*d > 100*n is set aside
+ *            and ordered last (ascending index).
+ *          PSP_ORDER_NATURAL: the identity.
+ *   fill   L = strictly lower symbolic factor of P S P^T (column pattern),
+ *          U = its transpose plus the diagonal.
+ *   etree  parent[j] = smallest row index of L(:, j), -1 for a root.
+ *   levels factor: etree height; L-solve: lev(i) = 1 + max lev(j) over
+ *          L_ij != 0; U-solve: lev(i) = 1 + max lev(j) over U_ij != 0, j > i;
+ *          each level lists its indices ascending.
+ * row_ptr (host, n+1) and col_idx (host, nnz) must describe a square CSR
+ * pattern with strictly ascending column indices in each row.
+ * ---------------------------------------------------------------------- */
+typedef struct psp_plan_s* psp_plan;
+
+enum { PSP_ORDER_MD = 0, PSP_ORDER_NATURAL = 1 };
+
+PSP_API psp_status psp_plan_create(int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
+                           uint32_t flags, psp_plan* out);
+
+typedef struct {
+    int32_t n;
+    int32_t nnz;               /* entries of A                                      */
+    int64_t nnz_l;             /* strictly lower entries of L (= strictly upper of U) */
+    int32_t ndense;            /* vertices set aside by the dense rule              */
+    int32_t nlev[3];           /* levels: factor, L-solve, U-solve                  */
+    int64_t flops_dense_factor;/* n(n-1)/2 divisions + 2 * sum_k (n-1-k)^2 fma flops */
+    int64_t flops_sparse_factor;/* sum_j (|L(:,j)| + 2*|L(:,j)|^2) on the fill      */
+} psp_plan_info_t;
+
+PSP_API psp_status psp_plan_info(psp_plan plan, psp_plan_info_t* out);
+
+/* Copies the symbolic arrays (host buffers sized from psp_plan_info):
+ * perm[n] (position -> original index), iperm[n], parent[n], l_ptr[n+1],
+ * l_idx[nnz_l] (rows of each L column, ascending, permuted numbering), and
+ * for t = 0, 1, 2 (factor, L-solve, U-solve) lev_ptr[t][nlev[t]+1] and
+ * lev_idx[t][n].  Any output may be NULL to skip it. */
+PSP_API psp_status psp_plan_export(psp_plan plan, int32_t* perm, int32_t* iperm, int32_t* parent,
+                           int32_t* l_ptr, int32_t* l_idx, int32_t* lev_ptr[3], int32_t* lev_idx[3]);
+
+PSP_API void psp_plan_destroy(psp_plan plan);
+
+/* ------------------------------------------------------------------------
+ * Weights (host): c_k = prod_{l != k} eps_l / (eps_l - eps_k), the unique
+ * solution of sum_k c_k eps_k^j = delta_{j0} for j < K.  For the paper's
+ * nodes +-alpha*eps (alpha = 1..m) this is c = beta_alpha / 2 with
+ * beta = (Gamma_m^T)^{-1} e1 (Remark 2).  eps (host, K), c (host, K).
+ * PSP_E_EPS if the nodes are not distinct, zero or finite.
+ * ---------------------------------------------------------------------- */
+PSP_API psp_status psp_weights(int32_t K, const double* eps, double* c);
+
+/* ------------------------------------------------------------------------
+ * Numeric paths.
+ *   PSP_PATH_DENSE   each perturbed system as a dense n x n matrix (the
+ *                    batched dense factorisation of Sec. IV), n <= 4096.
+ *   PSP_PATH_SPARSE  factors on the plan's fill pattern, level-scheduled
+ *                    (the sparse batched factorisation named in Sec. IV/V).
+ *   PSP_PATH_AUTO    the library's choice for the plan (tuned crossover).
+ * ---------------------------------------------------------------------- */
+enum { PSP_PATH_AUTO = 0, PSP_PATH_DENSE = 1, PSP_PATH_SPARSE = 2 };
+
+/* Bytes of device workspace psp_factor / psp_solve_batched need for `batch`
+ * Jacobians, K nodes and nrhs right-hand sides on `path`.  With keep != 0
+ * the factors of all batch*K systems stay resident for psp_solve and the
+ * adjoint. */
+PSP_API size_t psp_workspace_bytes(psp_plan plan, int32_t path, int32_t batch, int32_t K, int32_t nrhs,
+                           int32_t keep);
+
+/* ------------------------------------------------------------------------
+ * psp_solve_batched -- Alg. 1 steps 1-4 for a batch of Jacobians that share
+ * the plan's pattern, in one fused launch: for Jacobian s and node k it forms
+ * P (A_s + eps_k D) P^T, factors it without pivoting, solves with the
+ * nrhs right-hand sides, and accumulates x_hat_s = sum_k c_k x_sk (ascending
+ * k) into X.
+ *   values  device, batch x nnz           eps   host, K distinct nonzero
+ *   d       device, n (NULL: D = I)       B     device, batch x n x nrhs
+ *   X       device, batch x n x nrhs      info  device, batch x K (int32)
+ *   ws      device workspace of at least psp_workspace_bytes(plan, path,
+ *           batch, K, nrhs, 0) bytes.
+ * ---------------------------------------------------------------------- */
+PSP_API psp_status psp_solve_batched(psp_plan plan, int32_t path, int32_t batch, const double* values,
+                             int32_t K, const double* eps, const double* d, int32_t nrhs,
+                             const double* B, double* X, int32_t* info, void* ws, size_t ws_bytes,
+                             void* stream);
+
+/* ------------------------------------------------------------------------
+ * Split steps (plain, one call per step) -- the adjoint and the
+ * one-system-at-a-time baseline use these.
+ * psp_factor: factors all batch*K perturbed systems into the workspace
+ * (keep = 1 layout) and returns a host handle that refers to it.  The
+ * handle is valid while the workspace memory is alive and unmodified.
+ * ---------------------------------------------------------------------- */
+typedef struct psp_factors_s* psp_factors;
+
+PSP_API psp_status psp_factor(psp_plan plan, int32_t path, int32_t batch, const double* values, int32_t K,
+                      const double* eps, const double* d, int32_t* info, void* ws, size_t ws_bytes,
+                      void* stream, psp_factors* out);
+
+/* Solves every perturbed system with its factors: Xk[s][k] = (A_s + eps_k D)^{-1} B[s]
+ * (transpose = 0) or (A_s + eps_k D)^{-T} B[s] (transpose = 1).
+ * B device batch x n x nrhs; Xk device batch x K x n x nrhs.  nrhs must not
+ * exceed the nrhs the workspace was sized for. */
+PSP_API psp_status psp_solve(psp_factors f, int32_t nrhs, const double* B, double* Xk, int32_t transpose,
+                     void* stream);
+
+/* X[s] = sum_k c_k Xk[s][k], ascending k (Alg. 1 steps 3-4).  Device arrays. */
+PSP_API psp_status psp_combine(psp_factors f, int32_t nrhs, const double* Xk, double* X, void* stream);
+
+/* Adjoint of L = sum_r w_r . x_hat_r with respect to the values of A:
+ * gA[s][e] = - sum_k c_k sum_r Lamk[s][k][i][r] * Xk[s][k][j][r] for the CSR
+ * entry e = (i, j).  Lamk = psp_solve(..., W, transpose=1) and Xk =
+ * psp_solve(..., B, transpose=0); all device arrays. dL/dB is psp_combine of
+ * Lamk. */
+PSP_API psp_status psp_grad_values(psp_factors f, int32_t nrhs, const double* Lamk, const double* Xk,
+                           double* gA, void* stream);
+
+PSP_API psp_status psp_factors_release(psp_factors f);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PSP_H */

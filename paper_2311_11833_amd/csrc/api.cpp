@@ -1,0 +1,404 @@
+// api.cpp -- the extern "C" boundary of libpsp (declared in include/psp.h):
+// argument checks, status/error reporting, plan handles, workspace layout and
+// kernel launches.  All arithmetic of the method runs in the HIP kernels.
+#include "psp.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "plan.h"
+#include "sparse.h"
+
+#include "dense.h"
+
+using namespace psp;
+
+namespace {
+
+thread_local std::string g_err;
+
+psp_status fail(psp_status s, const std::string& msg) {
+    g_err = msg;
+    return s;
+}
+
+psp_status hip_fail(hipError_t e, const char* where) {
+    return fail(PSP_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(call, where)                       \
+    do {                                           \
+        hipError_t e_ = (call);                    \
+        if (e_ != hipSuccess) return hip_fail(e_, where); \
+    } while (0)
+
+constexpr int64_t kAlign = 256;
+int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+int device_cus() {
+    static int cus = 0;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        int dev = 0;
+        hipDeviceProp_t p;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess) cus = p.multiProcessorCount;
+        if (cus <= 0) cus = 256;
+    });
+    return cus;
+}
+
+}  // namespace
+
+struct psp_plan_s {
+    Symbolic sym;
+    // device copies of the index arrays, uploaded on first numeric use
+    std::mutex mu;
+    int device = -1;
+    int32_t* d_dst = nullptr;     // dense slot offsets, keyed by ld
+    int32_t d_dst_ld = 0;
+    int32_t* d_perm = nullptr;
+    int32_t* d_rows = nullptr;    // original row of each CSR entry
+    int32_t* d_cols = nullptr;
+    SparseDevice sp;              // sparse-path arrays
+    ~psp_plan_s() {
+        if (device >= 0) {
+            int cur = 0;
+            (void)hipGetDevice(&cur);
+            (void)hipSetDevice(device);
+            (void)hipFree(d_dst);
+            (void)hipFree(d_perm);
+            (void)hipFree(d_rows);
+            (void)hipFree(d_cols);
+            sparse_free(sp);
+            (void)hipSetDevice(cur);
+        }
+    }
+};
+
+struct psp_factors_s {
+    psp_plan plan;
+    int32_t path, batch, K, nrhs_cap;
+    EpsSet es;
+    char* ws;
+    size_t ws_bytes;
+    int32_t* info;
+    // dense layout
+    int32_t n_pad, ld;
+    int64_t slot_stride;   // doubles
+    int64_t off_slots, off_tmp;
+};
+
+namespace {
+
+struct DenseLayout {
+    int32_t n_pad, ld;
+    int64_t slot_stride;      // doubles per slot
+    int64_t nslots;
+    int64_t off_slots, off_xk, off_tmp, total;
+};
+
+DenseLayout dense_layout(const Symbolic& s, int32_t batch, int32_t K, int32_t nrhs, int32_t keep) {
+    DenseLayout L{};
+    const int nb = dense_panel();
+    L.n_pad = (s.n + nb - 1) / nb * nb;
+    L.ld = L.n_pad;
+    const int64_t ntasks = (int64_t)batch * K;
+    if (keep) {
+        L.slot_stride = align_up((int64_t)L.ld * L.n_pad, kAlign / 8);
+        L.nslots = ntasks;
+    } else {
+        L.slot_stride = align_up((int64_t)L.ld * (L.n_pad + nrhs), kAlign / 8);
+        L.nslots = std::min<int64_t>(ntasks, 2LL * device_cus());
+    }
+    L.off_slots = 0;
+    int64_t off = align_up(L.nslots * L.slot_stride * 8, kAlign);
+    L.off_xk = off;
+    if (!keep) off = align_up(off + ntasks * (int64_t)s.n * nrhs * 8, kAlign);
+    L.off_tmp = off;
+    if (keep) off = align_up(off + ntasks * (int64_t)L.ld * nrhs * 8, kAlign);
+    L.total = off;
+    return L;
+}
+
+psp_status upload_plan(psp_plan p, int32_t ld) {
+    std::lock_guard<std::mutex> g(p->mu);
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    if (p->device >= 0 && p->device != dev) return fail(PSP_E_STATE, "plan was first used on another device");
+    const Symbolic& s = p->sym;
+    if (p->device < 0) {
+        hipDeviceProp_t prop;
+        HIP_TRY(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
+        if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+            return fail(PSP_E_UNSUPPORTED, std::string("libpsp is built for gfx950, device is ") + prop.gcnArchName);
+        std::vector<int32_t> rows(s.nnz);
+        for (int32_t i = 0; i < s.n; ++i)
+            for (int32_t e = s.row_ptr[i]; e < s.row_ptr[i + 1]; ++e) rows[e] = i;
+        HIP_TRY(hipMalloc(&p->d_perm, sizeof(int32_t) * s.n), "hipMalloc(plan)");
+        HIP_TRY(hipMalloc(&p->d_rows, sizeof(int32_t) * std::max(1, s.nnz)), "hipMalloc(plan)");
+        HIP_TRY(hipMalloc(&p->d_cols, sizeof(int32_t) * std::max(1, s.nnz)), "hipMalloc(plan)");
+        HIP_TRY(hipMemcpy(p->d_perm, s.perm.data(), sizeof(int32_t) * s.n, hipMemcpyHostToDevice), "hipMemcpy(plan)");
+        HIP_TRY(hipMemcpy(p->d_rows, rows.data(), sizeof(int32_t) * s.nnz, hipMemcpyHostToDevice), "hipMemcpy(plan)");
+        HIP_TRY(hipMemcpy(p->d_cols, s.col_idx.data(), sizeof(int32_t) * s.nnz, hipMemcpyHostToDevice), "hipMemcpy(plan)");
+        p->device = dev;
+    }
+    if (ld > 0 && p->d_dst_ld != ld) {
+        std::vector<int32_t> dst(s.nnz);
+        for (int32_t i = 0; i < s.n; ++i)
+            for (int32_t e = s.row_ptr[i]; e < s.row_ptr[i + 1]; ++e) {
+                const int64_t off = (int64_t)s.iperm[s.col_idx[e]] * ld + s.iperm[i];
+                if (off > INT32_MAX) return fail(PSP_E_UNSUPPORTED, "dense slot too large for int32 offsets");
+                dst[e] = (int32_t)off;
+            }
+        if (p->d_dst) HIP_TRY(hipFree(p->d_dst), "hipFree(plan)");
+        p->d_dst = nullptr;
+        HIP_TRY(hipMalloc(&p->d_dst, sizeof(int32_t) * std::max(1, s.nnz)), "hipMalloc(plan)");
+        HIP_TRY(hipMemcpy(p->d_dst, dst.data(), sizeof(int32_t) * s.nnz, hipMemcpyHostToDevice), "hipMemcpy(plan)");
+        p->d_dst_ld = ld;
+    }
+    return PSP_OK;
+}
+
+psp_status make_eps(int32_t K, const double* eps, EpsSet& es) {
+    if (K < 1 || K > kMaxK) return fail(PSP_E_INVALID, "K must be in 1.." + std::to_string(kMaxK));
+    if (!eps) return fail(PSP_E_INVALID, "eps must not be NULL");
+    es.K = K;
+    const psp_status st = psp_weights(K, eps, es.c);
+    if (st != PSP_OK) return st;
+    for (int k = 0; k < K; ++k) es.eps[k] = eps[k];
+    return PSP_OK;
+}
+
+int32_t resolve_path(const Symbolic& s, int32_t path) {
+    if (path != PSP_PATH_AUTO) return path;
+    return (s.n <= 256) ? PSP_PATH_DENSE : PSP_PATH_SPARSE;
+}
+
+psp_status check_prior_hip() {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "error left by earlier device work");
+    return PSP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* psp_last_error(void) { return g_err.c_str(); }
+
+int32_t psp_version(void) { return 100; }
+
+psp_status psp_weights(int32_t K, const double* eps, double* c) {
+    if (K < 1 || !eps || !c) return fail(PSP_E_INVALID, "psp_weights: K >= 1 and non-NULL arrays required");
+    for (int k = 0; k < K; ++k) {
+        if (!std::isfinite(eps[k]) || eps[k] == 0.0) return fail(PSP_E_EPS, "perturbation nodes must be finite and nonzero");
+        for (int l = 0; l < k; ++l)
+            if (eps[l] == eps[k]) return fail(PSP_E_EPS, "perturbation nodes must be distinct");
+    }
+    // Lagrange basis at zero: prod over l != k of eps_l / (eps_l - eps_k), in ascending l.
+    for (int k = 0; k < K; ++k) {
+        double w = 1.0;
+        for (int l = 0; l < K; ++l)
+            if (l != k) w = w * (eps[l] / (eps[l] - eps[k]));
+        c[k] = w;
+    }
+    return PSP_OK;
+}
+
+psp_status psp_plan_create(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, uint32_t flags, psp_plan* out) {
+    if (!out) return fail(PSP_E_INVALID, "out must not be NULL");
+    *out = nullptr;
+    const std::string why = validate_csr(n, row_ptr, col_idx);
+    if (!why.empty()) return fail(PSP_E_INVALID, "psp_plan_create: " + why);
+    if (flags & ~1u) return fail(PSP_E_INVALID, "psp_plan_create: unknown flag bits");
+    try {
+        auto p = std::make_unique<psp_plan_s>();
+        analyse(n, row_ptr, col_idx, (flags & PSP_ORDER_NATURAL) != 0, p->sym);
+        *out = p.release();
+    } catch (const std::bad_alloc&) {
+        return fail(PSP_E_NOMEM, "psp_plan_create: host allocation failed");
+    }
+    return PSP_OK;
+}
+
+psp_status psp_plan_info(psp_plan p, psp_plan_info_t* o) {
+    if (!p || !o) return fail(PSP_E_INVALID, "psp_plan_info: NULL argument");
+    const Symbolic& s = p->sym;
+    o->n = s.n;
+    o->nnz = s.nnz;
+    o->nnz_l = s.l_ptr[s.n];
+    o->ndense = s.ndense;
+    for (int t = 0; t < 3; ++t) o->nlev[t] = (int32_t)s.lev_ptr[t].size() - 1;
+    o->flops_dense_factor = s.flops_dense;
+    o->flops_sparse_factor = s.flops_sparse;
+    return PSP_OK;
+}
+
+psp_status psp_plan_export(psp_plan p, int32_t* perm, int32_t* iperm, int32_t* parent, int32_t* l_ptr,
+                           int32_t* l_idx, int32_t* lev_ptr[3], int32_t* lev_idx[3]) {
+    if (!p) return fail(PSP_E_INVALID, "psp_plan_export: NULL plan");
+    const Symbolic& s = p->sym;
+    auto cp = [](int32_t* dst, const std::vector<int32_t>& v) { if (dst && !v.empty()) std::memcpy(dst, v.data(), v.size() * 4); };
+    cp(perm, s.perm);
+    cp(iperm, s.iperm);
+    cp(parent, s.parent);
+    cp(l_ptr, s.l_ptr);
+    cp(l_idx, s.l_idx);
+    for (int t = 0; t < 3; ++t) {
+        if (lev_ptr) cp(lev_ptr[t], s.lev_ptr[t]);
+        if (lev_idx) cp(lev_idx[t], s.lev_idx[t]);
+    }
+    return PSP_OK;
+}
+
+void psp_plan_destroy(psp_plan p) { delete p; }
+
+size_t psp_workspace_bytes(psp_plan p, int32_t path, int32_t batch, int32_t K, int32_t nrhs, int32_t keep) {
+    if (!p || batch < 1 || K < 1 || nrhs < 0) return 0;
+    const int32_t pth = resolve_path(p->sym, path);
+    if (pth == PSP_PATH_DENSE) return (size_t)dense_layout(p->sym, batch, K, nrhs, keep).total;
+    if (pth == PSP_PATH_SPARSE) return sparse_workspace_bytes(p->sym, batch, K, nrhs, keep);
+    return 0;
+}
+
+psp_status psp_solve_batched(psp_plan p, int32_t path, int32_t batch, const double* values, int32_t K,
+                             const double* eps, const double* d, int32_t nrhs, const double* B, double* X,
+                             int32_t* info, void* ws, size_t ws_bytes, void* stream) {
+    if (!p || batch < 1 || !values || !B || !X || !info || !ws) return fail(PSP_E_INVALID, "psp_solve_batched: NULL argument or batch < 1");
+    if (nrhs < 1 || nrhs > 64) return fail(PSP_E_INVALID, "psp_solve_batched: nrhs must be in 1..64");
+    EpsSet es;
+    if (psp_status st = make_eps(K, eps, es)) return st;
+    if (psp_status st = check_prior_hip()) return st;
+    const Symbolic& s = p->sym;
+    const hipStream_t st = (hipStream_t)stream;
+    const int32_t pth = resolve_path(s, path);
+    if (pth == PSP_PATH_DENSE) {
+        if (s.n > 4096) return fail(PSP_E_UNSUPPORTED, "dense path supports n <= 4096");
+        const DenseLayout L = dense_layout(s, batch, K, nrhs, 0);
+        if (ws_bytes < (size_t)L.total) return fail(PSP_E_NOMEM, "workspace too small: need " + std::to_string(L.total) + " bytes");
+        if (psp_status r = upload_plan(p, L.ld)) return r;
+        char* w = (char*)ws;
+        DenseArgs a{};
+        a.n = s.n; a.n_pad = L.n_pad; a.ld = L.ld; a.nrhs = nrhs; a.nnz = s.nnz; a.batch = batch;
+        a.dst = p->d_dst; a.perm = p->d_perm; a.values = values; a.dvec = d; a.B = B;
+        a.Xk = (double*)(w + L.off_xk); a.info = info; a.slots = (double*)(w + L.off_slots);
+        a.slot_stride = L.slot_stride; a.ntasks = batch * K; a.keep = 0;
+        int occ = 1;
+        if (dense_occupancy(&occ) != hipSuccess || occ < 1) occ = 1;
+        const int grid = (int)std::min<int64_t>({(int64_t)a.ntasks, L.nslots, (int64_t)occ * device_cus()});
+        HIP_TRY(launch_dense_factor_solve(a, es, grid, st), "dense factor/solve launch");
+        HIP_TRY(launch_combine((int64_t)s.n * nrhs, batch, es, a.Xk, X, st), "combine launch");
+        return PSP_OK;
+    }
+    if (pth == PSP_PATH_SPARSE) {
+        const size_t need = sparse_workspace_bytes(s, batch, K, nrhs, 0);
+        if (ws_bytes < need) return fail(PSP_E_NOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
+        if (psp_status r = upload_plan(p, 0)) return r;
+        {
+            std::lock_guard<std::mutex> g(p->mu);
+            HIP_TRY(sparse_upload(s, p->sp), "sparse plan upload");
+        }
+        HIP_TRY(sparse_solve_batched(s, p->sp, batch, values, es, d, nrhs, B, X, info, ws, st), "sparse launch");
+        return PSP_OK;
+    }
+    return fail(PSP_E_INVALID, "unknown path");
+}
+
+psp_status psp_factor(psp_plan p, int32_t path, int32_t batch, const double* values, int32_t K, const double* eps,
+                      const double* d, int32_t* info, void* ws, size_t ws_bytes, void* stream, psp_factors* out) {
+    if (!out) return fail(PSP_E_INVALID, "out must not be NULL");
+    *out = nullptr;
+    if (!p || batch < 1 || !values || !info || !ws) return fail(PSP_E_INVALID, "psp_factor: NULL argument or batch < 1");
+    EpsSet es;
+    if (psp_status st = make_eps(K, eps, es)) return st;
+    if (psp_status st = check_prior_hip()) return st;
+    const Symbolic& s = p->sym;
+    const int32_t pth = resolve_path(s, path);
+    const hipStream_t st = (hipStream_t)stream;
+    auto f = std::make_unique<psp_factors_s>();
+    f->plan = p; f->path = pth; f->batch = batch; f->K = K; f->es = es;
+    f->ws = (char*)ws; f->ws_bytes = ws_bytes; f->info = info;
+    if (pth == PSP_PATH_DENSE) {
+        if (s.n > 4096) return fail(PSP_E_UNSUPPORTED, "dense path supports n <= 4096");
+        // the nrhs capacity is whatever the workspace holds beyond the factors
+        const DenseLayout L0 = dense_layout(s, batch, K, 0, 1);
+        if (ws_bytes < (size_t)L0.total) return fail(PSP_E_NOMEM, "workspace too small for the factors");
+        const int64_t per_rhs = (int64_t)batch * K * L0.ld * 8;
+        f->nrhs_cap = (int32_t)std::min<int64_t>(64, ((int64_t)ws_bytes - L0.off_tmp) / per_rhs);
+        if (psp_status r = upload_plan(p, L0.ld)) return r;
+        f->n_pad = L0.n_pad; f->ld = L0.ld; f->slot_stride = L0.slot_stride;
+        f->off_slots = L0.off_slots; f->off_tmp = L0.off_tmp;
+        DenseArgs a{};
+        a.n = s.n; a.n_pad = L0.n_pad; a.ld = L0.ld; a.nrhs = 0; a.nnz = s.nnz; a.batch = batch;
+        a.dst = p->d_dst; a.perm = p->d_perm; a.values = values; a.dvec = d; a.B = nullptr; a.Xk = nullptr;
+        a.info = info; a.slots = (double*)(f->ws + L0.off_slots); a.slot_stride = L0.slot_stride;
+        a.ntasks = batch * K; a.keep = 1;
+        int occ = 1;
+        if (dense_occupancy(&occ) != hipSuccess || occ < 1) occ = 1;
+        const int grid = (int)std::min<int64_t>((int64_t)a.ntasks, (int64_t)occ * device_cus());
+        HIP_TRY(launch_dense_factor_solve(a, es, grid, st), "dense factor launch");
+    } else if (pth == PSP_PATH_SPARSE) {
+        const size_t need0 = sparse_workspace_bytes(s, batch, K, 0, 1);
+        if (ws_bytes < need0) return fail(PSP_E_NOMEM, "workspace too small for the factors");
+        if (psp_status r = upload_plan(p, 0)) return r;
+        {
+            std::lock_guard<std::mutex> g(p->mu);
+            HIP_TRY(sparse_upload(s, p->sp), "sparse plan upload");
+        }
+        f->nrhs_cap = sparse_nrhs_capacity(s, batch, K, ws_bytes);
+        HIP_TRY(sparse_factor(s, p->sp, batch, values, es, d, info, ws, st), "sparse factor launch");
+    } else {
+        return fail(PSP_E_INVALID, "unknown path");
+    }
+    *out = f.release();
+    return PSP_OK;
+}
+
+psp_status psp_solve(psp_factors f, int32_t nrhs, const double* B, double* Xk, int32_t transpose, void* stream) {
+    if (!f || !B || !Xk) return fail(PSP_E_INVALID, "psp_solve: NULL argument");
+    if (nrhs < 1 || nrhs > f->nrhs_cap) return fail(PSP_E_INVALID, "psp_solve: nrhs outside 1..capacity of the workspace");
+    const Symbolic& s = f->plan->sym;
+    const hipStream_t st = (hipStream_t)stream;
+    if (f->path == PSP_PATH_DENSE) {
+        DenseSolveArgs a{};
+        a.n = s.n; a.n_pad = f->n_pad; a.ld = f->ld; a.nrhs = nrhs; a.K = f->K; a.ntasks = f->batch * f->K;
+        a.trans = transpose ? 1 : 0; a.perm = f->plan->d_perm; a.slots = (const double*)(f->ws + f->off_slots);
+        a.slot_stride = f->slot_stride; a.B = B; a.Xk = Xk; a.info = f->info; a.tmp = (double*)(f->ws + f->off_tmp);
+        const int grid = std::min(a.ntasks, 2 * device_cus());
+        HIP_TRY(launch_dense_solve(a, grid, st), "dense solve launch");
+        return PSP_OK;
+    }
+    HIP_TRY(sparse_solve(s, f->plan->sp, f->batch, f->es, nrhs, B, Xk, transpose, f->info, f->ws, st), "sparse solve launch");
+    return PSP_OK;
+}
+
+psp_status psp_combine(psp_factors f, int32_t nrhs, const double* Xk, double* X, void* stream) {
+    if (!f || !Xk || !X || nrhs < 1) return fail(PSP_E_INVALID, "psp_combine: bad argument");
+    HIP_TRY(launch_combine((int64_t)f->plan->sym.n * nrhs, f->batch, f->es, Xk, X, (hipStream_t)stream), "combine launch");
+    return PSP_OK;
+}
+
+psp_status psp_grad_values(psp_factors f, int32_t nrhs, const double* Lamk, const double* Xk, double* gA, void* stream) {
+    if (!f || !Lamk || !Xk || !gA || nrhs < 1) return fail(PSP_E_INVALID, "psp_grad_values: bad argument");
+    const Symbolic& s = f->plan->sym;
+    HIP_TRY(launch_grad_values(s.n, s.nnz, f->batch, nrhs, f->es, f->plan->d_rows, f->plan->d_cols, Lamk, Xk, gA,
+                               (hipStream_t)stream),
+            "gradient launch");
+    return PSP_OK;
+}
+
+psp_status psp_factors_release(psp_factors f) {
+    delete f;
+    return PSP_OK;
+}
+
+}  // extern "C"

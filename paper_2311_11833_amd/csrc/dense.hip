@@ -1,0 +1,383 @@
+// dense.hip -- dense batched pivot-free LU, substitutions and combine for
+// gfx950, one workgroup (4 waves) per perturbed system.
+//
+// Each perturbed system P (A_s + eps_k D) P^T is assembled from the CSR
+// values straight into a column-major n_pad x (n_pad + nrhs) slot of the
+// workspace (n_pad = n rounded up to the panel width; the padding rows and
+// columns form an identity block, which leaves the leading n x n block's
+// arithmetic untouched).  The right-hand sides ride along as extra columns,
+// so the forward substitution L y = P b is performed by the factorisation
+// itself, exactly as elimination on [A | b] does.
+//
+// Factorisation: right-looking, panels of NB = 32 columns:
+//   1. GETRF of the NB x NB diagonal block by one wave (lane = row,
+//      pivot row broadcast with readlane);
+//   2. TRSM of the block column below (one thread per row) and of the block
+//      row to the right, RHS columns included (one thread per column);
+//   3. rank-NB update of the trailing matrix in 64 x 64 tiles staged in LDS.
+// Every entry receives its updates a <- fma(-l, u, a) in ascending pivot
+// order and every multiplier is an IEEE division, which is the operation
+// sequence of the reference factorisation; the results are therefore
+// identical bit for bit.
+//
+// Back substitution U x = y: blocks of 64 columns from the right; the
+// diagonal triangle is staged in LDS and solved by one wave per RHS column,
+// then the rows above are updated in descending column order.
+#include "dense.h"
+
+namespace psp {
+
+constexpr int NB = 32;        // panel width
+constexpr int TB = 64;        // trailing-update tile (TB x TB)
+constexpr int SB = 64;        // triangular-solve block
+constexpr int WG = 256;       // threads per workgroup
+
+// ---------------------------------------------------------------- assembly
+__device__ void assemble(const DenseArgs& a, double* M, int s, double eps, int ncols) {
+    const int tid = threadIdx.x;
+    const int64_t total = (int64_t)a.ld * ncols;
+    for (int64_t i = tid; i < total; i += WG) M[i] = 0.0;
+    __syncthreads();
+    const double* v = a.values + (int64_t)s * a.nnz;
+    for (int e = tid; e < a.nnz; e += WG) M[a.dst[e]] = v[e];
+    __syncthreads();
+    for (int q = tid; q < a.n_pad; q += WG) {
+        const int64_t o = (int64_t)q * a.ld + q;
+        if (q < a.n) {
+            const double dq = a.dvec ? a.dvec[a.perm[q]] : 1.0;
+            M[o] = __dadd_rn(M[o], __dmul_rn(eps, dq));
+        } else {
+            M[o] = 1.0;
+        }
+    }
+    if (a.nrhs > 0) {
+        const double* b = a.B + (int64_t)s * a.n * a.nrhs;
+        for (int t = tid; t < a.n * a.nrhs; t += WG) {
+            const int q = t / a.nrhs, r = t % a.nrhs;
+            M[(int64_t)(a.n_pad + r) * a.ld + q] = b[(int64_t)a.perm[q] * a.nrhs + r];
+        }
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------- factorisation
+// Returns 0 or the 1-based position of the first bad pivot (uniform across the WG).
+__device__ int factor_slot(double* M, int n_pad, int ld, int ncols, double* lds) {
+    double* D = lds;                      // NB x NB, row-major D[i*NB + j]
+    double* Ls = lds + NB * NB;           // NB x TB, Ls[k*TB + row]
+    double* Us = Ls + NB * TB;            // NB x TB, Us[k*TB + col]
+    __shared__ int s_info;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid == 0) s_info = 0;
+    __syncthreads();
+    for (int c0 = 0; c0 < n_pad; c0 += NB) {
+        // 1. diagonal block, wave 0, lane = row
+        if (wave == 0) {
+            double r[NB];
+            const bool act = lane < NB;
+#pragma unroll
+            for (int j = 0; j < NB; ++j) r[j] = act ? M[(int64_t)(c0 + j) * ld + c0 + lane] : 0.0;
+            int bad = 0;
+#pragma unroll
+            for (int k = 0; k < NB; ++k) {
+                const double ukk = readlane_d(r[k], k);
+                if (bad_pivot(ukk)) { bad = c0 + k + 1; break; }
+                double u[NB];
+#pragma unroll
+                for (int j = k + 1; j < NB; ++j) u[j] = readlane_d(r[j], k);
+                if (lane > k) {
+                    const double l = r[k] / ukk;
+                    r[k] = l;
+#pragma unroll
+                    for (int j = k + 1; j < NB; ++j) r[j] = fmad(-l, u[j], r[j]);
+                }
+            }
+            if (act) {
+#pragma unroll
+                for (int j = 0; j < NB; ++j) {
+                    M[(int64_t)(c0 + j) * ld + c0 + lane] = r[j];
+                    D[lane * NB + j] = r[j];
+                }
+            }
+            if (lane == 0 && bad) s_info = bad;
+        }
+        __syncthreads();
+        if (s_info) return s_info;
+        // 2. block column below (rows) and block row to the right (columns, RHS included)
+        const int r0 = c0 + NB;
+        const int nrows = n_pad - r0;
+        const int ncolr = ncols - r0;
+        for (int t = tid; t < nrows + ncolr; t += WG) {
+            double r[NB];
+            if (t < nrows) {
+                const int i = r0 + t;
+#pragma unroll
+                for (int j = 0; j < NB; ++j) r[j] = M[(int64_t)(c0 + j) * ld + i];
+#pragma unroll
+                for (int k = 0; k < NB; ++k) {
+                    const double l = r[k] / D[k * NB + k];
+                    r[k] = l;
+#pragma unroll
+                    for (int j = k + 1; j < NB; ++j) r[j] = fmad(-l, D[k * NB + j], r[j]);
+                }
+#pragma unroll
+                for (int j = 0; j < NB; ++j) M[(int64_t)(c0 + j) * ld + i] = r[j];
+            } else {
+                const int j = r0 + (t - nrows);
+                double* col = M + (int64_t)j * ld + c0;
+#pragma unroll
+                for (int i = 0; i < NB; ++i) r[i] = col[i];
+#pragma unroll
+                for (int k = 0; k < NB; ++k)
+#pragma unroll
+                    for (int i = k + 1; i < NB; ++i) r[i] = fmad(-D[i * NB + k], r[k], r[i]);
+#pragma unroll
+                for (int i = 0; i < NB; ++i) col[i] = r[i];
+            }
+        }
+        __syncthreads();
+        // 3. trailing update A22 -= L21 * U12, 64 x 64 tiles, 4 x 4 outputs per thread
+        const int ty = tid >> 4, tx = tid & 15;
+        for (int ti = r0; ti < n_pad; ti += TB) {
+            for (int t = tid; t < NB * TB; t += WG) {
+                const int k = t / TB, rr = t % TB;
+                Ls[k * TB + rr] = (ti + rr < n_pad) ? M[(int64_t)(c0 + k) * ld + ti + rr] : 0.0;
+            }
+            for (int tj = r0; tj < ncols; tj += TB) {
+                for (int t = tid; t < NB * TB; t += WG) {
+                    const int cc = t / NB, k = t % NB;
+                    Us[k * TB + cc] = (tj + cc < ncols) ? M[(int64_t)(tj + cc) * ld + c0 + k] : 0.0;
+                }
+                __syncthreads();
+                double acc[4][4];
+                const int i0 = ti + ty * 4, j0 = tj + tx * 4;
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+                    for (int ii = 0; ii < 4; ++ii)
+                        acc[ii][jj] = (i0 + ii < n_pad && j0 + jj < ncols) ? M[(int64_t)(j0 + jj) * ld + i0 + ii] : 0.0;
+#pragma unroll 4
+                for (int k = 0; k < NB; ++k) {
+                    double lv[4], uv[4];
+#pragma unroll
+                    for (int ii = 0; ii < 4; ++ii) lv[ii] = Ls[k * TB + ty * 4 + ii];
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj) uv[jj] = Us[k * TB + tx * 4 + jj];
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+                        for (int ii = 0; ii < 4; ++ii) acc[ii][jj] = fmad(-lv[ii], uv[jj], acc[ii][jj]);
+                }
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+                    for (int ii = 0; ii < 4; ++ii)
+                        if (i0 + ii < n_pad && j0 + jj < ncols) M[(int64_t)(j0 + jj) * ld + i0 + ii] = acc[ii][jj];
+                __syncthreads();
+            }
+        }
+    }
+    return 0;
+}
+
+// ---------------------------------------------------------------- triangular solves
+// T holds nrhs columns of length n_pad with stride ld.  Variants (reference order):
+//   LOWER=1, TRANS=0: L y = b  (unit, a_ik = M[i + k ld]), ascending
+//   LOWER=0, TRANS=0: U x = y  (a_ij = M[i + j ld], diag u_jj), descending
+//   LOWER=1, TRANS=1: U^T z = w (a_ik = M[k + i ld], diag u_kk), ascending
+//   LOWER=0, TRANS=1: L^T v = z (unit, a_ij = M[j + i ld]), descending
+template <int LOWER, int TRANS>
+__device__ void tri_solve(const double* M, int n_pad, int ld, double* T, int nrhs, double* lds) {
+    constexpr bool UNIT = (LOWER && !TRANS) || (!LOWER && TRANS);
+    double* Tri = lds;                 // SB x SB, Tri[i*SB + j] = a(b0+i, b0+j)
+    double* Xs = lds + SB * SB;        // SB x nrhs (nrhs <= 64)
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nblk = (n_pad + SB - 1) / SB;
+    for (int bb = 0; bb < nblk; ++bb) {
+        const int blk = LOWER ? bb : nblk - 1 - bb;
+        const int b0 = blk * SB, bs = min(SB, n_pad - b0);
+        for (int t = tid; t < SB * SB; t += WG) {
+            const int i = t % SB, j = t / SB;
+            double v = 0.0;
+            if (i < bs && j < bs) v = TRANS ? M[(int64_t)(b0 + i) * ld + b0 + j] : M[(int64_t)(b0 + j) * ld + b0 + i];
+            Tri[i * SB + j] = v;
+        }
+        __syncthreads();
+        for (int r = wave; r < nrhs; r += WG / 64) {
+            double* tc = T + (int64_t)r * ld + b0;
+            double t = lane < bs ? tc[lane] : 0.0;
+            if (LOWER) {
+                for (int k = 0; k < bs; ++k) {
+                    double xk = readlane_d(t, k);
+                    if (!UNIT) xk = xk / Tri[k * SB + k];
+                    if (lane == k) t = xk;
+                    if (lane > k) t = fmad(-Tri[lane * SB + k], xk, t);
+                    if (lane == 0) Xs[k * 64 + r] = xk;
+                }
+            } else {
+                for (int k = bs - 1; k >= 0; --k) {
+                    double xk = readlane_d(t, k);
+                    if (!UNIT) xk = xk / Tri[k * SB + k];
+                    if (lane == k) t = xk;
+                    if (lane < k) t = fmad(-Tri[lane * SB + k], xk, t);
+                    if (lane == 0) Xs[k * 64 + r] = xk;
+                }
+            }
+            if (lane < bs) tc[lane] = t;
+        }
+        __syncthreads();
+        // rows outside the block
+        const int lo = LOWER ? b0 + bs : 0, hi = LOWER ? n_pad : b0;
+        for (int t = tid; t < (hi - lo) * nrhs; t += WG) {
+            const int i = lo + t % (hi - lo), r = t / (hi - lo);
+            double v = T[(int64_t)r * ld + i];
+            if (LOWER) {
+                for (int k = 0; k < bs; ++k) {
+                    const double a = TRANS ? M[(int64_t)i * ld + b0 + k] : M[(int64_t)(b0 + k) * ld + i];
+                    v = fmad(-a, Xs[k * 64 + r], v);
+                }
+            } else {
+                for (int k = bs - 1; k >= 0; --k) {
+                    const double a = TRANS ? M[(int64_t)i * ld + b0 + k] : M[(int64_t)(b0 + k) * ld + i];
+                    v = fmad(-a, Xs[k * 64 + r], v);
+                }
+            }
+            T[(int64_t)r * ld + i] = v;
+        }
+        __syncthreads();
+    }
+}
+
+constexpr int kLdsFactor = (NB * NB + 2 * NB * TB) * 8;
+constexpr int kLdsSolve = (SB * SB + SB * 64) * 8;
+constexpr int kLdsDense = kLdsFactor > kLdsSolve ? kLdsFactor : kLdsSolve;
+
+// ---------------------------------------------------------------- kernels
+// Fused: assemble, factor, forward (augmented), back substitution, write x_k.
+__global__ __launch_bounds__(WG) void dense_factor_solve_kernel(DenseArgs a, EpsSet es) {
+    extern __shared__ double lds[];
+    const int K = es.K;
+    for (int task = blockIdx.x; task < a.ntasks; task += gridDim.x) {
+        const int s = task / K, k = task % K;
+        double* M = a.slots + (a.keep ? (int64_t)task : (int64_t)blockIdx.x) * a.slot_stride;
+        const int ncols = a.n_pad + a.nrhs;
+        assemble(a, M, s, es.eps[k], ncols);
+        const int info = factor_slot(M, a.n_pad, a.ld, ncols, lds);
+        if (info == 0 && a.nrhs > 0) tri_solve<0, 0>(M, a.n_pad, a.ld, M + (int64_t)a.n_pad * a.ld, a.nrhs, lds);
+        if (threadIdx.x == 0) a.info[task] = info;
+        if (a.nrhs > 0) {
+            double* x = a.Xk + (int64_t)task * a.n * a.nrhs;
+            for (int t = threadIdx.x; t < a.n * a.nrhs; t += WG) {
+                const int q = t / a.nrhs, r = t % a.nrhs;
+                x[(int64_t)a.perm[q] * a.nrhs + r] =
+                    info ? __builtin_nan("") : M[(int64_t)(a.n_pad + r) * a.ld + q];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Split solve with stored factors, one WG per (s, k).
+__global__ __launch_bounds__(WG) void dense_solve_kernel(DenseSolveArgs a) {
+    extern __shared__ double lds[];
+    for (int task = blockIdx.x; task < a.ntasks; task += gridDim.x) {
+        const int s = task / a.K;
+        const double* M = a.slots + (int64_t)task * a.slot_stride;
+        double* T = a.tmp + (int64_t)task * a.ld * a.nrhs;
+        const double* b = a.B + (int64_t)s * a.n * a.nrhs;
+        for (int t = threadIdx.x; t < a.n_pad * a.nrhs; t += WG) {
+            const int q = t % a.n_pad, r = t / a.n_pad;
+            T[(int64_t)r * a.ld + q] = q < a.n ? b[(int64_t)a.perm[q] * a.nrhs + r] : 0.0;
+        }
+        __syncthreads();
+        const int info = a.info[task];
+        if (!info) {
+            if (!a.trans) {
+                tri_solve<1, 0>(M, a.n_pad, a.ld, T, a.nrhs, lds);
+                tri_solve<0, 0>(M, a.n_pad, a.ld, T, a.nrhs, lds);
+            } else {
+                tri_solve<1, 1>(M, a.n_pad, a.ld, T, a.nrhs, lds);
+                tri_solve<0, 1>(M, a.n_pad, a.ld, T, a.nrhs, lds);
+            }
+        }
+        double* x = a.Xk + (int64_t)task * a.n * a.nrhs;
+        for (int t = threadIdx.x; t < a.n * a.nrhs; t += WG) {
+            const int q = t / a.nrhs, r = t % a.nrhs;
+            x[(int64_t)a.perm[q] * a.nrhs + r] = info ? __builtin_nan("") : T[(int64_t)r * a.ld + q];
+        }
+        __syncthreads();
+    }
+}
+
+// X[s] = sum_k c_k Xk[s][k], ascending k, fma chain from zero.
+__global__ void combine_kernel(int64_t len, int32_t batch, EpsSet es, const double* Xk, double* X) {
+    const int64_t total = len * batch;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t s = t / len, i = t % len;
+        const double* p = Xk + s * es.K * len + i;
+        double acc = 0.0;
+        for (int k = 0; k < es.K; ++k) acc = fmad(es.c[k], p[k * len], acc);
+        X[t] = acc;
+    }
+}
+
+// gA[s][e] = - sum_k c_k sum_r Lam[s][k][i][r] X[s][k][j][r] on the CSR entries of A.
+__global__ void grad_values_kernel(int32_t n, int32_t nnz, int32_t batch, int32_t nrhs, EpsSet es,
+                                   const int32_t* rows, const int32_t* cols,
+                                   const double* Lamk, const double* Xk, double* gA) {
+    const int64_t total = (int64_t)nnz * batch;
+    const int64_t blk = (int64_t)n * nrhs;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t s = t / nnz;
+        const int e = (int)(t % nnz);
+        const int i = rows[e], j = cols[e];
+        double acc = 0.0;
+        for (int k = 0; k < es.K; ++k) {
+            const double* lam = Lamk + (s * es.K + k) * blk + (int64_t)i * nrhs;
+            const double* x = Xk + (s * es.K + k) * blk + (int64_t)j * nrhs;
+            double sum = 0.0;
+            for (int r = 0; r < nrhs; ++r) sum = fmad(lam[r], x[r], sum);
+            acc = fmad(es.c[k], sum, acc);
+        }
+        gA[t] = -acc;
+    }
+}
+
+// ---------------------------------------------------------------- host launchers
+int dense_lds_bytes() { return kLdsDense; }
+int dense_panel() { return NB; }
+
+hipError_t launch_dense_factor_solve(const DenseArgs& a, const EpsSet& es, int grid, hipStream_t st) {
+    hipLaunchKernelGGL(dense_factor_solve_kernel, dim3(grid), dim3(WG), kLdsDense, st, a, es);
+    return hipGetLastError();
+}
+
+hipError_t launch_dense_solve(const DenseSolveArgs& a, int grid, hipStream_t st) {
+    hipLaunchKernelGGL(dense_solve_kernel, dim3(grid), dim3(WG), kLdsDense, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_combine(int64_t len, int32_t batch, const EpsSet& es, const double* Xk, double* X, hipStream_t st) {
+    const int64_t total = len * batch;
+    int grid = (int)std::min<int64_t>((total + 255) / 256, 4096);
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(combine_kernel, dim3(grid), dim3(256), 0, st, len, batch, es, Xk, X);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_values(int32_t n, int32_t nnz, int32_t batch, int32_t nrhs, const EpsSet& es,
+                              const int32_t* rows, const int32_t* cols, const double* Lamk, const double* Xk,
+                              double* gA, hipStream_t st) {
+    const int64_t total = (int64_t)nnz * batch;
+    int grid = (int)std::min<int64_t>((total + 255) / 256, 8192);
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(grad_values_kernel, dim3(grid), dim3(256), 0, st, n, nnz, batch, nrhs, es, rows, cols, Lamk,
+                       Xk, gA);
+    return hipGetLastError();
+}
+
+hipError_t dense_occupancy(int* blocks_per_cu) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, dense_factor_solve_kernel, WG, kLdsDense);
+}
+
+}  // namespace psp

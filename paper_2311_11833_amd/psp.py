@@ -1,0 +1,245 @@
+"""ctypes binding of libpsp (include/psp.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+behind the C ABI.  PyTorch supplies device memory (tensors) and the stream
+(torch.cuda.current_stream()); the calls are asynchronous on that stream.
+If libpsp.so is missing this module raises at load time: there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpsp.so")
+
+PSP_OK, PSP_E_INVALID, PSP_E_EPS, PSP_E_NOMEM, PSP_E_HIP, PSP_E_STATE, PSP_E_UNSUPPORTED = range(7)
+PATHS = {"auto": 0, "dense": 1, "sparse": 2}
+ORDERS = {"md": 0, "natural": 1}
+EXPORTED = ["psp_last_error", "psp_version", "psp_plan_create", "psp_plan_info", "psp_plan_export",
+            "psp_plan_destroy", "psp_weights", "psp_workspace_bytes", "psp_solve_batched", "psp_factor",
+            "psp_solve", "psp_combine", "psp_grad_values", "psp_factors_release"]
+
+
+class PSPError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"psp status {status}: {msg}")
+        self.status = status
+
+
+class PlanInfo(C.Structure):
+    _fields_ = [("n", C.c_int32), ("nnz", C.c_int32), ("nnz_l", C.c_int64), ("ndense", C.c_int32),
+                ("nlev", C.c_int32 * 3), ("flops_dense_factor", C.c_int64), ("flops_sparse_factor", C.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        L.psp_last_error.restype = C.c_char_p
+        L.psp_version.restype = i32
+        L.psp_plan_create.argtypes = [i32, vp, vp, C.c_uint32, C.POINTER(vp)]
+        L.psp_plan_info.argtypes = [vp, C.POINTER(PlanInfo)]
+        L.psp_plan_export.argtypes = [vp, vp, vp, vp, vp, vp, C.POINTER(vp), C.POINTER(vp)]
+        L.psp_plan_destroy.argtypes = [vp]
+        L.psp_plan_destroy.restype = None
+        L.psp_weights.argtypes = [i32, vp, vp]
+        L.psp_workspace_bytes.argtypes = [vp, i32, i32, i32, i32, i32]
+        L.psp_workspace_bytes.restype = C.c_size_t
+        L.psp_solve_batched.argtypes = [vp, i32, i32, vp, i32, vp, vp, i32, vp, vp, vp, vp, C.c_size_t, vp]
+        L.psp_factor.argtypes = [vp, i32, i32, vp, i32, vp, vp, vp, vp, C.c_size_t, vp, C.POINTER(vp)]
+        L.psp_solve.argtypes = [vp, i32, vp, vp, i32, vp]
+        L.psp_combine.argtypes = [vp, i32, vp, vp, vp]
+        L.psp_grad_values.argtypes = [vp, i32, vp, vp, vp, vp]
+        L.psp_factors_release.argtypes = [vp]
+        for f in EXPORTED:
+            if f not in ("psp_last_error", "psp_version", "psp_plan_destroy", "psp_workspace_bytes"):
+                getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != PSP_OK:
+        raise PSPError(status, lib().psp_last_error().decode())
+
+
+def _np_ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _dptr(t):
+    """Device pointer of a CUDA tensor (or None)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def weights(eps) -> np.ndarray:
+    e = np.ascontiguousarray(eps, dtype=np.float64)
+    c = np.zeros_like(e)
+    _check(lib().psp_weights(len(e), _np_ptr(e), _np_ptr(c)))
+    return c
+
+
+@dataclass
+class SymbolicArrays:
+    perm: np.ndarray
+    iperm: np.ndarray
+    parent: np.ndarray
+    l_ptr: np.ndarray
+    l_idx: np.ndarray
+    levels: tuple   # ((ptr, idx) factor, L-solve, U-solve)
+
+
+class Plan:
+    """Symbolic analysis of one CSR pattern (host), reused by every numeric call."""
+
+    def __init__(self, indptr, indices, order: str = "md"):
+        ip = np.ascontiguousarray(indptr, dtype=np.int32)
+        ix = np.ascontiguousarray(indices, dtype=np.int32)
+        self.n = len(ip) - 1
+        self.nnz = int(ip[-1]) if len(ip) else 0
+        h = C.c_void_p()
+        _check(lib().psp_plan_create(self.n, _np_ptr(ip), _np_ptr(ix), ORDERS[order], C.byref(h)))
+        self._h = h
+        self._ws = {}
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.psp_plan_destroy(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> PlanInfo:
+        o = PlanInfo()
+        _check(lib().psp_plan_info(self._h, C.byref(o)))
+        return o
+
+    def export(self) -> SymbolicArrays:
+        inf = self.info()
+        n, nl = self.n, int(inf.nnz_l)
+        perm, iperm, parent = (np.zeros(n, np.int32) for _ in range(3))
+        lp = np.zeros(n + 1, np.int32)
+        li = np.zeros(max(nl, 1), np.int32)
+        lvp = [np.zeros(inf.nlev[t] + 1, np.int32) for t in range(3)]
+        lvi = [np.zeros(n, np.int32) for _ in range(3)]
+        P = (C.c_void_p * 3)(*[_np_ptr(a).value for a in lvp])
+        I = (C.c_void_p * 3)(*[_np_ptr(a).value for a in lvi])
+        _check(lib().psp_plan_export(self._h, _np_ptr(perm), _np_ptr(iperm), _np_ptr(parent), _np_ptr(lp),
+                                     _np_ptr(li), P, I))
+        return SymbolicArrays(perm, iperm, parent, lp, li[:nl], tuple(zip(lvp, lvi)))
+
+    def workspace_bytes(self, path="auto", batch=1, K=1, nrhs=1, keep=False) -> int:
+        return int(lib().psp_workspace_bytes(self._h, PATHS[path], batch, K, nrhs, 1 if keep else 0))
+
+    def workspace(self, nbytes: int, device):
+        """Device workspace cached per plan (grown on demand)."""
+        import torch
+        key = str(device)
+        w = self._ws.get(key)
+        if w is None or w.numel() < nbytes:
+            w = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+            self._ws[key] = w
+        return w
+
+
+def solve_batched(plan: Plan, values, eps, b, path: str = "auto", d=None, workspace=None, stream=None):
+    """Alg. 1 steps 1-4 in one fused launch (+ a combine launch).
+
+    values: (batch, nnz) float64 device tensor; b: (batch, n) or (batch, n, nrhs).
+    Returns (x, info) with x shaped like b and info (batch, K) int32.
+    """
+    import torch
+    batch = values.shape[0]
+    nrhs = 1 if b.dim() == 2 else b.shape[2]
+    eps_h = np.ascontiguousarray(eps, dtype=np.float64)
+    K = len(eps_h)
+    if values.dtype != torch.float64 or b.dtype != torch.float64:
+        raise TypeError("values and b must be float64")
+    if values.shape[1] != plan.nnz or b.shape[1] != plan.n or b.shape[0] != batch:
+        raise ValueError("shape mismatch with the plan")
+    x = torch.empty_like(b)
+    info = torch.empty((batch, K), dtype=torch.int32, device=values.device)
+    need = plan.workspace_bytes(path, batch, K, nrhs, keep=False)
+    ws = plan.workspace(need, values.device) if workspace is None else workspace
+    _check(lib().psp_solve_batched(plan.handle, PATHS[path], batch, _dptr(values), K, _np_ptr(eps_h), _dptr(d),
+                                   nrhs, _dptr(b.contiguous()), _dptr(x), _dptr(info), _dptr(ws), ws.numel(),
+                                   _stream(stream)))
+    return x, info
+
+
+class Factors:
+    """Perturbed factors of batch x K systems kept in a device workspace."""
+
+    def __init__(self, plan: Plan, values, eps, path: str = "auto", d=None, nrhs_cap: int = 64, stream=None):
+        import torch
+        self.plan = plan
+        self.batch = values.shape[0]
+        self.eps = np.ascontiguousarray(eps, dtype=np.float64)
+        self.K = len(self.eps)
+        self.c = weights(self.eps)
+        self.device = values.device
+        need = plan.workspace_bytes(path, self.batch, self.K, nrhs_cap, keep=True)
+        self.ws = torch.empty(max(need, 256), dtype=torch.uint8, device=values.device)
+        self.info = torch.empty((self.batch, self.K), dtype=torch.int32, device=values.device)
+        h = C.c_void_p()
+        _check(lib().psp_factor(plan.handle, PATHS[path], self.batch, _dptr(values.contiguous()), self.K,
+                                _np_ptr(self.eps), _dptr(d), _dptr(self.info), _dptr(self.ws), self.ws.numel(),
+                                _stream(stream), C.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.psp_factors_release(h)
+            self._h = None
+
+    def solve(self, B, transpose: bool = False, stream=None):
+        """Per-system solutions, (batch, K, n, nrhs)."""
+        import torch
+        B3 = B if B.dim() == 3 else B.unsqueeze(-1)
+        nrhs = B3.shape[2]
+        Xk = torch.empty((self.batch, self.K, self.plan.n, nrhs), dtype=torch.float64, device=self.device)
+        _check(lib().psp_solve(self._h, nrhs, _dptr(B3.contiguous()), _dptr(Xk), 1 if transpose else 0,
+                               _stream(stream)))
+        return Xk
+
+    def combine(self, Xk, stream=None):
+        import torch
+        nrhs = Xk.shape[3]
+        X = torch.empty((self.batch, self.plan.n, nrhs), dtype=torch.float64, device=self.device)
+        _check(lib().psp_combine(self._h, nrhs, _dptr(Xk.contiguous()), _dptr(X), _stream(stream)))
+        return X
+
+    def grad_values(self, Lamk, Xk, stream=None):
+        import torch
+        nrhs = Xk.shape[3]
+        gA = torch.empty((self.batch, self.plan.nnz), dtype=torch.float64, device=self.device)
+        _check(lib().psp_grad_values(self._h, nrhs, _dptr(Lamk.contiguous()), _dptr(Xk.contiguous()), _dptr(gA),
+                                     _stream(stream)))
+        return gA

@@ -1,0 +1,96 @@
+"""CPU-side checks of the C-ABI library: it loads without a GPU, exports every
+symbol include/psp.h declares, rejects bad input with the documented status,
+and its symbolic analysis equals the oracle's bit for bit."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def psp():
+    from paper_2311_11833_amd import psp as m
+    m.lib()
+    return m
+
+
+def test_exports_every_declared_symbol(psp):
+    hdr = open(os.path.join(ROOT, "include", "psp.h")).read()
+    declared = set(re.findall(r"PSP_API\s+[\w\s\*]+?\b(psp_\w+)\s*\(", hdr))
+    assert declared == set(psp.EXPORTED)
+    for name in declared:
+        assert hasattr(psp.lib(), name), name
+
+
+def test_weights_and_errors(psp, O):
+    for eps in ([1e-2, 5e-3, 2.5e-3], [1e-3 * 0.5 ** k for k in range(5)], [2e-3, -2e-3, 4e-3, -4e-3]):
+        assert np.array_equal(psp.weights(eps), O.weights(eps))
+    for bad in ([1e-3, 1e-3], [0.0], [float("nan")]):
+        with pytest.raises(psp.PSPError) as e:
+            psp.weights(bad)
+        assert e.value.status == psp.PSP_E_EPS
+
+
+@pytest.mark.parametrize("bad", ["unsorted", "range", "ptr"])
+def test_plan_rejects_malformed_csr(psp, bad):
+    ip = np.array([0, 2, 3, 5], np.int32)
+    ix = np.array([0, 2, 1, 0, 2], np.int32)
+    if bad == "unsorted":
+        ix = np.array([2, 0, 1, 0, 2], np.int32)
+    elif bad == "range":
+        ix = np.array([0, 3, 1, 0, 2], np.int32)
+    else:
+        ip = np.array([0, 3, 2, 5], np.int32)
+    with pytest.raises(psp.PSPError) as e:
+        psp.Plan(ip, ix)
+    assert e.value.status == psp.PSP_E_INVALID
+
+
+def _same(a, s):
+    return (np.array_equal(a.perm, s.perm) and np.array_equal(a.iperm, s.iperm) and np.array_equal(a.parent, s.parent)
+            and np.array_equal(a.l_ptr, s.lp) and np.array_equal(a.l_idx, s.li)
+            and all(np.array_equal(a.levels[t][0], s.levels[t][0]) and np.array_equal(a.levels[t][1], s.levels[t][1])
+                    for t in range(3)))
+
+
+@pytest.mark.parametrize("N", [14, 30, 118, 300, 500, 1354])
+@pytest.mark.parametrize("order", ["md", "natural"])
+def test_symbolic_bit_exact_with_oracle(psp, O, W, N, order):
+    ip, ix, _, _ = W.scenario_batch(N, 1)
+    n = len(ip) - 1
+    if order == "natural" and n > 1100:
+        pytest.skip("natural-order fill of the largest pattern is covered at n=1001")
+    a = psp.Plan(ip, ix, order=order).export()
+    s = O.symbolic(n, ip, ix, natural=(order == "natural"))
+    assert _same(a, s)
+
+
+def test_symbolic_bit_exact_random_patterns(psp, O):
+    import scipy.sparse as sp
+    rng = np.random.default_rng(21)
+    for t in range(12):
+        n = int(rng.integers(5, 300))
+        M = sp.random(n, n, density=float(rng.uniform(0.005, 0.1)), random_state=np.random.RandomState(t), format="csr")
+        M = (M + sp.eye(n)).tocsr()
+        if t % 3 == 0:
+            M = M.tolil()
+            for r in rng.choice(n, min(3, n), replace=False):
+                M[r, :] = 1.0
+            M = M.tocsr()
+        M.sort_indices()
+        ip, ix = M.indptr.astype(np.int32), M.indices.astype(np.int32)
+        assert _same(psp.Plan(ip, ix).export(), O.symbolic(n, ip, ix)), t
+
+
+@pytest.mark.slow
+def test_symbolic_bit_exact_large(psp, O, W):
+    """The 20,001-unknown pattern (10,000-bus network)."""
+    net = W.make_network(10000)
+    vm, va, p = W.make_state(10000, W.seed_state(10000, 0))
+    J = W.jacobian(net, vm, va, p)
+    a = psp.Plan(J.indptr, J.indices).export()
+    s = O.symbolic(J.n, J.indptr, J.indices)
+    assert _same(a, s)
