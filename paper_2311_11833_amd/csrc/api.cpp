@@ -294,9 +294,14 @@ psp_status psp_solve_batched(psp_plan p, int32_t path, int32_t batch, const doub
         a.slot_stride = L.slot_stride; a.ntasks = batch * K; a.keep = 0;
         int occ = 1;
         if (dense_occupancy(&occ) != hipSuccess || occ < 1) occ = 1;
-        const int grid = (int)std::min<int64_t>({(int64_t)a.ntasks, L.nslots, (int64_t)occ * device_cus()});
+        const int64_t resident = std::min<int64_t>(L.nslots, (int64_t)occ * device_cus());
+        // Enough Jacobians to fill the GPU: one task per Jacobian, combine fused.
+        a.per_jacobian = batch >= resident ? 1 : 0;
+        a.X = X;
+        const int64_t tasks = a.per_jacobian ? batch : a.ntasks;
+        const int grid = (int)std::min<int64_t>(tasks, resident);
         HIP_TRY(launch_dense_factor_solve(a, es, grid, st), "dense factor/solve launch");
-        HIP_TRY(launch_combine((int64_t)s.n * nrhs, batch, es, a.Xk, X, st), "combine launch");
+        if (!a.per_jacobian) HIP_TRY(launch_combine((int64_t)s.n * nrhs, batch, es, a.Xk, X, st), "combine launch");
         return PSP_OK;
     }
     if (pth == PSP_PATH_SPARSE) {

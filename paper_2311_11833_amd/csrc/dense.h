@@ -18,6 +18,8 @@ struct DenseArgs {
     int64_t slot_stride;      // doubles per slot
     int32_t ntasks;           // batch * K
     int32_t keep;             // slot = task (1) or slot = blockIdx.x (0)
+    int32_t per_jacobian;     // 1: one task per Jacobian, combine into X in-kernel
+    double* X;                // batch x n x nrhs (per_jacobian only)
 };
 
 struct DenseSolveArgs {

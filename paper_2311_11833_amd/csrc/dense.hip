@@ -81,15 +81,14 @@ __device__ int factor_slot(double* M, int n_pad, int ld, int ncols, double* lds)
 #pragma unroll
             for (int k = 0; k < NB; ++k) {
                 const double ukk = readlane_d(r[k], k);
-                if (bad_pivot(ukk)) { bad = c0 + k + 1; break; }
-                double u[NB];
+                if (!bad && bad_pivot(ukk)) bad = c0 + k + 1;
+                const bool below = lane > k;
+                const double l = r[k] / ukk;
+                r[k] = below ? l : r[k];
 #pragma unroll
-                for (int j = k + 1; j < NB; ++j) u[j] = readlane_d(r[j], k);
-                if (lane > k) {
-                    const double l = r[k] / ukk;
-                    r[k] = l;
-#pragma unroll
-                    for (int j = k + 1; j < NB; ++j) r[j] = fmad(-l, u[j], r[j]);
+                for (int j = k + 1; j < NB; ++j) {
+                    const double ukj = readlane_d(r[j], k);
+                    r[j] = below ? fmad(-l, ukj, r[j]) : r[j];
                 }
             }
             if (act) {
@@ -254,26 +253,36 @@ constexpr int kLdsDense = kLdsFactor > kLdsSolve ? kLdsFactor : kLdsSolve;
 
 // ---------------------------------------------------------------- kernels
 // Fused: assemble, factor, forward (augmented), back substitution, write x_k.
+// Tasks are either single systems (s, k), writing x_sk to Xk, or whole
+// Jacobians s (per_jacobian), which run their K systems one after the other
+// and accumulate x_s = sum_k c_k x_sk in ascending k straight into X, each
+// thread owning the same entries for every k.
 __global__ __launch_bounds__(WG) void dense_factor_solve_kernel(DenseArgs a, EpsSet es) {
     extern __shared__ double lds[];
     const int K = es.K;
-    for (int task = blockIdx.x; task < a.ntasks; task += gridDim.x) {
-        const int s = task / K, k = task % K;
-        double* M = a.slots + (a.keep ? (int64_t)task : (int64_t)blockIdx.x) * a.slot_stride;
-        const int ncols = a.n_pad + a.nrhs;
-        assemble(a, M, s, es.eps[k], ncols);
-        const int info = factor_slot(M, a.n_pad, a.ld, ncols, lds);
-        if (info == 0 && a.nrhs > 0) tri_solve<0, 0>(M, a.n_pad, a.ld, M + (int64_t)a.n_pad * a.ld, a.nrhs, lds);
-        if (threadIdx.x == 0) a.info[task] = info;
-        if (a.nrhs > 0) {
-            double* x = a.Xk + (int64_t)task * a.n * a.nrhs;
-            for (int t = threadIdx.x; t < a.n * a.nrhs; t += WG) {
-                const int q = t / a.nrhs, r = t % a.nrhs;
-                x[(int64_t)a.perm[q] * a.nrhs + r] =
-                    info ? __builtin_nan("") : M[(int64_t)(a.n_pad + r) * a.ld + q];
+    const int ntask = a.per_jacobian ? a.batch : a.ntasks;
+    for (int task = blockIdx.x; task < ntask; task += gridDim.x) {
+        const int s = a.per_jacobian ? task : task / K;
+        const int k0 = a.per_jacobian ? 0 : task % K, k1 = a.per_jacobian ? K : k0 + 1;
+        for (int k = k0; k < k1; ++k) {
+            const int sys = s * K + k;
+            double* M = a.slots + (a.keep ? (int64_t)sys : (int64_t)blockIdx.x) * a.slot_stride;
+            const int ncols = a.n_pad + a.nrhs;
+            assemble(a, M, s, es.eps[k], ncols);
+            const int info = factor_slot(M, a.n_pad, a.ld, ncols, lds);
+            if (info == 0 && a.nrhs > 0) tri_solve<0, 0>(M, a.n_pad, a.ld, M + (int64_t)a.n_pad * a.ld, a.nrhs, lds);
+            if (threadIdx.x == 0) a.info[sys] = info;
+            if (a.nrhs > 0) {
+                double* x = a.per_jacobian ? a.X + (int64_t)s * a.n * a.nrhs : a.Xk + (int64_t)sys * a.n * a.nrhs;
+                for (int t = threadIdx.x; t < a.n * a.nrhs; t += WG) {
+                    const int q = t / a.nrhs, r = t % a.nrhs;
+                    const double v = info ? __builtin_nan("") : M[(int64_t)(a.n_pad + r) * a.ld + q];
+                    double* dst = x + (int64_t)a.perm[q] * a.nrhs + r;
+                    *dst = a.per_jacobian ? fmad(es.c[k], v, k == 0 ? 0.0 : *dst) : v;
+                }
             }
+            __syncthreads();
         }
-        __syncthreads();
     }
 }
 

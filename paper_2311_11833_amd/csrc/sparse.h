@@ -6,17 +6,39 @@
 
 namespace psp {
 
-// Device copies of the plan's sparse index arrays.
+// Device copies of the plan's index arrays for the sparse path, in one
+// allocation.  Positions t index the L column pattern (CSC); the strictly
+// upper part of U is stored at the same positions (row k of U has the column
+// pattern of column k of L).
+struct SpIdx {
+    int32_t n, nnzl, nlev[3];
+    const int32_t* perm;        // n
+    const int32_t* l_ptr;       // n+1   L columns
+    const int32_t* l_idx;       // nnzl  rows of each L column, ascending
+    const int32_t* col_of;      // nnzl  column of position t
+    const int32_t* r_ptr;       // n+1   L rows
+    const int32_t* r_idx;       // nnzl  columns k of row i, ascending
+    const int32_t* r_pos;       // nnzl  position of (i, k) in the column pattern
+    const int32_t* src_l;       // nnzl  CSR entry of A feeding L position t (or -1)
+    const int32_t* src_u;       // nnzl  CSR entry of A feeding U position t (or -1)
+    const int32_t* src_d;       // n     CSR entry of the diagonal (or -1)
+    const int32_t* lev_ptr[3];  // factor, L-solve, U-solve
+    const int32_t* lev_idx[3];
+    const int32_t* lpos_ptr;    // factor level -> range in lpos
+    const int32_t* lpos;        // positions t of the columns of each factor level
+};
+
 struct SparseDevice {
     bool ready = false;
-    int32_t* buf = nullptr;   // one allocation holding every array below
-    const int32_t *perm, *l_ptr, *l_idx, *lrow_ptr, *lrow_idx, *upos, *lev_ptr[3], *lev_idx[3];
-    const int32_t *a_ptr, *a_row, *a_src;   // permuted matrix by columns: row and CSR entry index
-    const int32_t *diag_src;                 // per position: CSR entry of the diagonal or -1
+    int32_t* buf = nullptr;
+    SpIdx idx{};
+    std::vector<int32_t> h_lev_ptr[3];   // host copies for per-level launches
+    std::vector<int32_t> h_lpos_ptr;
 };
 
 hipError_t sparse_upload(const Symbolic& s, SparseDevice& d);
 void sparse_free(SparseDevice& d);
+bool sparse_fits_lds(const Symbolic& s, int32_t nrhs);
 size_t sparse_workspace_bytes(const Symbolic& s, int32_t batch, int32_t K, int32_t nrhs, int32_t keep);
 int32_t sparse_nrhs_capacity(const Symbolic& s, int32_t batch, int32_t K, size_t ws_bytes);
 hipError_t sparse_solve_batched(const Symbolic& s, const SparseDevice& d, int32_t batch, const double* values,

@@ -1,23 +1,540 @@
-// sparse.hip -- sparse (fill-pattern) path: placeholder until its kernels land.
+// sparse.hip -- pivot-free LU and substitutions on the plan's fill pattern,
+// level-scheduled, for gfx950.
+//
+// Factorisation in dot-product (Crout) form.  With R_i the columns k < i of
+// row i of L (ascending) and S symmetric, every factor entry is one sparse dot
+// product over the intersection of two rows of L:
+//   u_jj = a_jj - sum_{k in R_j}        l_jk u_kj
+//   u_jm = a_jm - sum_{k in R_j ^ R_m}  l_jk u_km     (m in struct L(:,j))
+//   l_ij = (a_ij - sum_{k in R_i ^ R_j} l_ik u_kj) / u_jj
+// each summed as an fma chain in ascending k -- the same operations, in the
+// same order, that left-looking elimination applies to that entry -- so the
+// factors equal the reference factors bit for bit.  Column j and row j depend
+// only on the columns in R_j, which are etree descendants of j, so the etree
+// height gives the schedule: per level, the diagonals first, then every other
+// entry of the level's columns and rows in parallel.
+//
+// Substitutions are row-oriented and level-scheduled, one lane per
+// right-hand side (RHS vectors are row-major, so a row's RHS values are
+// contiguous):
+//   L y = b     y_i -= l_ik y_k    k in R_i ascending
+//   U x = y     x_i = (y_i - sum u_im x_m) / u_ii, m in struct L(:,i) descending
+//   U^T z = w   z_i = (w_i - sum u_ki z_k) / u_ii, k in R_i ascending
+//   L^T v = z   v_i -= l_mi v_m   m in struct L(:,i) descending
+// which again reproduces the reference order per entry.
+//
+// Two executions of the same device code:
+//   * in-LDS: one workgroup per perturbed system keeps that system's factors
+//     and RHS in LDS and runs every level with workgroup barriers (used when
+//     (n + 2 nnz(L) + n nrhs) doubles fit);
+//   * global: factors in the workspace, one launch per level and phase, all
+//     systems of the batch in each launch.
+#include <algorithm>
+#include <climits>
+#include <vector>
+
+#include "dense.h"
 #include "sparse.h"
 
 namespace psp {
 
-hipError_t sparse_upload(const Symbolic&, SparseDevice&) { return hipErrorNotSupported; }
-void sparse_free(SparseDevice& d) { if (d.buf) (void)hipFree(d.buf); d.buf = nullptr; d.ready = false; }
-size_t sparse_workspace_bytes(const Symbolic&, int32_t, int32_t, int32_t, int32_t) { return 0; }
-int32_t sparse_nrhs_capacity(const Symbolic&, int32_t, int32_t, size_t) { return 0; }
-hipError_t sparse_solve_batched(const Symbolic&, const SparseDevice&, int32_t, const double*, const EpsSet&,
-                                const double*, int32_t, const double*, double*, int32_t*, void*, hipStream_t) {
-    return hipErrorNotSupported;
+namespace {
+constexpr int kLdsLimit = 152 * 1024;    // bytes of LDS the in-LDS kernel may use
+constexpr int kLdsThreads = 512;
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ double merge_dot(const SpIdx& ix, int a, int b, const double* lv, const double* uv,
+                                            double acc) {
+    // acc - sum_{k in R_a ^ R_b} lv[pos(a,k)] * uv[pos(b,k)], ascending k
+    int p = ix.r_ptr[a], pe = ix.r_ptr[a + 1];
+    int q = ix.r_ptr[b], qe = ix.r_ptr[b + 1];
+    while (p < pe && q < qe) {
+        const int ka = ix.r_idx[p], kb = ix.r_idx[q];
+        if (ka == kb) {
+            acc = fmad(-lv[ix.r_pos[p]], uv[ix.r_pos[q]], acc);
+            ++p;
+            ++q;
+        } else if (ka < kb) {
+            ++p;
+        } else {
+            ++q;
+        }
+    }
+    return acc;
 }
-hipError_t sparse_factor(const Symbolic&, const SparseDevice&, int32_t, const double*, const EpsSet&, const double*,
-                         int32_t*, void*, hipStream_t) {
-    return hipErrorNotSupported;
+
+__device__ __forceinline__ double diag_dot(const SpIdx& ix, int j, const double* lv, const double* uv, double acc) {
+    for (int p = ix.r_ptr[j]; p < ix.r_ptr[j + 1]; ++p) {
+        const int t = ix.r_pos[p];
+        acc = fmad(-lv[t], uv[t], acc);
+    }
+    return acc;
 }
-hipError_t sparse_solve(const Symbolic&, const SparseDevice&, int32_t, const EpsSet&, int32_t, const double*, double*,
-                        int32_t, const int32_t*, void*, hipStream_t) {
-    return hipErrorNotSupported;
+
+// Values of P (A + eps D) P^T on the fill pattern.
+__device__ __forceinline__ void gather_item(const SpIdx& ix, int t, const double* v, double* lv, double* uv) {
+    const int sl = ix.src_l[t], su = ix.src_u[t];
+    lv[t] = sl >= 0 ? v[sl] : 0.0;
+    uv[t] = su >= 0 ? v[su] : 0.0;
+}
+
+__device__ __forceinline__ double gather_diag(const SpIdx& ix, int j, const double* v, double eps, const double* dvec) {
+    const int sd = ix.src_d[j];
+    const double a = sd >= 0 ? v[sd] : 0.0;
+    const double dq = dvec ? dvec[ix.perm[j]] : 1.0;
+    return __dadd_rn(a, __dmul_rn(eps, dq));
+}
+
+// phase B item: it < npos -> U entry at position t, else L entry at position t
+__device__ __forceinline__ void factor_item(const SpIdx& ix, int t, bool is_l, double* ud, double* lv, double* uv) {
+    const int j = ix.col_of[t], m = ix.l_idx[t];
+    if (!is_l) {
+        uv[t] = merge_dot(ix, j, m, lv, uv, uv[t]);
+    } else {
+        lv[t] = merge_dot(ix, m, j, lv, uv, lv[t]) / ud[j];
+    }
+}
+
+template <int TRANS>
+__device__ __forceinline__ double fwd_row(const SpIdx& ix, int i, int r, int nrhs, const double* ud, const double* lv,
+                                          const double* uv, const double* y) {
+    double acc = y[(int64_t)i * nrhs + r];
+    for (int p = ix.r_ptr[i]; p < ix.r_ptr[i + 1]; ++p) {
+        const double a = TRANS ? uv[ix.r_pos[p]] : lv[ix.r_pos[p]];
+        acc = fmad(-a, y[(int64_t)ix.r_idx[p] * nrhs + r], acc);
+    }
+    return TRANS ? acc / ud[i] : acc;
+}
+
+template <int TRANS>
+__device__ __forceinline__ double bwd_row(const SpIdx& ix, int i, int r, int nrhs, const double* ud, const double* lv,
+                                          const double* uv, const double* y) {
+    double acc = y[(int64_t)i * nrhs + r];
+    for (int t = ix.l_ptr[i + 1] - 1; t >= ix.l_ptr[i]; --t) {
+        const double a = TRANS ? lv[t] : uv[t];
+        acc = fmad(-a, y[(int64_t)ix.l_idx[t] * nrhs + r], acc);
+    }
+    return TRANS ? acc : acc / ud[i];
+}
+
+struct SpArgs {
+    SpIdx ix;
+    int32_t nnz, nrhs, ntasks, K, trans;
+    const double* values;   // batch x nnz
+    const double* dvec;
+    const double* B;        // batch x n x nrhs
+    double* Xk;             // batch x K x n x nrhs
+    int32_t* info;          // batch x K
+    double* fac;            // global factors: ntasks x fstride (ud | lv | uv)
+    int64_t fstride;
+    double* y;              // global RHS scratch: ntasks x n x nrhs
+    double* X;              // batch x n x nrhs, combined in-kernel when per_jacobian
+    int32_t per_jacobian, batch;
+};
+
+// ---------------------------------------------------------------- in-LDS kernel
+__global__ __launch_bounds__(kLdsThreads) void sparse_lds_kernel(SpArgs a, EpsSet es, int store_factors) {
+    extern __shared__ double lds[];
+    const SpIdx& ix = a.ix;
+    const int n = ix.n, nl = ix.nnzl, nrhs = a.nrhs, tid = threadIdx.x;
+    double* ud = lds;
+    double* lv = ud + n;
+    double* uv = lv + nl;
+    double* y = uv + nl;
+    __shared__ int s_bad;
+    const int ntask = a.per_jacobian ? a.batch : a.ntasks;
+    for (int tk = blockIdx.x; tk < ntask; tk += gridDim.x) {
+      const int s = a.per_jacobian ? tk : tk / es.K;
+      const int k0 = a.per_jacobian ? 0 : tk % es.K, k1 = a.per_jacobian ? es.K : k0 + 1;
+      for (int kk = k0; kk < k1; ++kk) {
+        const int task = s * es.K + kk;
+        const double* v = a.values + (int64_t)s * a.nnz;
+        if (tid == 0) s_bad = INT_MAX;
+        for (int t = tid; t < nl; t += kLdsThreads) gather_item(ix, t, v, lv, uv);
+        for (int j = tid; j < n; j += kLdsThreads) ud[j] = gather_diag(ix, j, v, es.eps[kk], a.dvec);
+        if (nrhs > 0) {
+            const double* b = a.B + (int64_t)s * n * nrhs;
+            for (int t = tid; t < n * nrhs; t += kLdsThreads) {
+                const int q = t / nrhs, r = t % nrhs;
+                y[t] = b[(int64_t)ix.perm[q] * nrhs + r];
+            }
+        }
+        __syncthreads();
+        for (int l = 0; l < ix.nlev[0]; ++l) {
+            const int c0 = ix.lev_ptr[0][l], c1 = ix.lev_ptr[0][l + 1];
+            for (int t = c0 + tid; t < c1; t += kLdsThreads) {
+                const int j = ix.lev_idx[0][t];
+                const double u = diag_dot(ix, j, lv, uv, ud[j]);
+                ud[j] = u;
+                if (bad_pivot(u)) atomicMin(&s_bad, j + 1);
+            }
+            __syncthreads();
+            const int p0 = ix.lpos_ptr[l], np = ix.lpos_ptr[l + 1] - p0;
+            for (int it = tid; it < 2 * np; it += kLdsThreads) {
+                const bool is_l = it >= np;
+                factor_item(ix, ix.lpos[p0 + (is_l ? it - np : it)], is_l, ud, lv, uv);
+            }
+            __syncthreads();
+        }
+        const int bad = s_bad == INT_MAX ? 0 : s_bad;
+        if (store_factors) {
+            double* f = a.fac + (int64_t)task * a.fstride;
+            for (int t = tid; t < n + 2 * nl; t += kLdsThreads) f[t] = lds[t];
+        }
+        if (nrhs > 0) {
+            if (!bad) {
+                for (int l = 0; l < ix.nlev[1]; ++l) {
+                    const int c0 = ix.lev_ptr[1][l], c1 = ix.lev_ptr[1][l + 1];
+                    for (int t = c0 * nrhs + tid; t < c1 * nrhs; t += kLdsThreads) {
+                        const int i = ix.lev_idx[1][t / nrhs], r = t % nrhs;
+                        y[(int64_t)i * nrhs + r] = fwd_row<0>(ix, i, r, nrhs, ud, lv, uv, y);
+                    }
+                    __syncthreads();
+                }
+                for (int l = 0; l < ix.nlev[2]; ++l) {
+                    const int c0 = ix.lev_ptr[2][l], c1 = ix.lev_ptr[2][l + 1];
+                    for (int t = c0 * nrhs + tid; t < c1 * nrhs; t += kLdsThreads) {
+                        const int i = ix.lev_idx[2][t / nrhs], r = t % nrhs;
+                        y[(int64_t)i * nrhs + r] = bwd_row<0>(ix, i, r, nrhs, ud, lv, uv, y);
+                    }
+                    __syncthreads();
+                }
+            }
+            double* x = a.per_jacobian ? a.X + (int64_t)s * n * nrhs : a.Xk + (int64_t)task * n * nrhs;
+            for (int t = tid; t < n * nrhs; t += kLdsThreads) {
+                const int q = t / nrhs, r = t % nrhs;
+                const double val = bad ? __builtin_nan("") : y[t];
+                double* dst = x + (int64_t)ix.perm[q] * nrhs + r;
+                *dst = a.per_jacobian ? fmad(es.c[kk], val, kk == 0 ? 0.0 : *dst) : val;
+            }
+        }
+        if (tid == 0) a.info[task] = bad;
+        __syncthreads();
+      }
+    }
+}
+
+// ---------------------------------------------------------------- global, per-level kernels
+__global__ void sp_gather_kernel(SpArgs a, EpsSet es) {
+    const SpIdx& ix = a.ix;
+    const int n = ix.n, nl = ix.nnzl;
+    const int64_t per = n + nl;
+    const int64_t total = per * a.ntasks;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+        const int task = (int)(g / per), t = (int)(g % per);
+        const int s = task / es.K, kk = task % es.K;
+        const double* v = a.values + (int64_t)s * a.nnz;
+        double* ud = a.fac + (int64_t)task * a.fstride;
+        if (t < nl) gather_item(ix, t, v, ud + n, ud + n + nl);
+        else ud[t - nl] = gather_diag(ix, t - nl, v, es.eps[kk], a.dvec);
+        if (t == 0) a.info[task] = INT_MAX;
+    }
+}
+
+__global__ void sp_diag_kernel(SpArgs a, int c0, int cnt) {
+    const SpIdx& ix = a.ix;
+    const int n = ix.n, nl = ix.nnzl;
+    const int64_t total = (int64_t)cnt * a.ntasks;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+        const int task = (int)(g / cnt), j = ix.lev_idx[0][c0 + (int)(g % cnt)];
+        double* ud = a.fac + (int64_t)task * a.fstride;
+        const double u = diag_dot(ix, j, ud + n, ud + n + nl, ud[j]);
+        ud[j] = u;
+        if (bad_pivot(u)) atomicMin(&a.info[task], j + 1);
+    }
+}
+
+__global__ void sp_offdiag_kernel(SpArgs a, int p0, int np) {
+    const SpIdx& ix = a.ix;
+    const int n = ix.n, nl = ix.nnzl;
+    const int64_t total = (int64_t)2 * np * a.ntasks;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+        const int task = (int)(g / (2 * np)), it = (int)(g % (2 * np));
+        const bool is_l = it >= np;
+        double* ud = a.fac + (int64_t)task * a.fstride;
+        factor_item(ix, ix.lpos[p0 + (is_l ? it - np : it)], is_l, ud, ud + n, ud + n + nl);
+    }
+}
+
+__global__ void sp_info_kernel(int32_t* info, int ntasks) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < ntasks && info[t] == INT_MAX) info[t] = 0;
+}
+
+__global__ void sp_rhs_in_kernel(SpArgs a) {
+    const SpIdx& ix = a.ix;
+    const int n = ix.n, nrhs = a.nrhs;
+    const int64_t per = (int64_t)n * nrhs, total = per * a.ntasks;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+        const int task = (int)(g / per), t = (int)(g % per);
+        const int s = task / a.K, q = t / nrhs, r = t % nrhs;
+        a.y[g] = a.B[(int64_t)s * per + (int64_t)ix.perm[q] * nrhs + r];
+    }
+}
+
+template <int UPPER_PASS>
+__global__ void sp_solve_level_kernel(SpArgs a, int c0, int cnt) {
+    const SpIdx& ix = a.ix;
+    const int n = ix.n, nl = ix.nnzl, nrhs = a.nrhs;
+    const int64_t per = (int64_t)cnt * nrhs, total = per * a.ntasks;
+    // pass 0: L (or U^T when transposed), ascending schedule; pass 1: U (or L^T), descending schedule
+    const int sched = UPPER_PASS ? 2 : 1;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+        const int task = (int)(g / per), t = (int)(g % per);
+        if (a.info[task]) continue;
+        const int i = ix.lev_idx[sched][c0 + t / nrhs], r = t % nrhs;
+        const double* ud = a.fac + (int64_t)task * a.fstride;
+        double* y = a.y + (int64_t)task * n * nrhs;
+        double v;
+        if (!UPPER_PASS) v = a.trans ? fwd_row<1>(ix, i, r, nrhs, ud, ud + n, ud + n + nl, y)
+                                     : fwd_row<0>(ix, i, r, nrhs, ud, ud + n, ud + n + nl, y);
+        else v = a.trans ? bwd_row<1>(ix, i, r, nrhs, ud, ud + n, ud + n + nl, y)
+                         : bwd_row<0>(ix, i, r, nrhs, ud, ud + n, ud + n + nl, y);
+        y[(int64_t)i * nrhs + r] = v;
+    }
+}
+
+__global__ void sp_rhs_out_kernel(SpArgs a) {
+    const SpIdx& ix = a.ix;
+    const int n = ix.n, nrhs = a.nrhs;
+    const int64_t per = (int64_t)n * nrhs, total = per * a.ntasks;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+        const int task = (int)(g / per), t = (int)(g % per);
+        const int q = t / nrhs, r = t % nrhs;
+        a.Xk[(int64_t)task * per + (int64_t)ix.perm[q] * nrhs + r] = a.info[task] ? __builtin_nan("") : a.y[g];
+    }
+}
+
+int grid_for(int64_t items, int threads) {
+    int64_t g = (items + threads - 1) / threads;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(g, 65536));
+}
+
+int64_t lds_bytes(const Symbolic& s, int nrhs) {
+    return ((int64_t)s.n + 2 * (int64_t)s.l_ptr[s.n] + (int64_t)s.n * nrhs) * 8;
+}
+
+int64_t align256(int64_t v) { return (v + 255) / 256 * 256; }
+
+int64_t fstride_of(const Symbolic& s) { return (s.n + 2 * (int64_t)s.l_ptr[s.n] + 31) / 32 * 32; }
+
+// workspace: [ factors (ntasks x fstride) | y (ntasks x n x nrhs) | Xk (ntasks x n x nrhs) ]
+struct SpLayout {
+    int64_t off_fac, off_y, off_xk, total;
+};
+
+SpLayout sp_layout(const Symbolic& s, int32_t batch, int32_t K, int32_t nrhs, int32_t keep) {
+    const int64_t ntasks = (int64_t)batch * K;
+    SpLayout L{};
+    const bool lds = !keep && sparse_fits_lds(s, nrhs);
+    L.off_fac = 0;
+    int64_t off = lds ? 0 : align256(ntasks * fstride_of(s) * 8);
+    L.off_y = off;
+    if (!lds) off = align256(off + ntasks * (int64_t)s.n * nrhs * 8);
+    L.off_xk = off;
+    if (!keep) off = align256(off + ntasks * (int64_t)s.n * nrhs * 8);
+    L.total = std::max<int64_t>(off, 256);
+    return L;
+}
+
+SpArgs make_args(const SparseDevice& d, const Symbolic& s, int32_t ntasks, int32_t K, int32_t nrhs) {
+    SpArgs a{};
+    a.ix = d.idx;
+    a.nnz = s.nnz;
+    a.nrhs = nrhs;
+    a.ntasks = ntasks;
+    a.K = K;
+    a.fstride = fstride_of(s);
+    return a;
+}
+
+hipError_t factor_global(const SparseDevice& d, SpArgs a, const EpsSet& es, hipStream_t st) {
+    hipLaunchKernelGGL(sp_gather_kernel, dim3(grid_for((int64_t)(a.ix.n + a.ix.nnzl) * a.ntasks, kThreads)),
+                       dim3(kThreads), 0, st, a, es);
+    for (int l = 0; l < a.ix.nlev[0]; ++l) {
+        const int c0 = d.h_lev_ptr[0][l], cnt = d.h_lev_ptr[0][l + 1] - c0;
+        hipLaunchKernelGGL(sp_diag_kernel, dim3(grid_for((int64_t)cnt * a.ntasks, kThreads)), dim3(kThreads), 0, st,
+                           a, c0, cnt);
+        const int p0 = d.h_lpos_ptr[l], np = d.h_lpos_ptr[l + 1] - p0;
+        if (np > 0)
+            hipLaunchKernelGGL(sp_offdiag_kernel, dim3(grid_for((int64_t)2 * np * a.ntasks, kThreads)), dim3(kThreads),
+                               0, st, a, p0, np);
+    }
+    hipLaunchKernelGGL(sp_info_kernel, dim3((a.ntasks + 255) / 256), dim3(256), 0, st, a.info, a.ntasks);
+    return hipGetLastError();
+}
+
+hipError_t solve_global(const SparseDevice& d, SpArgs a, hipStream_t st) {
+    const int64_t items = (int64_t)a.ix.n * a.nrhs * a.ntasks;
+    hipLaunchKernelGGL(sp_rhs_in_kernel, dim3(grid_for(items, kThreads)), dim3(kThreads), 0, st, a);
+    // forward pass uses the L-solve levels, backward pass the U-solve levels (both for the transposed solve)
+    for (int l = 0; l < a.ix.nlev[1]; ++l) {
+        const int c0 = d.h_lev_ptr[1][l], cnt = d.h_lev_ptr[1][l + 1] - c0;
+        hipLaunchKernelGGL(sp_solve_level_kernel<0>, dim3(grid_for((int64_t)cnt * a.nrhs * a.ntasks, kThreads)),
+                           dim3(kThreads), 0, st, a, c0, cnt);
+    }
+    for (int l = 0; l < a.ix.nlev[2]; ++l) {
+        const int c0 = d.h_lev_ptr[2][l], cnt = d.h_lev_ptr[2][l + 1] - c0;
+        hipLaunchKernelGGL(sp_solve_level_kernel<1>, dim3(grid_for((int64_t)cnt * a.nrhs * a.ntasks, kThreads)),
+                           dim3(kThreads), 0, st, a, c0, cnt);
+    }
+    hipLaunchKernelGGL(sp_rhs_out_kernel, dim3(grid_for(items, kThreads)), dim3(kThreads), 0, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+bool sparse_fits_lds(const Symbolic& s, int32_t nrhs) { return lds_bytes(s, nrhs) <= kLdsLimit; }
+
+hipError_t sparse_upload(const Symbolic& s, SparseDevice& d) {
+    if (d.ready) return hipSuccess;
+    const int n = s.n, nl = s.l_ptr[n];
+    std::vector<int32_t> col_of(nl), r_pos(nl), src_l(nl, -1), src_u(nl, -1), src_d(n, -1);
+    for (int j = 0; j < n; ++j)
+        for (int t = s.l_ptr[j]; t < s.l_ptr[j + 1]; ++t) col_of[t] = j;
+    auto pos_in_col = [&](int col, int row) {
+        const int* b = s.l_idx.data() + s.l_ptr[col];
+        const int* e = s.l_idx.data() + s.l_ptr[col + 1];
+        const int* p = std::lower_bound(b, e, row);
+        return (p != e && *p == row) ? (int)(p - s.l_idx.data()) : -1;
+    };
+    for (int i = 0; i < n; ++i)
+        for (int p = s.lrow_ptr[i]; p < s.lrow_ptr[i + 1]; ++p) r_pos[p] = pos_in_col(s.lrow_idx[p], i);
+    for (int r = 0; r < n; ++r)
+        for (int e = s.row_ptr[r]; e < s.row_ptr[r + 1]; ++e) {
+            const int pr = s.iperm[r], pc = s.iperm[s.col_idx[e]];
+            if (pr == pc) src_d[pr] = e;
+            else if (pr > pc) src_l[pos_in_col(pc, pr)] = e;
+            else src_u[pos_in_col(pr, pc)] = e;
+        }
+    // positions of the columns of each factor level
+    const int L0 = (int)s.lev_ptr[0].size() - 1;
+    std::vector<int32_t> lpos_ptr(L0 + 1, 0), lpos;
+    lpos.reserve(nl);
+    for (int l = 0; l < L0; ++l) {
+        for (int t = s.lev_ptr[0][l]; t < s.lev_ptr[0][l + 1]; ++t) {
+            const int j = s.lev_idx[0][t];
+            for (int q = s.l_ptr[j]; q < s.l_ptr[j + 1]; ++q) lpos.push_back(q);
+        }
+        lpos_ptr[l + 1] = (int32_t)lpos.size();
+    }
+    std::vector<const std::vector<int32_t>*> parts = {&s.perm, &s.l_ptr, &s.l_idx, &col_of, &s.lrow_ptr, &s.lrow_idx,
+                                                      &r_pos, &src_l, &src_u, &src_d};
+    for (int t = 0; t < 3; ++t) { parts.push_back(&s.lev_ptr[t]); parts.push_back(&s.lev_idx[t]); }
+    parts.push_back(&lpos_ptr);
+    parts.push_back(&lpos);
+    std::vector<int64_t> off;
+    int64_t total = 0;
+    for (auto* p : parts) { off.push_back(total); total += ((int64_t)p->size() + 63) / 64 * 64; }
+    std::vector<int32_t> host(std::max<int64_t>(total, 1), 0);
+    for (size_t i = 0; i < parts.size(); ++i) std::copy(parts[i]->begin(), parts[i]->end(), host.begin() + off[i]);
+    hipError_t e = hipMalloc(&d.buf, sizeof(int32_t) * host.size());
+    if (e != hipSuccess) return e;
+    e = hipMemcpy(d.buf, host.data(), sizeof(int32_t) * host.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return e;
+    int k = 0;
+    auto ptr = [&](void) { return (const int32_t*)(d.buf + off[k++]); };
+    SpIdx& ix = d.idx;
+    ix.n = n;
+    ix.nnzl = nl;
+    ix.perm = ptr(); ix.l_ptr = ptr(); ix.l_idx = ptr(); ix.col_of = ptr(); ix.r_ptr = ptr(); ix.r_idx = ptr();
+    ix.r_pos = ptr(); ix.src_l = ptr(); ix.src_u = ptr(); ix.src_d = ptr();
+    for (int t = 0; t < 3; ++t) {
+        ix.lev_ptr[t] = ptr();
+        ix.lev_idx[t] = ptr();
+        ix.nlev[t] = (int32_t)s.lev_ptr[t].size() - 1;
+        d.h_lev_ptr[t] = s.lev_ptr[t];
+    }
+    ix.lpos_ptr = ptr();
+    ix.lpos = ptr();
+    d.h_lpos_ptr = lpos_ptr;
+    d.ready = true;
+    return hipSuccess;
+}
+
+void sparse_free(SparseDevice& d) {
+    if (d.buf) (void)hipFree(d.buf);
+    d.buf = nullptr;
+    d.ready = false;
+}
+
+size_t sparse_workspace_bytes(const Symbolic& s, int32_t batch, int32_t K, int32_t nrhs, int32_t keep) {
+    return (size_t)sp_layout(s, batch, K, nrhs, keep).total;
+}
+
+int32_t sparse_nrhs_capacity(const Symbolic& s, int32_t batch, int32_t K, size_t ws_bytes) {
+    const SpLayout L = sp_layout(s, batch, K, 0, 1);
+    const int64_t per = (int64_t)batch * K * s.n * 8;
+    return (int32_t)std::min<int64_t>(64, std::max<int64_t>(0, ((int64_t)ws_bytes - L.off_y) / per));
+}
+
+hipError_t sparse_solve_batched(const Symbolic& s, const SparseDevice& d, int32_t batch, const double* values,
+                                const EpsSet& es, const double* dvec, int32_t nrhs, const double* B, double* X,
+                                int32_t* info, void* ws, hipStream_t st) {
+    const int32_t ntasks = batch * es.K;
+    const SpLayout L = sp_layout(s, batch, es.K, nrhs, 0);
+    char* w = (char*)ws;
+    SpArgs a = make_args(d, s, ntasks, es.K, nrhs);
+    a.values = values; a.dvec = dvec; a.B = B; a.info = info;
+    a.Xk = (double*)(w + L.off_xk);
+    if (sparse_fits_lds(s, nrhs)) {
+        const int lds = (int)lds_bytes(s, nrhs);
+        hipError_t e = hipFuncSetAttribute((const void*)sparse_lds_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        if (e != hipSuccess) return e;
+        int dev = 0, cus = 256;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        const int resident = cus * std::max(1, (160 * 1024) / std::max(lds, 1));
+        // Enough Jacobians to fill the GPU: one task per Jacobian, combine fused.
+        a.per_jacobian = batch >= resident ? 1 : 0;
+        a.batch = batch;
+        a.X = X;
+        const int grid = std::min(a.per_jacobian ? batch : ntasks, resident);
+        hipLaunchKernelGGL(sparse_lds_kernel, dim3(grid), dim3(kLdsThreads), lds, st, a, es, 0);
+        e = hipGetLastError();
+        if (e != hipSuccess || a.per_jacobian) return e;
+    } else {
+        a.fac = (double*)(w + L.off_fac);
+        a.y = (double*)(w + L.off_y);
+        hipError_t e = factor_global(d, a, es, st);
+        if (e != hipSuccess) return e;
+        e = solve_global(d, a, st);
+        if (e != hipSuccess) return e;
+    }
+    return launch_combine((int64_t)s.n * nrhs, batch, es, a.Xk, X, st);
+}
+
+hipError_t sparse_factor(const Symbolic& s, const SparseDevice& d, int32_t batch, const double* values,
+                         const EpsSet& es, const double* dvec, int32_t* info, void* ws, hipStream_t st) {
+    const int32_t ntasks = batch * es.K;
+    const SpLayout L = sp_layout(s, batch, es.K, 0, 1);
+    SpArgs a = make_args(d, s, ntasks, es.K, 0);
+    a.values = values; a.dvec = dvec; a.info = info;
+    a.fac = (double*)((char*)ws + L.off_fac);
+    if (sparse_fits_lds(s, 0)) {
+        const int lds = (int)lds_bytes(s, 0);
+        hipError_t e = hipFuncSetAttribute((const void*)sparse_lds_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        if (e != hipSuccess) return e;
+        int dev = 0, cus = 256;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        const int grid = std::min(ntasks, cus * std::max(1, (160 * 1024) / std::max(lds, 1)));
+        hipLaunchKernelGGL(sparse_lds_kernel, dim3(grid), dim3(kLdsThreads), lds, st, a, es, 1);
+        return hipGetLastError();
+    }
+    return factor_global(d, a, es, st);
+}
+
+hipError_t sparse_solve(const Symbolic& s, const SparseDevice& d, int32_t batch, const EpsSet& es, int32_t nrhs,
+                        const double* B, double* Xk, int32_t transpose, const int32_t* info, void* ws,
+                        hipStream_t st) {
+    const int32_t ntasks = batch * es.K;
+    const SpLayout L = sp_layout(s, batch, es.K, 0, 1);
+    SpArgs a = make_args(d, s, ntasks, es.K, nrhs);
+    a.B = B; a.Xk = Xk; a.info = const_cast<int32_t*>(info); a.trans = transpose ? 1 : 0;
+    a.fac = (double*)((char*)ws + L.off_fac);
+    a.y = (double*)((char*)ws + L.off_y);
+    return solve_global(d, a, st);
 }
 
 }  // namespace psp

@@ -191,6 +191,17 @@ def config_eps(name: str) -> np.ndarray:
     raise KeyError(name)
 
 
+def large_eps(K: int = 4) -> np.ndarray:
+    """Nodes for the 20,001-unknown workload: eps0 = 1e-5, ratio 1/2.
+
+    The Neumann series of (A + eps D)^{-1} converges for |eps| rho(A^{-1} D) < 1
+    (Sec. II-B).  For the seeded 10,000-bus states rho(A^{-1}) is 2e2 to 1e3
+    (measured offline by power iteration), so eps0 = 10^-(ceil(log10 rho) + 2)
+    keeps eps0 * rho near 1e-2 and the K = 4 truncation near 1e-10.
+    """
+    return geometric_eps(1e-5, K)
+
+
 def scenario_batch(N: int, count: int, inst: int = 0, first: int = 0,
                    scale_range: tuple[float, float] | None = None):
     """`count` Jacobians of one network at seeded states, plus their RHS.

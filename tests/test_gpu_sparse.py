@@ -1,0 +1,123 @@
+"""GPU parity of the sparse (fill-pattern) path against the oracle, through the C ABI.
+
+The level-scheduled kernels evaluate every factor entry and every substitution
+row with the oracle's operations in the oracle's order, so factors, perturbed
+solutions and combined solutions are compared bit for bit (the 1e-12 relative
+bound is asserted first so a failure names which bar broke)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def psp():
+    from paper_2311_11833_amd import psp as m
+    m.lib()
+    return m
+
+
+def _cmp(xg, xo):
+    rel = np.abs(xg - xo).max() / np.abs(xo).max()
+    assert rel <= 1e-12, rel
+    assert np.array_equal(xg, xo)
+
+
+@pytest.mark.parametrize("N,count,nrhs", [(14, 3, 1), (30, 4, 1), (30, 2, 7), (118, 2, 1), (300, 3, 1),
+                                          (500, 1, 2), (1354, 2, 1)])
+def test_fused_sparse_matches_oracle(psp, O, W, dev, N, count, nrhs):
+    ip, ix, vals, bs = W.scenario_batch(N, count)
+    n = len(ip) - 1
+    if nrhs > 1:
+        bs = np.random.default_rng(N).standard_normal((count, n, nrhs))
+    eps = W.config_eps("small" if N == 14 else "n601")
+    print(f"[gpu sparse] N={N} n={n} count={count} nrhs={nrhs}", flush=True)
+    plan = psp.Plan(ip, ix)
+    x, info = psp.solve_batched(plan, torch.from_numpy(vals).to(dev), eps, torch.from_numpy(bs).to(dev), path="sparse")
+    torch.cuda.synchronize()
+    sym = O.symbolic(n, ip, ix)
+    xo, io, _, _ = O.sparse_batch(n, ip, ix, vals, sym, eps, bs)
+    assert np.array_equal(info.cpu().numpy(), io)
+    _cmp(x.cpu().numpy(), xo)
+
+
+@pytest.mark.parametrize("N", [30, 1354])
+def test_split_sparse_solve_trans_grad(psp, O, W, dev, N):
+    ip, ix, vals, _ = W.scenario_batch(N, 2)
+    n = len(ip) - 1
+    eps = W.config_eps("n601")
+    rng = np.random.default_rng(3)
+    B = rng.standard_normal((2, n, 4))
+    Wt = rng.standard_normal((2, n, 4))
+    plan = psp.Plan(ip, ix)
+    F = psp.Factors(plan, torch.from_numpy(vals).to(dev), eps, path="sparse", nrhs_cap=4)
+    Xk = F.solve(torch.from_numpy(B).to(dev))
+    Lk = F.solve(torch.from_numpy(Wt).to(dev), transpose=True)
+    X = F.combine(Xk)
+    gA = F.grad_values(Lk, Xk)
+    torch.cuda.synchronize()
+    assert np.all(F.info.cpu().numpy() == 0)
+    sym = O.symbolic(n, ip, ix)
+    c = O.weights(eps)
+    for s in range(2):
+        xk = np.stack([O.sparse_system(n, ip, ix, vals[s], sym, e, B[s])[0] for e in eps])
+        lk = np.stack([O.sparse_system(n, ip, ix, vals[s], sym, e, Wt[s], trans=True)[0] for e in eps])
+        _cmp(Xk[s].cpu().numpy(), xk)
+        _cmp(Lk[s].cpu().numpy(), lk)
+        _cmp(X[s].cpu().numpy(), O.combine(c, xk))
+        _cmp(gA[s].cpu().numpy(), O.grad_values(n, ip, ix, c, xk, lk))
+
+
+@pytest.mark.parametrize("N", [14, 1354])
+def test_sparse_breakdown_info(psp, O, W, dev, N):
+    ip, ix, vals, bs = W.scenario_batch(N, 2)
+    vals = vals.copy()
+    vals[1, 3] = np.inf
+    n = len(ip) - 1
+    eps = W.config_eps("small")
+    plan = psp.Plan(ip, ix)
+    x, info = psp.solve_batched(plan, torch.from_numpy(vals).to(dev), eps, torch.from_numpy(bs).to(dev), path="sparse")
+    torch.cuda.synchronize()
+    sym = O.symbolic(n, ip, ix)
+    xo, io, _, _ = O.sparse_batch(n, ip, ix, vals, sym, eps, bs)
+    ig = info.cpu().numpy()
+    assert np.array_equal(ig, io) and np.all(ig[1] > 0) and np.all(ig[0] == 0)
+    xg = x.cpu().numpy()
+    assert np.all(np.isnan(xg[1]))
+    _cmp(xg[0], xo[0])
+
+
+def test_large_sparse_sampled(psp, O, W, dev):
+    """20,001 unknowns (10,000-bus network), K = 4, 32 right-hand sides, forward and
+    transposed solves in the launch configuration of the benchmark; one perturbed
+    system and four RHS columns recomputed by the oracle."""
+    from paper_2311_11833_amd.workloads import make_network, make_state, jacobian, seed_state
+    net = make_network(10000)
+    vm, va, p = make_state(10000, seed_state(10000, 0))
+    J = jacobian(net, vm, va, p)
+    n = J.n
+    eps = W.large_eps()
+    rng = np.random.default_rng(10)
+    B = rng.standard_normal((1, n, 32))
+    plan = psp.Plan(J.indptr, J.indices)
+    F = psp.Factors(plan, torch.from_numpy(J.data[None]).to(dev), eps, path="sparse", nrhs_cap=32)
+    Xk = F.solve(torch.from_numpy(B).to(dev))
+    Lk = F.solve(torch.from_numpy(B).to(dev), transpose=True)
+    torch.cuda.synchronize()
+    assert np.all(F.info.cpu().numpy() == 0)
+    sym = O.symbolic(n, J.indptr, J.indices)
+    xo, info = O.sparse_system(n, J.indptr, J.indices, J.data, sym, eps[0], B[0][:, :4].copy())
+    lo, _ = O.sparse_system(n, J.indptr, J.indices, J.data, sym, eps[0], B[0][:, :4].copy(), trans=True)
+    assert info == 0
+    _cmp(Xk[0, 0, :, :4].cpu().numpy(), xo)
+    _cmp(Lk[0, 0, :, :4].cpu().numpy(), lo)
+    assert np.all(np.isfinite(Xk.cpu().numpy()))
