@@ -16,6 +16,21 @@ struct EpsSet {
     double c[kMaxK];
 };
 
+// Reads eps[k] / c[k] with compile-time indices only: a run-time index into a
+// by-value kernel argument would make the compiler copy it to scratch.
+__device__ __forceinline__ double eps_at(const EpsSet& es, int k) {
+    double v = 0.0;
+#pragma unroll
+    for (int i = 0; i < kMaxK; ++i) v = (i == k) ? es.eps[i] : v;
+    return v;
+}
+__device__ __forceinline__ double c_at(const EpsSet& es, int k) {
+    double v = 0.0;
+#pragma unroll
+    for (int i = 0; i < kMaxK; ++i) v = (i == k) ? es.c[i] : v;
+    return v;
+}
+
 // The exact operation sequence matters (results are compared bit for bit
 // with the CPU reference), so every multiply-add below is an explicit fma,
 // the product eps*d is rounded before it is added, and division is IEEE

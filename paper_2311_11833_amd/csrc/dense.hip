@@ -33,7 +33,7 @@ constexpr int SB = 64;        // triangular-solve block
 constexpr int WG = 256;       // threads per workgroup
 
 // ---------------------------------------------------------------- assembly
-__device__ void assemble(const DenseArgs& a, double* M, int s, double eps, int ncols) {
+__device__ __forceinline__ void assemble(const DenseArgs& a, double* M, int s, double eps, int ncols) {
     const int tid = threadIdx.x;
     const int64_t total = (int64_t)a.ld * ncols;
     for (int64_t i = tid; i < total; i += WG) M[i] = 0.0;
@@ -61,119 +61,206 @@ __device__ void assemble(const DenseArgs& a, double* M, int s, double eps, int n
 }
 
 // ---------------------------------------------------------------- factorisation
-// Returns 0 or the 1-based position of the first bad pivot (uniform across the WG).
-__device__ int factor_slot(double* M, int n_pad, int ld, int ncols, double* lds) {
-    double* D = lds;                      // NB x NB, row-major D[i*NB + j]
-    double* Ls = lds + NB * NB;           // NB x TB, Ls[k*TB + row]
-    double* Us = Ls + NB * TB;            // NB x TB, Us[k*TB + col]
-    __shared__ int s_info;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    if (tid == 0) s_info = 0;
-    __syncthreads();
-    for (int c0 = 0; c0 < n_pad; c0 += NB) {
-        // 1. diagonal block, wave 0, lane = row
-        if (wave == 0) {
-            double r[NB];
-            const bool act = lane < NB;
+// GETRF of the NB x NB diagonal block at (c0, c0) by wave 0 (lane = row); the
+// factored block is left in M and in D (row-major, LDS).  Returns the 1-based
+// position of the first bad pivot or 0 (valid in wave 0 only).
+__device__ __forceinline__ int panel_getrf(double* M, int ld, int c0, double* D) {
+    const int lane = threadIdx.x & 63;
+    double r[NB];
+    const bool act = lane < NB;
 #pragma unroll
-            for (int j = 0; j < NB; ++j) r[j] = act ? M[(int64_t)(c0 + j) * ld + c0 + lane] : 0.0;
-            int bad = 0;
+    for (int j = 0; j < NB; ++j) r[j] = act ? M[(int64_t)(c0 + j) * ld + c0 + lane] : 0.0;
+    int bad = 0;
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        const double ukk = readlane_d(r[k], k);
+        if (!bad && bad_pivot(ukk)) bad = c0 + k + 1;
+        const bool below = lane > k;
+        const double l = r[k] / ukk;
+        r[k] = below ? l : r[k];
+#pragma unroll
+        for (int j = k + 1; j < NB; ++j) {
+            const double ukj = readlane_d(r[j], k);
+            r[j] = below ? fmad(-l, ukj, r[j]) : r[j];
+        }
+    }
+    if (act) {
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            M[(int64_t)(c0 + j) * ld + c0 + lane] = r[j];
+            D[lane * NB + j] = r[j];
+        }
+    }
+    return bad;
+}
+
+// Load the factored diagonal block at (c0, c0) into D.
+__device__ __forceinline__ void load_diag(const double* M, int ld, int c0, double* D) {
+    for (int t = threadIdx.x; t < NB * NB; t += WG) {
+        const int i = t % NB, j = t / NB;
+        D[i * NB + j] = M[(int64_t)(c0 + j) * ld + c0 + i];
+    }
+}
+
+// One thread per item: rows [r_lo, r_hi) get l = a U^{-1} on the panel columns
+// (TRSM from the right with the upper triangle of D, IEEE divisions), columns
+// [c_lo, c_hi) get u = L^{-1} a on the panel rows (unit lower triangle of D).
+__device__ __forceinline__ void panel_trsm(double* M, int ld, int c0, const double* D, int r_lo, int r_hi, int c_lo, int c_hi) {
+    const int nrows = max(0, r_hi - r_lo), ncolr = max(0, c_hi - c_lo);
+    for (int t = threadIdx.x; t < nrows + ncolr; t += WG) {
+        double r[NB];
+        // keep the LDS reads of D inside the loop (hoisting them all would exhaust registers)
+        const double* Dv = D;
+        asm volatile("" : "+v"(Dv));
+        if (t < nrows) {
+            const int i = r_lo + t;
+#pragma unroll
+            for (int j = 0; j < NB; ++j) r[j] = M[(int64_t)(c0 + j) * ld + i];
 #pragma unroll
             for (int k = 0; k < NB; ++k) {
-                const double ukk = readlane_d(r[k], k);
-                if (!bad && bad_pivot(ukk)) bad = c0 + k + 1;
-                const bool below = lane > k;
-                const double l = r[k] / ukk;
-                r[k] = below ? l : r[k];
+                const double l = r[k] / Dv[k * NB + k];
+                r[k] = l;
 #pragma unroll
-                for (int j = k + 1; j < NB; ++j) {
-                    const double ukj = readlane_d(r[j], k);
-                    r[j] = below ? fmad(-l, ukj, r[j]) : r[j];
-                }
+                for (int j = k + 1; j < NB; ++j) r[j] = fmad(-l, Dv[k * NB + j], r[j]);
             }
-            if (act) {
 #pragma unroll
-                for (int j = 0; j < NB; ++j) {
-                    M[(int64_t)(c0 + j) * ld + c0 + lane] = r[j];
-                    D[lane * NB + j] = r[j];
-                }
-            }
-            if (lane == 0 && bad) s_info = bad;
+            for (int j = 0; j < NB; ++j) M[(int64_t)(c0 + j) * ld + i] = r[j];
+        } else {
+            const int j = c_lo + (t - nrows);
+            double* col = M + (int64_t)j * ld + c0;
+#pragma unroll
+            for (int i = 0; i < NB; ++i) r[i] = col[i];
+#pragma unroll
+            for (int k = 0; k < NB; ++k)
+#pragma unroll
+                for (int i = k + 1; i < NB; ++i) r[i] = fmad(-Dv[i * NB + k], r[k], r[i]);
+#pragma unroll
+            for (int i = 0; i < NB; ++i) col[i] = r[i];
         }
-        __syncthreads();
-        if (s_info) return s_info;
-        // 2. block column below (rows) and block row to the right (columns, RHS included)
-        const int r0 = c0 + NB;
-        const int nrows = n_pad - r0;
-        const int ncolr = ncols - r0;
-        for (int t = tid; t < nrows + ncolr; t += WG) {
-            double r[NB];
-            if (t < nrows) {
-                const int i = r0 + t;
+    }
+}
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// C[r_lo:r_hi, c_lo:c_hi] -= L[:, k_lo:k_lo+KD] * U[k_lo:k_lo+KD, :] on the
+// MFMA unit.  v_mfma_f64_16x16x4f64 accumulates each output as a chain of
+// fmas in ascending k (checked on gfx950), so feeding k in ascending order
+// keeps the reference operation sequence.  Each 16 x 16 block is computed
+// transposed (D = (-U)^T L^T + C^T) so that a lane's accumulators run down a
+// column of the column-major matrix: lane l, register q holds
+// C[row0 + l%16][col0 + 4q + l/16].  Each wave keeps its 32 rows of L
+// (the b operand) in registers for the whole sweep; the U tile (KD x 64) is
+// staged in LDS and shared by the 4 waves; the workgroup covers 128 rows x 64
+// columns per step.
+constexpr int KDMAX = 128;
+
+__device__ __forceinline__ void gemm_mfma(double* M, int ld, int r_lo, int r_hi, int c_lo, int c_hi, int k_lo, int kd,
+                                          double* Us) {
+    constexpr int KS = KDMAX / 4;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int ks = kd / 4;
+    for (int rg = r_lo; rg < r_hi; rg += 128) {
+        const int wr = rg + 32 * wave;
+        const bool wact = wr < r_hi;
+        double bop[KS][2];
+        {
+            const double* lb = M + (int64_t)(k_lo + lk) * ld + wr + li;
 #pragma unroll
-                for (int j = 0; j < NB; ++j) r[j] = M[(int64_t)(c0 + j) * ld + i];
+            for (int s = 0; s < KS; ++s)
 #pragma unroll
-                for (int k = 0; k < NB; ++k) {
-                    const double l = r[k] / D[k * NB + k];
-                    r[k] = l;
-#pragma unroll
-                    for (int j = k + 1; j < NB; ++j) r[j] = fmad(-l, D[k * NB + j], r[j]);
+                for (int rb = 0; rb < 2; ++rb) {
+                    const bool ok = wact && s < ks && wr + 16 * rb + li < r_hi;
+                    bop[s][rb] = ok ? lb[(int64_t)(4 * s) * ld + 16 * rb] : 0.0;
                 }
-#pragma unroll
-                for (int j = 0; j < NB; ++j) M[(int64_t)(c0 + j) * ld + i] = r[j];
-            } else {
-                const int j = r0 + (t - nrows);
-                double* col = M + (int64_t)j * ld + c0;
-#pragma unroll
-                for (int i = 0; i < NB; ++i) r[i] = col[i];
-#pragma unroll
-                for (int k = 0; k < NB; ++k)
-#pragma unroll
-                    for (int i = k + 1; i < NB; ++i) r[i] = fmad(-D[i * NB + k], r[k], r[i]);
-#pragma unroll
-                for (int i = 0; i < NB; ++i) col[i] = r[i];
-            }
         }
-        __syncthreads();
-        // 3. trailing update A22 -= L21 * U12, 64 x 64 tiles, 4 x 4 outputs per thread
-        const int ty = tid >> 4, tx = tid & 15;
-        for (int ti = r0; ti < n_pad; ti += TB) {
-            for (int t = tid; t < NB * TB; t += WG) {
-                const int k = t / TB, rr = t % TB;
-                Ls[k * TB + rr] = (ti + rr < n_pad) ? M[(int64_t)(c0 + k) * ld + ti + rr] : 0.0;
+        for (int ct = c_lo; ct < c_hi; ct += 64) {
+            __syncthreads();
+            for (int t = tid; t < kd * 64; t += WG) {
+                const int k = t % kd, c = t / kd;
+                Us[k * 64 + c] = (ct + c < c_hi) ? -M[(int64_t)(ct + c) * ld + k_lo + k] : 0.0;
             }
-            for (int tj = r0; tj < ncols; tj += TB) {
-                for (int t = tid; t < NB * TB; t += WG) {
-                    const int cc = t / NB, k = t % NB;
-                    Us[k * TB + cc] = (tj + cc < ncols) ? M[(int64_t)(tj + cc) * ld + c0 + k] : 0.0;
+            __syncthreads();
+            if (!wact) continue;
+            double* cb0 = M + (int64_t)(ct + lk) * ld + wr + li;
+            v4d acc[2][4];
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const bool ok = (wr + 16 * rb + li < r_hi) && (ct + 16 * cb + 4 * q + lk < c_hi);
+                        acc[rb][cb][q] = ok ? cb0[(int64_t)(16 * cb + 4 * q) * ld + 16 * rb] : 0.0;
+                    }
+#pragma unroll
+            for (int s = 0; s < KS; ++s) {
+                if (s < ks) {
+                    double aop[4];
+#pragma unroll
+                    for (int cb = 0; cb < 4; ++cb) aop[cb] = Us[(4 * s + lk) * 64 + 16 * cb + li];
+#pragma unroll
+                    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                        for (int cb = 0; cb < 4; ++cb)
+                            acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[cb], bop[s][rb], acc[rb][cb], 0, 0, 0);
                 }
-                __syncthreads();
-                double acc[4][4];
-                const int i0 = ti + ty * 4, j0 = tj + tx * 4;
-#pragma unroll
-                for (int jj = 0; jj < 4; ++jj)
-#pragma unroll
-                    for (int ii = 0; ii < 4; ++ii)
-                        acc[ii][jj] = (i0 + ii < n_pad && j0 + jj < ncols) ? M[(int64_t)(j0 + jj) * ld + i0 + ii] : 0.0;
-#pragma unroll 4
-                for (int k = 0; k < NB; ++k) {
-                    double lv[4], uv[4];
-#pragma unroll
-                    for (int ii = 0; ii < 4; ++ii) lv[ii] = Ls[k * TB + ty * 4 + ii];
-#pragma unroll
-                    for (int jj = 0; jj < 4; ++jj) uv[jj] = Us[k * TB + tx * 4 + jj];
-#pragma unroll
-                    for (int jj = 0; jj < 4; ++jj)
-#pragma unroll
-                        for (int ii = 0; ii < 4; ++ii) acc[ii][jj] = fmad(-lv[ii], uv[jj], acc[ii][jj]);
-                }
-#pragma unroll
-                for (int jj = 0; jj < 4; ++jj)
-#pragma unroll
-                    for (int ii = 0; ii < 4; ++ii)
-                        if (i0 + ii < n_pad && j0 + jj < ncols) M[(int64_t)(j0 + jj) * ld + i0 + ii] = acc[ii][jj];
-                __syncthreads();
             }
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const bool ok = (wr + 16 * rb + li < r_hi) && (ct + 16 * cb + 4 * q + lk < c_hi);
+                        if (ok) cb0[(int64_t)(16 * cb + 4 * q) * ld + 16 * rb] = acc[rb][cb][q];
+                    }
+        }
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void gemm_kd(int kd, double* M, int ld, int r_lo, int r_hi, int c_lo, int c_hi, int k_lo,
+                                        double* Us) {
+    if (r_lo >= r_hi || c_lo >= c_hi) return;
+    gemm_mfma(M, ld, r_lo, r_hi, c_lo, c_hi, k_lo, kd, Us);
+}
+
+// Right-looking factorisation with super-panels of SP = 4 NB columns:
+//   inside a super-panel, NB-wide panels are factored left to right and the
+//   rest of the super-panel is updated after each (GETRF, TRSM, rank-NB);
+//   the block row to the right is then solved panel by panel (TRSM, rank-NB
+//   update of the lower panel rows), and the trailing matrix receives one
+//   rank-SP update.  Every entry still sees its updates in ascending pivot
+//   order.  Returns 0 or the 1-based position of the first bad pivot.
+constexpr int SP = 4 * NB;
+__device__ __forceinline__ int factor_slot(double* M, int n_pad, int ld, int ncols, double* lds) {
+    double* D = lds;                // NB x NB
+    double* Us = lds + NB * NB;     // SP x 64
+    __shared__ int s_info;
+    const int tid = threadIdx.x, wave = tid >> 6;
+    for (int c0 = 0; c0 < n_pad; c0 += SP) {
+        const int ce = min(c0 + SP, n_pad);
+        for (int p = c0; p < ce; p += NB) {
+            if (wave == 0) {
+                const int bad = panel_getrf(M, ld, p, D);
+                if ((tid & 63) == 0) s_info = bad;
+            }
+            __syncthreads();
+            if (s_info) return s_info;
+            panel_trsm(M, ld, p, D, p + NB, n_pad, p + NB, ce);
+            __syncthreads();
+            gemm_kd(NB, M, ld, p + NB, n_pad, p + NB, ce, p, Us);
+        }
+        if (ce < ncols) {
+            for (int p = c0; p < ce; p += NB) {
+                load_diag(M, ld, p, D);
+                __syncthreads();
+                panel_trsm(M, ld, p, D, 0, 0, ce, ncols);
+                __syncthreads();
+                gemm_kd(NB, M, ld, p + NB, ce, ce, ncols, p, Us);
+            }
+            gemm_kd(ce - c0, M, ld, ce, n_pad, ce, ncols, c0, Us);
         }
     }
     return 0;
@@ -186,7 +273,7 @@ __device__ int factor_slot(double* M, int n_pad, int ld, int ncols, double* lds)
 //   LOWER=1, TRANS=1: U^T z = w (a_ik = M[k + i ld], diag u_kk), ascending
 //   LOWER=0, TRANS=1: L^T v = z (unit, a_ij = M[j + i ld]), descending
 template <int LOWER, int TRANS>
-__device__ void tri_solve(const double* M, int n_pad, int ld, double* T, int nrhs, double* lds) {
+__device__ __forceinline__ void tri_solve(const double* M, int n_pad, int ld, double* T, int nrhs, double* lds) {
     constexpr bool UNIT = (LOWER && !TRANS) || (!LOWER && TRANS);
     double* Tri = lds;                 // SB x SB, Tri[i*SB + j] = a(b0+i, b0+j)
     double* Xs = lds + SB * SB;        // SB x nrhs (nrhs <= 64)
@@ -247,7 +334,7 @@ __device__ void tri_solve(const double* M, int n_pad, int ld, double* T, int nrh
     }
 }
 
-constexpr int kLdsFactor = (NB * NB + 2 * NB * TB) * 8;
+constexpr int kLdsFactor = (NB * NB + SP * 64) * 8;
 constexpr int kLdsSolve = (SB * SB + SB * 64) * 8;
 constexpr int kLdsDense = kLdsFactor > kLdsSolve ? kLdsFactor : kLdsSolve;
 
@@ -268,7 +355,7 @@ __global__ __launch_bounds__(WG) void dense_factor_solve_kernel(DenseArgs a, Eps
             const int sys = s * K + k;
             double* M = a.slots + (a.keep ? (int64_t)sys : (int64_t)blockIdx.x) * a.slot_stride;
             const int ncols = a.n_pad + a.nrhs;
-            assemble(a, M, s, es.eps[k], ncols);
+            assemble(a, M, s, eps_at(es, k), ncols);
             const int info = factor_slot(M, a.n_pad, a.ld, ncols, lds);
             if (info == 0 && a.nrhs > 0) tri_solve<0, 0>(M, a.n_pad, a.ld, M + (int64_t)a.n_pad * a.ld, a.nrhs, lds);
             if (threadIdx.x == 0) a.info[sys] = info;
@@ -278,7 +365,7 @@ __global__ __launch_bounds__(WG) void dense_factor_solve_kernel(DenseArgs a, Eps
                     const int q = t / a.nrhs, r = t % a.nrhs;
                     const double v = info ? __builtin_nan("") : M[(int64_t)(a.n_pad + r) * a.ld + q];
                     double* dst = x + (int64_t)a.perm[q] * a.nrhs + r;
-                    *dst = a.per_jacobian ? fmad(es.c[k], v, k == 0 ? 0.0 : *dst) : v;
+                    *dst = a.per_jacobian ? fmad(c_at(es, k), v, k == 0 ? 0.0 : *dst) : v;
                 }
             }
             __syncthreads();
@@ -325,7 +412,7 @@ __global__ void combine_kernel(int64_t len, int32_t batch, EpsSet es, const doub
         const int64_t s = t / len, i = t % len;
         const double* p = Xk + s * es.K * len + i;
         double acc = 0.0;
-        for (int k = 0; k < es.K; ++k) acc = fmad(es.c[k], p[k * len], acc);
+        for (int k = 0; k < es.K; ++k) acc = fmad(c_at(es, k), p[k * len], acc);
         X[t] = acc;
     }
 }
@@ -346,7 +433,7 @@ __global__ void grad_values_kernel(int32_t n, int32_t nnz, int32_t batch, int32_
             const double* x = Xk + (s * es.K + k) * blk + (int64_t)j * nrhs;
             double sum = 0.0;
             for (int r = 0; r < nrhs; ++r) sum = fmad(lam[r], x[r], sum);
-            acc = fmad(es.c[k], sum, acc);
+            acc = fmad(c_at(es, k), sum, acc);
         }
         gA[t] = -acc;
     }

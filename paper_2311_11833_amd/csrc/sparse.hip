@@ -151,7 +151,7 @@ __global__ __launch_bounds__(kLdsThreads) void sparse_lds_kernel(SpArgs a, EpsSe
         const double* v = a.values + (int64_t)s * a.nnz;
         if (tid == 0) s_bad = INT_MAX;
         for (int t = tid; t < nl; t += kLdsThreads) gather_item(ix, t, v, lv, uv);
-        for (int j = tid; j < n; j += kLdsThreads) ud[j] = gather_diag(ix, j, v, es.eps[kk], a.dvec);
+        for (int j = tid; j < n; j += kLdsThreads) ud[j] = gather_diag(ix, j, v, eps_at(es, kk), a.dvec);
         if (nrhs > 0) {
             const double* b = a.B + (int64_t)s * n * nrhs;
             for (int t = tid; t < n * nrhs; t += kLdsThreads) {
@@ -205,7 +205,7 @@ __global__ __launch_bounds__(kLdsThreads) void sparse_lds_kernel(SpArgs a, EpsSe
                 const int q = t / nrhs, r = t % nrhs;
                 const double val = bad ? __builtin_nan("") : y[t];
                 double* dst = x + (int64_t)ix.perm[q] * nrhs + r;
-                *dst = a.per_jacobian ? fmad(es.c[kk], val, kk == 0 ? 0.0 : *dst) : val;
+                *dst = a.per_jacobian ? fmad(c_at(es, kk), val, kk == 0 ? 0.0 : *dst) : val;
             }
         }
         if (tid == 0) a.info[task] = bad;
@@ -226,7 +226,7 @@ __global__ void sp_gather_kernel(SpArgs a, EpsSet es) {
         const double* v = a.values + (int64_t)s * a.nnz;
         double* ud = a.fac + (int64_t)task * a.fstride;
         if (t < nl) gather_item(ix, t, v, ud + n, ud + n + nl);
-        else ud[t - nl] = gather_diag(ix, t - nl, v, es.eps[kk], a.dvec);
+        else ud[t - nl] = gather_diag(ix, t - nl, v, eps_at(es, kk), a.dvec);
         if (t == 0) a.info[task] = INT_MAX;
     }
 }
