@@ -116,13 +116,30 @@ PSP_API psp_status psp_weights(int32_t K, const double* eps, double* c);
 
 /* ------------------------------------------------------------------------
  * Numeric paths.
- *   PSP_PATH_DENSE   each perturbed system as a dense n x n matrix (the
- *                    batched dense factorisation of Sec. IV), n <= 4096.
- *   PSP_PATH_SPARSE  factors on the plan's fill pattern, level-scheduled
- *                    (the sparse batched factorisation named in Sec. IV/V).
- *   PSP_PATH_AUTO    the library's choice for the plan (tuned crossover).
+ *   PSP_PATH_DENSE    each perturbed system as a dense n x n matrix (the
+ *                     batched dense factorisation of Sec. IV), n <= 4096.
+ *   PSP_PATH_SPARSE   factors on the plan's fill pattern, level-scheduled
+ *                     (the sparse batched factorisation named in Sec. IV/V);
+ *                     the library picks one of the three executions below.
+ *   PSP_PATH_SPARSE_BATCHED  systems interleaved across lanes, one launch per
+ *                     level for the whole batch (needs the plan's update
+ *                     lists: at most 32 Mi multiply-adds per factorisation).
+ *   PSP_PATH_SPARSE_LDS      one workgroup per system, factors in LDS (needs
+ *                     (n + 2 nnz_l + n nrhs) * 8 <= 152 KiB).
+ *   PSP_PATH_SPARSE_LEVELS   one launch per level, factors in the workspace.
+ *   PSP_PATH_AUTO     the path psp_tune chose for this (batch, K, nrhs), else
+ *                     a size heuristic.
+ * A path that cannot run the plan returns PSP_E_UNSUPPORTED.  Every path
+ * returns the same bits (each applies the same operation sequence).
  * ---------------------------------------------------------------------- */
-enum { PSP_PATH_AUTO = 0, PSP_PATH_DENSE = 1, PSP_PATH_SPARSE = 2 };
+enum {
+    PSP_PATH_AUTO = 0,
+    PSP_PATH_DENSE = 1,
+    PSP_PATH_SPARSE = 2,
+    PSP_PATH_SPARSE_BATCHED = 3,
+    PSP_PATH_SPARSE_LDS = 4,
+    PSP_PATH_SPARSE_LEVELS = 5
+};
 
 /* Bytes of device workspace psp_factor / psp_solve_batched need for `batch`
  * Jacobians, K nodes and nrhs right-hand sides on `path`.  With keep != 0
@@ -147,6 +164,22 @@ PSP_API psp_status psp_solve_batched(psp_plan plan, int32_t path, int32_t batch,
                              int32_t K, const double* eps, const double* d, int32_t nrhs,
                              const double* B, double* X, int32_t* info, void* ws, size_t ws_bytes,
                              void* stream);
+
+/* ------------------------------------------------------------------------
+ * psp_tune -- autotuner: runs psp_solve_batched on the caller's data with
+ * every path that can run this plan and fits ws_bytes (one warm-up, three
+ * timed runs each, HIP events on `stream`; the call synchronises the stream),
+ * and records the fastest as the PSP_PATH_AUTO choice for (batch, K, nrhs).
+ * Arguments as for psp_solve_batched (X and info receive the last run's
+ * results, which are the same on every path).  chosen (host, may be NULL)
+ * receives the path id; ms (host, may be NULL, 6 entries indexed by path id)
+ * receives the mean time per call, -1 for a path not run.  Size the
+ * workspace with psp_workspace_bytes(plan, PSP_PATH_AUTO, ...), which covers
+ * every candidate.
+ * ---------------------------------------------------------------------- */
+PSP_API psp_status psp_tune(psp_plan plan, int32_t batch, const double* values, int32_t K, const double* eps,
+                            const double* d, int32_t nrhs, const double* B, double* X, int32_t* info, void* ws,
+                            size_t ws_bytes, void* stream, int32_t* chosen, float* ms);
 
 /* ------------------------------------------------------------------------
  * Split steps (plain, one call per step) -- the adjoint and the

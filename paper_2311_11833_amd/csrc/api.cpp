@@ -9,7 +9,9 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <new>
 #include <string>
 #include <vector>
@@ -69,6 +71,7 @@ struct psp_plan_s {
     int32_t* d_rows = nullptr;    // original row of each CSR entry
     int32_t* d_cols = nullptr;
     SparseDevice sp;              // sparse-path arrays
+    std::map<std::tuple<int32_t, int32_t, int32_t>, int32_t> tuned;   // (batch, K, nrhs) -> path id
     ~psp_plan_s() {
         if (device >= 0) {
             int cur = 0;
@@ -178,15 +181,43 @@ psp_status make_eps(int32_t K, const double* eps, EpsSet& es) {
     return PSP_OK;
 }
 
-int32_t resolve_path(const Symbolic& s, int32_t path) {
-    if (path != PSP_PATH_AUTO) return path;
-    return (s.n <= 256) ? PSP_PATH_DENSE : PSP_PATH_SPARSE;
+// Path id -> (base path, sparse execution or -1).
+struct PathSel {
+    int32_t base;
+    int forced;
+};
+
+PathSel split_path(int32_t path) {
+    switch (path) {
+        case PSP_PATH_DENSE: return {PSP_PATH_DENSE, -1};
+        case PSP_PATH_SPARSE: return {PSP_PATH_SPARSE, -1};
+        case PSP_PATH_SPARSE_BATCHED: return {PSP_PATH_SPARSE, kVarBatched};
+        case PSP_PATH_SPARSE_LDS: return {PSP_PATH_SPARSE, kVarLds};
+        case PSP_PATH_SPARSE_LEVELS: return {PSP_PATH_SPARSE, kVarGlobal};
+        default: return {-1, -1};
+    }
 }
+
+int32_t heuristic_path(const Symbolic& s) { return (s.n <= 128) ? PSP_PATH_DENSE : PSP_PATH_SPARSE; }
 
 psp_status check_prior_hip() {
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "error left by earlier device work");
     return PSP_OK;
+}
+
+int32_t resolve_path(psp_plan p, int32_t path, int32_t batch, int32_t K, int32_t nrhs) {
+    if (path != PSP_PATH_AUTO) return path;
+    std::lock_guard<std::mutex> g(p->mu);
+    auto it = p->tuned.find(std::make_tuple(batch, K, nrhs));
+    return it != p->tuned.end() ? it->second : heuristic_path(p->sym);
+}
+
+size_t path_workspace(const Symbolic& s, int32_t path, int32_t batch, int32_t K, int32_t nrhs, int32_t keep) {
+    const PathSel ps = split_path(path);
+    if (ps.base == PSP_PATH_DENSE) return (size_t)dense_layout(s, batch, K, nrhs, keep).total;
+    if (ps.base == PSP_PATH_SPARSE) return sparse_workspace_bytes(s, batch, K, nrhs, keep, ps.forced);
+    return 0;
 }
 
 }  // namespace
@@ -264,10 +295,13 @@ void psp_plan_destroy(psp_plan p) { delete p; }
 
 size_t psp_workspace_bytes(psp_plan p, int32_t path, int32_t batch, int32_t K, int32_t nrhs, int32_t keep) {
     if (!p || batch < 1 || K < 1 || nrhs < 0) return 0;
-    const int32_t pth = resolve_path(p->sym, path);
-    if (pth == PSP_PATH_DENSE) return (size_t)dense_layout(p->sym, batch, K, nrhs, keep).total;
-    if (pth == PSP_PATH_SPARSE) return sparse_workspace_bytes(p->sym, batch, K, nrhs, keep);
-    return 0;
+    if (path == PSP_PATH_AUTO) {
+        size_t m = 0;
+        for (int32_t c = PSP_PATH_DENSE; c <= PSP_PATH_SPARSE_LEVELS; ++c)
+            if (c != PSP_PATH_DENSE || p->sym.n <= 4096) m = std::max(m, path_workspace(p->sym, c, batch, K, nrhs, keep));
+        return m;
+    }
+    return path_workspace(p->sym, path, batch, K, nrhs, keep);
 }
 
 psp_status psp_solve_batched(psp_plan p, int32_t path, int32_t batch, const double* values, int32_t K,
@@ -280,8 +314,8 @@ psp_status psp_solve_batched(psp_plan p, int32_t path, int32_t batch, const doub
     if (psp_status st = check_prior_hip()) return st;
     const Symbolic& s = p->sym;
     const hipStream_t st = (hipStream_t)stream;
-    const int32_t pth = resolve_path(s, path);
-    if (pth == PSP_PATH_DENSE) {
+    const PathSel ps = split_path(resolve_path(p, path, batch, K, nrhs));
+    if (ps.base == PSP_PATH_DENSE) {
         if (s.n > 4096) return fail(PSP_E_UNSUPPORTED, "dense path supports n <= 4096");
         const DenseLayout L = dense_layout(s, batch, K, nrhs, 0);
         if (ws_bytes < (size_t)L.total) return fail(PSP_E_NOMEM, "workspace too small: need " + std::to_string(L.total) + " bytes");
@@ -304,18 +338,64 @@ psp_status psp_solve_batched(psp_plan p, int32_t path, int32_t batch, const doub
         if (!a.per_jacobian) HIP_TRY(launch_combine((int64_t)s.n * nrhs, batch, es, a.Xk, X, st), "combine launch");
         return PSP_OK;
     }
-    if (pth == PSP_PATH_SPARSE) {
-        const size_t need = sparse_workspace_bytes(s, batch, K, nrhs, 0);
+    if (ps.base == PSP_PATH_SPARSE) {
+        if (sparse_variant(s, (int64_t)batch * K, nrhs, ps.forced) < 0)
+            return fail(PSP_E_UNSUPPORTED, "this sparse execution cannot run the plan (update lists or LDS size)");
+        const size_t need = sparse_workspace_bytes(s, batch, K, nrhs, 0, ps.forced);
         if (ws_bytes < need) return fail(PSP_E_NOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
         if (psp_status r = upload_plan(p, 0)) return r;
         {
             std::lock_guard<std::mutex> g(p->mu);
             HIP_TRY(sparse_upload(s, p->sp), "sparse plan upload");
         }
-        HIP_TRY(sparse_solve_batched(s, p->sp, batch, values, es, d, nrhs, B, X, info, ws, st), "sparse launch");
+        HIP_TRY(sparse_solve_batched(s, p->sp, batch, values, es, d, nrhs, B, X, info, ws, st, ps.forced), "sparse launch");
         return PSP_OK;
     }
     return fail(PSP_E_INVALID, "unknown path");
+}
+
+psp_status psp_tune(psp_plan p, int32_t batch, const double* values, int32_t K, const double* eps, const double* d,
+                    int32_t nrhs, const double* B, double* X, int32_t* info, void* ws, size_t ws_bytes, void* stream,
+                    int32_t* chosen, float* ms) {
+    if (!p) return fail(PSP_E_INVALID, "psp_tune: NULL plan");
+    const hipStream_t st = (hipStream_t)stream;
+    if (ms)
+        for (int c = 0; c < 6; ++c) ms[c] = -1.0f;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
+    HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
+    int32_t best = -1;
+    float best_ms = 0.0f;
+    psp_status last = PSP_OK;
+    for (int32_t c = PSP_PATH_DENSE; c <= PSP_PATH_SPARSE_LEVELS; ++c) {
+        if (c == PSP_PATH_SPARSE) continue;   // its executions are tried one by one
+        if (path_workspace(p->sym, c, batch, K, nrhs, 0) > ws_bytes) continue;
+        psp_status r = psp_solve_batched(p, c, batch, values, K, eps, d, nrhs, B, X, info, ws, ws_bytes, stream);
+        if (r == PSP_E_UNSUPPORTED) continue;
+        if (r != PSP_OK) { last = r; break; }
+        HIP_TRY(hipEventRecord(e0, st), "hipEventRecord");
+        for (int rep = 0; rep < 3 && r == PSP_OK; ++rep)
+            r = psp_solve_batched(p, c, batch, values, K, eps, d, nrhs, B, X, info, ws, ws_bytes, stream);
+        if (r != PSP_OK) { last = r; break; }
+        HIP_TRY(hipEventRecord(e1, st), "hipEventRecord");
+        HIP_TRY(hipEventSynchronize(e1), "hipEventSynchronize");
+        float t = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&t, e0, e1), "hipEventElapsedTime");
+        t /= 3.0f;
+        if (ms) ms[c] = t;
+        if (best < 0 || t < best_ms) { best = c; best_ms = t; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (last != PSP_OK) return last;
+    if (best < 0) return fail(PSP_E_UNSUPPORTED, "psp_tune: no path fits the workspace");
+    {
+        std::lock_guard<std::mutex> g(p->mu);
+        p->tuned[std::make_tuple(batch, K, nrhs)] = best;
+    }
+    if (chosen) *chosen = best;
+    // leave X / info from the chosen path
+    return psp_solve_batched(p, best, batch, values, K, eps, d, nrhs, B, X, info, ws, ws_bytes, stream);
 }
 
 psp_status psp_factor(psp_plan p, int32_t path, int32_t batch, const double* values, int32_t K, const double* eps,
@@ -327,7 +407,8 @@ psp_status psp_factor(psp_plan p, int32_t path, int32_t batch, const double* val
     if (psp_status st = make_eps(K, eps, es)) return st;
     if (psp_status st = check_prior_hip()) return st;
     const Symbolic& s = p->sym;
-    const int32_t pth = resolve_path(s, path);
+    int32_t pth = split_path(path == PSP_PATH_AUTO ? heuristic_path(s) : path).base;
+    if (pth < 0) return fail(PSP_E_INVALID, "unknown path");
     const hipStream_t st = (hipStream_t)stream;
     auto f = std::make_unique<psp_factors_s>();
     f->plan = p; f->path = pth; f->batch = batch; f->K = K; f->es = es;

@@ -30,7 +30,7 @@ namespace psp {
 constexpr int NB = 32;        // panel width
 constexpr int TB = 64;        // trailing-update tile (TB x TB)
 constexpr int SB = 64;        // triangular-solve block
-constexpr int WG = 256;       // threads per workgroup
+constexpr int WG = 512;       // threads per workgroup (8 waves)
 
 // ---------------------------------------------------------------- assembly
 __device__ __forceinline__ void assemble(const DenseArgs& a, double* M, int s, double eps, int ncols) {
@@ -110,8 +110,9 @@ __device__ __forceinline__ void panel_trsm(double* M, int ld, int c0, const doub
     for (int t = threadIdx.x; t < nrows + ncolr; t += WG) {
         double r[NB];
         // keep the LDS reads of D inside the loop (hoisting them all would exhaust registers)
-        const double* Dv = D;
-        asm volatile("" : "+v"(Dv));
+        int z;
+        asm volatile("v_mov_b32 %0, 0" : "=v"(z));   // opaque zero offset
+        const double* Dv = D + z;
         if (t < nrows) {
             const int i = r_lo + t;
 #pragma unroll
@@ -148,31 +149,28 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // keeps the reference operation sequence.  Each 16 x 16 block is computed
 // transposed (D = (-U)^T L^T + C^T) so that a lane's accumulators run down a
 // column of the column-major matrix: lane l, register q holds
-// C[row0 + l%16][col0 + 4q + l/16].  Each wave keeps its 32 rows of L
+// C[row0 + l%16][col0 + 4q + l/16].  Each wave keeps its 16 rows of L
 // (the b operand) in registers for the whole sweep; the U tile (KD x 64) is
-// staged in LDS and shared by the 4 waves; the workgroup covers 128 rows x 64
+// staged in LDS and shared by the 8 waves; the workgroup covers 128 rows x 64
 // columns per step.
 constexpr int KDMAX = 128;
 
 __device__ __forceinline__ void gemm_mfma(double* M, int ld, int r_lo, int r_hi, int c_lo, int c_hi, int k_lo, int kd,
                                           double* Us) {
     constexpr int KS = KDMAX / 4;
+    constexpr int NW = WG / 64;                 // waves; each owns 16 rows of the 16*NW-row group
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lk = lane >> 4;
     const int ks = kd / 4;
-    for (int rg = r_lo; rg < r_hi; rg += 128) {
-        const int wr = rg + 32 * wave;
+    for (int rg = r_lo; rg < r_hi; rg += 16 * NW) {
+        const int wr = rg + 16 * wave;
         const bool wact = wr < r_hi;
-        double bop[KS][2];
+        const bool rok = wact && wr + li < r_hi;
+        double bop[KS];
         {
             const double* lb = M + (int64_t)(k_lo + lk) * ld + wr + li;
 #pragma unroll
-            for (int s = 0; s < KS; ++s)
-#pragma unroll
-                for (int rb = 0; rb < 2; ++rb) {
-                    const bool ok = wact && s < ks && wr + 16 * rb + li < r_hi;
-                    bop[s][rb] = ok ? lb[(int64_t)(4 * s) * ld + 16 * rb] : 0.0;
-                }
+            for (int s = 0; s < KS; ++s) bop[s] = (rok && s < ks) ? lb[(int64_t)(4 * s) * ld] : 0.0;
         }
         for (int ct = c_lo; ct < c_hi; ct += 64) {
             __syncthreads();
@@ -183,16 +181,14 @@ __device__ __forceinline__ void gemm_mfma(double* M, int ld, int r_lo, int r_hi,
             __syncthreads();
             if (!wact) continue;
             double* cb0 = M + (int64_t)(ct + lk) * ld + wr + li;
-            v4d acc[2][4];
+            v4d acc[4];
 #pragma unroll
-            for (int rb = 0; rb < 2; ++rb)
+            for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
-                for (int cb = 0; cb < 4; ++cb)
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const bool ok = (wr + 16 * rb + li < r_hi) && (ct + 16 * cb + 4 * q + lk < c_hi);
-                        acc[rb][cb][q] = ok ? cb0[(int64_t)(16 * cb + 4 * q) * ld + 16 * rb] : 0.0;
-                    }
+                for (int q = 0; q < 4; ++q) {
+                    const bool ok = rok && (ct + 16 * cb + 4 * q + lk < c_hi);
+                    acc[cb][q] = ok ? cb0[(int64_t)(16 * cb + 4 * q) * ld] : 0.0;
+                }
 #pragma unroll
             for (int s = 0; s < KS; ++s) {
                 if (s < ks) {
@@ -200,21 +196,17 @@ __device__ __forceinline__ void gemm_mfma(double* M, int ld, int r_lo, int r_hi,
 #pragma unroll
                     for (int cb = 0; cb < 4; ++cb) aop[cb] = Us[(4 * s + lk) * 64 + 16 * cb + li];
 #pragma unroll
-                    for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-                        for (int cb = 0; cb < 4; ++cb)
-                            acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[cb], bop[s][rb], acc[rb][cb], 0, 0, 0);
+                    for (int cb = 0; cb < 4; ++cb)
+                        acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[cb], bop[s], acc[cb], 0, 0, 0);
                 }
             }
 #pragma unroll
-            for (int rb = 0; rb < 2; ++rb)
+            for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
-                for (int cb = 0; cb < 4; ++cb)
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const bool ok = (wr + 16 * rb + li < r_hi) && (ct + 16 * cb + 4 * q + lk < c_hi);
-                        if (ok) cb0[(int64_t)(16 * cb + 4 * q) * ld + 16 * rb] = acc[rb][cb][q];
-                    }
+                for (int q = 0; q < 4; ++q) {
+                    const bool ok = rok && (ct + 16 * cb + 4 * q + lk < c_hi);
+                    if (ok) cb0[(int64_t)(16 * cb + 4 * q) * ld] = acc[cb][q];
+                }
         }
     }
     __syncthreads();

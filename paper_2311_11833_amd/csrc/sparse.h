@@ -26,6 +26,13 @@ struct SpIdx {
     const int32_t* lev_idx[3];
     const int32_t* lpos_ptr;    // factor level -> range in lpos
     const int32_t* lpos;        // positions t of the columns of each factor level
+    // Update lists (present when use_pairs): for factor item id (diagonal j ->
+    // j, U position t -> n + t, L position t -> n + nnzl + t), the (L position,
+    // U position) pairs of its dot product in ascending k, items
+    // [pair_ptr[id], pair_ptr[id+1]) of pairs (two int32 each).
+    int32_t use_pairs;
+    const int32_t* pair_ptr;    // n + 2 nnzl + 1
+    const int2* pairs;
 };
 
 struct SparseDevice {
@@ -36,14 +43,17 @@ struct SparseDevice {
     std::vector<int32_t> h_lpos_ptr;
 };
 
+enum { kVarLds = 0, kVarGlobal = 1, kVarBatched = 2 };
+int sparse_variant(const Symbolic& s, int64_t ntasks, int32_t nrhs, int forced);
+
 hipError_t sparse_upload(const Symbolic& s, SparseDevice& d);
 void sparse_free(SparseDevice& d);
 bool sparse_fits_lds(const Symbolic& s, int32_t nrhs);
-size_t sparse_workspace_bytes(const Symbolic& s, int32_t batch, int32_t K, int32_t nrhs, int32_t keep);
+size_t sparse_workspace_bytes(const Symbolic& s, int32_t batch, int32_t K, int32_t nrhs, int32_t keep, int forced = -1);
 int32_t sparse_nrhs_capacity(const Symbolic& s, int32_t batch, int32_t K, size_t ws_bytes);
 hipError_t sparse_solve_batched(const Symbolic& s, const SparseDevice& d, int32_t batch, const double* values,
                                 const EpsSet& es, const double* dvec, int32_t nrhs, const double* B, double* X,
-                                int32_t* info, void* ws, hipStream_t st);
+                                int32_t* info, void* ws, hipStream_t st, int forced = -1);
 hipError_t sparse_factor(const Symbolic& s, const SparseDevice& d, int32_t batch, const double* values,
                          const EpsSet& es, const double* dvec, int32_t* info, void* ws, hipStream_t st);
 hipError_t sparse_solve(const Symbolic& s, const SparseDevice& d, int32_t batch, const EpsSet& es, int32_t nrhs,

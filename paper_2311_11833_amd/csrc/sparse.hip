@@ -38,10 +38,13 @@
 
 namespace psp {
 
+bool sparse_fits_lds(const Symbolic& s, int32_t nrhs);
+
 namespace {
 constexpr int kLdsLimit = 152 * 1024;    // bytes of LDS the in-LDS kernel may use
 constexpr int kLdsThreads = 512;
 constexpr int kThreads = 256;
+constexpr int64_t kMaxPairs = 32LL << 20;   // precomputed update pairs kept at most (256 MB)
 
 __device__ __forceinline__ double merge_dot(const SpIdx& ix, int a, int b, const double* lv, const double* uv,
                                             double acc) {
@@ -63,7 +66,18 @@ __device__ __forceinline__ double merge_dot(const SpIdx& ix, int a, int b, const
     return acc;
 }
 
+// acc - sum lv[pl] * uv[pu] over the precomputed pairs of item id, in order
+__device__ __forceinline__ double pair_dot(const SpIdx& ix, int id, const double* lv, const double* uv, double acc) {
+    const int p1 = ix.pair_ptr[id + 1];
+    for (int p = ix.pair_ptr[id]; p < p1; ++p) {
+        const int2 pq = ix.pairs[p];
+        acc = fmad(-lv[pq.x], uv[pq.y], acc);
+    }
+    return acc;
+}
+
 __device__ __forceinline__ double diag_dot(const SpIdx& ix, int j, const double* lv, const double* uv, double acc) {
+    if (ix.use_pairs) return pair_dot(ix, j, lv, uv, acc);
     for (int p = ix.r_ptr[j]; p < ix.r_ptr[j + 1]; ++p) {
         const int t = ix.r_pos[p];
         acc = fmad(-lv[t], uv[t], acc);
@@ -88,6 +102,11 @@ __device__ __forceinline__ double gather_diag(const SpIdx& ix, int j, const doub
 // phase B item: it < npos -> U entry at position t, else L entry at position t
 __device__ __forceinline__ void factor_item(const SpIdx& ix, int t, bool is_l, double* ud, double* lv, double* uv) {
     const int j = ix.col_of[t], m = ix.l_idx[t];
+    if (ix.use_pairs) {
+        if (!is_l) uv[t] = pair_dot(ix, ix.n + t, lv, uv, uv[t]);
+        else lv[t] = pair_dot(ix, ix.n + ix.nnzl + t, lv, uv, lv[t]) / ud[j];
+        return;
+    }
     if (!is_l) {
         uv[t] = merge_dot(ix, j, m, lv, uv, uv[t]);
     } else {
@@ -305,6 +324,156 @@ __global__ void sp_rhs_out_kernel(SpArgs a) {
     }
 }
 
+// ---------------------------------------------------------------- batched, systems interleaved
+// Many systems share one pattern, so the index data of an item is the same for
+// all of them.  Values are stored system-innermost, value v of task q at
+// v * TP + q (TP = ntasks rounded up to 64), and a wave handles one item for 64
+// consecutive systems: the index loads are uniform and the value loads are
+// contiguous.  One launch per level and phase covers every system.
+struct IlArgs {
+    SpIdx ix;
+    int32_t nnz, nrhs, ntasks, TP, K, batch;
+    const double* values;
+    const double* dvec;
+    const double* B;
+    double* X;
+    int32_t* info;
+    double* fac;     // (n + 2 nnzl) x TP
+    double* y;       // (n * nrhs) x TP
+};
+
+__device__ __forceinline__ double il_pair_dot(const SpIdx& ix, int id, const double* lv, const double* uv, int TP,
+                                              int q, double acc) {
+    const int p0 = __builtin_amdgcn_readfirstlane(ix.pair_ptr[id]);
+    const int p1 = __builtin_amdgcn_readfirstlane(ix.pair_ptr[id + 1]);
+    for (int p = p0; p < p1; ++p) {
+        const int2 pq = ix.pairs[p];
+        acc = fmad(-lv[(int64_t)pq.x * TP + q], uv[(int64_t)pq.y * TP + q], acc);
+    }
+    return acc;
+}
+
+__global__ void il_gather_kernel(IlArgs a, EpsSet es) {
+    const SpIdx& ix = a.ix;
+    const int n = ix.n, nl = ix.nnzl;
+    const int64_t total = (int64_t)(n + nl) * a.TP;
+    double* ud = a.fac;
+    double* lv = a.fac + (int64_t)n * a.TP;
+    double* uv = lv + (int64_t)nl * a.TP;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+        const int q = (int)(g % a.TP), v = (int)(g / a.TP);
+        if (q >= a.ntasks) continue;
+        const int s = q / es.K, kk = q % es.K;
+        const double* vals = a.values + (int64_t)s * a.nnz;
+        if (v < nl) {
+            const int sl = ix.src_l[v], su = ix.src_u[v];
+            lv[g] = sl >= 0 ? vals[sl] : 0.0;
+            uv[g] = su >= 0 ? vals[su] : 0.0;
+        } else {
+            const int j = v - nl;
+            ud[(int64_t)j * a.TP + q] = gather_diag(ix, j, vals, eps_at(es, kk), a.dvec);
+            if (j == 0) a.info[q] = INT_MAX;
+        }
+    }
+}
+
+__global__ void il_diag_kernel(IlArgs a, int c0, int cnt) {
+    const SpIdx& ix = a.ix;
+    const int n = ix.n, nl = ix.nnzl;
+    const int64_t total = (int64_t)cnt * a.TP;
+    double* ud = a.fac;
+    const double* lv = a.fac + (int64_t)n * a.TP;
+    const double* uv = lv + (int64_t)nl * a.TP;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+        const int q = (int)(g % a.TP);
+        const int j = ix.lev_idx[0][c0 + (int)(g / a.TP)];
+        if (q >= a.ntasks) continue;
+        const double u = il_pair_dot(ix, j, lv, uv, a.TP, q, ud[(int64_t)j * a.TP + q]);
+        ud[(int64_t)j * a.TP + q] = u;
+        if (bad_pivot(u)) atomicMin(&a.info[q], j + 1);
+    }
+}
+
+__global__ void il_offdiag_kernel(IlArgs a, int p0, int np) {
+    const SpIdx& ix = a.ix;
+    const int n = ix.n, nl = ix.nnzl;
+    const int64_t total = (int64_t)2 * np * a.TP;
+    const double* ud = a.fac;
+    double* lv = a.fac + (int64_t)n * a.TP;
+    double* uv = lv + (int64_t)nl * a.TP;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+        const int q = (int)(g % a.TP), it = (int)(g / a.TP);
+        if (q >= a.ntasks) continue;
+        const bool is_l = it >= np;
+        const int t = ix.lpos[p0 + (is_l ? it - np : it)];
+        const int64_t o = (int64_t)t * a.TP + q;
+        if (!is_l) {
+            uv[o] = il_pair_dot(ix, n + t, lv, uv, a.TP, q, uv[o]);
+        } else {
+            const int j = ix.col_of[t];
+            lv[o] = il_pair_dot(ix, n + nl + t, lv, uv, a.TP, q, lv[o]) / ud[(int64_t)j * a.TP + q];
+        }
+    }
+}
+
+__global__ void il_rhs_in_kernel(IlArgs a) {
+    const SpIdx& ix = a.ix;
+    const int n = ix.n, nrhs = a.nrhs;
+    const int64_t total = (int64_t)n * nrhs * a.TP;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+        const int q = (int)(g % a.TP), v = (int)(g / a.TP);
+        if (q >= a.ntasks) continue;
+        if (q < a.ntasks && v == 0 && a.info[q] == INT_MAX) a.info[q] = 0;
+        const int s = q / a.K, i = v / nrhs, r = v % nrhs;
+        a.y[g] = a.B[((int64_t)s * n + ix.perm[i]) * nrhs + r];
+    }
+}
+
+template <int UPPER>
+__global__ void il_solve_level_kernel(IlArgs a, int c0, int cnt) {
+    const SpIdx& ix = a.ix;
+    const int n = ix.n, nl = ix.nnzl, nrhs = a.nrhs, TP = a.TP;
+    const int64_t total = (int64_t)cnt * nrhs * TP;
+    const double* ud = a.fac;
+    const double* lv = a.fac + (int64_t)n * TP;
+    const double* uv = lv + (int64_t)nl * TP;
+    double* y = a.y;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+        const int q = (int)(g % TP), v = (int)(g / TP);
+        if (q >= a.ntasks) continue;
+        const int i = ix.lev_idx[UPPER ? 2 : 1][c0 + v / nrhs], r = v % nrhs;
+        double acc = y[((int64_t)i * nrhs + r) * TP + q];
+        if (!UPPER) {
+            const int p0 = ix.r_ptr[i], p1 = ix.r_ptr[i + 1];
+            for (int p = p0; p < p1; ++p)
+                acc = fmad(-lv[(int64_t)ix.r_pos[p] * TP + q], y[((int64_t)ix.r_idx[p] * nrhs + r) * TP + q], acc);
+        } else {
+            for (int t = ix.l_ptr[i + 1] - 1; t >= ix.l_ptr[i]; --t)
+                acc = fmad(-uv[(int64_t)t * TP + q], y[((int64_t)ix.l_idx[t] * nrhs + r) * TP + q], acc);
+            acc = acc / ud[(int64_t)i * TP + q];
+        }
+        y[((int64_t)i * nrhs + r) * TP + q] = acc;
+    }
+}
+
+// X[s][perm[i]][r] = sum_k c_k x_(s,k)[i][r], ascending k; NaN for a broken-down system
+__global__ void il_combine_kernel(IlArgs a, EpsSet es) {
+    const SpIdx& ix = a.ix;
+    const int n = ix.n, nrhs = a.nrhs;
+    const int64_t total = (int64_t)a.batch * n * nrhs;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+        const int s = (int)(g / ((int64_t)n * nrhs)), v = (int)(g % ((int64_t)n * nrhs));
+        const int i = v / nrhs, r = v % nrhs;
+        double acc = 0.0;
+        for (int k = 0; k < es.K; ++k) {
+            const int q = s * es.K + k;
+            const double x = a.info[q] ? __builtin_nan("") : a.y[(int64_t)v * a.TP + q];
+            acc = fmad(c_at(es, k), x, acc);
+        }
+        a.X[((int64_t)s * n + ix.perm[i]) * nrhs + r] = acc;
+    }
+}
+
 int grid_for(int64_t items, int threads) {
     int64_t g = (items + threads - 1) / threads;
     return (int)std::max<int64_t>(1, std::min<int64_t>(g, 65536));
@@ -318,16 +487,46 @@ int64_t align256(int64_t v) { return (v + 255) / 256 * 256; }
 
 int64_t fstride_of(const Symbolic& s) { return (s.n + 2 * (int64_t)s.l_ptr[s.n] + 31) / 32 * 32; }
 
-// workspace: [ factors (ntasks x fstride) | y (ntasks x n x nrhs) | Xk (ntasks x n x nrhs) ]
+int64_t tp_of(int64_t ntasks) { return (ntasks + 63) / 64 * 64; }
+
+bool pairs_ok(const Symbolic& s) { return (s.flops_sparse - s.l_ptr[s.n]) / 2 <= kMaxPairs; }
+
+// Fused-call variant: many systems -> interleaved batched kernels; a small
+// fill -> one workgroup per system in LDS; otherwise per-level kernels over
+// task-major factors.  `forced` (a kVar value, or -1) selects one explicitly;
+// an impossible choice returns -1.
+int variant_of(const Symbolic& s, int64_t ntasks, int32_t nrhs, int forced) {
+    if (forced == kVarLds) return sparse_fits_lds(s, nrhs) ? kVarLds : -1;
+    if (forced == kVarBatched) return pairs_ok(s) ? kVarBatched : -1;
+    if (forced == kVarGlobal) return kVarGlobal;
+    if (ntasks >= 256 && pairs_ok(s)) return kVarBatched;
+    if (sparse_fits_lds(s, nrhs)) return kVarLds;
+    return kVarGlobal;
+}
+
+// workspace, keep = 0:
+//   LDS      [ Xk (ntasks x n x nrhs) ]
+//   global   [ factors (ntasks x fstride) | y (ntasks x n x nrhs) | Xk ]
+//   batched  [ factors ((n + 2 nnzl) x TP) | y ((n nrhs) x TP) ]
+// keep = 1:  [ factors (ntasks x fstride) | y (ntasks x n x nrhs) ]
 struct SpLayout {
     int64_t off_fac, off_y, off_xk, total;
 };
 
-SpLayout sp_layout(const Symbolic& s, int32_t batch, int32_t K, int32_t nrhs, int32_t keep) {
+SpLayout sp_layout(const Symbolic& s, int32_t batch, int32_t K, int32_t nrhs, int32_t keep, int forced = -1) {
     const int64_t ntasks = (int64_t)batch * K;
     SpLayout L{};
-    const bool lds = !keep && sparse_fits_lds(s, nrhs);
     L.off_fac = 0;
+    int var = keep ? kVarGlobal : variant_of(s, ntasks, nrhs, forced);
+    if (var < 0) var = kVarGlobal;
+    if (var == kVarBatched) {
+        const int64_t TP = tp_of(ntasks);
+        L.off_y = align256(((int64_t)s.n + 2 * (int64_t)s.l_ptr[s.n]) * TP * 8);
+        L.off_xk = align256(L.off_y + (int64_t)s.n * nrhs * TP * 8);
+        L.total = L.off_xk;
+        return L;
+    }
+    const bool lds = var == kVarLds;
     int64_t off = lds ? 0 : align256(ntasks * fstride_of(s) * 8);
     L.off_y = off;
     if (!lds) off = align256(off + ntasks * (int64_t)s.n * nrhs * 8);
@@ -335,6 +534,41 @@ SpLayout sp_layout(const Symbolic& s, int32_t batch, int32_t K, int32_t nrhs, in
     if (!keep) off = align256(off + ntasks * (int64_t)s.n * nrhs * 8);
     L.total = std::max<int64_t>(off, 256);
     return L;
+}
+
+hipError_t batched_run(const Symbolic& s, const SparseDevice& d, int32_t batch, const double* values, const EpsSet& es,
+                       const double* dvec, int32_t nrhs, const double* B, double* X, int32_t* info, char* w,
+                       const SpLayout& L, hipStream_t st) {
+    IlArgs a{};
+    a.ix = d.idx;
+    a.nnz = s.nnz; a.nrhs = nrhs; a.ntasks = batch * es.K; a.TP = (int32_t)tp_of(a.ntasks); a.K = es.K;
+    a.batch = batch; a.values = values; a.dvec = dvec; a.B = B; a.X = X; a.info = info;
+    a.fac = (double*)(w + L.off_fac);
+    a.y = (double*)(w + L.off_y);
+    const int n = s.n, nl = s.l_ptr[n];
+    hipLaunchKernelGGL(il_gather_kernel, dim3(grid_for((int64_t)(n + nl) * a.TP, kThreads)), dim3(kThreads), 0, st, a, es);
+    for (int l = 0; l < a.ix.nlev[0]; ++l) {
+        const int c0 = d.h_lev_ptr[0][l], cnt = d.h_lev_ptr[0][l + 1] - c0;
+        hipLaunchKernelGGL(il_diag_kernel, dim3(grid_for((int64_t)cnt * a.TP, kThreads)), dim3(kThreads), 0, st, a, c0, cnt);
+        const int p0 = d.h_lpos_ptr[l], np = d.h_lpos_ptr[l + 1] - p0;
+        if (np > 0)
+            hipLaunchKernelGGL(il_offdiag_kernel, dim3(grid_for((int64_t)2 * np * a.TP, kThreads)), dim3(kThreads), 0, st,
+                               a, p0, np);
+    }
+    hipLaunchKernelGGL(il_rhs_in_kernel, dim3(grid_for((int64_t)n * nrhs * a.TP, kThreads)), dim3(kThreads), 0, st, a);
+    for (int l = 0; l < a.ix.nlev[1]; ++l) {
+        const int c0 = d.h_lev_ptr[1][l], cnt = d.h_lev_ptr[1][l + 1] - c0;
+        hipLaunchKernelGGL(il_solve_level_kernel<0>, dim3(grid_for((int64_t)cnt * nrhs * a.TP, kThreads)),
+                           dim3(kThreads), 0, st, a, c0, cnt);
+    }
+    for (int l = 0; l < a.ix.nlev[2]; ++l) {
+        const int c0 = d.h_lev_ptr[2][l], cnt = d.h_lev_ptr[2][l + 1] - c0;
+        hipLaunchKernelGGL(il_solve_level_kernel<1>, dim3(grid_for((int64_t)cnt * nrhs * a.TP, kThreads)),
+                           dim3(kThreads), 0, st, a, c0, cnt);
+    }
+    hipLaunchKernelGGL(il_combine_kernel, dim3(grid_for((int64_t)batch * n * nrhs, kThreads)), dim3(kThreads), 0, st, a,
+                       es);
+    return hipGetLastError();
 }
 
 SpArgs make_args(const SparseDevice& d, const Symbolic& s, int32_t ntasks, int32_t K, int32_t nrhs) {
@@ -386,6 +620,10 @@ hipError_t solve_global(const SparseDevice& d, SpArgs a, hipStream_t st) {
 
 bool sparse_fits_lds(const Symbolic& s, int32_t nrhs) { return lds_bytes(s, nrhs) <= kLdsLimit; }
 
+int sparse_variant(const Symbolic& s, int64_t ntasks, int32_t nrhs, int forced) {
+    return variant_of(s, ntasks, nrhs, forced);
+}
+
 hipError_t sparse_upload(const Symbolic& s, SparseDevice& d) {
     if (d.ready) return hipSuccess;
     const int n = s.n, nl = s.l_ptr[n];
@@ -418,11 +656,38 @@ hipError_t sparse_upload(const Symbolic& s, SparseDevice& d) {
         }
         lpos_ptr[l + 1] = (int32_t)lpos.size();
     }
+    // update lists, when the total stays modest
+    const int64_t npairs_est = (s.flops_sparse - nl) / 2;
+    std::vector<int32_t> pair_ptr, pairs;
+    const bool use_pairs = npairs_est <= kMaxPairs;
+    if (use_pairs) {
+        pair_ptr.assign((size_t)n + 2 * (size_t)nl + 1, 0);
+        pairs.reserve(2 * (size_t)std::max<int64_t>(npairs_est, 1));
+        auto push_merge = [&](int a, int b) {   // pairs (pos(a,k), pos(b,k)) for k in R_a ^ R_b
+            int p = s.lrow_ptr[a], pe = s.lrow_ptr[a + 1], q = s.lrow_ptr[b], qe = s.lrow_ptr[b + 1];
+            while (p < pe && q < qe) {
+                const int ka = s.lrow_idx[p], kb = s.lrow_idx[q];
+                if (ka == kb) { pairs.push_back(r_pos[p]); pairs.push_back(r_pos[q]); ++p; ++q; }
+                else if (ka < kb) ++p;
+                else ++q;
+            }
+        };
+        int64_t id = 0;
+        for (int j = 0; j < n; ++j, ++id) {
+            pair_ptr[id] = (int32_t)(pairs.size() / 2);
+            for (int p = s.lrow_ptr[j]; p < s.lrow_ptr[j + 1]; ++p) { pairs.push_back(r_pos[p]); pairs.push_back(r_pos[p]); }
+        }
+        for (int t = 0; t < nl; ++t, ++id) { pair_ptr[id] = (int32_t)(pairs.size() / 2); push_merge(col_of[t], s.l_idx[t]); }
+        for (int t = 0; t < nl; ++t, ++id) { pair_ptr[id] = (int32_t)(pairs.size() / 2); push_merge(s.l_idx[t], col_of[t]); }
+        pair_ptr[id] = (int32_t)(pairs.size() / 2);
+    }
     std::vector<const std::vector<int32_t>*> parts = {&s.perm, &s.l_ptr, &s.l_idx, &col_of, &s.lrow_ptr, &s.lrow_idx,
                                                       &r_pos, &src_l, &src_u, &src_d};
     for (int t = 0; t < 3; ++t) { parts.push_back(&s.lev_ptr[t]); parts.push_back(&s.lev_idx[t]); }
     parts.push_back(&lpos_ptr);
     parts.push_back(&lpos);
+    parts.push_back(&pair_ptr);
+    parts.push_back(&pairs);
     std::vector<int64_t> off;
     int64_t total = 0;
     for (auto* p : parts) { off.push_back(total); total += ((int64_t)p->size() + 63) / 64 * 64; }
@@ -447,6 +712,9 @@ hipError_t sparse_upload(const Symbolic& s, SparseDevice& d) {
     }
     ix.lpos_ptr = ptr();
     ix.lpos = ptr();
+    ix.use_pairs = use_pairs ? 1 : 0;
+    ix.pair_ptr = ptr();
+    ix.pairs = (const int2*)ptr();
     d.h_lpos_ptr = lpos_ptr;
     d.ready = true;
     return hipSuccess;
@@ -458,8 +726,8 @@ void sparse_free(SparseDevice& d) {
     d.ready = false;
 }
 
-size_t sparse_workspace_bytes(const Symbolic& s, int32_t batch, int32_t K, int32_t nrhs, int32_t keep) {
-    return (size_t)sp_layout(s, batch, K, nrhs, keep).total;
+size_t sparse_workspace_bytes(const Symbolic& s, int32_t batch, int32_t K, int32_t nrhs, int32_t keep, int forced) {
+    return (size_t)sp_layout(s, batch, K, nrhs, keep, forced).total;
 }
 
 int32_t sparse_nrhs_capacity(const Symbolic& s, int32_t batch, int32_t K, size_t ws_bytes) {
@@ -470,14 +738,17 @@ int32_t sparse_nrhs_capacity(const Symbolic& s, int32_t batch, int32_t K, size_t
 
 hipError_t sparse_solve_batched(const Symbolic& s, const SparseDevice& d, int32_t batch, const double* values,
                                 const EpsSet& es, const double* dvec, int32_t nrhs, const double* B, double* X,
-                                int32_t* info, void* ws, hipStream_t st) {
+                                int32_t* info, void* ws, hipStream_t st, int forced) {
     const int32_t ntasks = batch * es.K;
-    const SpLayout L = sp_layout(s, batch, es.K, nrhs, 0);
+    const SpLayout L = sp_layout(s, batch, es.K, nrhs, 0, forced);
     char* w = (char*)ws;
     SpArgs a = make_args(d, s, ntasks, es.K, nrhs);
     a.values = values; a.dvec = dvec; a.B = B; a.info = info;
     a.Xk = (double*)(w + L.off_xk);
-    if (sparse_fits_lds(s, nrhs)) {
+    const int var = variant_of(s, ntasks, nrhs, forced);
+    if (var < 0) return hipErrorInvalidValue;
+    if (var == kVarBatched) return batched_run(s, d, batch, values, es, dvec, nrhs, B, X, info, w, L, st);
+    if (var == kVarLds) {
         const int lds = (int)lds_bytes(s, nrhs);
         hipError_t e = hipFuncSetAttribute((const void*)sparse_lds_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
         if (e != hipSuccess) return e;

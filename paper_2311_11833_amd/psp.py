@@ -18,10 +18,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpsp.so")
 
 PSP_OK, PSP_E_INVALID, PSP_E_EPS, PSP_E_NOMEM, PSP_E_HIP, PSP_E_STATE, PSP_E_UNSUPPORTED = range(7)
-PATHS = {"auto": 0, "dense": 1, "sparse": 2}
+PATHS = {"auto": 0, "dense": 1, "sparse": 2, "sparse_batched": 3, "sparse_lds": 4, "sparse_levels": 5}
+PATH_NAMES = {v: k for k, v in PATHS.items()}
 ORDERS = {"md": 0, "natural": 1}
 EXPORTED = ["psp_last_error", "psp_version", "psp_plan_create", "psp_plan_info", "psp_plan_export",
-            "psp_plan_destroy", "psp_weights", "psp_workspace_bytes", "psp_solve_batched", "psp_factor",
+            "psp_plan_destroy", "psp_weights", "psp_workspace_bytes", "psp_solve_batched", "psp_tune", "psp_factor",
             "psp_solve", "psp_combine", "psp_grad_values", "psp_factors_release"]
 
 
@@ -57,6 +58,7 @@ def lib():
         L.psp_workspace_bytes.argtypes = [vp, i32, i32, i32, i32, i32]
         L.psp_workspace_bytes.restype = C.c_size_t
         L.psp_solve_batched.argtypes = [vp, i32, i32, vp, i32, vp, vp, i32, vp, vp, vp, vp, C.c_size_t, vp]
+        L.psp_tune.argtypes = [vp, i32, vp, i32, vp, vp, i32, vp, vp, vp, vp, C.c_size_t, vp, vp, vp]
         L.psp_factor.argtypes = [vp, i32, i32, vp, i32, vp, vp, vp, vp, C.c_size_t, vp, C.POINTER(vp)]
         L.psp_solve.argtypes = [vp, i32, vp, vp, i32, vp]
         L.psp_combine.argtypes = [vp, i32, vp, vp, vp]
@@ -191,6 +193,26 @@ def solve_batched(plan: Plan, values, eps, b, path: str = "auto", d=None, worksp
                                    nrhs, _dptr(b.contiguous()), _dptr(x), _dptr(info), _dptr(ws), ws.numel(),
                                    _stream(stream)))
     return x, info
+
+
+def tune(plan: Plan, values, eps, b, d=None, stream=None):
+    """Autotune the fused call for this (batch, K, nrhs): returns (chosen path name,
+    {path name: ms per call}); later solve_batched(..., path="auto") uses the choice."""
+    import torch
+    batch = values.shape[0]
+    nrhs = 1 if b.dim() == 2 else b.shape[2]
+    eps_h = np.ascontiguousarray(eps, dtype=np.float64)
+    K = len(eps_h)
+    x = torch.empty_like(b)
+    info = torch.empty((batch, K), dtype=torch.int32, device=values.device)
+    need = plan.workspace_bytes("auto", batch, K, nrhs, keep=False)
+    ws = plan.workspace(need, values.device)
+    chosen = C.c_int32(-1)
+    ms = (C.c_float * 6)()
+    _check(lib().psp_tune(plan.handle, batch, _dptr(values), K, _np_ptr(eps_h), _dptr(d), nrhs, _dptr(b.contiguous()),
+                          _dptr(x), _dptr(info), _dptr(ws), ws.numel(), _stream(stream), C.byref(chosen), ms))
+    times = {PATH_NAMES[i]: float(ms[i]) for i in range(1, 6) if ms[i] >= 0}
+    return PATH_NAMES[chosen.value], times
 
 
 class Factors:

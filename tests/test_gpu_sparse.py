@@ -121,3 +121,61 @@ def test_large_sparse_sampled(psp, O, W, dev):
     _cmp(Xk[0, 0, :, :4].cpu().numpy(), xo)
     _cmp(Lk[0, 0, :, :4].cpu().numpy(), lo)
     assert np.all(np.isfinite(Xk.cpu().numpy()))
+
+
+@pytest.mark.parametrize("variant", ["sparse_batched", "sparse_lds", "sparse_levels"])
+def test_sparse_variants_match_oracle(psp, O, W, dev, variant):
+    """The three executions of the sparse path (systems interleaved across lanes, one
+    workgroup per system in LDS, per-level kernels over task-major factors) on the same
+    64-Jacobian batch: each equal to the oracle bitwise."""
+    ip, ix, vals, bs = W.scenario_batch(118, 64)
+    n = len(ip) - 1
+    eps = W.config_eps("n601")
+    plan = psp.Plan(ip, ix)
+    x, info = psp.solve_batched(plan, torch.from_numpy(vals).to(dev), eps, torch.from_numpy(bs).to(dev), path=variant)
+    torch.cuda.synchronize()
+    sym = O.symbolic(n, ip, ix)
+    xo, io, _, _ = O.sparse_batch(n, ip, ix, vals, sym, eps, bs)
+    assert np.array_equal(info.cpu().numpy(), io)
+    _cmp(x.cpu().numpy(), xo)
+
+
+def test_tuner_picks_a_path_and_auto_uses_it(psp, O, W, dev):
+    ip, ix, vals, bs = W.scenario_batch(118, 64)
+    n = len(ip) - 1
+    eps = W.config_eps("n601")
+    plan = psp.Plan(ip, ix)
+    v, b = torch.from_numpy(vals).to(dev), torch.from_numpy(bs).to(dev)
+    chosen, times = psp.tune(plan, v, eps, b)
+    assert chosen in times and times[chosen] == min(times.values())
+    assert set(times) >= {"dense", "sparse_batched", "sparse_lds", "sparse_levels"}
+    x, info = psp.solve_batched(plan, v, eps, b, path="auto")
+    torch.cuda.synchronize()
+    sym = O.symbolic(n, ip, ix)
+    xo, io, _, _ = O.sparse_batch(n, ip, ix, vals, sym, eps, bs)
+    _cmp(x.cpu().numpy(), xo)
+
+
+def test_sparse_full_size_batched_sampled(psp, O, W, dev):
+    """n=601, 512 Jacobians x K=5 in the benchmark's launch configuration: every
+    system info == 0, all finite, sampled Jacobians equal to the oracle bitwise,
+    and a broken-down Jacobian among them reported alone."""
+    ip, ix, vals, bs = W.scenario_batch(300, 512)
+    vals = vals.copy()
+    vals[300, 10] = np.nan
+    n = len(ip) - 1
+    eps = W.config_eps("n601")
+    plan = psp.Plan(ip, ix)
+    x, info = psp.solve_batched(plan, torch.from_numpy(vals).to(dev), eps, torch.from_numpy(bs).to(dev), path="sparse")
+    torch.cuda.synchronize()
+    xg, ig = x.cpu().numpy(), info.cpu().numpy()
+    bad = np.zeros(512, bool)
+    bad[300] = True
+    assert np.all(ig[~bad] == 0) and np.all(ig[300] > 0)
+    assert np.all(np.isfinite(xg[~bad])) and np.all(np.isnan(xg[300]))
+    sym = O.symbolic(n, ip, ix)
+    for s in (0, 255, 300, 511):
+        xo, io, _, _ = O.sparse_batch(n, ip, ix, vals[s:s + 1], sym, eps, bs[s:s + 1])
+        assert np.array_equal(ig[s:s + 1], io)
+        if s != 300:
+            _cmp(xg[s:s + 1], xo)

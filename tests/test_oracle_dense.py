@@ -280,3 +280,14 @@ def test_batch_equals_single_systems(O, W):
             assert np.array_equal(xs_k, xk[s, k])
             parts.append(xs_k)
         assert np.array_equal(O.combine(c, np.stack(parts)), x[s])
+
+
+def test_spectral_radius_helper_vs_lapack(O, W):
+    """rho(A^{-1} D) by power iteration against LAPACK eigenvalues (diagnostics helper)."""
+    for N, scen in ((14, 0), (30, 1)):
+        n, ip, ix, v, b = _jac(W, N, scen)
+        A = W.to_dense(n, ip, ix, v)
+        d = np.linspace(0.5, 1.0, n)
+        rho = O.spectral_radius_AinvD(A, d, iters=600)
+        ref = np.abs(np.linalg.eigvals(np.linalg.solve(A, np.diag(d)))).max()
+        assert rho == pytest.approx(ref, rel=2e-2)
