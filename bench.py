@@ -4,15 +4,15 @@
 One step = Alg. 1 steps 1-4 over the whole batch: 512 Jacobians (seeded load
 scenarios of one network) x K = 5 perturbations = 2560 perturbed systems of
 601 unknowns, each factored without pivoting, solved, and combined into 512
-recovered solutions, in one fused launch of the library.  Inputs are resident
-in device memory before the timed region starts.
+recovered solutions, by one call of the library (psp_solve_batched).  Inputs
+are resident in device memory before the timed region starts.
 
-Also reported on the same GPU:
-  * the plain path: one system per launch (K launches per Jacobian + combine);
-  * the other numeric path (dense vs sparse) for the same workload;
-  * the oracle (plain CPU FP64 code) on a bounded sample, for context;
-  * relative error of the recovered solutions against the pivoted oracle on a
-    sample of Jacobians.
+The library's autotuner (psp_tune) first times every numeric path on this
+batch; the chosen path is the headline (`value`, `config.path`), timed both as
+eager calls and as a replayed HIP graph (the better is reported).  Also on the
+same GPU: every other path, the plain path (one system per launch), the oracle
+(plain CPU FP64 code) on a bounded sample, and the error of the recovered
+solutions against the pivoted oracle on a sample of Jacobians.
 
 Prints ONE JSON line.  Only one GPU is supported.
 """
@@ -29,12 +29,16 @@ sys.path.insert(0, ROOT)
 
 METRIC = "pivot-free FP64 solves/s at n≈600, batched vs plain; rel err vs pivoted oracle"
 PEAK_FP64 = 78.6e12          # MI355X FP64 (vector and matrix), FLOP/s
-PEAK_HBM = 8.0e12            # MI355X HBM3E, B/s
+
+KERNELS = {"dense": "dense_factor_solve_kernel (one launch per step)",
+           "sparse_batched": "all launches of one step: il_gather, il_diag + il_offdiag per factor level, "
+                             "il_solve_level per solve level, il_combine",
+           "sparse_lds": "sparse_lds_kernel (one launch per step)",
+           "sparse_levels": "all launches of one step (per-level kernels)"}
 
 
 def dense_flops(n, nrhs=1):
-    f = n * (n - 1) / 2 + (n - 1) * n * (2 * n - 1) / 3
-    return f + nrhs * (2 * n * n - n)
+    return n * (n - 1) / 2 + (n - 1) * n * (2 * n - 1) / 3 + nrhs * (2 * n * n - n)
 
 
 def sparse_flops(info, n, nrhs=1):
@@ -46,10 +50,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--path", choices=["best", "dense", "sparse"], default="best")
+    ap.add_argument("--path", default="auto",
+                    choices=["auto", "dense", "sparse_batched", "sparse_lds", "sparse_levels"])
     ap.add_argument("--jacobians", type=int, default=512)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-system-per-launch timing")
+    ap.add_argument("--no-graph", action="store_true", help="skip the HIP-graph replay timing")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only (this build has no multi-GPU path); run with --gpus 1", file=sys.stderr)
@@ -69,7 +75,14 @@ def main():
     pinfo = plan.info()
     vals_d = torch.from_numpy(vals).to(dev)
     b_d = torch.from_numpy(bs).to(dev)
+    systems = S * K
     print(f"[bench] inputs ready n={n} jacobians={S} K={K} ({time.time() - t0:.1f}s)", file=sys.stderr, flush=True)
+
+    chosen, tuner_ms = psp.tune(plan, vals_d, eps, b_d)
+    torch.cuda.synchronize()
+    if args.path != "auto":
+        chosen = args.path
+    print(f"[bench] tuner: {tuner_ms} -> {chosen}", file=sys.stderr, flush=True)
 
     def run(path, steps, warmup):
         for _ in range(warmup):
@@ -78,106 +91,139 @@ def main():
         st = torch.cuda.current_stream()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        w0 = time.perf_counter()
         e0.record(st)
         for _ in range(steps):
             x, info = psp.solve_batched(plan, vals_d, eps, b_d, path=path)
         e1.record(st)
         torch.cuda.synchronize()
-        wall = (time.perf_counter() - w0) * 1e3 / steps
-        return e0.elapsed_time(e1) / steps, wall, x, info
+        return e0.elapsed_time(e1) / steps, x, info
 
     results = {}
-    paths = ["dense", "sparse"] if args.path == "best" else [args.path]
-    for p in paths:
-        ms, wall, x, info = run(p, args.steps, args.warmup)
-        results[p] = dict(ms=ms, wall_ms=wall, x=x, info=info)
-        print(f"[bench] {p}: {ms:.3f} ms/step (event), {wall:.3f} ms wall", file=sys.stderr, flush=True)
-    best = min(results, key=lambda p: results[p]["ms"])
-    r = results[best]
-    ms = r["ms"]
-    systems = S * K
+    for p in ["dense", "sparse_batched", "sparse_lds"]:
+        if p not in tuner_ms and p != chosen:
+            continue
+        ms, x, info = run(p, args.steps, args.warmup)
+        results[p] = dict(ms=ms, x=x, info=info)
+        print(f"[bench] {p}: {ms:.3f} ms/step", file=sys.stderr, flush=True)
+
+    graph_ms = None
+    if not args.no_graph:
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            psp.solve_batched(plan, vals_d, eps, b_d, path=chosen)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g):
+            xg, ig = psp.solve_batched(plan, vals_d, eps, b_d, path=chosen)
+        for _ in range(args.warmup):
+            g.replay()
+        torch.cuda.synchronize()
+        st = torch.cuda.current_stream()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(args.steps):
+            g.replay()
+        e1.record(st)
+        torch.cuda.synchronize()
+        graph_ms = e0.elapsed_time(e1) / args.steps
+        results[chosen]["graph_equal"] = bool(torch.equal(xg, results[chosen]["x"]))
+        print(f"[bench] {chosen} graph replay: {graph_ms:.3f} ms/step", file=sys.stderr, flush=True)
+
+    r = results[chosen]
+    eager_ms = r["ms"]
+    ms = min(eager_ms, graph_ms) if graph_ms is not None else eager_ms
     value = systems / (ms / 1e3)
 
-    per_sys = dense_flops(n) if best == "dense" else sparse_flops(pinfo, n)
-    achieved = per_sys * systems / (ms / 1e3)
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64, "traffic": None,
-                "kernel": "dense_factor_solve_kernel" if best == "dense" else "sparse_lds_kernel",
-                "flops_per_system": per_sys}
+    def flops_of(p):
+        return dense_flops(n) if p == "dense" else sparse_flops(pinfo, n)
 
-    others = {}
+    achieved = flops_of(chosen) * systems / (ms / 1e3)
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP64, "traffic": None, "kernel": KERNELS[chosen],
+                "flops_per_system": flops_of(chosen)}
+    roofline_dense = None
+    if "dense" in results:
+        a_d = dense_flops(n) * systems / (results["dense"]["ms"] / 1e3)
+        roofline_dense = {"bound": "alu", "achieved": a_d / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
+                          "frac": a_d / PEAK_FP64, "traffic": None, "kernel": KERNELS["dense"],
+                          "flops_per_system": dense_flops(n), "solves_per_s": systems / (results["dense"]["ms"] / 1e3)}
+
+    paths = {}
     for p, rr in results.items():
-        f = dense_flops(n) if p == "dense" else sparse_flops(pinfo, n)
-        others[p] = {"ms_per_step": rr["ms"], "solves_per_s": systems / (rr["ms"] / 1e3),
-                     "tflops": f * systems / (rr["ms"] / 1e3) / 1e12}
-    if len(results) == 2:
-        xa, xb = results["dense"]["x"].cpu().numpy(), results["sparse"]["x"].cpu().numpy()
-        others["dense_vs_sparse_bitwise_equal"] = bool(np.array_equal(xa, xb))
+        paths[p] = {"ms_per_step": rr["ms"], "solves_per_s": systems / (rr["ms"] / 1e3),
+                    "tflops": flops_of(p) * systems / (rr["ms"] / 1e3) / 1e12}
+    xs = [rr["x"] for rr in results.values()]
+    paths["all_paths_bitwise_equal"] = bool(all(torch.equal(xs[0], x) for x in xs[1:]))
 
     info_np = r["info"].cpu().numpy()
     x_np = r["x"].cpu().numpy()
     from oracle import oracle as O
-    # error of the recovered solution against the pivoted oracle on a sample
     errs, resid = [], []
     for s in (0, 1, 2, 3):
         A = W.to_dense(n, ip, ix, vals[s])
-        xs = O.pivoted_solve(A, bs[s])
-        errs.append(float(np.abs(x_np[s] - xs).max() / np.abs(xs).max()))
+        xs_ = O.pivoted_solve(A, bs[s])
+        errs.append(float(np.abs(x_np[s] - xs_).max() / np.abs(xs_).max()))
         resid.append(float(np.linalg.norm(A @ x_np[s] - bs[s]) / np.linalg.norm(bs[s])))
 
     plain = None
     if not args.no_plain:
-        # one system per launch: each (s, k) alone (batch=1, K=1), then the combine
+        # one system per launch: each (s, k) alone (batch = 1, K = 1), then the weighted sum
         J = min(S, 8)
-        c = psp.weights(eps)
         for _ in range(2):
             for s in range(J):
                 for k in range(K):
-                    psp.solve_batched(plan, vals_d[s:s + 1], eps[k:k + 1], b_d[s:s + 1], path=best)
+                    psp.solve_batched(plan, vals_d[s:s + 1], eps[k:k + 1], b_d[s:s + 1], path=chosen)
         torch.cuda.synchronize()
         w0 = time.perf_counter()
         for s in range(J):
-            xk = []
             for k in range(K):
-                xk.append(psp.solve_batched(plan, vals_d[s:s + 1], eps[k:k + 1], b_d[s:s + 1], path=best)[0])
+                psp.solve_batched(plan, vals_d[s:s + 1], eps[k:k + 1], b_d[s:s + 1], path=chosen)
         torch.cuda.synchronize()
         pms = (time.perf_counter() - w0) * 1e3
-        plain = {"solves_per_s": J * K / (pms / 1e3), "systems": J * K, "ms": pms,
+        plain = {"solves_per_s": J * K / (pms / 1e3), "systems": J * K, "ms": pms, "path": chosen,
                  "batched_speedup": value / (J * K / (pms / 1e3))}
 
     cpu = None
     if not args.no_cpu:
         sym = O.symbolic(n, ip, ix)
-        cnt = 8 if best == "dense" else 256
-        t = time.perf_counter()
-        if best == "dense":
+        if chosen == "dense":
+            cnt = 8
+            t = time.perf_counter()
             xo, io, _, thr = O.dense_batch(n, ip, ix, vals[:cnt], eps, bs[:cnt], perm=sym.perm)
         else:
+            cnt = S
+            t = time.perf_counter()
             xo, io, _, thr = O.sparse_batch(n, ip, ix, vals[:cnt], sym, eps, bs[:cnt])
         dt = time.perf_counter() - t
         cpu = {"value": cnt * K / dt, "unit": "solves/s", "cores": int(thr), "kind": "oracle",
-               "sample": f"{cnt} Jacobians x K={K} = {cnt * K} systems of n={n}, {best} oracle, {dt:.1f} s",
+               "sample": f"{cnt} Jacobians x K={K} = {cnt * K} systems of n={n}, "
+                         f"{'dense' if chosen == 'dense' else 'sparse'} oracle, {dt:.2f} s",
                "bitwise_equal_to_gpu": bool(np.array_equal(xo, x_np[:cnt]))}
 
     out = {
         "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "n601_batched", "network_buses": N, "n": n, "nnz": int(pinfo.nnz),
-                   "jacobians": S, "K": K, "systems_per_step": systems, "nrhs": 1, "path": best,
-                   "eps": [float(e) for e in eps], "ordering": "minimum degree",
-                   "parallelism": "single GPU"},
+        "config": {"workload": "n601_batched: 300-bus network, 512 scenarios x K=5", "network_buses": N, "n": n,
+                   "nnz": int(pinfo.nnz), "jacobians": S, "K": K, "systems_per_step": systems, "nrhs": 1,
+                   "path": chosen, "timed_as": "graph replay" if graph_ms is not None and graph_ms <= eager_ms
+                   else "eager calls", "eps": [float(e) for e in eps], "ordering": "minimum degree"},
         "roofline": roofline,
+        "roofline_dense": roofline_dense,
         "cpu_baseline": cpu,
         "plain": plain,
-        "paths": others,
+        "paths": paths,
+        "tuner_ms": tuner_ms,
+        "eager_ms_per_step": eager_ms,
+        "graph_ms_per_step": graph_ms,
+        "graph_bitwise_equal": r.get("graph_equal"),
         "recovered_solutions_per_s": S / (ms / 1e3),
         "rel_err_vs_pivoted": {"max": max(errs), "median": float(np.median(errs)), "sample": 4,
                                "residual_max": max(resid)},
         "info_nonzero": int(np.count_nonzero(info_np)),
-        "wall_ms_per_step": r["wall_ms"],
     }
     print(json.dumps(out))
 

@@ -67,9 +67,25 @@ __device__ __forceinline__ double merge_dot(const SpIdx& ix, int a, int b, const
 }
 
 // acc - sum lv[pl] * uv[pu] over the precomputed pairs of item id, in order
+// The loads of a block of U iterations are issued before its fma chain so
+// that U index/value fetches are in flight at once; the chain itself keeps
+// the ascending order.
+constexpr int U8 = 8;
+
 __device__ __forceinline__ double pair_dot(const SpIdx& ix, int id, const double* lv, const double* uv, double acc) {
     const int p1 = ix.pair_ptr[id + 1];
-    for (int p = ix.pair_ptr[id]; p < p1; ++p) {
+    int p = ix.pair_ptr[id];
+    for (; p + U8 <= p1; p += U8) {
+        int2 pq[U8];
+        double a[U8], b[U8];
+#pragma unroll
+        for (int u = 0; u < U8; ++u) pq[u] = ix.pairs[p + u];
+#pragma unroll
+        for (int u = 0; u < U8; ++u) { a[u] = lv[pq[u].x]; b[u] = uv[pq[u].y]; }
+#pragma unroll
+        for (int u = 0; u < U8; ++u) acc = fmad(-a[u], b[u], acc);
+    }
+    for (; p < p1; ++p) {
         const int2 pq = ix.pairs[p];
         acc = fmad(-lv[pq.x], uv[pq.y], acc);
     }
@@ -118,10 +134,17 @@ template <int TRANS>
 __device__ __forceinline__ double fwd_row(const SpIdx& ix, int i, int r, int nrhs, const double* ud, const double* lv,
                                           const double* uv, const double* y) {
     double acc = y[(int64_t)i * nrhs + r];
-    for (int p = ix.r_ptr[i]; p < ix.r_ptr[i + 1]; ++p) {
-        const double a = TRANS ? uv[ix.r_pos[p]] : lv[ix.r_pos[p]];
-        acc = fmad(-a, y[(int64_t)ix.r_idx[p] * nrhs + r], acc);
+    const double* m = TRANS ? uv : lv;
+    const int p1 = ix.r_ptr[i + 1];
+    int p = ix.r_ptr[i];
+    for (; p + U8 <= p1; p += U8) {
+        double a[U8], b[U8];
+#pragma unroll
+        for (int u = 0; u < U8; ++u) { a[u] = m[ix.r_pos[p + u]]; b[u] = y[(int64_t)ix.r_idx[p + u] * nrhs + r]; }
+#pragma unroll
+        for (int u = 0; u < U8; ++u) acc = fmad(-a[u], b[u], acc);
     }
+    for (; p < p1; ++p) acc = fmad(-m[ix.r_pos[p]], y[(int64_t)ix.r_idx[p] * nrhs + r], acc);
     return TRANS ? acc / ud[i] : acc;
 }
 
@@ -129,10 +152,17 @@ template <int TRANS>
 __device__ __forceinline__ double bwd_row(const SpIdx& ix, int i, int r, int nrhs, const double* ud, const double* lv,
                                           const double* uv, const double* y) {
     double acc = y[(int64_t)i * nrhs + r];
-    for (int t = ix.l_ptr[i + 1] - 1; t >= ix.l_ptr[i]; --t) {
-        const double a = TRANS ? lv[t] : uv[t];
-        acc = fmad(-a, y[(int64_t)ix.l_idx[t] * nrhs + r], acc);
+    const double* m = TRANS ? lv : uv;
+    const int t0 = ix.l_ptr[i];
+    int t = ix.l_ptr[i + 1] - 1;
+    for (; t - U8 + 1 >= t0; t -= U8) {
+        double a[U8], b[U8];
+#pragma unroll
+        for (int u = 0; u < U8; ++u) { a[u] = m[t - u]; b[u] = y[(int64_t)ix.l_idx[t - u] * nrhs + r]; }
+#pragma unroll
+        for (int u = 0; u < U8; ++u) acc = fmad(-a[u], b[u], acc);
     }
+    for (; t >= t0; --t) acc = fmad(-m[t], y[(int64_t)ix.l_idx[t] * nrhs + r], acc);
     return TRANS ? acc : acc / ud[i];
 }
 
@@ -346,7 +376,21 @@ __device__ __forceinline__ double il_pair_dot(const SpIdx& ix, int id, const dou
                                               int q, double acc) {
     const int p0 = __builtin_amdgcn_readfirstlane(ix.pair_ptr[id]);
     const int p1 = __builtin_amdgcn_readfirstlane(ix.pair_ptr[id + 1]);
-    for (int p = p0; p < p1; ++p) {
+    int p = p0;
+    for (; p + U8 <= p1; p += U8) {
+        int2 pq[U8];
+        double a[U8], b[U8];
+#pragma unroll
+        for (int u = 0; u < U8; ++u) pq[u] = ix.pairs[p + u];
+#pragma unroll
+        for (int u = 0; u < U8; ++u) {
+            a[u] = lv[(int64_t)pq[u].x * TP + q];
+            b[u] = uv[(int64_t)pq[u].y * TP + q];
+        }
+#pragma unroll
+        for (int u = 0; u < U8; ++u) acc = fmad(-a[u], b[u], acc);
+    }
+    for (; p < p1; ++p) {
         const int2 pq = ix.pairs[p];
         acc = fmad(-lv[(int64_t)pq.x * TP + q], uv[(int64_t)pq.y * TP + q], acc);
     }
@@ -444,11 +488,34 @@ __global__ void il_solve_level_kernel(IlArgs a, int c0, int cnt) {
         const int i = ix.lev_idx[UPPER ? 2 : 1][c0 + v / nrhs], r = v % nrhs;
         double acc = y[((int64_t)i * nrhs + r) * TP + q];
         if (!UPPER) {
-            const int p0 = ix.r_ptr[i], p1 = ix.r_ptr[i + 1];
-            for (int p = p0; p < p1; ++p)
+            const int p1 = ix.r_ptr[i + 1];
+            int p = ix.r_ptr[i];
+            for (; p + U8 <= p1; p += U8) {
+                double a[U8], b[U8];
+#pragma unroll
+                for (int u = 0; u < U8; ++u) {
+                    a[u] = lv[(int64_t)ix.r_pos[p + u] * TP + q];
+                    b[u] = y[((int64_t)ix.r_idx[p + u] * nrhs + r) * TP + q];
+                }
+#pragma unroll
+                for (int u = 0; u < U8; ++u) acc = fmad(-a[u], b[u], acc);
+            }
+            for (; p < p1; ++p)
                 acc = fmad(-lv[(int64_t)ix.r_pos[p] * TP + q], y[((int64_t)ix.r_idx[p] * nrhs + r) * TP + q], acc);
         } else {
-            for (int t = ix.l_ptr[i + 1] - 1; t >= ix.l_ptr[i]; --t)
+            const int t0 = ix.l_ptr[i];
+            int t = ix.l_ptr[i + 1] - 1;
+            for (; t - U8 + 1 >= t0; t -= U8) {
+                double a[U8], b[U8];
+#pragma unroll
+                for (int u = 0; u < U8; ++u) {
+                    a[u] = uv[(int64_t)(t - u) * TP + q];
+                    b[u] = y[((int64_t)ix.l_idx[t - u] * nrhs + r) * TP + q];
+                }
+#pragma unroll
+                for (int u = 0; u < U8; ++u) acc = fmad(-a[u], b[u], acc);
+            }
+            for (; t >= t0; --t)
                 acc = fmad(-uv[(int64_t)t * TP + q], y[((int64_t)ix.l_idx[t] * nrhs + r) * TP + q], acc);
             acc = acc / ud[(int64_t)i * TP + q];
         }
