@@ -127,6 +127,9 @@ PSP_API psp_status psp_weights(int32_t K, const double* eps, double* c);
  *   PSP_PATH_SPARSE_LDS      one workgroup per system, factors in LDS (needs
  *                     (n + 2 nnz_l + n nrhs) * 8 <= 152 KiB).
  *   PSP_PATH_SPARSE_LEVELS   one launch per level, factors in the workspace.
+ *   PSP_PATH_SPARSE_GROUPED  systems interleaved as in _BATCHED, but each
+ *                     workgroup walks all levels for 32 systems with
+ *                     workgroup barriers (two launches per call).
  *   PSP_PATH_AUTO     the path psp_tune chose for this (batch, K, nrhs), else
  *                     a size heuristic.
  * A path that cannot run the plan returns PSP_E_UNSUPPORTED.  Every path
@@ -138,7 +141,8 @@ enum {
     PSP_PATH_SPARSE = 2,
     PSP_PATH_SPARSE_BATCHED = 3,
     PSP_PATH_SPARSE_LDS = 4,
-    PSP_PATH_SPARSE_LEVELS = 5
+    PSP_PATH_SPARSE_LEVELS = 5,
+    PSP_PATH_SPARSE_GROUPED = 6
 };
 
 /* Bytes of device workspace psp_factor / psp_solve_batched need for `batch`
@@ -172,7 +176,7 @@ PSP_API psp_status psp_solve_batched(psp_plan plan, int32_t path, int32_t batch,
  * and records the fastest as the PSP_PATH_AUTO choice for (batch, K, nrhs).
  * Arguments as for psp_solve_batched (X and info receive the last run's
  * results, which are the same on every path).  chosen (host, may be NULL)
- * receives the path id; ms (host, may be NULL, 6 entries indexed by path id)
+ * receives the path id; ms (host, may be NULL, 7 entries indexed by path id)
  * receives the mean time per call, -1 for a path not run.  Size the
  * workspace with psp_workspace_bytes(plan, PSP_PATH_AUTO, ...), which covers
  * every candidate.

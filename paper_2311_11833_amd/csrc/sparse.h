@@ -43,7 +43,7 @@ struct SparseDevice {
     std::vector<int32_t> h_lpos_ptr;
 };
 
-enum { kVarLds = 0, kVarGlobal = 1, kVarBatched = 2 };
+enum { kVarLds = 0, kVarGlobal = 1, kVarBatched = 2, kVarGrouped = 3 };
 int sparse_variant(const Symbolic& s, int64_t ntasks, int32_t nrhs, int forced);
 
 hipError_t sparse_upload(const Symbolic& s, SparseDevice& d);

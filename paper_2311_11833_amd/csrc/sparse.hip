@@ -372,10 +372,14 @@ struct IlArgs {
     double* y;       // (n * nrhs) x TP
 };
 
+// UNIFORM: every lane of the wave works on the same item (the per-level
+// kernels, where a wave covers 64 consecutive tasks of one item), so the pair
+// range is made wave-uniform; the grouped kernel mixes items within a wave.
+template <bool UNIFORM>
 __device__ __forceinline__ double il_pair_dot(const SpIdx& ix, int id, const double* lv, const double* uv, int TP,
                                               int q, double acc) {
-    const int p0 = __builtin_amdgcn_readfirstlane(ix.pair_ptr[id]);
-    const int p1 = __builtin_amdgcn_readfirstlane(ix.pair_ptr[id + 1]);
+    const int p0 = UNIFORM ? __builtin_amdgcn_readfirstlane(ix.pair_ptr[id]) : ix.pair_ptr[id];
+    const int p1 = UNIFORM ? __builtin_amdgcn_readfirstlane(ix.pair_ptr[id + 1]) : ix.pair_ptr[id + 1];
     int p = p0;
     for (; p + U8 <= p1; p += U8) {
         int2 pq[U8];
@@ -397,129 +401,193 @@ __device__ __forceinline__ double il_pair_dot(const SpIdx& ix, int id, const dou
     return acc;
 }
 
-__global__ void il_gather_kernel(IlArgs a, EpsSet es) {
+// ---- per-item work of the batched execution, shared by the per-level
+// kernels and the grouped kernel (q = task index)
+__device__ __forceinline__ void il_gather_item(const IlArgs& a, const EpsSet& es, int v, int q) {
     const SpIdx& ix = a.ix;
     const int n = ix.n, nl = ix.nnzl;
-    const int64_t total = (int64_t)(n + nl) * a.TP;
     double* ud = a.fac;
     double* lv = a.fac + (int64_t)n * a.TP;
     double* uv = lv + (int64_t)nl * a.TP;
-    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
-        const int q = (int)(g % a.TP), v = (int)(g / a.TP);
-        if (q >= a.ntasks) continue;
-        const int s = q / es.K, kk = q % es.K;
-        const double* vals = a.values + (int64_t)s * a.nnz;
-        if (v < nl) {
-            const int sl = ix.src_l[v], su = ix.src_u[v];
-            lv[g] = sl >= 0 ? vals[sl] : 0.0;
-            uv[g] = su >= 0 ? vals[su] : 0.0;
-        } else {
-            const int j = v - nl;
-            ud[(int64_t)j * a.TP + q] = gather_diag(ix, j, vals, eps_at(es, kk), a.dvec);
-            if (j == 0) a.info[q] = INT_MAX;
+    const int s = q / es.K, kk = q % es.K;
+    const double* vals = a.values + (int64_t)s * a.nnz;
+    if (v < nl) {
+        const int sl = ix.src_l[v], su = ix.src_u[v];
+        lv[(int64_t)v * a.TP + q] = sl >= 0 ? vals[sl] : 0.0;
+        uv[(int64_t)v * a.TP + q] = su >= 0 ? vals[su] : 0.0;
+    } else {
+        const int j = v - nl;
+        ud[(int64_t)j * a.TP + q] = gather_diag(ix, j, vals, eps_at(es, kk), a.dvec);
+        if (j == 0) a.info[q] = INT_MAX;
+    }
+}
+
+template <bool UNIFORM>
+__device__ __forceinline__ void il_diag_item(const IlArgs& a, int j, int q) {
+    const SpIdx& ix = a.ix;
+    double* ud = a.fac;
+    const double* lv = a.fac + (int64_t)ix.n * a.TP;
+    const double* uv = lv + (int64_t)ix.nnzl * a.TP;
+    const double u = il_pair_dot<UNIFORM>(ix, j, lv, uv, a.TP, q, ud[(int64_t)j * a.TP + q]);
+    ud[(int64_t)j * a.TP + q] = u;
+    if (bad_pivot(u)) atomicMin(&a.info[q], j + 1);
+}
+
+template <bool UNIFORM>
+__device__ __forceinline__ void il_offdiag_item(const IlArgs& a, int p0, int np, int it, int q) {
+    const SpIdx& ix = a.ix;
+    const int n = ix.n, nl = ix.nnzl;
+    const double* ud = a.fac;
+    double* lv = a.fac + (int64_t)n * a.TP;
+    double* uv = lv + (int64_t)nl * a.TP;
+    const bool is_l = it >= np;
+    const int t = ix.lpos[p0 + (is_l ? it - np : it)];
+    const int64_t o = (int64_t)t * a.TP + q;
+    if (!is_l) {
+        uv[o] = il_pair_dot<UNIFORM>(ix, n + t, lv, uv, a.TP, q, uv[o]);
+    } else {
+        const int j = ix.col_of[t];
+        lv[o] = il_pair_dot<UNIFORM>(ix, n + nl + t, lv, uv, a.TP, q, lv[o]) / ud[(int64_t)j * a.TP + q];
+    }
+}
+
+__device__ __forceinline__ void il_rhs_item(const IlArgs& a, int v, int q) {
+    const SpIdx& ix = a.ix;
+    const int n = ix.n, nrhs = a.nrhs;
+    const int s = q / a.K, i = v / nrhs, r = v % nrhs;
+    a.y[(int64_t)v * a.TP + q] = a.B[((int64_t)s * n + ix.perm[i]) * nrhs + r];
+}
+
+template <int UPPER>
+__device__ __forceinline__ void il_solve_item(const IlArgs& a, int i, int r, int q) {
+    const SpIdx& ix = a.ix;
+    const int n = ix.n, nl = ix.nnzl, nrhs = a.nrhs, TP = a.TP;
+    const double* ud = a.fac;
+    const double* lv = a.fac + (int64_t)n * TP;
+    const double* uv = lv + (int64_t)nl * TP;
+    double* y = a.y;
+    double acc = y[((int64_t)i * nrhs + r) * TP + q];
+    if (!UPPER) {
+        const int p1 = ix.r_ptr[i + 1];
+        int p = ix.r_ptr[i];
+        for (; p + U8 <= p1; p += U8) {
+            double x[U8], z[U8];
+#pragma unroll
+            for (int u = 0; u < U8; ++u) {
+                x[u] = lv[(int64_t)ix.r_pos[p + u] * TP + q];
+                z[u] = y[((int64_t)ix.r_idx[p + u] * nrhs + r) * TP + q];
+            }
+#pragma unroll
+            for (int u = 0; u < U8; ++u) acc = fmad(-x[u], z[u], acc);
         }
+        for (; p < p1; ++p)
+            acc = fmad(-lv[(int64_t)ix.r_pos[p] * TP + q], y[((int64_t)ix.r_idx[p] * nrhs + r) * TP + q], acc);
+    } else {
+        const int t0 = ix.l_ptr[i];
+        int t = ix.l_ptr[i + 1] - 1;
+        for (; t - U8 + 1 >= t0; t -= U8) {
+            double x[U8], z[U8];
+#pragma unroll
+            for (int u = 0; u < U8; ++u) {
+                x[u] = uv[(int64_t)(t - u) * TP + q];
+                z[u] = y[((int64_t)ix.l_idx[t - u] * nrhs + r) * TP + q];
+            }
+#pragma unroll
+            for (int u = 0; u < U8; ++u) acc = fmad(-x[u], z[u], acc);
+        }
+        for (; t >= t0; --t)
+            acc = fmad(-uv[(int64_t)t * TP + q], y[((int64_t)ix.l_idx[t] * nrhs + r) * TP + q], acc);
+        acc = acc / ud[(int64_t)i * TP + q];
+    }
+    y[((int64_t)i * nrhs + r) * TP + q] = acc;
+}
+
+__global__ void il_gather_kernel(IlArgs a, EpsSet es) {
+    const int64_t total = (int64_t)(a.ix.n + a.ix.nnzl) * a.TP;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+        const int q = (int)(g % a.TP);
+        if (q < a.ntasks) il_gather_item(a, es, (int)(g / a.TP), q);
     }
 }
 
 __global__ void il_diag_kernel(IlArgs a, int c0, int cnt) {
-    const SpIdx& ix = a.ix;
-    const int n = ix.n, nl = ix.nnzl;
     const int64_t total = (int64_t)cnt * a.TP;
-    double* ud = a.fac;
-    const double* lv = a.fac + (int64_t)n * a.TP;
-    const double* uv = lv + (int64_t)nl * a.TP;
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
         const int q = (int)(g % a.TP);
-        const int j = ix.lev_idx[0][c0 + (int)(g / a.TP)];
-        if (q >= a.ntasks) continue;
-        const double u = il_pair_dot(ix, j, lv, uv, a.TP, q, ud[(int64_t)j * a.TP + q]);
-        ud[(int64_t)j * a.TP + q] = u;
-        if (bad_pivot(u)) atomicMin(&a.info[q], j + 1);
+        if (q < a.ntasks) il_diag_item<true>(a, a.ix.lev_idx[0][c0 + (int)(g / a.TP)], q);
     }
 }
 
 __global__ void il_offdiag_kernel(IlArgs a, int p0, int np) {
-    const SpIdx& ix = a.ix;
-    const int n = ix.n, nl = ix.nnzl;
     const int64_t total = (int64_t)2 * np * a.TP;
-    const double* ud = a.fac;
-    double* lv = a.fac + (int64_t)n * a.TP;
-    double* uv = lv + (int64_t)nl * a.TP;
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
-        const int q = (int)(g % a.TP), it = (int)(g / a.TP);
-        if (q >= a.ntasks) continue;
-        const bool is_l = it >= np;
-        const int t = ix.lpos[p0 + (is_l ? it - np : it)];
-        const int64_t o = (int64_t)t * a.TP + q;
-        if (!is_l) {
-            uv[o] = il_pair_dot(ix, n + t, lv, uv, a.TP, q, uv[o]);
-        } else {
-            const int j = ix.col_of[t];
-            lv[o] = il_pair_dot(ix, n + nl + t, lv, uv, a.TP, q, lv[o]) / ud[(int64_t)j * a.TP + q];
-        }
+        const int q = (int)(g % a.TP);
+        if (q < a.ntasks) il_offdiag_item<true>(a, p0, np, (int)(g / a.TP), q);
     }
 }
 
 __global__ void il_rhs_in_kernel(IlArgs a) {
-    const SpIdx& ix = a.ix;
-    const int n = ix.n, nrhs = a.nrhs;
-    const int64_t total = (int64_t)n * nrhs * a.TP;
+    const int64_t total = (int64_t)a.ix.n * a.nrhs * a.TP;
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
         const int q = (int)(g % a.TP), v = (int)(g / a.TP);
         if (q >= a.ntasks) continue;
-        if (q < a.ntasks && v == 0 && a.info[q] == INT_MAX) a.info[q] = 0;
-        const int s = q / a.K, i = v / nrhs, r = v % nrhs;
-        a.y[g] = a.B[((int64_t)s * n + ix.perm[i]) * nrhs + r];
+        if (v == 0 && a.info[q] == INT_MAX) a.info[q] = 0;
+        il_rhs_item(a, v, q);
     }
 }
 
 template <int UPPER>
 __global__ void il_solve_level_kernel(IlArgs a, int c0, int cnt) {
-    const SpIdx& ix = a.ix;
-    const int n = ix.n, nl = ix.nnzl, nrhs = a.nrhs, TP = a.TP;
-    const int64_t total = (int64_t)cnt * nrhs * TP;
-    const double* ud = a.fac;
-    const double* lv = a.fac + (int64_t)n * TP;
-    const double* uv = lv + (int64_t)nl * TP;
-    double* y = a.y;
+    const int nrhs = a.nrhs;
+    const int64_t total = (int64_t)cnt * nrhs * a.TP;
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
-        const int q = (int)(g % TP), v = (int)(g / TP);
-        if (q >= a.ntasks) continue;
-        const int i = ix.lev_idx[UPPER ? 2 : 1][c0 + v / nrhs], r = v % nrhs;
-        double acc = y[((int64_t)i * nrhs + r) * TP + q];
-        if (!UPPER) {
-            const int p1 = ix.r_ptr[i + 1];
-            int p = ix.r_ptr[i];
-            for (; p + U8 <= p1; p += U8) {
-                double a[U8], b[U8];
-#pragma unroll
-                for (int u = 0; u < U8; ++u) {
-                    a[u] = lv[(int64_t)ix.r_pos[p + u] * TP + q];
-                    b[u] = y[((int64_t)ix.r_idx[p + u] * nrhs + r) * TP + q];
-                }
-#pragma unroll
-                for (int u = 0; u < U8; ++u) acc = fmad(-a[u], b[u], acc);
-            }
-            for (; p < p1; ++p)
-                acc = fmad(-lv[(int64_t)ix.r_pos[p] * TP + q], y[((int64_t)ix.r_idx[p] * nrhs + r) * TP + q], acc);
-        } else {
-            const int t0 = ix.l_ptr[i];
-            int t = ix.l_ptr[i + 1] - 1;
-            for (; t - U8 + 1 >= t0; t -= U8) {
-                double a[U8], b[U8];
-#pragma unroll
-                for (int u = 0; u < U8; ++u) {
-                    a[u] = uv[(int64_t)(t - u) * TP + q];
-                    b[u] = y[((int64_t)ix.l_idx[t - u] * nrhs + r) * TP + q];
-                }
-#pragma unroll
-                for (int u = 0; u < U8; ++u) acc = fmad(-a[u], b[u], acc);
-            }
-            for (; t >= t0; --t)
-                acc = fmad(-uv[(int64_t)t * TP + q], y[((int64_t)ix.l_idx[t] * nrhs + r) * TP + q], acc);
-            acc = acc / ud[(int64_t)i * TP + q];
-        }
-        y[((int64_t)i * nrhs + r) * TP + q] = acc;
+        const int q = (int)(g % a.TP), v = (int)(g / a.TP);
+        if (q < a.ntasks) il_solve_item<UPPER>(a, a.ix.lev_idx[UPPER ? 2 : 1][c0 + v / nrhs], v % nrhs, q);
+    }
+}
+
+// Grouped execution: workgroup g owns tasks [g*GS, g*GS + GS) and walks every
+// level of the factorisation and both substitutions itself, with workgroup
+// barriers between phases instead of kernel boundaries.  Lane l serves task
+// g*GS + l%GS; the 64/GS lane groups of a wave and the waves of the
+// workgroup share out the items of a phase.
+template <int GS>
+__global__ __launch_bounds__(512) void il_group_kernel(IlArgs a, EpsSet es) {
+    const SpIdx& ix = a.ix;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int slot = wave * (64 / GS) + lane / GS;
+    const int nslot = (blockDim.x >> 6) * (64 / GS);
+    const int q = blockIdx.x * GS + lane % GS;
+    const bool act = q < a.ntasks;
+    const int n = ix.n, nl = ix.nnzl, nrhs = a.nrhs;
+    for (int v = slot; v < n + nl; v += nslot)
+        if (act) il_gather_item(a, es, v, q);
+    __syncthreads();
+    for (int l = 0; l < ix.nlev[0]; ++l) {
+        const int c0 = ix.lev_ptr[0][l], cnt = ix.lev_ptr[0][l + 1] - c0;
+        for (int ci = slot; ci < cnt; ci += nslot)
+            if (act) il_diag_item<GS == 64>(a, ix.lev_idx[0][c0 + ci], q);
+        __syncthreads();
+        const int p0 = ix.lpos_ptr[l], np = ix.lpos_ptr[l + 1] - p0;
+        for (int it = slot; it < 2 * np; it += nslot)
+            if (act) il_offdiag_item<GS == 64>(a, p0, np, it, q);
+        __syncthreads();
+    }
+    if (act && slot == 0 && a.info[q] == INT_MAX) a.info[q] = 0;
+    for (int v = slot; v < n * nrhs; v += nslot)
+        if (act) il_rhs_item(a, v, q);
+    __syncthreads();
+    for (int l = 0; l < ix.nlev[1]; ++l) {
+        const int c0 = ix.lev_ptr[1][l], cnt = ix.lev_ptr[1][l + 1] - c0;
+        for (int t = slot; t < cnt * nrhs; t += nslot)
+            if (act) il_solve_item<0>(a, ix.lev_idx[1][c0 + t / nrhs], t % nrhs, q);
+        __syncthreads();
+    }
+    for (int l = 0; l < ix.nlev[2]; ++l) {
+        const int c0 = ix.lev_ptr[2][l], cnt = ix.lev_ptr[2][l + 1] - c0;
+        for (int t = slot; t < cnt * nrhs; t += nslot)
+            if (act) il_solve_item<1>(a, ix.lev_idx[2][c0 + t / nrhs], t % nrhs, q);
+        __syncthreads();
     }
 }
 
@@ -565,6 +633,7 @@ bool pairs_ok(const Symbolic& s) { return (s.flops_sparse - s.l_ptr[s.n]) / 2 <=
 int variant_of(const Symbolic& s, int64_t ntasks, int32_t nrhs, int forced) {
     if (forced == kVarLds) return sparse_fits_lds(s, nrhs) ? kVarLds : -1;
     if (forced == kVarBatched) return pairs_ok(s) ? kVarBatched : -1;
+    if (forced == kVarGrouped) return pairs_ok(s) ? kVarGrouped : -1;
     if (forced == kVarGlobal) return kVarGlobal;
     if (ntasks >= 256 && pairs_ok(s)) return kVarBatched;
     if (sparse_fits_lds(s, nrhs)) return kVarLds;
@@ -586,7 +655,7 @@ SpLayout sp_layout(const Symbolic& s, int32_t batch, int32_t K, int32_t nrhs, in
     L.off_fac = 0;
     int var = keep ? kVarGlobal : variant_of(s, ntasks, nrhs, forced);
     if (var < 0) var = kVarGlobal;
-    if (var == kVarBatched) {
+    if (var == kVarBatched || var == kVarGrouped) {
         const int64_t TP = tp_of(ntasks);
         L.off_y = align256(((int64_t)s.n + 2 * (int64_t)s.l_ptr[s.n]) * TP * 8);
         L.off_xk = align256(L.off_y + (int64_t)s.n * nrhs * TP * 8);
@@ -605,7 +674,7 @@ SpLayout sp_layout(const Symbolic& s, int32_t batch, int32_t K, int32_t nrhs, in
 
 hipError_t batched_run(const Symbolic& s, const SparseDevice& d, int32_t batch, const double* values, const EpsSet& es,
                        const double* dvec, int32_t nrhs, const double* B, double* X, int32_t* info, char* w,
-                       const SpLayout& L, hipStream_t st) {
+                       const SpLayout& L, hipStream_t st, bool grouped) {
     IlArgs a{};
     a.ix = d.idx;
     a.nnz = s.nnz; a.nrhs = nrhs; a.ntasks = batch * es.K; a.TP = (int32_t)tp_of(a.ntasks); a.K = es.K;
@@ -613,6 +682,13 @@ hipError_t batched_run(const Symbolic& s, const SparseDevice& d, int32_t batch, 
     a.fac = (double*)(w + L.off_fac);
     a.y = (double*)(w + L.off_y);
     const int n = s.n, nl = s.l_ptr[n];
+    if (grouped) {
+        constexpr int GS = 32;
+        hipLaunchKernelGGL(il_group_kernel<GS>, dim3((a.ntasks + GS - 1) / GS), dim3(512), 0, st, a, es);
+        hipLaunchKernelGGL(il_combine_kernel, dim3(grid_for((int64_t)batch * n * nrhs, kThreads)), dim3(kThreads), 0, st,
+                           a, es);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(il_gather_kernel, dim3(grid_for((int64_t)(n + nl) * a.TP, kThreads)), dim3(kThreads), 0, st, a, es);
     for (int l = 0; l < a.ix.nlev[0]; ++l) {
         const int c0 = d.h_lev_ptr[0][l], cnt = d.h_lev_ptr[0][l + 1] - c0;
@@ -814,7 +890,8 @@ hipError_t sparse_solve_batched(const Symbolic& s, const SparseDevice& d, int32_
     a.Xk = (double*)(w + L.off_xk);
     const int var = variant_of(s, ntasks, nrhs, forced);
     if (var < 0) return hipErrorInvalidValue;
-    if (var == kVarBatched) return batched_run(s, d, batch, values, es, dvec, nrhs, B, X, info, w, L, st);
+    if (var == kVarBatched || var == kVarGrouped)
+        return batched_run(s, d, batch, values, es, dvec, nrhs, B, X, info, w, L, st, var == kVarGrouped);
     if (var == kVarLds) {
         const int lds = (int)lds_bytes(s, nrhs);
         hipError_t e = hipFuncSetAttribute((const void*)sparse_lds_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, lds);

@@ -123,7 +123,7 @@ def test_large_sparse_sampled(psp, O, W, dev):
     assert np.all(np.isfinite(Xk.cpu().numpy()))
 
 
-@pytest.mark.parametrize("variant", ["sparse_batched", "sparse_lds", "sparse_levels"])
+@pytest.mark.parametrize("variant", ["sparse_batched", "sparse_grouped", "sparse_lds", "sparse_levels"])
 def test_sparse_variants_match_oracle(psp, O, W, dev, variant):
     """The three executions of the sparse path (systems interleaved across lanes, one
     workgroup per system in LDS, per-level kernels over task-major factors) on the same
@@ -148,7 +148,7 @@ def test_tuner_picks_a_path_and_auto_uses_it(psp, O, W, dev):
     v, b = torch.from_numpy(vals).to(dev), torch.from_numpy(bs).to(dev)
     chosen, times = psp.tune(plan, v, eps, b)
     assert chosen in times and times[chosen] == min(times.values())
-    assert set(times) >= {"dense", "sparse_batched", "sparse_lds", "sparse_levels"}
+    assert set(times) >= {"dense", "sparse_batched", "sparse_grouped", "sparse_lds", "sparse_levels"}
     x, info = psp.solve_batched(plan, v, eps, b, path="auto")
     torch.cuda.synchronize()
     sym = O.symbolic(n, ip, ix)
