@@ -35,6 +35,7 @@ KERNELS = {"dense": "dense_factor_solve_kernel (one launch per step)",
                              "il_solve_level per solve level, il_combine",
            "sparse_lds": "sparse_lds_kernel (one launch per step)",
            "sparse_grouped": "il_group_kernel + il_combine (two launches per step)",
+           "sparse_steps": "steps_kernel (one launch per step, combine fused)",
            "sparse_levels": "all launches of one step (per-level kernels)"}
 
 
@@ -52,7 +53,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--path", default="auto",
-                    choices=["auto", "dense", "sparse_batched", "sparse_grouped", "sparse_lds", "sparse_levels"])
+                    choices=["auto", "dense", "sparse_batched", "sparse_grouped", "sparse_lds", "sparse_levels",
+                             "sparse_steps"])
     ap.add_argument("--jacobians", type=int, default=512)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-system-per-launch timing")
@@ -100,7 +102,7 @@ def main():
         return e0.elapsed_time(e1) / steps, x, info
 
     results = {}
-    for p in ["dense", "sparse_batched", "sparse_grouped", "sparse_lds"]:
+    for p in ["dense", "sparse_batched", "sparse_grouped", "sparse_lds", "sparse_steps"]:
         if p not in tuner_ms and p != chosen:
             continue
         ms, x, info = run(p, args.steps, args.warmup)

@@ -130,6 +130,12 @@ PSP_API psp_status psp_weights(int32_t K, const double* eps, double* c);
  *   PSP_PATH_SPARSE_GROUPED  systems interleaved as in _BATCHED, but each
  *                     workgroup walks all levels for 32 systems with
  *                     workgroup barriers (two launches per call).
+ *   PSP_PATH_SPARSE_STEPS    one workgroup per Jacobian runs its K systems in
+ *                     LDS on a dataflow step schedule: every factor and RHS
+ *                     entry advances its own update chain as soon as its
+ *                     inputs are final, forward substitution overlapping the
+ *                     factorisation; one launch per call (needs nrhs = 1 and
+ *                     (3 n + 2 nnz_l) * 8 <= 152 KiB).
  *   PSP_PATH_AUTO     the path psp_tune chose for this (batch, K, nrhs), else
  *                     a size heuristic.
  * A path that cannot run the plan returns PSP_E_UNSUPPORTED.  Every path
@@ -142,7 +148,8 @@ enum {
     PSP_PATH_SPARSE_BATCHED = 3,
     PSP_PATH_SPARSE_LDS = 4,
     PSP_PATH_SPARSE_LEVELS = 5,
-    PSP_PATH_SPARSE_GROUPED = 6
+    PSP_PATH_SPARSE_GROUPED = 6,
+    PSP_PATH_SPARSE_STEPS = 7
 };
 
 /* Bytes of device workspace psp_factor / psp_solve_batched need for `batch`
@@ -176,7 +183,7 @@ PSP_API psp_status psp_solve_batched(psp_plan plan, int32_t path, int32_t batch,
  * and records the fastest as the PSP_PATH_AUTO choice for (batch, K, nrhs).
  * Arguments as for psp_solve_batched (X and info receive the last run's
  * results, which are the same on every path).  chosen (host, may be NULL)
- * receives the path id; ms (host, may be NULL, 7 entries indexed by path id)
+ * receives the path id; ms (host, may be NULL, 8 entries indexed by path id)
  * receives the mean time per call, -1 for a path not run.  Size the
  * workspace with psp_workspace_bytes(plan, PSP_PATH_AUTO, ...), which covers
  * every candidate.

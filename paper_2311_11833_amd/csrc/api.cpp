@@ -195,6 +195,7 @@ PathSel split_path(int32_t path) {
         case PSP_PATH_SPARSE_LDS: return {PSP_PATH_SPARSE, kVarLds};
         case PSP_PATH_SPARSE_LEVELS: return {PSP_PATH_SPARSE, kVarGlobal};
         case PSP_PATH_SPARSE_GROUPED: return {PSP_PATH_SPARSE, kVarGrouped};
+        case PSP_PATH_SPARSE_STEPS: return {PSP_PATH_SPARSE, kVarSteps};
         default: return {-1, -1};
     }
 }
@@ -298,7 +299,7 @@ size_t psp_workspace_bytes(psp_plan p, int32_t path, int32_t batch, int32_t K, i
     if (!p || batch < 1 || K < 1 || nrhs < 0) return 0;
     if (path == PSP_PATH_AUTO) {
         size_t m = 0;
-        for (int32_t c = PSP_PATH_DENSE; c <= PSP_PATH_SPARSE_GROUPED; ++c)
+        for (int32_t c = PSP_PATH_DENSE; c <= PSP_PATH_SPARSE_STEPS; ++c)
             if (c != PSP_PATH_DENSE || p->sym.n <= 4096) m = std::max(m, path_workspace(p->sym, c, batch, K, nrhs, keep));
         return m;
     }
@@ -349,6 +350,8 @@ psp_status psp_solve_batched(psp_plan p, int32_t path, int32_t batch, const doub
             std::lock_guard<std::mutex> g(p->mu);
             HIP_TRY(sparse_upload(s, p->sp), "sparse plan upload");
         }
+        if (ps.forced == kVarSteps && !steps_ready(p->sp))
+            return fail(PSP_E_UNSUPPORTED, "this sparse execution cannot run the plan (step schedule does not fit in LDS)");
         HIP_TRY(sparse_solve_batched(s, p->sp, batch, values, es, d, nrhs, B, X, info, ws, st, ps.forced), "sparse launch");
         return PSP_OK;
     }
@@ -361,14 +364,14 @@ psp_status psp_tune(psp_plan p, int32_t batch, const double* values, int32_t K, 
     if (!p) return fail(PSP_E_INVALID, "psp_tune: NULL plan");
     const hipStream_t st = (hipStream_t)stream;
     if (ms)
-        for (int c = 0; c < 7; ++c) ms[c] = -1.0f;
+        for (int c = 0; c <= PSP_PATH_SPARSE_STEPS; ++c) ms[c] = -1.0f;
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
     HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
     int32_t best = -1;
     float best_ms = 0.0f;
     psp_status last = PSP_OK;
-    for (int32_t c = PSP_PATH_DENSE; c <= PSP_PATH_SPARSE_GROUPED; ++c) {
+    for (int32_t c = PSP_PATH_DENSE; c <= PSP_PATH_SPARSE_STEPS; ++c) {
         if (c == PSP_PATH_SPARSE) continue;   // its executions are tried one by one
         if (path_workspace(p->sym, c, batch, K, nrhs, 0) > ws_bytes) continue;
         psp_status r = psp_solve_batched(p, c, batch, values, K, eps, d, nrhs, B, X, info, ws, ws_bytes, stream);

@@ -35,18 +35,42 @@ struct SpIdx {
     const int2* pairs;
 };
 
+// Dataflow step schedule of one perturbed system (factor, forward and
+// backward substitution), for the step kernel.  Each factor or RHS entry
+// advances its own fma chain, in the reference order, as soon as the inputs
+// of its next updates are final; a step is the set of such chain segments
+// that can run between two workgroup barriers.  Descriptors are laid out
+// per step as rows x active threads, row r of thread t at base + r*tact + t.
+struct StepIdx {
+    int32_t nsteps = 0, threads = 0, ndesc = 0;
+    const int4* meta = nullptr;       // per step: slot base, active threads, rows, 0
+    const int2* desc = nullptr;       // task descriptors (see steps.hip)
+    const uint32_t* xp = nullptr;     // update lists of tasks with two or more updates
+};
+
 struct SparseDevice {
     bool ready = false;
     int32_t* buf = nullptr;
     SpIdx idx{};
     std::vector<int32_t> h_lev_ptr[3];   // host copies for per-level launches
     std::vector<int32_t> h_lpos_ptr;
+    int32_t* st_buf = nullptr;           // step schedule (absent when the system does not fit in LDS)
+    StepIdx st{};
 };
 
-enum { kVarLds = 0, kVarGlobal = 1, kVarBatched = 2, kVarGrouped = 3 };
+enum { kVarLds = 0, kVarGlobal = 1, kVarBatched = 2, kVarGrouped = 3, kVarSteps = 4 };
 int sparse_variant(const Symbolic& s, int64_t ntasks, int32_t nrhs, int forced);
 
 hipError_t sparse_upload(const Symbolic& s, SparseDevice& d);
+// step schedule (steps.hip): built by sparse_upload when the system fits
+bool steps_fit(const Symbolic& s, int32_t nrhs);
+bool steps_ready(const SparseDevice& d);   // schedule built (it may not fit even when steps_fit holds)
+hipError_t steps_upload(const Symbolic& s, const std::vector<int32_t>& r_pos, SparseDevice& d);
+void steps_free(SparseDevice& d);
+// one launch; X (batch x n) combined in-kernel when per_jacobian, else Xk (batch x K x n) is written
+hipError_t steps_run(const SparseDevice& d, int32_t nnz, int32_t batch, const double* values, const EpsSet& es,
+                     const double* dvec, const double* B, double* X, double* Xk, int32_t* info, bool per_jacobian,
+                     hipStream_t st);
 void sparse_free(SparseDevice& d);
 bool sparse_fits_lds(const Symbolic& s, int32_t nrhs);
 size_t sparse_workspace_bytes(const Symbolic& s, int32_t batch, int32_t K, int32_t nrhs, int32_t keep, int forced = -1);

@@ -635,6 +635,7 @@ int variant_of(const Symbolic& s, int64_t ntasks, int32_t nrhs, int forced) {
     if (forced == kVarBatched) return pairs_ok(s) ? kVarBatched : -1;
     if (forced == kVarGrouped) return pairs_ok(s) ? kVarGrouped : -1;
     if (forced == kVarGlobal) return kVarGlobal;
+    if (forced == kVarSteps) return steps_fit(s, nrhs) ? kVarSteps : -1;
     if (ntasks >= 256 && pairs_ok(s)) return kVarBatched;
     if (sparse_fits_lds(s, nrhs)) return kVarLds;
     return kVarGlobal;
@@ -662,7 +663,7 @@ SpLayout sp_layout(const Symbolic& s, int32_t batch, int32_t K, int32_t nrhs, in
         L.total = L.off_xk;
         return L;
     }
-    const bool lds = var == kVarLds;
+    const bool lds = var == kVarLds || var == kVarSteps;
     int64_t off = lds ? 0 : align256(ntasks * fstride_of(s) * 8);
     L.off_y = off;
     if (!lds) off = align256(off + ntasks * (int64_t)s.n * nrhs * 8);
@@ -859,11 +860,14 @@ hipError_t sparse_upload(const Symbolic& s, SparseDevice& d) {
     ix.pair_ptr = ptr();
     ix.pairs = (const int2*)ptr();
     d.h_lpos_ptr = lpos_ptr;
+    e = steps_upload(s, r_pos, d);
+    if (e != hipSuccess) return e;
     d.ready = true;
     return hipSuccess;
 }
 
 void sparse_free(SparseDevice& d) {
+    steps_free(d);
     if (d.buf) (void)hipFree(d.buf);
     d.buf = nullptr;
     d.ready = false;
@@ -888,10 +892,27 @@ hipError_t sparse_solve_batched(const Symbolic& s, const SparseDevice& d, int32_
     SpArgs a = make_args(d, s, ntasks, es.K, nrhs);
     a.values = values; a.dvec = dvec; a.B = B; a.info = info;
     a.Xk = (double*)(w + L.off_xk);
-    const int var = variant_of(s, ntasks, nrhs, forced);
+    int var = variant_of(s, ntasks, nrhs, forced);
     if (var < 0) return hipErrorInvalidValue;
+    if (forced < 0 && var == kVarBatched && nrhs == 1 && steps_ready(d)) {
+        // the step schedule beats the per-level launches whenever it exists; its
+        // Xk (when not fused) fits in the interleaved layout reserved above
+        var = kVarSteps;
+        a.Xk = (double*)w;
+    }
     if (var == kVarBatched || var == kVarGrouped)
         return batched_run(s, d, batch, values, es, dvec, nrhs, B, X, info, w, L, st, var == kVarGrouped);
+    if (var == kVarSteps) {
+        if (!steps_ready(d)) return hipErrorInvalidValue;
+        int dev = 0, cus = 256;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        // enough Jacobians to give every CU one: one workgroup per Jacobian, combine fused
+        const bool per_jacobian = batch >= cus;
+        hipError_t e = steps_run(d, s.nnz, batch, values, es, dvec, B, X, a.Xk, info, per_jacobian, st);
+        if (e != hipSuccess || per_jacobian) return e;
+        return launch_combine((int64_t)s.n, batch, es, a.Xk, X, st);
+    }
     if (var == kVarLds) {
         const int lds = (int)lds_bytes(s, nrhs);
         hipError_t e = hipFuncSetAttribute((const void*)sparse_lds_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, lds);

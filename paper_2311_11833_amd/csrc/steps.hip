@@ -1,0 +1,422 @@
+// steps.hip -- dataflow-scheduled sparse LU and substitutions in LDS, one
+// workgroup per Jacobian, for gfx950.
+//
+// Every entry of the factors and of the RHS is an fma chain with a fixed
+// order (Sec. 2 / Alg. 1 steps 2-3 realised without pivoting):
+//   u_jj, u_jm, l_ij   updates l_ik u_kj over k in R_i ^ R_j ascending
+//                      (l_ij divided by u_jj at the end);
+//   forward  y_i       updates l_ik y_k, k ascending (column-oriented order);
+//   backward y_i       updates u_ij x_j, j descending, then x_i = y_i / u_ii.
+// The level schedule waits for whole etree levels and then runs each chain in
+// one go; its critical path is the sum over levels of the longest chain of
+// the level.  Here each update is placed at the earliest barrier step at which
+// both of its inputs are final and all earlier updates of the same chain have
+// run, so chains advance while their inputs are still being produced.  The
+// per-entry operations and their order are unchanged, so the results equal
+// the reference bit for bit; only the interleaving across entries differs.
+// Forward substitution shares the factor's timeline (y_i needs only the final
+// l_ik and y_k); backward substitution follows it.
+//
+// Host side: the schedule is built once per plan (a few hundred thousand
+// tasks at n ~ 1000).  A task is one run of consecutive chain updates of one
+// entry within one step, optionally ending with the division.  Thread t of the
+// workgroup runs task t of a step; a step with more tasks than threads is
+// split into consecutive sub-steps.  A step's descriptors are contiguous, one
+// coalesced 8-byte load per lane, issued several steps ahead: a step itself is
+// a few hundred cycles of LDS work, far less than one round trip to L2.
+//
+// Descriptor (int2), LDS indices < 2^15:
+//   x = dst | long << 15 | div << 16   (div = 0xFFFF: no division)
+//   y = short task: packed pair a | b << 16 (-1: no update)
+//       long task (two or more updates): offset in xp of [cnt, 0, 0, 0, pairs..]
+// An empty slot has x = -1.  Update of a pair: v[dst] = fma(-v[a], v[b], v[dst]).
+//
+// Device side: LDS holds [u_jj (n) | L values (nnzL) | U values (nnzL) |
+// y (n) | combine accumulator (n)] in doubles; one workgroup takes a Jacobian,
+// runs its K perturbed systems one after the other and accumulates
+// sum_k c_k x_k in the order of the reference combine (ascending k, fma chain
+// from 0).
+#include <algorithm>
+#include <climits>
+#include <queue>
+#include <vector>
+
+#include "dense.h"
+#include "sparse.h"
+
+namespace psp {
+
+namespace {
+constexpr int kStThreads = 1024;         // workgroup size; the schedule is built for it (one task per thread and step)
+constexpr int kStAhead = 8;              // steps whose descriptors are in flight
+constexpr int kStLdsLimit = 152 * 1024;  // bytes of LDS the kernel may use
+
+int64_t st_lds_doubles(const Symbolic& s) { return 3 * (int64_t)s.n + 2 * (int64_t)s.l_ptr[s.n]; }
+constexpr int64_t kStLdsMax = 160 * 1024 - 64;   // values + per-step metadata (+ the static pivot flag)
+// bytes: values (rounded to 16 B) then nsteps x int4 of metadata
+__host__ __device__ constexpr int st_padded(int S) { return (S + kStAhead - 1) / kStAhead * kStAhead; }
+int64_t st_lds_total(int64_t n, int64_t nl, int64_t S) {
+    return ((3 * n + 2 * nl + 1) & ~1LL) * 8 + 16 * ((int64_t)st_padded((int)S) + kStAhead + 1);
+}
+int64_t st_lds_total(const Symbolic& s, int64_t S) { return st_lds_total(s.n, s.l_ptr[s.n], S); }
+
+struct StTask {
+    int32_t step, dst, div, off, cnt;
+};
+
+// Builds the step schedule.  Returns false when the plan does not fit.
+bool build_schedule(const Symbolic& s, const std::vector<int32_t>& r_pos, int T, std::vector<int32_t>& meta,
+                    std::vector<int32_t>& desc, std::vector<uint32_t>& xp, int32_t& nsteps) {
+    const int n = s.n, nl = s.l_ptr[n];
+    if (st_lds_doubles(s) * 8 > kStLdsLimit || st_lds_doubles(s) >= 0x7FFF) return false;
+    const int ybase = n + 2 * nl;
+    auto LX = [&](int t) { return n + t; };
+    auto UX = [&](int t) { return n + nl + t; };
+    auto YX = [&](int i) { return ybase + i; };
+    auto pk = [](int a, int b) { return (uint32_t)a | ((uint32_t)b << 16); };
+
+    std::vector<int32_t> fin(ybase + n, 0);   // step after which an entry holds its final value (0: gathered)
+    std::vector<uint32_t> P;                  // all updates, grouped by task
+    std::vector<StTask> tasks;
+    std::vector<uint32_t> chain;
+
+    // Splits the chain of `dst` (in `chain`, in order) into steps; base: first step - 1.
+    auto place = [&](int dst, int div, int base) {
+        int seg_step = -1, seg_cnt = 0;
+        int64_t seg_off = 0;
+        for (uint32_t q : chain) {
+            const int a = (int)(q & 0xFFFF), b = (int)(q >> 16);
+            const int ready = std::max(std::max(fin[a], fin[b]), base) + 1;
+            const int stp = std::max(ready, seg_step);
+            if (stp != seg_step) {
+                if (seg_cnt) tasks.push_back({seg_step, dst, -1, (int32_t)seg_off, seg_cnt});
+                seg_step = stp;
+                seg_off = (int64_t)P.size();
+                seg_cnt = 0;
+            }
+            P.push_back(q);
+            ++seg_cnt;
+        }
+        if (seg_cnt) tasks.push_back({seg_step, dst, -1, (int32_t)seg_off, seg_cnt});
+        int last = seg_cnt ? seg_step : -1;
+        if (div >= 0) {
+            const int need = std::max(fin[div], base) + 1;
+            if (seg_cnt && seg_step >= need) {
+                tasks.back().div = div;
+            } else {
+                tasks.push_back({need, dst, div, 0, 0});
+                last = need;
+            }
+        }
+        if (last >= 0) fin[dst] = last;
+    };
+    // (l at pos(a,k), u at pos(b,k)) for k in R_a ^ R_b ascending
+    auto merge = [&](int a, int b) {
+        int p = s.lrow_ptr[a], pe = s.lrow_ptr[a + 1], q = s.lrow_ptr[b], qe = s.lrow_ptr[b + 1];
+        while (p < pe && q < qe) {
+            const int ka = s.lrow_idx[p], kb = s.lrow_idx[q];
+            if (ka == kb) {
+                chain.push_back(pk(LX(r_pos[p]), UX(r_pos[q])));
+                ++p;
+                ++q;
+            } else if (ka < kb) {
+                ++p;
+            } else {
+                ++q;
+            }
+        }
+    };
+    // factor, column by column (every input of column j lies in earlier columns)
+    for (int j = 0; j < n; ++j) {
+        chain.clear();
+        for (int p = s.lrow_ptr[j]; p < s.lrow_ptr[j + 1]; ++p) chain.push_back(pk(LX(r_pos[p]), UX(r_pos[p])));
+        place(j, -1, 0);
+        for (int t = s.l_ptr[j]; t < s.l_ptr[j + 1]; ++t) {
+            const int m = s.l_idx[t];
+            chain.clear();
+            merge(j, m);     // u_jm: l_jk u_km
+            place(UX(t), -1, 0);
+            chain.clear();
+            merge(m, j);     // l_mj: l_mk u_kj, then / u_jj
+            place(LX(t), j, 0);
+        }
+    }
+    // forward substitution on the same timeline
+    for (int i = 0; i < n; ++i) {
+        chain.clear();
+        for (int p = s.lrow_ptr[i]; p < s.lrow_ptr[i + 1]; ++p) chain.push_back(pk(LX(r_pos[p]), YX(s.lrow_idx[p])));
+        place(YX(i), -1, 0);
+    }
+    int s1 = 0;
+    for (const StTask& t : tasks) s1 = std::max(s1, t.step);
+    // backward substitution after it: row i of U has the pattern of column i of L
+    for (int i = n - 1; i >= 0; --i) {
+        chain.clear();
+        for (int t = s.l_ptr[i + 1] - 1; t >= s.l_ptr[i]; --t) chain.push_back(pk(UX(t), YX(s.l_idx[t])));
+        place(YX(i), i, s1);
+    }
+    int S = 0;
+    for (const StTask& t : tasks) S = std::max(S, t.step);
+
+    // Group by step; a step with more tasks than threads becomes consecutive
+    // sub-steps (its tasks are independent), longest tasks first so that
+    // the long ones share a sub-step.  Thread t runs task t of its sub-step.
+    std::vector<std::vector<int32_t>> by_step(S + 1);
+    for (int32_t i = 0; i < (int32_t)tasks.size(); ++i) by_step[tasks[i].step].push_back(i);
+    meta.clear();
+    desc.clear();
+    xp.clear();
+    auto cost = [&](const StTask& t) { return 6 + 2 * t.cnt + (t.div >= 0 ? 8 : 0); };
+    for (int st = 1; st <= S; ++st) {
+        std::vector<int32_t>& list = by_step[st];
+        std::stable_sort(list.begin(), list.end(),
+                         [&](int32_t a, int32_t b) { return cost(tasks[a]) > cost(tasks[b]); });
+        for (size_t c0 = 0; c0 < list.size(); c0 += (size_t)T) {
+            const int cnt = (int)std::min<size_t>((size_t)T, list.size() - c0);
+            const int tact = (cnt + 63) / 64 * 64;
+            const int64_t base = (int64_t)desc.size() / 2;
+            if (base + tact > INT_MAX / 2) return false;
+            meta.push_back((int32_t)base);
+            meta.push_back(tact);
+            meta.push_back(1);
+            meta.push_back(0);
+            desc.resize(desc.size() + 2 * (size_t)tact, -1);
+            for (int t = 0; t < cnt; ++t) {
+                const StTask& k = tasks[list[c0 + t]];
+                const size_t at = 2 * (size_t)(base + t);
+                const uint32_t x = (uint32_t)k.dst | (k.cnt >= 2 ? 0x8000u : 0u) |
+                                   ((uint32_t)(k.div >= 0 ? k.div : 0xFFFF) << 16);
+                int32_t y = -1;
+                if (k.cnt == 1) {
+                    y = (int32_t)P[k.off];
+                } else if (k.cnt >= 2) {
+                    y = (int32_t)xp.size();
+                    xp.push_back((uint32_t)k.cnt);
+                    xp.push_back(0);
+                    xp.push_back(0);
+                    xp.push_back(0);
+                    for (int c = 0; c < k.cnt; ++c) xp.push_back(P[k.off + c]);
+                    while (xp.size() % 4) xp.push_back(0);
+                }
+                desc[at] = (int32_t)x;
+                desc[at + 1] = y;
+            }
+        }
+    }
+    S = (int)(meta.size() / 4);
+    if (st_lds_total(s, S) > kStLdsMax) return false;
+    nsteps = S;
+    return true;
+}
+
+struct StArgs {
+    StepIdx sx;
+    SpIdx ix;
+    int32_t nnz, batch, K, per_jacobian;
+    const double* values;   // batch x nnz
+    const double* dvec;
+    const double* B;        // batch x n
+    double* X;              // batch x n        (per_jacobian)
+    double* Xk;             // batch x K x n    (otherwise)
+    int32_t* info;          // batch x K
+};
+
+__device__ __forceinline__ void st_exec(const StArgs& a, double* v, int2 d) {
+    if (d.x == -1) return;
+    const int dst = d.x & 0x7FFF;
+    const int div = (int)((uint32_t)d.x >> 16);
+    double acc = v[dst];
+    if (!(d.x & 0x8000)) {
+        if (d.y != -1) acc = fmad(-v[d.y & 0xFFFF], v[(uint32_t)d.y >> 16], acc);
+    } else {
+        const uint32_t* p = a.sx.xp + d.y;
+        const int cnt = (int)p[0];
+        const uint4* q = (const uint4*)(p + 4);
+        int c = 0;
+        for (; c + 8 <= cnt; c += 8) {
+            const uint4 w0 = q[c / 4], w1 = q[c / 4 + 1];
+            const uint32_t w[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+            double l[8], u[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) { l[e] = v[w[e] & 0xFFFF]; u[e] = v[w[e] >> 16]; }
+#pragma unroll
+            for (int e = 0; e < 8; ++e) acc = fmad(-l[e], u[e], acc);
+        }
+        for (; c < cnt; ++c) {
+            const uint32_t w = p[4 + c];
+            acc = fmad(-v[w & 0xFFFF], v[w >> 16], acc);
+        }
+    }
+    if (div != 0xFFFF) acc = acc / v[div];
+    v[dst] = acc;
+}
+
+// Descriptor of thread tid in a step, through a bounds-checked buffer load:
+// threads past the step's active count pass an out-of-range offset, which
+// returns zeros without a memory access.  (A plain load from a shared dummy
+// slot sends every idle lane of every CU to one cache line at once.)  The
+// instruction is issued by every thread, so the loads in flight stay static.
+__device__ __forceinline__ int2 st_desc(__amdgpu_buffer_rsrc_t r, int4 m, int tid) {
+    const int off = tid < m.y ? (m.x + tid) * 8 : -1;
+    const auto w = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+    int2 d;
+    __builtin_memcpy(&d, &w, sizeof(d));
+    return d;
+}
+
+template <int T>
+__global__ __launch_bounds__(T) void steps_kernel(StArgs a, EpsSet es) {
+    extern __shared__ double v[];
+    __shared__ int s_bad;
+    const SpIdx& ix = a.ix;
+    const int n = ix.n, nl = ix.nnzl, tid = threadIdx.x;
+    const int ybase = n + 2 * nl;
+    double* y = v + ybase;
+    double* cx = y + n;
+    const int S = a.sx.nsteps;
+    const int Sp = st_padded(S);
+    // per-step metadata, read by every step of every system: kept in LDS,
+    // followed by empty steps up to a multiple of the ring depth and one ring beyond
+    int4* sm = reinterpret_cast<int4*>(v + ((3 * n + 2 * nl + 1) & ~1));
+    for (int i = tid; i < Sp + kStAhead + 1; i += T) sm[i] = i < S ? a.sx.meta[i] : make_int4(0, 0, 1, 0);
+    __syncthreads();
+    // gfx9-family buffer resource: raw (stride 0), range = the descriptor array
+    const __amdgpu_buffer_rsrc_t drs =
+        __builtin_amdgcn_make_buffer_rsrc((void*)a.sx.desc, (short)0, a.sx.ndesc * 8, 0x00020000);
+    const int njobs = a.per_jacobian ? a.batch : a.batch * es.K;
+    for (int job = blockIdx.x; job < njobs; job += gridDim.x) {
+        const int s = a.per_jacobian ? job : job / es.K;
+        const int k0 = a.per_jacobian ? 0 : job % es.K, k1 = a.per_jacobian ? es.K : k0 + 1;
+        const double* vals = a.values + (int64_t)s * a.nnz;
+        for (int kk = k0; kk < k1; ++kk) {
+            // descriptor ring: step st runs while steps st+1 .. st+kStAhead-1 are in
+            // flight; each step waits for its own load only.
+            int2 ring[kStAhead];
+#pragma unroll
+            for (int d = 0; d < kStAhead; ++d) {
+                ring[d] = st_desc(drs, sm[d], tid);
+            }
+            int4 m = sm[0];
+            // A + eps_k D permuted onto the fill pattern, and P b
+            for (int t = tid; t < nl; t += T) {
+                const int sl = ix.src_l[t], su = ix.src_u[t];
+                v[n + t] = sl >= 0 ? vals[sl] : 0.0;
+                v[n + nl + t] = su >= 0 ? vals[su] : 0.0;
+            }
+            const double ek = eps_at(es, kk);
+            for (int j = tid; j < n; j += T) {
+                const int sd = ix.src_d[j], pj = ix.perm[j];
+                const double ajj = sd >= 0 ? vals[sd] : 0.0;
+                v[j] = __dadd_rn(ajj, __dmul_rn(ek, a.dvec ? a.dvec[pj] : 1.0));
+                y[j] = a.B[(int64_t)s * n + pj];
+            }
+            if (tid == 0) s_bad = INT_MAX;
+            __syncthreads();
+            // No guard inside the rotation (the padded steps have no tasks): a
+            // conditional here makes the compiler copy in-flight registers,
+            // which waits for the loads.  Each slot is reloaded after its task
+            // ran, so old and new descriptors share registers.
+            for (int st0 = 0; st0 < Sp; st0 += kStAhead) {
+#pragma unroll
+                for (int d = 0; d < kStAhead; ++d) {
+                    const int st = st0 + d;
+                    const int4 m1 = sm[st + 1];
+                    const int4 ma = sm[st + kStAhead];
+                    if (tid < m.y) st_exec(a, v, ring[d]);
+                    ring[d] = st_desc(drs, ma, tid);
+                    __syncthreads();
+                    m = m1;
+                }
+            }
+            // first zero or non-finite pivot in elimination order (the values before it are exact)
+            for (int j = tid; j < n; j += T)
+                if (bad_pivot(v[j])) atomicMin(&s_bad, j + 1);
+            __syncthreads();
+            const int bad = s_bad == INT_MAX ? 0 : s_bad;
+            if (a.per_jacobian) {
+                const double c = c_at(es, kk);
+                for (int q = tid; q < n; q += T) {
+                    const double xq = bad ? __builtin_nan("") : y[q];
+                    cx[q] = fmad(c, xq, kk == 0 ? 0.0 : cx[q]);
+                }
+            } else {
+                double* xk = a.Xk + ((int64_t)s * es.K + kk) * n;
+                for (int q = tid; q < n; q += T) xk[ix.perm[q]] = bad ? __builtin_nan("") : y[q];
+            }
+            if (tid == 0) a.info[s * es.K + kk] = bad;
+            __syncthreads();
+        }
+        if (a.per_jacobian)
+            for (int q = tid; q < n; q += T) a.X[(int64_t)s * n + ix.perm[q]] = cx[q];
+    }
+}
+
+}  // namespace
+
+bool steps_fit(const Symbolic& s, int32_t nrhs) {
+    return nrhs == 1 && st_lds_doubles(s) * 8 <= kStLdsLimit && st_lds_doubles(s) < 0x7FFF;
+}
+
+bool steps_ready(const SparseDevice& d) { return d.st_buf != nullptr; }
+
+hipError_t steps_upload(const Symbolic& s, const std::vector<int32_t>& r_pos, SparseDevice& d) {
+    if (d.st_buf || !steps_fit(s, 1)) return hipSuccess;
+    std::vector<int32_t> meta, desc;
+    std::vector<uint32_t> xp;
+    int32_t S = 0;
+    if (!build_schedule(s, r_pos, kStThreads, meta, desc, xp, S) || S < 1) return hipSuccess;
+    auto up16 = [](size_t words) { return (words + 63) / 64 * 64; };
+    const size_t o_meta = 0, o_desc = up16(meta.size()), o_xp = o_desc + up16(desc.size());
+    const size_t total = o_xp + up16(std::max<size_t>(xp.size(), 4));
+    // Rounded up to whole 2 MiB fragments: the kernel streams this array once
+    // per system from every CU, and small-page mappings make each new page a
+    // translation miss.
+    const size_t frag = (size_t)2 << 20;
+    const size_t bytes = (sizeof(int32_t) * total + frag - 1) / frag * frag;
+    hipError_t e = hipMalloc(&d.st_buf, std::max(bytes, (size_t)4 * frag));
+    if (e != hipSuccess) { d.st_buf = nullptr; return e; }
+    std::vector<int32_t> host(total, 0);
+    std::copy(meta.begin(), meta.end(), host.begin() + o_meta);
+    std::copy(desc.begin(), desc.end(), host.begin() + o_desc);
+    std::copy(xp.begin(), xp.end(), host.begin() + o_xp);
+    e = hipMemcpy(d.st_buf, host.data(), sizeof(int32_t) * total, hipMemcpyHostToDevice);
+    if (e != hipSuccess) { (void)hipFree(d.st_buf); d.st_buf = nullptr; return e; }
+    d.st.nsteps = S;
+    d.st.threads = kStThreads;
+    d.st.ndesc = (int32_t)(desc.size() / 2);
+    d.st.meta = (const int4*)(d.st_buf + o_meta);
+    d.st.desc = (const int2*)(d.st_buf + o_desc);
+    d.st.xp = (const uint32_t*)(d.st_buf + o_xp);
+    return hipSuccess;
+}
+
+void steps_free(SparseDevice& d) {
+    if (d.st_buf) (void)hipFree(d.st_buf);
+    d.st_buf = nullptr;
+    d.st = StepIdx{};
+}
+
+hipError_t steps_run(const SparseDevice& d, int32_t nnz, int32_t batch, const double* values, const EpsSet& es,
+                     const double* dvec, const double* B, double* X, double* Xk, int32_t* info, bool per_jacobian,
+                     hipStream_t st) {
+    if (!d.st_buf || d.st.threads != kStThreads) return hipErrorInvalidValue;
+    StArgs a{};
+    a.sx = d.st;
+    a.ix = d.idx;
+    a.nnz = nnz; a.batch = batch; a.K = es.K; a.per_jacobian = per_jacobian ? 1 : 0;
+    a.values = values; a.dvec = dvec; a.B = B; a.X = X; a.Xk = Xk; a.info = info;
+    const int lds = (int)st_lds_total(d.idx.n, d.idx.nnzl, d.st.nsteps);
+    hipError_t e = hipFuncSetAttribute((const void*)steps_kernel<kStThreads>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    int dev = 0, cus = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int resident = cus * std::max(1, (160 * 1024) / std::max(lds, 1));
+    const int64_t jobs = per_jacobian ? batch : (int64_t)batch * es.K;
+    const int grid = (int)std::min<int64_t>(jobs, resident);
+    hipLaunchKernelGGL(steps_kernel<kStThreads>, dim3(grid), dim3(kStThreads), lds, st, a, es);
+    return hipGetLastError();
+}
+
+}  // namespace psp

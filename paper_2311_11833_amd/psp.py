@@ -18,7 +18,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpsp.so")
 
 PSP_OK, PSP_E_INVALID, PSP_E_EPS, PSP_E_NOMEM, PSP_E_HIP, PSP_E_STATE, PSP_E_UNSUPPORTED = range(7)
-PATHS = {"auto": 0, "dense": 1, "sparse": 2, "sparse_batched": 3, "sparse_lds": 4, "sparse_levels": 5, "sparse_grouped": 6}
+PATHS = {"auto": 0, "dense": 1, "sparse": 2, "sparse_batched": 3, "sparse_lds": 4, "sparse_levels": 5, "sparse_grouped": 6,
+         "sparse_steps": 7}
 PATH_NAMES = {v: k for k, v in PATHS.items()}
 ORDERS = {"md": 0, "natural": 1}
 EXPORTED = ["psp_last_error", "psp_version", "psp_plan_create", "psp_plan_info", "psp_plan_export",
@@ -208,10 +209,10 @@ def tune(plan: Plan, values, eps, b, d=None, stream=None):
     need = plan.workspace_bytes("auto", batch, K, nrhs, keep=False)
     ws = plan.workspace(need, values.device)
     chosen = C.c_int32(-1)
-    ms = (C.c_float * 7)()
+    ms = (C.c_float * len(PATHS))()
     _check(lib().psp_tune(plan.handle, batch, _dptr(values), K, _np_ptr(eps_h), _dptr(d), nrhs, _dptr(b.contiguous()),
                           _dptr(x), _dptr(info), _dptr(ws), ws.numel(), _stream(stream), C.byref(chosen), ms))
-    times = {PATH_NAMES[i]: float(ms[i]) for i in range(1, 7) if ms[i] >= 0}
+    times = {PATH_NAMES[i]: float(ms[i]) for i in range(1, len(PATHS)) if ms[i] >= 0}
     return PATH_NAMES[chosen.value], times
 
 

@@ -123,11 +123,12 @@ def test_large_sparse_sampled(psp, O, W, dev):
     assert np.all(np.isfinite(Xk.cpu().numpy()))
 
 
-@pytest.mark.parametrize("variant", ["sparse_batched", "sparse_grouped", "sparse_lds", "sparse_levels"])
+@pytest.mark.parametrize("variant", ["sparse_batched", "sparse_grouped", "sparse_lds", "sparse_levels", "sparse_steps"])
 def test_sparse_variants_match_oracle(psp, O, W, dev, variant):
-    """The three executions of the sparse path (systems interleaved across lanes, one
-    workgroup per system in LDS, per-level kernels over task-major factors) on the same
-    64-Jacobian batch: each equal to the oracle bitwise."""
+    """The executions of the sparse path (systems interleaved across lanes per level or
+    per group, one workgroup per system in LDS by levels or by dataflow steps, per-level
+    kernels over task-major factors) on the same 64-Jacobian batch: each equal to the
+    oracle bitwise."""
     ip, ix, vals, bs = W.scenario_batch(118, 64)
     n = len(ip) - 1
     eps = W.config_eps("n601")
@@ -148,7 +149,7 @@ def test_tuner_picks_a_path_and_auto_uses_it(psp, O, W, dev):
     v, b = torch.from_numpy(vals).to(dev), torch.from_numpy(bs).to(dev)
     chosen, times = psp.tune(plan, v, eps, b)
     assert chosen in times and times[chosen] == min(times.values())
-    assert set(times) >= {"dense", "sparse_batched", "sparse_grouped", "sparse_lds", "sparse_levels"}
+    assert set(times) >= {"dense", "sparse_batched", "sparse_grouped", "sparse_lds", "sparse_levels", "sparse_steps"}
     x, info = psp.solve_batched(plan, v, eps, b, path="auto")
     torch.cuda.synchronize()
     sym = O.symbolic(n, ip, ix)
@@ -156,8 +157,9 @@ def test_tuner_picks_a_path_and_auto_uses_it(psp, O, W, dev):
     _cmp(x.cpu().numpy(), xo)
 
 
-def test_sparse_full_size_batched_sampled(psp, O, W, dev):
-    """n=601, 512 Jacobians x K=5 in the benchmark's launch configuration: every
+@pytest.mark.parametrize("path", ["sparse", "sparse_steps"])
+def test_sparse_full_size_batched_sampled(psp, O, W, dev, path):
+    """n=601, 512 Jacobians x K=5 in the benchmark's launch configurations: every
     system info == 0, all finite, sampled Jacobians equal to the oracle bitwise,
     and a broken-down Jacobian among them reported alone."""
     ip, ix, vals, bs = W.scenario_batch(300, 512)
@@ -166,7 +168,8 @@ def test_sparse_full_size_batched_sampled(psp, O, W, dev):
     n = len(ip) - 1
     eps = W.config_eps("n601")
     plan = psp.Plan(ip, ix)
-    x, info = psp.solve_batched(plan, torch.from_numpy(vals).to(dev), eps, torch.from_numpy(bs).to(dev), path="sparse")
+    print(f"[gpu sparse] full size path={path}", flush=True)
+    x, info = psp.solve_batched(plan, torch.from_numpy(vals).to(dev), eps, torch.from_numpy(bs).to(dev), path=path)
     torch.cuda.synchronize()
     xg, ig = x.cpu().numpy(), info.cpu().numpy()
     bad = np.zeros(512, bool)
@@ -179,3 +182,44 @@ def test_sparse_full_size_batched_sampled(psp, O, W, dev):
         assert np.array_equal(ig[s:s + 1], io)
         if s != 300:
             _cmp(xg[s:s + 1], xo)
+
+
+@pytest.mark.parametrize("N,count", [(14, 3), (30, 300), (118, 260)])
+def test_steps_path_modes_and_breakdown(psp, O, W, dev, N, count):
+    """Dataflow-step execution in both launch modes (one workgroup per perturbed system
+    plus a combine launch when the batch is smaller than the CU count, one workgroup per
+    Jacobian with the combine fused otherwise), with one Jacobian broken by an infinite
+    entry: info and solutions equal to the oracle, the broken Jacobian NaN."""
+    ip, ix, vals, bs = W.scenario_batch(N, count)
+    vals = vals.copy()
+    vals[1, 2] = np.inf
+    n = len(ip) - 1
+    eps = W.config_eps("small" if N == 14 else "n601")
+    print(f"[gpu sparse] steps N={N} count={count}", flush=True)
+    plan = psp.Plan(ip, ix)
+    x, info = psp.solve_batched(plan, torch.from_numpy(vals).to(dev), eps, torch.from_numpy(bs).to(dev),
+                                path="sparse_steps")
+    torch.cuda.synchronize()
+    sym = O.symbolic(n, ip, ix)
+    xo, io, _, _ = O.sparse_batch(n, ip, ix, vals, sym, eps, bs)
+    ig, xg = info.cpu().numpy(), x.cpu().numpy()
+    assert np.array_equal(ig, io) and np.all(ig[1] > 0)
+    assert np.all(np.isnan(xg[1]))
+    keep = np.ones(count, bool)
+    keep[1] = False
+    _cmp(xg[keep], xo[keep])
+
+
+def test_steps_path_rejects_what_it_cannot_run(psp, W, dev):
+    """nrhs > 1, and a fill too large for LDS, are refused with PSP_E_UNSUPPORTED."""
+    ip, ix, vals, bs = W.scenario_batch(30, 2)
+    n = len(ip) - 1
+    plan = psp.Plan(ip, ix)
+    b2 = torch.zeros((2, n, 2), dtype=torch.float64, device=dev)
+    with pytest.raises(psp.PSPError, match="UNSUPPORTED|cannot run"):
+        psp.solve_batched(plan, torch.from_numpy(vals).to(dev), W.config_eps("n601"), b2, path="sparse_steps")
+    ip, ix, vals, bs = W.scenario_batch(500, 1)
+    plan = psp.Plan(ip, ix)
+    with pytest.raises(psp.PSPError, match="UNSUPPORTED|cannot run"):
+        psp.solve_batched(plan, torch.from_numpy(vals).to(dev), W.config_eps("n601"),
+                          torch.from_numpy(bs).to(dev), path="sparse_steps")
