@@ -266,7 +266,9 @@ __device__ __forceinline__ int2 st_desc(__amdgpu_buffer_rsrc_t r, int4 m, int ti
 
 template <int T>
 __global__ __launch_bounds__(T) void steps_kernel(StArgs a, EpsSet es) {
-    extern __shared__ double v[];
+    // 16-byte aligned: the step metadata after the values is read as int4
+    // (a misaligned ds_read_b128 every step costs several times the step)
+    extern __shared__ __align__(16) double v[];
     __shared__ int s_bad;
     const SpIdx& ix = a.ix;
     const int n = ix.n, nl = ix.nnzl, tid = threadIdx.x;
