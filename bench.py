@@ -47,6 +47,77 @@ def sparse_flops(info, n, nrhs=1):
     return info.flops_sparse_factor + nrhs * (4 * info.nnz_l + n)
 
 
+def _events(torch, fn, reps):
+    st = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        out = fn()
+    e1.record(st)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps, out
+
+
+def extra_configs(psp, W, torch, dev):
+    """The adjoint with 64 right-hand sides at n=601, and the 20,001-unknown system
+    with 32 right-hand sides (forward and adjoint), timed with HIP events."""
+    from paper_2311_11833_amd.autograd import perturbed_solve
+    out = {}
+    # 64 Jacobians of the 300-bus network, K=5, 64 RHS: forward and backward of the autograd op
+    J, R = 64, 64
+    ip, ix, vals, _ = W.scenario_batch(300, J)
+    n = len(ip) - 1
+    eps = W.config_eps("n601")
+    plan = psp.Plan(ip, ix)
+    rng = np.random.default_rng(4)
+    v = torch.from_numpy(vals).to(dev).requires_grad_(True)
+    B = torch.from_numpy(rng.standard_normal((J, n, R))).to(dev).requires_grad_(True)
+    G = torch.from_numpy(rng.standard_normal((J, n, R))).to(dev)
+
+    def fwd():
+        return perturbed_solve(v, B, plan, eps, path="sparse")
+
+    def fwd_bwd():
+        x = perturbed_solve(v, B, plan, eps, path="sparse")
+        return torch.autograd.grad(x, (v, B), G)
+
+    fwd_bwd()
+    torch.cuda.synchronize()
+    f_ms, _ = _events(torch, fwd, 3)
+    fb_ms, _ = _events(torch, fwd_bwd, 3)
+    out["n601_adjoint_64rhs"] = {"jacobians": J, "K": len(eps), "nrhs": R, "path": "sparse (split steps)",
+                                 "forward_ms": f_ms, "backward_ms": fb_ms - f_ms,
+                                 "forward_rhs_solves_per_s": J * len(eps) * R / (f_ms / 1e3)}
+    print(f"[bench] n601 adjoint 64 rhs: fwd {f_ms:.3f} ms, bwd {fb_ms - f_ms:.3f} ms", file=sys.stderr, flush=True)
+    # 10,000-bus network, n = 20,001, K = 4, 32 RHS
+    from paper_2311_11833_amd.workloads import make_network, make_state, jacobian, seed_state
+    net = make_network(10000)
+    vm, va, p = make_state(10000, seed_state(10000, 0))
+    Jc = jacobian(net, vm, va, p)
+    eps4 = W.large_eps()
+    plan4 = psp.Plan(Jc.indptr, Jc.indices)
+    v4 = torch.from_numpy(Jc.data[None]).to(dev)
+    B4 = torch.from_numpy(rng.standard_normal((1, Jc.n, 32))).to(dev)
+    F = psp.Factors(plan4, v4, eps4, path="sparse", nrhs_cap=32)
+    torch.cuda.synchronize()
+    fac_ms, F = _events(torch, lambda: psp.Factors(plan4, v4, eps4, path="sparse", nrhs_cap=32), 2)
+    sol_ms, Xk = _events(torch, lambda: F.solve(B4), 3)
+    tr_ms, Lk = _events(torch, lambda: F.solve(B4, transpose=True), 3)
+    gr_ms, _ = _events(torch, lambda: F.grad_values(Lk, Xk), 3)
+    X = F.combine(Xk)
+    rn, bn = psp.residual(plan4, v4, B4, X, keep_r=True)[:2]
+    info = plan4.info()
+    out["n20001_32rhs"] = {"n": Jc.n, "nnz": int(info.nnz), "nnz_l": int(info.nnz_l), "K": len(eps4), "nrhs": 32,
+                           "eps": [float(e) for e in eps4], "factor_ms": fac_ms, "solve_ms": sol_ms,
+                           "transposed_solve_ms": tr_ms, "grad_values_ms": gr_ms,
+                           "factor_tflops": len(eps4) * info.flops_sparse_factor / (fac_ms / 1e3) / 1e12,
+                           "residual_rel_max": float((rn / bn).max())}
+    print(f"[bench] n20001: factor {fac_ms:.2f} ms, solve {sol_ms:.2f} ms, trans {tr_ms:.2f} ms, grad {gr_ms:.2f} ms",
+          file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -59,6 +130,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-system-per-launch timing")
     ap.add_argument("--no-graph", action="store_true", help="skip the HIP-graph replay timing")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the 64-RHS adjoint and the 20,001-unknown timings")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only (this build has no multi-GPU path); run with --gpus 1", file=sys.stderr)
@@ -161,6 +234,10 @@ def main():
     xs = [rr["x"] for rr in results.values()]
     paths["all_paths_bitwise_equal"] = bool(all(torch.equal(xs[0], x) for x in xs[1:]))
 
+    # error test (Alg. 1 step 5) on the device for every Jacobian of the batch
+    rn, bn = psp.residual(plan, vals_d, b_d, r["x"])
+    rel_res = (rn / bn).cpu().numpy()
+
     info_np = r["info"].cpu().numpy()
     x_np = r["x"].cpu().numpy()
     from oracle import oracle as O
@@ -188,6 +265,8 @@ def main():
         pms = (time.perf_counter() - w0) * 1e3
         plain = {"solves_per_s": J * K / (pms / 1e3), "systems": J * K, "ms": pms, "path": chosen,
                  "batched_speedup": value / (J * K / (pms / 1e3))}
+
+    extra = None if args.no_extra else extra_configs(psp, W, torch, dev)
 
     cpu = None
     if not args.no_cpu:
@@ -227,6 +306,11 @@ def main():
         "rel_err_vs_pivoted": {"max": max(errs), "median": float(np.median(errs)), "sample": 4,
                                "residual_max": max(resid)},
         "info_nonzero": int(np.count_nonzero(info_np)),
+        "residual_rel_all": {"max": float(rel_res.max()), "median": float(np.median(rel_res)),
+                             "jacobians": int(rel_res.size), "above_1e-9": int(np.sum(rel_res > 1e-9)),
+                             "above_1e-6": int(np.sum(rel_res > 1e-6)), "kernel": "residual_kernel (device)",
+                             "note": "scenarios with eps_0 * rho(A^-1 D) > 1 lie outside the series' convergence"},
+        "extra": extra,
     }
     print(json.dumps(out))
 

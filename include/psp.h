@@ -225,6 +225,23 @@ PSP_API psp_status psp_grad_values(psp_factors f, int32_t nrhs, const double* La
 
 PSP_API psp_status psp_factors_release(psp_factors f);
 
+/* ------------------------------------------------------------------------
+ * Error test (Alg. 1 step 5, optional): for every Jacobian s and RHS column r,
+ *   R[s][:, r] = B[s][:, r] - A_s X[s][:, r]
+ *   rnorm[s*nrhs + r] = ||R[s][:, r]||_2,  bnorm[s*nrhs + r] = ||B[s][:, r]||_2
+ * (the residual norm of the paper's Fig. 1; divide for the relative one).
+ * Each R entry is b_i followed by fma(-a_ie, x_j, .) over row i in the
+ * plan's CSR order; each norm is sqrt of the fma sum of squares in ascending
+ * row order.  values device batch x nnz (CSR order); B, X device batch x n x
+ * nrhs (row-major); R device batch x n x nrhs, or NULL when not wanted
+ * (required for n > 16384); rnorm device batch x nrhs; bnorm device batch x
+ * nrhs or NULL.  Asynchronous on `stream`.  PSP_E_INVALID for NULL required
+ * pointers or batch/nrhs < 1, PSP_E_UNSUPPORTED for R = NULL with n > 16384.
+ * ---------------------------------------------------------------------- */
+PSP_API psp_status psp_residual(psp_plan plan, int32_t batch, const double* values, int32_t nrhs,
+                                const double* B, const double* X, double* R, double* rnorm, double* bnorm,
+                                void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -56,6 +56,8 @@ def lib():
             getattr(L, f).restype = None
         L.oracle_combine.argtypes = [C.c_int, C.c_int64, _dp, _dp, _dp]
         L.oracle_combine.restype = None
+        L.oracle_residual.argtypes = [C.c_int, _ip, _ip, _dp, C.c_int, _dp, _dp, C.c_void_p, _dp, C.c_void_p]
+        L.oracle_residual.restype = None
         L.oracle_lu_partial.argtypes = [C.c_int, _dp, C.c_int, _ip]
         L.oracle_lu_partial_solve.argtypes = [C.c_int, _dp, C.c_int, _ip, _dp]
         L.oracle_lu_partial_solve.restype = None
@@ -141,6 +143,19 @@ def combine(c, xk: np.ndarray) -> np.ndarray:
     flat = out.reshape(-1)
     lib().oracle_combine(K, flat.size, c, xk.reshape(K, -1), flat)
     return flat.reshape(xk.shape[1:])
+
+
+def residual(n, indptr, indices, values, b, x):
+    """Alg. 1 step 5: r = b - A x (A in CSR), ||r||_2 and ||b||_2 per RHS column.
+    b, x: (n,) or (n, nrhs).  Returns (r, rnorm, bnorm) with norms of shape (nrhs,)."""
+    b = _f64(b)
+    x = _f64(x)
+    nrhs = 1 if b.ndim == 1 else b.shape[1]
+    r = np.zeros_like(b)
+    rn = np.zeros(nrhs)
+    bn = np.zeros(nrhs)
+    lib().oracle_residual(n, _i32(indptr), _i32(indices), _f64(values), nrhs, b, x, _ptr(r), rn, _ptr(bn))
+    return r, rn, bn
 
 
 def pivoted_solve(A: np.ndarray, b: np.ndarray) -> np.ndarray:

@@ -27,6 +27,8 @@
  *   sparse LU    the same factorisation restricted to the symbolic fill
  *                (the sparse batched factorisation of Sec. IV / V).
  *   gradient     adjoint of x = sum_k c_k (A + eps_k D)^{-1} b.
+ *   residual     Alg. 1 step 5 (optional error test): r = b - A x and the
+ *                2-norms of r and b (the residual norm of Fig. 1).
  */
 #include <math.h>
 #include <stdint.h>
@@ -136,6 +138,29 @@ EXPORT void oracle_combine(int K, int64_t len, const double* c, const double* xk
         double acc = 0.0;
         for (int k = 0; k < K; ++k) acc = fma(c[k], xk[(size_t)k * len + i], acc);
         x[i] = acc;
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Error test (Alg. 1 step 5): r = b - A x for CSR A, each r_i taken as   */
+/* b_i followed by fma(-a_ie, x_j, .) over row i in CSR order; ||r||_2 and */
+/* ||b||_2 as sqrt of the sum of squares accumulated by fma in ascending   */
+/* row order.  b, x, r are n x nrhs row-major; rnorm, bnorm are nrhs long; */
+/* r and bnorm may be NULL.                                                */
+/* ------------------------------------------------------------------ */
+EXPORT void oracle_residual(int n, const int* rowptr, const int* colidx, const double* val, int nrhs,
+                            const double* b, const double* x, double* r, double* rnorm, double* bnorm) {
+    for (int q = 0; q < nrhs; ++q) {
+        double sr = 0.0, sb = 0.0;
+        for (int i = 0; i < n; ++i) {
+            double acc = b[(size_t)i * nrhs + q];
+            for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) acc = fma(-val[e], x[(size_t)colidx[e] * nrhs + q], acc);
+            if (r) r[(size_t)i * nrhs + q] = acc;
+            sr = fma(acc, acc, sr);
+            sb = fma(b[(size_t)i * nrhs + q], b[(size_t)i * nrhs + q], sb);
+        }
+        rnorm[q] = sqrt(sr);
+        if (bnorm) bnorm[q] = sqrt(sb);
     }
 }
 

@@ -70,6 +70,7 @@ struct psp_plan_s {
     int32_t* d_perm = nullptr;
     int32_t* d_rows = nullptr;    // original row of each CSR entry
     int32_t* d_cols = nullptr;
+    int32_t* d_rowptr = nullptr;  // user CSR row pointers
     SparseDevice sp;              // sparse-path arrays
     std::map<std::tuple<int32_t, int32_t, int32_t>, int32_t> tuned;   // (batch, K, nrhs) -> path id
     ~psp_plan_s() {
@@ -81,6 +82,7 @@ struct psp_plan_s {
             (void)hipFree(d_perm);
             (void)hipFree(d_rows);
             (void)hipFree(d_cols);
+            (void)hipFree(d_rowptr);
             sparse_free(sp);
             (void)hipSetDevice(cur);
         }
@@ -152,6 +154,9 @@ psp_status upload_plan(psp_plan p, int32_t ld) {
         HIP_TRY(hipMemcpy(p->d_perm, s.perm.data(), sizeof(int32_t) * s.n, hipMemcpyHostToDevice), "hipMemcpy(plan)");
         HIP_TRY(hipMemcpy(p->d_rows, rows.data(), sizeof(int32_t) * s.nnz, hipMemcpyHostToDevice), "hipMemcpy(plan)");
         HIP_TRY(hipMemcpy(p->d_cols, s.col_idx.data(), sizeof(int32_t) * s.nnz, hipMemcpyHostToDevice), "hipMemcpy(plan)");
+        HIP_TRY(hipMalloc(&p->d_rowptr, sizeof(int32_t) * (s.n + 1)), "hipMalloc(plan)");
+        HIP_TRY(hipMemcpy(p->d_rowptr, s.row_ptr.data(), sizeof(int32_t) * (s.n + 1), hipMemcpyHostToDevice),
+                "hipMemcpy(plan)");
         p->device = dev;
     }
     if (ld > 0 && p->d_dst_ld != ld) {
@@ -483,6 +488,24 @@ psp_status psp_grad_values(psp_factors f, int32_t nrhs, const double* Lamk, cons
     HIP_TRY(launch_grad_values(s.n, s.nnz, f->batch, nrhs, f->es, f->plan->d_rows, f->plan->d_cols, Lamk, Xk, gA,
                                (hipStream_t)stream),
             "gradient launch");
+    return PSP_OK;
+}
+
+psp_status psp_residual(psp_plan p, int32_t batch, const double* values, int32_t nrhs, const double* B,
+                        const double* X, double* R, double* rnorm, double* bnorm, void* stream) {
+    if (!p || batch < 1 || nrhs < 1 || !values || !B || !X || !rnorm)
+        return fail(PSP_E_INVALID, "psp_residual: NULL argument, batch < 1 or nrhs < 1");
+    if ((int64_t)batch * nrhs > INT32_MAX) return fail(PSP_E_INVALID, "psp_residual: batch * nrhs too large");
+    if (!R && p->sym.n > kResLds)
+        return fail(PSP_E_UNSUPPORTED, "psp_residual: n > " + std::to_string(kResLds) + " needs the R output");
+    if (psp_status st = check_prior_hip()) return st;
+    if (psp_status r = upload_plan(p, 0)) return r;
+    const Symbolic& s = p->sym;
+    ResArgs a{};
+    a.n = s.n; a.nnz = s.nnz; a.batch = batch; a.nrhs = nrhs;
+    a.rowptr = p->d_rowptr; a.cols = p->d_cols; a.values = values; a.B = B; a.X = X;
+    a.R = R; a.rnorm = rnorm; a.bnorm = bnorm;
+    HIP_TRY(launch_residual(a, (hipStream_t)stream), "residual launch");
     return PSP_OK;
 }
 

@@ -38,6 +38,21 @@ int dense_panel();
 hipError_t launch_dense_factor_solve(const DenseArgs& a, const EpsSet& es, int grid, hipStream_t st);
 hipError_t launch_dense_solve(const DenseSolveArgs& a, int grid, hipStream_t st);
 hipError_t launch_combine(int64_t len, int32_t batch, const EpsSet& es, const double* Xk, double* X, hipStream_t st);
+
+// error test (residual.hip)
+constexpr int32_t kResLds = 16384;   // rows whose residual is staged in LDS; beyond, R is required
+struct ResArgs {
+    int32_t n, nnz, batch, nrhs, stage;
+    const int32_t* rowptr;   // n+1, user CSR
+    const int32_t* cols;     // nnz
+    const double* values;    // batch x nnz
+    const double* B;         // batch x n x nrhs
+    const double* X;         // batch x n x nrhs
+    double* R;               // batch x n x nrhs or NULL
+    double* rnorm;           // batch x nrhs
+    double* bnorm;           // batch x nrhs or NULL
+};
+hipError_t launch_residual(ResArgs a, hipStream_t st);
 hipError_t launch_grad_values(int32_t n, int32_t nnz, int32_t batch, int32_t nrhs, const EpsSet& es,
                               const int32_t* rows, const int32_t* cols, const double* Lamk, const double* Xk,
                               double* gA, hipStream_t st);

@@ -24,7 +24,7 @@ PATH_NAMES = {v: k for k, v in PATHS.items()}
 ORDERS = {"md": 0, "natural": 1}
 EXPORTED = ["psp_last_error", "psp_version", "psp_plan_create", "psp_plan_info", "psp_plan_export",
             "psp_plan_destroy", "psp_weights", "psp_workspace_bytes", "psp_solve_batched", "psp_tune", "psp_factor",
-            "psp_solve", "psp_combine", "psp_grad_values", "psp_factors_release"]
+            "psp_solve", "psp_combine", "psp_grad_values", "psp_factors_release", "psp_residual"]
 
 
 class PSPError(RuntimeError):
@@ -65,6 +65,7 @@ def lib():
         L.psp_combine.argtypes = [vp, i32, vp, vp, vp]
         L.psp_grad_values.argtypes = [vp, i32, vp, vp, vp, vp]
         L.psp_factors_release.argtypes = [vp]
+        L.psp_residual.argtypes = [vp, i32, vp, i32, vp, vp, vp, vp, vp, vp]
         for f in EXPORTED:
             if f not in ("psp_last_error", "psp_version", "psp_plan_destroy", "psp_workspace_bytes"):
                 getattr(L, f).restype = C.c_int
@@ -194,6 +195,27 @@ def solve_batched(plan: Plan, values, eps, b, path: str = "auto", d=None, worksp
                                    nrhs, _dptr(b.contiguous()), _dptr(x), _dptr(info), _dptr(ws), ws.numel(),
                                    _stream(stream)))
     return x, info
+
+
+def residual(plan: Plan, values, b, x, keep_r: bool = False, stream=None):
+    """Alg. 1 step 5 (optional error test): r = b - A x per Jacobian and RHS column.
+
+    values: (batch, nnz); b, x: (batch, n) or (batch, n, nrhs), float64 device tensors.
+    Returns (rnorm, bnorm), each (batch, nrhs) = ||r||_2 and ||b||_2, plus r (shaped like
+    b) when keep_r."""
+    import torch
+    batch = values.shape[0]
+    nrhs = 1 if b.dim() == 2 else b.shape[2]
+    if values.dtype != torch.float64 or b.dtype != torch.float64 or x.dtype != torch.float64:
+        raise TypeError("values, b and x must be float64")
+    if values.shape[1] != plan.nnz or b.shape != x.shape or b.shape[0] != batch or b.shape[1] != plan.n:
+        raise ValueError("shape mismatch with the plan")
+    rn = torch.empty((batch, nrhs), dtype=torch.float64, device=values.device)
+    bn = torch.empty_like(rn)
+    r = torch.empty_like(b) if keep_r else None
+    _check(lib().psp_residual(plan.handle, batch, _dptr(values), nrhs, _dptr(b.contiguous()), _dptr(x.contiguous()),
+                              _dptr(r), _dptr(rn), _dptr(bn), _stream(stream)))
+    return (rn, bn, r) if keep_r else (rn, bn)
 
 
 def tune(plan: Plan, values, eps, b, d=None, stream=None):

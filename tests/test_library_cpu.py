@@ -94,3 +94,20 @@ def test_symbolic_bit_exact_large(psp, O, W):
     a = psp.Plan(J.indptr, J.indices).export()
     s = O.symbolic(J.n, J.indptr, J.indices)
     assert _same(a, s)
+
+
+def test_residual_argument_errors_before_any_device_call(psp):
+    """psp_residual validates on the host: NULL required pointers -> PSP_E_INVALID, and
+    n > 16384 without the R output -> PSP_E_UNSUPPORTED (no device memory is touched)."""
+    import ctypes as C
+    L = psp.lib()
+    ip = np.array([0, 1, 2], np.int32)
+    ix = np.array([0, 1], np.int32)
+    plan = psp.Plan(ip, ix)
+    assert L.psp_residual(plan.handle, 1, None, 1, None, None, None, None, None, None) == psp.PSP_E_INVALID
+    assert L.psp_residual(None, 1, None, 1, None, None, None, None, None, None) == psp.PSP_E_INVALID
+    n = 16385
+    big = psp.Plan(np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32))
+    dummy = C.c_void_p(16)    # never dereferenced: the size check comes first
+    st = L.psp_residual(big.handle, 1, dummy, 1, dummy, dummy, None, dummy, None, None)
+    assert st == psp.PSP_E_UNSUPPORTED and b"needs the R output" in L.psp_last_error()
