@@ -109,6 +109,24 @@ def extra_configs(psp, W, torch, dev):
                                  "forward_ms": f_ms, "backward_ms": fb_ms - f_ms,
                                  "forward_rhs_solves_per_s": J * len(eps) * R / (f_ms / 1e3)}
     print(f"[bench] n601 adjoint 64 rhs: fwd {f_ms:.3f} ms, bwd {fb_ms - f_ms:.3f} ms", file=sys.stderr, flush=True)
+    # uneven batch: 512 Jacobians of five networks (n = 61 .. 2709), one psp_solve_group call
+    groups = W.uneven_batch(512)
+    items, paths_u, flops_u, sizes = [], {}, 0.0, {}
+    for N, ipu, ixu, valsu, bsu in groups:
+        pu = psp.Plan(ipu, ixu)
+        vu, bu = torch.from_numpy(valsu).to(dev), torch.from_numpy(bsu).to(dev)
+        ch, _ = psp.tune(pu, vu, eps, bu)
+        paths_u[len(ipu) - 1] = ch
+        sizes[len(ipu) - 1] = int(valsu.shape[0])
+        flops_u += valsu.shape[0] * len(eps) * sparse_flops(pu.info(), len(ipu) - 1)
+        items.append((pu, vu, bu))
+    psp.solve_group(items, eps)
+    torch.cuda.synchronize()
+    g_ms, _ = _events(torch, lambda: psp.solve_group(items, eps), 3)
+    out["uneven_512"] = {"jacobians_by_n": sizes, "K": len(eps), "path_by_n": paths_u, "ms_per_call": g_ms,
+                         "solves_per_s": 512 * len(eps) / (g_ms / 1e3),
+                         "sparse_tflops": flops_u / (g_ms / 1e3) / 1e12}
+    print(f"[bench] uneven 512: {g_ms:.3f} ms, paths {paths_u}", file=sys.stderr, flush=True)
     # 10,000-bus network, n = 20,001, K = 4, 32 RHS
     from paper_2311_11833_amd.workloads import make_network, make_state, jacobian, seed_state
     net = make_network(10000)

@@ -177,6 +177,35 @@ PSP_API psp_status psp_solve_batched(psp_plan plan, int32_t path, int32_t batch,
                              void* stream);
 
 /* ------------------------------------------------------------------------
+ * Uneven batches (Alg. 1 steps 1-4 for Jacobians of different patterns):
+ * item i holds items[i].batch Jacobians that share items[i].plan's pattern.
+ *   path    PSP_PATH_* for this item; PSP_PATH_AUTO takes the plan's tuned
+ *           choice for (batch, K, nrhs), else the size heuristic
+ *   values  device batch x nnz;  d device n (diagonal of D) or NULL (D = I)
+ *   B, X    device batch x n x nrhs;  info device batch x K
+ * Every item runs on `stream`, in the given order, in its own slice of one
+ * device workspace of at least psp_group_workspace_bytes(...) bytes, which
+ * is the sum of the items' psp_workspace_bytes (256-byte aligned).  Errors are
+ * as for psp_solve_batched; the first failing item stops the call (items
+ * before it are already queued).  psp_group_workspace_bytes returns 0 for an
+ * invalid item list.
+ * ---------------------------------------------------------------------- */
+typedef struct psp_group_item {
+    psp_plan plan;
+    int32_t batch;
+    int32_t path;
+    const double* values;
+    const double* d;
+    const double* B;
+    double* X;
+    int32_t* info;
+} psp_group_item_t;
+
+PSP_API size_t psp_group_workspace_bytes(int32_t nitems, const psp_group_item_t* items, int32_t K, int32_t nrhs);
+PSP_API psp_status psp_solve_group(int32_t nitems, const psp_group_item_t* items, int32_t K, const double* eps,
+                                   int32_t nrhs, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
  * psp_tune -- autotuner: runs psp_solve_batched on the caller's data with
  * every path that can run this plan and fits ws_bytes (one warm-up, three
  * timed runs each, HIP events on `stream`; the call synchronises the stream),

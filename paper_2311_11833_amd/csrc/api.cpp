@@ -363,6 +363,37 @@ psp_status psp_solve_batched(psp_plan p, int32_t path, int32_t batch, const doub
     return fail(PSP_E_INVALID, "unknown path");
 }
 
+size_t psp_group_workspace_bytes(int32_t nitems, const psp_group_item_t* items, int32_t K, int32_t nrhs) {
+    if (nitems < 1 || !items) return 0;
+    size_t total = 0;
+    for (int32_t i = 0; i < nitems; ++i) {
+        const psp_group_item_t& it = items[i];
+        if (!it.plan || it.batch < 1) return 0;
+        const size_t w = psp_workspace_bytes(it.plan, it.path, it.batch, K, nrhs, 0);
+        if (w == 0) return 0;
+        total += (w + 255) / 256 * 256;
+    }
+    return total;
+}
+
+psp_status psp_solve_group(int32_t nitems, const psp_group_item_t* items, int32_t K, const double* eps, int32_t nrhs,
+                           void* ws, size_t ws_bytes, void* stream) {
+    if (nitems < 1 || !items || !ws) return fail(PSP_E_INVALID, "psp_solve_group: no items or NULL workspace");
+    const size_t need = psp_group_workspace_bytes(nitems, items, K, nrhs);
+    if (need == 0) return fail(PSP_E_INVALID, "psp_solve_group: an item has a NULL plan, batch < 1 or bad sizes");
+    if (ws_bytes < need) return fail(PSP_E_NOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
+    char* w = (char*)ws;
+    for (int32_t i = 0; i < nitems; ++i) {
+        const psp_group_item_t& it = items[i];
+        const size_t wi = (psp_workspace_bytes(it.plan, it.path, it.batch, K, nrhs, 0) + 255) / 256 * 256;
+        psp_status st = psp_solve_batched(it.plan, it.path, it.batch, it.values, K, eps, it.d, nrhs, it.B, it.X,
+                                          it.info, w, wi, stream);
+        if (st != PSP_OK) return fail(st, "psp_solve_group: item " + std::to_string(i) + ": " + g_err);
+        w += wi;
+    }
+    return PSP_OK;
+}
+
 psp_status psp_tune(psp_plan p, int32_t batch, const double* values, int32_t K, const double* eps, const double* d,
                     int32_t nrhs, const double* B, double* X, int32_t* info, void* ws, size_t ws_bytes, void* stream,
                     int32_t* chosen, float* ms) {

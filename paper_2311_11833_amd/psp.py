@@ -24,7 +24,8 @@ PATH_NAMES = {v: k for k, v in PATHS.items()}
 ORDERS = {"md": 0, "natural": 1}
 EXPORTED = ["psp_last_error", "psp_version", "psp_plan_create", "psp_plan_info", "psp_plan_export",
             "psp_plan_destroy", "psp_weights", "psp_workspace_bytes", "psp_solve_batched", "psp_tune", "psp_factor",
-            "psp_solve", "psp_combine", "psp_grad_values", "psp_factors_release", "psp_residual"]
+            "psp_solve", "psp_combine", "psp_grad_values", "psp_factors_release", "psp_residual",
+            "psp_group_workspace_bytes", "psp_solve_group"]
 
 
 class PSPError(RuntimeError):
@@ -36,6 +37,11 @@ class PSPError(RuntimeError):
 class PlanInfo(C.Structure):
     _fields_ = [("n", C.c_int32), ("nnz", C.c_int32), ("nnz_l", C.c_int64), ("ndense", C.c_int32),
                 ("nlev", C.c_int32 * 3), ("flops_dense_factor", C.c_int64), ("flops_sparse_factor", C.c_int64)]
+
+
+class GroupItem(C.Structure):
+    _fields_ = [("plan", C.c_void_p), ("batch", C.c_int32), ("path", C.c_int32), ("values", C.c_void_p),
+                ("d", C.c_void_p), ("B", C.c_void_p), ("X", C.c_void_p), ("info", C.c_void_p)]
 
 
 _lib = None
@@ -66,8 +72,12 @@ def lib():
         L.psp_grad_values.argtypes = [vp, i32, vp, vp, vp, vp]
         L.psp_factors_release.argtypes = [vp]
         L.psp_residual.argtypes = [vp, i32, vp, i32, vp, vp, vp, vp, vp, vp]
+        L.psp_group_workspace_bytes.argtypes = [i32, vp, i32, i32]
+        L.psp_group_workspace_bytes.restype = C.c_size_t
+        L.psp_solve_group.argtypes = [i32, vp, i32, vp, i32, vp, C.c_size_t, vp]
         for f in EXPORTED:
-            if f not in ("psp_last_error", "psp_version", "psp_plan_destroy", "psp_workspace_bytes"):
+            if f not in ("psp_last_error", "psp_version", "psp_plan_destroy", "psp_workspace_bytes",
+                         "psp_group_workspace_bytes"):
                 getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -195,6 +205,40 @@ def solve_batched(plan: Plan, values, eps, b, path: str = "auto", d=None, worksp
                                    nrhs, _dptr(b.contiguous()), _dptr(x), _dptr(info), _dptr(ws), ws.numel(),
                                    _stream(stream)))
     return x, info
+
+
+def solve_group(items, eps, path: str = "auto", d=None, stream=None, workspace=None):
+    """Uneven batch: items is a list of (plan, values, b), each values (batch_i, nnz_i) and b
+    (batch_i, n_i) or (batch_i, n_i, nrhs) float64 device tensors (same nrhs everywhere).
+    All items run on one stream in one workspace.  Returns [(x_i, info_i)]."""
+    import torch
+    eps_h = np.ascontiguousarray(eps, dtype=np.float64)
+    K = len(eps_h)
+    nrhs = 1 if items[0][2].dim() == 2 else items[0][2].shape[2]
+    arr = (GroupItem * len(items))()
+    outs, keep = [], []
+    for i, (plan, values, b) in enumerate(items):
+        if values.dtype != torch.float64 or b.dtype != torch.float64:
+            raise TypeError("values and b must be float64")
+        if values.shape[1] != plan.nnz or b.shape[1] != plan.n or b.shape[0] != values.shape[0]:
+            raise ValueError(f"item {i}: shape mismatch with its plan")
+        if (1 if b.dim() == 2 else b.shape[2]) != nrhs:
+            raise ValueError("every item needs the same number of right-hand sides")
+        bc = b.contiguous()
+        x = torch.empty_like(bc)
+        info = torch.empty((values.shape[0], K), dtype=torch.int32, device=values.device)
+        keep.append(bc)
+        arr[i] = GroupItem(plan.handle, values.shape[0], PATHS[path], _dptr(values).value, _dptr(d).value if d is not None else None,
+                           _dptr(bc).value, _dptr(x).value, _dptr(info).value)
+        outs.append((x, info))
+    need = lib().psp_group_workspace_bytes(len(items), C.byref(arr), K, nrhs)
+    if need == 0:
+        raise PSPError(PSP_E_INVALID, "invalid group item list")
+    dev = items[0][1].device
+    ws = workspace if workspace is not None else torch.empty(need, dtype=torch.uint8, device=dev)
+    _check(lib().psp_solve_group(len(items), C.byref(arr), K, _np_ptr(eps_h), nrhs, _dptr(ws), ws.numel(),
+                                 _stream(stream)))
+    return outs
 
 
 def residual(plan: Plan, values, b, x, keep_r: bool = False, stream=None):

@@ -225,6 +225,22 @@ def scenario_batch(N: int, count: int, inst: int = 0, first: int = 0,
     return pat[0], pat[1], np.stack(vals), np.stack(bs)
 
 
+UNEVEN_NETWORKS = (30, 118, 300, 500, 1354)
+
+
+def uneven_batch(total: int = 512, networks=UNEVEN_NETWORKS, seed: int = 2311):
+    """Jacobians of several networks in one batch: each of `total` Jacobians picks its
+    network uniformly (seeded), then gets its own seeded state and RHS.  Returns a list
+    of (N, indptr, indices, values[count, nnz], b[count, n]) per network that was drawn."""
+    pick = np.random.default_rng(seed).integers(0, len(networks), size=total)
+    out = []
+    for i, N in enumerate(networks):
+        count = int(np.sum(pick == i))
+        if count:
+            out.append((N,) + scenario_batch(N, count))
+    return out
+
+
 def to_dense(n: int, indptr: np.ndarray, indices: np.ndarray, data: np.ndarray) -> np.ndarray:
     A = np.zeros((n, n))
     for i in range(n):

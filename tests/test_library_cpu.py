@@ -111,3 +111,25 @@ def test_residual_argument_errors_before_any_device_call(psp):
     dummy = C.c_void_p(16)    # never dereferenced: the size check comes first
     st = L.psp_residual(big.handle, 1, dummy, 1, dummy, dummy, None, dummy, None, None)
     assert st == psp.PSP_E_UNSUPPORTED and b"needs the R output" in L.psp_last_error()
+
+
+def test_group_rejects_bad_items_on_the_host(psp):
+    """psp_group_workspace_bytes returns 0 and psp_solve_group PSP_E_INVALID for an empty
+    list, a NULL plan or batch < 1 -- before any device call."""
+    import ctypes as C
+    L = psp.lib()
+    ip = np.array([0, 1, 2], np.int32)
+    ix = np.array([0, 1], np.int32)
+    plan = psp.Plan(ip, ix)
+    arr = (psp.GroupItem * 2)()
+    arr[0] = psp.GroupItem(plan.handle, 3, 0, None, None, None, None, None)
+    arr[1] = psp.GroupItem(None, 3, 0, None, None, None, None, None)
+    eps = np.array([1e-3, 5e-4])
+    assert L.psp_group_workspace_bytes(1, C.byref(arr), 2, 1) > 0
+    assert L.psp_group_workspace_bytes(2, C.byref(arr), 2, 1) == 0
+    assert L.psp_group_workspace_bytes(0, C.byref(arr), 2, 1) == 0
+    dummy = C.c_void_p(16)
+    assert L.psp_solve_group(2, C.byref(arr), 2, eps.ctypes.data_as(C.c_void_p), 1, dummy, 1 << 30, None) == psp.PSP_E_INVALID
+    arr[1] = psp.GroupItem(plan.handle, 0, 0, None, None, None, None, None)
+    assert L.psp_solve_group(2, C.byref(arr), 2, eps.ctypes.data_as(C.c_void_p), 1, dummy, 1 << 30, None) == psp.PSP_E_INVALID
+    assert L.psp_solve_group(0, None, 2, eps.ctypes.data_as(C.c_void_p), 1, dummy, 1 << 30, None) == psp.PSP_E_INVALID
