@@ -44,8 +44,7 @@ struct SpIdx {
 struct StepIdx {
     int32_t nsteps = 0, threads = 0, ndesc = 0;
     const int4* meta = nullptr;       // per step: slot base, active threads, rows, 0
-    const int2* desc = nullptr;       // task descriptors (see steps.hip)
-    const uint32_t* xp = nullptr;     // update lists of tasks with two or more updates
+    const int4* desc = nullptr;       // task descriptors, 16 bytes each (see steps.hip)
 };
 
 struct SparseDevice {

@@ -25,10 +25,10 @@
 // coalesced 8-byte load per lane, issued several steps ahead: a step itself is
 // a few hundred cycles of LDS work, far less than one round trip to L2.
 //
-// Descriptor (int2), LDS indices < 2^15:
-//   x = dst | long << 15 | div << 16   (div = 0xFFFF: no division)
-//   y = short task: packed pair a | b << 16 (-1: no update)
-//       long task (two or more updates): offset in xp of [cnt, 0, 0, 0, pairs..]
+// Descriptor (int4, 16 bytes), LDS indices < 2^15, at most kStSegMax = 3
+// updates per task:
+//   x = dst | cnt << 15 | div << 17   (cnt 0..3; div = 0x7FFF: no division)
+//   y, z, w = update pairs a | b << 16, in chain order (unused: 0)
 // An empty slot has x = -1.  Update of a pair: v[dst] = fma(-v[a], v[b], v[dst]).
 //
 // Device side: LDS holds [u_jj (n) | L values (nnzL) | U values (nnzL) |
@@ -49,6 +49,11 @@ namespace psp {
 namespace {
 constexpr int kStThreads = 1024;         // workgroup size; the schedule is built for it (one task per thread and step)
 constexpr int kStAhead = 8;              // steps whose descriptors are in flight
+// Longest run of one chain inside a step, so that every task's updates fit in
+// its descriptor (no second, dependent load).  The long runs belong mostly to
+// the dense slack row, whose value is needed only at the end; at n = 601 the
+// cap raises the step count from 294 to 340 and removes every in-step fetch.
+constexpr int kStSegMax = 3;
 constexpr int kStLdsLimit = 152 * 1024;  // bytes of LDS the kernel may use
 
 int64_t st_lds_doubles(const Symbolic& s) { return 3 * (int64_t)s.n + 2 * (int64_t)s.l_ptr[s.n]; }
@@ -66,7 +71,7 @@ struct StTask {
 
 // Builds the step schedule.  Returns false when the plan does not fit.
 bool build_schedule(const Symbolic& s, const std::vector<int32_t>& r_pos, int T, std::vector<int32_t>& meta,
-                    std::vector<int32_t>& desc, std::vector<uint32_t>& xp, int32_t& nsteps) {
+                    std::vector<int32_t>& desc, int32_t& nsteps, int seg_max = kStSegMax) {
     const int n = s.n, nl = s.l_ptr[n];
     if (st_lds_doubles(s) * 8 > kStLdsLimit || st_lds_doubles(s) >= 0x7FFF) return false;
     const int ybase = n + 2 * nl;
@@ -87,7 +92,8 @@ bool build_schedule(const Symbolic& s, const std::vector<int32_t>& r_pos, int T,
         for (uint32_t q : chain) {
             const int a = (int)(q & 0xFFFF), b = (int)(q >> 16);
             const int ready = std::max(std::max(fin[a], fin[b]), base) + 1;
-            const int stp = std::max(ready, seg_step);
+            int stp = std::max(ready, seg_step);
+            if (stp == seg_step && seg_cnt == seg_max) stp = seg_step + 1;   // long runs continue next step
             if (stp != seg_step) {
                 if (seg_cnt) tasks.push_back({seg_step, dst, -1, (int32_t)seg_off, seg_cnt});
                 seg_step = stp;
@@ -165,7 +171,6 @@ bool build_schedule(const Symbolic& s, const std::vector<int32_t>& r_pos, int T,
     for (int32_t i = 0; i < (int32_t)tasks.size(); ++i) by_step[tasks[i].step].push_back(i);
     meta.clear();
     desc.clear();
-    xp.clear();
     auto cost = [&](const StTask& t) { return 6 + 2 * t.cnt + (t.div >= 0 ? 8 : 0); };
     for (int st = 1; st <= S; ++st) {
         std::vector<int32_t>& list = by_step[st];
@@ -174,32 +179,21 @@ bool build_schedule(const Symbolic& s, const std::vector<int32_t>& r_pos, int T,
         for (size_t c0 = 0; c0 < list.size(); c0 += (size_t)T) {
             const int cnt = (int)std::min<size_t>((size_t)T, list.size() - c0);
             const int tact = (cnt + 63) / 64 * 64;
-            const int64_t base = (int64_t)desc.size() / 2;
+            const int64_t base = (int64_t)desc.size() / 4;
             if (base + tact > INT_MAX / 2) return false;
             meta.push_back((int32_t)base);
             meta.push_back(tact);
             meta.push_back(1);
             meta.push_back(0);
-            desc.resize(desc.size() + 2 * (size_t)tact, -1);
+            desc.resize(desc.size() + 4 * (size_t)tact, 0);
+            for (int t = cnt; t < tact; ++t) desc[4 * (size_t)(base + t)] = -1;
             for (int t = 0; t < cnt; ++t) {
                 const StTask& k = tasks[list[c0 + t]];
-                const size_t at = 2 * (size_t)(base + t);
-                const uint32_t x = (uint32_t)k.dst | (k.cnt >= 2 ? 0x8000u : 0u) |
-                                   ((uint32_t)(k.div >= 0 ? k.div : 0xFFFF) << 16);
-                int32_t y = -1;
-                if (k.cnt == 1) {
-                    y = (int32_t)P[k.off];
-                } else if (k.cnt >= 2) {
-                    y = (int32_t)xp.size();
-                    xp.push_back((uint32_t)k.cnt);
-                    xp.push_back(0);
-                    xp.push_back(0);
-                    xp.push_back(0);
-                    for (int c = 0; c < k.cnt; ++c) xp.push_back(P[k.off + c]);
-                    while (xp.size() % 4) xp.push_back(0);
-                }
-                desc[at] = (int32_t)x;
-                desc[at + 1] = y;
+                if (k.cnt > 3) return false;
+                const size_t at = 4 * (size_t)(base + t);
+                desc[at] = (int32_t)((uint32_t)k.dst | ((uint32_t)k.cnt << 15) |
+                                     ((uint32_t)(k.div >= 0 ? k.div : 0x7FFF) << 17));
+                for (int c = 0; c < k.cnt; ++c) desc[at + 1 + c] = (int32_t)P[k.off + c];
             }
         }
     }
@@ -221,33 +215,21 @@ struct StArgs {
     int32_t* info;          // batch x K
 };
 
-__device__ __forceinline__ void st_exec(const StArgs& a, double* v, int2 d) {
+__device__ __forceinline__ void st_exec(double* v, int4 d) {
     if (d.x == -1) return;
     const int dst = d.x & 0x7FFF;
-    const int div = (int)((uint32_t)d.x >> 16);
-    double acc = v[dst];
-    if (!(d.x & 0x8000)) {
-        if (d.y != -1) acc = fmad(-v[d.y & 0xFFFF], v[(uint32_t)d.y >> 16], acc);
-    } else {
-        const uint32_t* p = a.sx.xp + d.y;
-        const int cnt = (int)p[0];
-        const uint4* q = (const uint4*)(p + 4);
-        int c = 0;
-        for (; c + 8 <= cnt; c += 8) {
-            const uint4 w0 = q[c / 4], w1 = q[c / 4 + 1];
-            const uint32_t w[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
-            double l[8], u[8];
-#pragma unroll
-            for (int e = 0; e < 8; ++e) { l[e] = v[w[e] & 0xFFFF]; u[e] = v[w[e] >> 16]; }
-#pragma unroll
-            for (int e = 0; e < 8; ++e) acc = fmad(-l[e], u[e], acc);
-        }
-        for (; c < cnt; ++c) {
-            const uint32_t w = p[4 + c];
-            acc = fmad(-v[w & 0xFFFF], v[w >> 16], acc);
-        }
-    }
-    if (div != 0xFFFF) acc = acc / v[div];
+    const int cnt = (d.x >> 15) & 3;
+    const int div = (int)((uint32_t)d.x >> 17);
+    // all operands first (unused pairs read slot 0), then the chain in order
+    const double acc0 = v[dst];
+    const double l0 = v[d.y & 0xFFFF], u0 = v[(uint32_t)d.y >> 16];
+    const double l1 = v[d.z & 0xFFFF], u1 = v[(uint32_t)d.z >> 16];
+    const double l2 = v[d.w & 0xFFFF], u2 = v[(uint32_t)d.w >> 16];
+    double acc = acc0;
+    if (cnt > 0) acc = fmad(-l0, u0, acc);
+    if (cnt > 1) acc = fmad(-l1, u1, acc);
+    if (cnt > 2) acc = fmad(-l2, u2, acc);
+    if (div != 0x7FFF) acc = acc / v[div];
     v[dst] = acc;
 }
 
@@ -256,10 +238,10 @@ __device__ __forceinline__ void st_exec(const StArgs& a, double* v, int2 d) {
 // returns zeros without a memory access.  (A plain load from a shared dummy
 // slot sends every idle lane of every CU to one cache line at once.)  The
 // instruction is issued by every thread, so the loads in flight stay static.
-__device__ __forceinline__ int2 st_desc(__amdgpu_buffer_rsrc_t r, int4 m, int tid) {
-    const int off = tid < m.y ? (m.x + tid) * 8 : -1;
-    const auto w = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
-    int2 d;
+__device__ __forceinline__ int4 st_desc(__amdgpu_buffer_rsrc_t r, int2 m, int tid) {
+    const int off = tid < m.y ? (m.x + tid) * 16 : -1;
+    const auto w = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+    int4 d;
     __builtin_memcpy(&d, &w, sizeof(d));
     return d;
 }
@@ -279,12 +261,15 @@ __global__ __launch_bounds__(T) void steps_kernel(StArgs a, EpsSet es) {
     const int Sp = st_padded(S);
     // per-step metadata, read by every step of every system: kept in LDS,
     // followed by empty steps up to a multiple of the ring depth and one ring beyond
-    int4* sm = reinterpret_cast<int4*>(v + ((3 * n + 2 * nl + 1) & ~1));
-    for (int i = tid; i < Sp + kStAhead + 1; i += T) sm[i] = i < S ? a.sx.meta[i] : make_int4(0, 0, 1, 0);
+    int2* sm = reinterpret_cast<int2*>(v + ((3 * n + 2 * nl + 1) & ~1));
+    for (int i = tid; i < Sp + kStAhead + 1; i += T) {
+        const int4 mi = i < S ? a.sx.meta[i] : make_int4(0, 0, 1, 0);
+        sm[i] = make_int2(mi.x, mi.y);
+    }
     __syncthreads();
     // gfx9-family buffer resource: raw (stride 0), range = the descriptor array
     const __amdgpu_buffer_rsrc_t drs =
-        __builtin_amdgcn_make_buffer_rsrc((void*)a.sx.desc, (short)0, a.sx.ndesc * 8, 0x00020000);
+        __builtin_amdgcn_make_buffer_rsrc((void*)a.sx.desc, (short)0, a.sx.ndesc * 16, 0x00020000);
     const int njobs = a.per_jacobian ? a.batch : a.batch * es.K;
     for (int job = blockIdx.x; job < njobs; job += gridDim.x) {
         const int s = a.per_jacobian ? job : job / es.K;
@@ -293,12 +278,12 @@ __global__ __launch_bounds__(T) void steps_kernel(StArgs a, EpsSet es) {
         for (int kk = k0; kk < k1; ++kk) {
             // descriptor ring: step st runs while steps st+1 .. st+kStAhead-1 are in
             // flight; each step waits for its own load only.
-            int2 ring[kStAhead];
+            int4 ring[kStAhead];
 #pragma unroll
             for (int d = 0; d < kStAhead; ++d) {
                 ring[d] = st_desc(drs, sm[d], tid);
             }
-            int4 m = sm[0];
+            int2 m = sm[0];
             // A + eps_k D permuted onto the fill pattern, and P b
             for (int t = tid; t < nl; t += T) {
                 const int sl = ix.src_l[t], su = ix.src_u[t];
@@ -322,9 +307,10 @@ __global__ __launch_bounds__(T) void steps_kernel(StArgs a, EpsSet es) {
 #pragma unroll
                 for (int d = 0; d < kStAhead; ++d) {
                     const int st = st0 + d;
-                    const int4 m1 = sm[st + 1];
-                    const int4 ma = sm[st + kStAhead];
-                    if (tid < m.y) st_exec(a, v, ring[d]);
+                    if (tid < m.y) st_exec(v, ring[d]);
+                    // the next steps' metadata after the task: its latency overlaps the barrier
+                    const int2 m1 = sm[st + 1];
+                    const int2 ma = sm[st + kStAhead];
                     ring[d] = st_desc(drs, ma, tid);
                     __syncthreads();
                     m = m1;
@@ -364,12 +350,12 @@ bool steps_ready(const SparseDevice& d) { return d.st_buf != nullptr; }
 hipError_t steps_upload(const Symbolic& s, const std::vector<int32_t>& r_pos, SparseDevice& d) {
     if (d.st_buf || !steps_fit(s, 1)) return hipSuccess;
     std::vector<int32_t> meta, desc;
-    std::vector<uint32_t> xp;
     int32_t S = 0;
-    if (!build_schedule(s, r_pos, kStThreads, meta, desc, xp, S) || S < 1) return hipSuccess;
+    if (!build_schedule(s, r_pos, kStThreads, meta, desc, S) || S < 1) return hipSuccess;
+    if (desc.size() / 4 * 16 > (size_t)INT32_MAX) return hipSuccess;
     auto up16 = [](size_t words) { return (words + 63) / 64 * 64; };
-    const size_t o_meta = 0, o_desc = up16(meta.size()), o_xp = o_desc + up16(desc.size());
-    const size_t total = o_xp + up16(std::max<size_t>(xp.size(), 4));
+    const size_t o_meta = 0, o_desc = up16(meta.size());
+    const size_t total = o_desc + up16(desc.size());
     // Rounded up to whole 2 MiB fragments: the kernel streams this array once
     // per system from every CU, and small-page mappings make each new page a
     // translation miss.
@@ -380,15 +366,13 @@ hipError_t steps_upload(const Symbolic& s, const std::vector<int32_t>& r_pos, Sp
     std::vector<int32_t> host(total, 0);
     std::copy(meta.begin(), meta.end(), host.begin() + o_meta);
     std::copy(desc.begin(), desc.end(), host.begin() + o_desc);
-    std::copy(xp.begin(), xp.end(), host.begin() + o_xp);
     e = hipMemcpy(d.st_buf, host.data(), sizeof(int32_t) * total, hipMemcpyHostToDevice);
     if (e != hipSuccess) { (void)hipFree(d.st_buf); d.st_buf = nullptr; return e; }
     d.st.nsteps = S;
     d.st.threads = kStThreads;
-    d.st.ndesc = (int32_t)(desc.size() / 2);
+    d.st.ndesc = (int32_t)(desc.size() / 4);
     d.st.meta = (const int4*)(d.st_buf + o_meta);
-    d.st.desc = (const int2*)(d.st_buf + o_desc);
-    d.st.xp = (const uint32_t*)(d.st_buf + o_xp);
+    d.st.desc = (const int4*)(d.st_buf + o_desc);
     return hipSuccess;
 }
 
