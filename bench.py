@@ -105,10 +105,27 @@ def extra_configs(psp, W, torch, dev):
     torch.cuda.synchronize()
     f_ms, _ = _events(torch, fwd, 3)
     fb_ms, _ = _events(torch, fwd_bwd, 3)
+    # the same per Jacobian, one Jacobian per call (the plain path), on the first 8
+    JP = 8
+
+    def plain_fwd_bwd():
+        for s_ in range(JP):
+            vs = v[s_:s_ + 1].detach().requires_grad_(True)
+            Bs = B[s_:s_ + 1].detach().requires_grad_(True)
+            xs = perturbed_solve(vs, Bs, plan, eps, path="sparse")
+            torch.autograd.grad(xs, (vs, Bs), G[s_:s_ + 1])
+
+    plain_fwd_bwd()
+    torch.cuda.synchronize()
+    p_ms, _ = _events(torch, plain_fwd_bwd, 2)
     out["n601_adjoint_64rhs"] = {"jacobians": J, "K": len(eps), "nrhs": R, "path": "sparse (split steps)",
                                  "forward_ms": f_ms, "backward_ms": fb_ms - f_ms,
-                                 "forward_rhs_solves_per_s": J * len(eps) * R / (f_ms / 1e3)}
-    print(f"[bench] n601 adjoint 64 rhs: fwd {f_ms:.3f} ms, bwd {fb_ms - f_ms:.3f} ms", file=sys.stderr, flush=True)
+                                 "forward_rhs_solves_per_s": J * len(eps) * R / (f_ms / 1e3),
+                                 "plain_fwd_bwd_ms_per_jacobian": p_ms / JP,
+                                 "batched_fwd_bwd_ms_per_jacobian": fb_ms / J,
+                                 "batched_speedup": (p_ms / JP) / (fb_ms / J)}
+    print(f"[bench] n601 adjoint 64 rhs: fwd {f_ms:.3f} ms, bwd {fb_ms - f_ms:.3f} ms; plain {p_ms / JP:.3f} ms "
+          f"per Jacobian vs batched {fb_ms / J:.3f}", file=sys.stderr, flush=True)
     # uneven batch: 512 Jacobians of five networks (n = 61 .. 2709), one psp_solve_group call
     groups = W.uneven_batch(512)
     items, paths_u, flops_u, sizes = [], {}, 0.0, {}

@@ -16,7 +16,7 @@ def dev():
     return torch.device("cuda:0")
 
 
-@pytest.mark.parametrize("path,N,count", [("dense", 30, 8), ("sparse", 300, 64), ("sparse", 30, 4)])
+@pytest.mark.parametrize("path,N,count", [("dense", 30, 8), ("sparse", 300, 64), ("sparse", 30, 4), ("sparse_steps", 300, 300)])
 def test_graph_replays_match_eager(dev, W, path, N, count):
     from paper_2311_11833_amd import psp
     ip, ix, vals, bs = W.scenario_batch(N, count)
