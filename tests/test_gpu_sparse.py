@@ -223,3 +223,53 @@ def test_steps_path_rejects_what_it_cannot_run(psp, W, dev):
     with pytest.raises(psp.PSPError, match="UNSUPPORTED|cannot run"):
         psp.solve_batched(plan, torch.from_numpy(vals).to(dev), W.config_eps("n601"),
                           torch.from_numpy(bs).to(dev), path="sparse_steps")
+
+
+@pytest.mark.parametrize("variant", ["sparse_batched", "sparse_grouped", "sparse_lds", "sparse_levels", "sparse_steps"])
+def test_gaussian_diagonal_and_symmetric_nodes(psp, O, W, dev, variant):
+    """The paper's own scheme (nodes +-alpha eps, alpha = 1, 2, eps = 2e-3) with a diagonal
+    D of normally distributed entries scaled to max |d_i| = 1, on every sparse execution:
+    bitwise equal to the oracle with the same D."""
+    ip, ix, vals, bs = W.scenario_batch(118, 12)
+    n = len(ip) - 1
+    eps = np.array([2e-3, -2e-3, 4e-3, -4e-3])
+    d = np.random.default_rng(41).standard_normal(n)
+    d /= np.abs(d).max()
+    plan = psp.Plan(ip, ix)
+    print(f"[gpu sparse] gaussian D, symmetric nodes, {variant}", flush=True)
+    x, info = psp.solve_batched(plan, torch.from_numpy(vals).to(dev), eps, torch.from_numpy(bs).to(dev),
+                                path=variant, d=torch.from_numpy(d).to(dev))
+    torch.cuda.synchronize()
+    sym = O.symbolic(n, ip, ix)
+    xo, io, _, _ = O.sparse_batch(n, ip, ix, vals, sym, eps, bs, d=d)
+    assert np.array_equal(info.cpu().numpy(), io)
+    _cmp(x.cpu().numpy(), xo)
+
+
+def test_gaussian_diagonal_split_steps_and_adjoint(psp, O, W, dev):
+    """Split calls (kept factors, forward and transposed solves, gradient) with the same
+    Gaussian D: equal to the oracle bitwise."""
+    ip, ix, vals, _ = W.scenario_batch(30, 3)
+    n = len(ip) - 1
+    eps = np.array([2e-3, -2e-3, 4e-3, -4e-3])
+    rng = np.random.default_rng(42)
+    d = rng.standard_normal(n)
+    d /= np.abs(d).max()
+    B = rng.standard_normal((3, n, 2))
+    Wt = rng.standard_normal((3, n, 2))
+    plan = psp.Plan(ip, ix)
+    F = psp.Factors(plan, torch.from_numpy(vals).to(dev), eps, path="sparse", d=torch.from_numpy(d).to(dev), nrhs_cap=2)
+    Xk = F.solve(torch.from_numpy(B).to(dev))
+    Lk = F.solve(torch.from_numpy(Wt).to(dev), transpose=True)
+    X = F.combine(Xk)
+    gA = F.grad_values(Lk, Xk)
+    torch.cuda.synchronize()
+    sym = O.symbolic(n, ip, ix)
+    c = O.weights(eps)
+    for s in range(3):
+        xo, _, xko, _ = O.sparse_batch(n, ip, ix, vals[s:s + 1], sym, eps, B[s:s + 1], d=d, keep_xk=True)
+        lo, _, lko, _ = O.sparse_batch(n, ip, ix, vals[s:s + 1], sym, eps, Wt[s:s + 1], d=d, trans=True, keep_xk=True)
+        _cmp(Xk[s].cpu().numpy(), xko[0])
+        _cmp(Lk[s].cpu().numpy(), lko[0])
+        _cmp(X[s].cpu().numpy(), xo[0])
+        _cmp(gA[s].cpu().numpy(), O.grad_values(n, ip, ix, c, xko[0], lko[0]))
