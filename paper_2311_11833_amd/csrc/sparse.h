@@ -55,6 +55,7 @@ struct SparseDevice {
     std::vector<int32_t> h_lpos_ptr;
     int32_t* st_buf = nullptr;           // step schedule (absent when the system does not fit in LDS)
     StepIdx st{};
+    int32_t* pair_buf = nullptr;         // update lists built on the device (too large for the host build)
 };
 
 enum { kVarLds = 0, kVarGlobal = 1, kVarBatched = 2, kVarGrouped = 3, kVarSteps = 4 };

@@ -44,7 +44,10 @@ namespace {
 constexpr int kLdsLimit = 152 * 1024;    // bytes of LDS the in-LDS kernel may use
 constexpr int kLdsThreads = 512;
 constexpr int kThreads = 256;
-constexpr int64_t kMaxPairs = 32LL << 20;   // precomputed update pairs kept at most (256 MB)
+constexpr int64_t kMaxPairs = 32LL << 20;   // update pairs built on the host at most (256 MB)
+// Larger update lists are built on the device (count, prefix sum, write) up
+// to int32 offsets and this many bytes of HBM.
+constexpr int64_t kMaxDevPairBytes = 24LL << 30;
 
 __device__ __forceinline__ double merge_dot(const SpIdx& ix, int a, int b, const double* lv, const double* uv,
                                             double acc) {
@@ -609,6 +612,104 @@ __global__ void il_combine_kernel(IlArgs a, EpsSet es) {
     }
 }
 
+// Update lists on the device.  Item id: diagonal j -> j, U position t -> n + t,
+// L position t -> n + nnzl + t (the order of the host build).  Entry t of
+// column j, row m: U pairs (pos(j,k), pos(m,k)), L pairs (pos(m,k), pos(j,k)),
+// k in R_j ^ R_m ascending; the U and L items of t have the same length.
+__global__ void pair_count_kernel(SpIdx ix, int32_t* cnt) {
+    const int n = ix.n, nl = ix.nnzl;
+    for (int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; id < (int64_t)n + nl;
+         id += (int64_t)gridDim.x * blockDim.x) {
+        if (id < n) {
+            cnt[id] = ix.r_ptr[id + 1] - ix.r_ptr[id];
+            continue;
+        }
+        const int t = (int)(id - n), j = ix.col_of[t], m = ix.l_idx[t];
+        int p = ix.r_ptr[j], pe = ix.r_ptr[j + 1], q = ix.r_ptr[m], qe = ix.r_ptr[m + 1], c = 0;
+        while (p < pe && q < qe) {
+            const int kp = ix.r_idx[p], kq = ix.r_idx[q];
+            c += kp == kq;
+            p += kp <= kq;
+            q += kq <= kp;
+        }
+        cnt[n + t] = c;
+        cnt[n + nl + t] = c;
+    }
+}
+
+__global__ void pair_write_kernel(SpIdx ix, const int32_t* ptr, int2* pairs) {
+    const int n = ix.n, nl = ix.nnzl;
+    for (int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; id < (int64_t)n + nl;
+         id += (int64_t)gridDim.x * blockDim.x) {
+        if (id < n) {
+            int2* out = pairs + ptr[id];
+            for (int p = ix.r_ptr[id]; p < ix.r_ptr[id + 1]; ++p) {
+                const int t = ix.r_pos[p];
+                *out++ = make_int2(t, t);
+            }
+            continue;
+        }
+        const int t = (int)(id - n), j = ix.col_of[t], m = ix.l_idx[t];
+        int2* ou = pairs + ptr[n + t];
+        int2* ol = pairs + ptr[n + nl + t];
+        int p = ix.r_ptr[j], pe = ix.r_ptr[j + 1], q = ix.r_ptr[m], qe = ix.r_ptr[m + 1];
+        while (p < pe && q < qe) {
+            const int kp = ix.r_idx[p], kq = ix.r_idx[q];
+            if (kp == kq) {
+                *ou++ = make_int2(ix.r_pos[p], ix.r_pos[q]);
+                *ol++ = make_int2(ix.r_pos[q], ix.r_pos[p]);
+            }
+            p += kp <= kq;
+            q += kq <= kp;
+        }
+    }
+}
+
+// Builds the update lists on the device when they are too large for the host
+// build; leaves ix.use_pairs = 0 when they do not fit either.
+hipError_t build_pairs_on_device(const Symbolic& s, SparseDevice& d) {
+    const int n = s.n, nl = s.l_ptr[n];
+    const int64_t items = (int64_t)n + 2 * (int64_t)nl;
+    const int64_t est = (s.flops_sparse - nl) / 2;
+    if (est <= kMaxPairs || est * 8 > kMaxDevPairBytes || est >= INT32_MAX) return hipSuccess;
+    int32_t* cnt = nullptr;
+    hipError_t e = hipMalloc(&cnt, sizeof(int32_t) * (items + 1));
+    if (e != hipSuccess) return e;
+    const int threads = 256;
+    const int grid = (int)std::min<int64_t>(((int64_t)n + nl + threads - 1) / threads, 65536);
+    hipLaunchKernelGGL(pair_count_kernel, dim3(grid), dim3(threads), 0, 0, d.idx, cnt);
+    std::vector<int32_t> h(items + 1, 0);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpy(h.data(), cnt, sizeof(int32_t) * items, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) { (void)hipFree(cnt); return e; }
+    int64_t total = 0;
+    for (int64_t i = 0; i < items; ++i) {
+        const int32_t c = h[i];
+        h[i] = (int32_t)total;
+        total += c;
+        if (total >= INT32_MAX) { (void)hipFree(cnt); return hipSuccess; }   // offsets would not fit: no lists
+    }
+    h[items] = (int32_t)total;
+    const size_t ptr_words = (size_t)(items + 1 + 63) / 64 * 64;
+    e = hipMalloc(&d.pair_buf, sizeof(int32_t) * ptr_words + sizeof(int2) * (size_t)std::max<int64_t>(total, 1));
+    if (e == hipSuccess) e = hipMemcpy(d.pair_buf, h.data(), sizeof(int32_t) * (items + 1), hipMemcpyHostToDevice);
+    (void)hipFree(cnt);
+    if (e != hipSuccess) {
+        if (d.pair_buf) (void)hipFree(d.pair_buf);
+        d.pair_buf = nullptr;
+        return e;
+    }
+    int2* pairs = (int2*)(d.pair_buf + ptr_words);
+    hipLaunchKernelGGL(pair_write_kernel, dim3(grid), dim3(threads), 0, 0, d.idx, d.pair_buf, pairs);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) return e;
+    d.idx.pair_ptr = d.pair_buf;
+    d.idx.pairs = pairs;
+    d.idx.use_pairs = 1;
+    return hipSuccess;
+}
+
 int grid_for(int64_t items, int threads) {
     int64_t g = (items + threads - 1) / threads;
     return (int)std::max<int64_t>(1, std::min<int64_t>(g, 65536));
@@ -860,6 +961,10 @@ hipError_t sparse_upload(const Symbolic& s, SparseDevice& d) {
     ix.pair_ptr = ptr();
     ix.pairs = (const int2*)ptr();
     d.h_lpos_ptr = lpos_ptr;
+    if (!use_pairs) {
+        e = build_pairs_on_device(s, d);
+        if (e != hipSuccess) return e;
+    }
     e = steps_upload(s, r_pos, d);
     if (e != hipSuccess) return e;
     d.ready = true;
@@ -868,6 +973,8 @@ hipError_t sparse_upload(const Symbolic& s, SparseDevice& d) {
 
 void sparse_free(SparseDevice& d) {
     steps_free(d);
+    if (d.pair_buf) (void)hipFree(d.pair_buf);
+    d.pair_buf = nullptr;
     if (d.buf) (void)hipFree(d.buf);
     d.buf = nullptr;
     d.ready = false;
