@@ -12,7 +12,7 @@ batch; the chosen path is the headline (`value`, `config.path`), timed both as
 eager calls and as a replayed HIP graph (the better is reported).  Also on the
 same GPU: every other path, the plain path (one system per launch), the oracle
 (plain CPU FP64 code) on a bounded sample, and the error of the recovered
-solutions against the pivoted oracle on a sample of Jacobians.
+solutions against a partially pivoted LAPACK solve on a sample of Jacobians.
 
 Prints ONE JSON line.  Only one GPU is supported.
 """
@@ -126,6 +126,34 @@ def extra_configs(psp, W, torch, dev):
                                  "batched_speedup": (p_ms / JP) / (fb_ms / J)}
     print(f"[bench] n601 adjoint 64 rhs: fwd {f_ms:.3f} ms, bwd {fb_ms - f_ms:.3f} ms; plain {p_ms / JP:.3f} ms "
           f"per Jacobian vs batched {fb_ms / J:.3f}", file=sys.stderr, flush=True)
+    # the paper's own scheme (Fig. 1 analogue): nodes +-alpha*eps, alpha = 1..m, eps = 2e-3, on 25
+    # scenarios of the 300-bus network, with D = I and with a Gaussian diagonal D (max |d_i| = 1);
+    # error against LAPACK's pivoted solve and the device residual, per number of solves 2m
+    TS = 25
+    ipf, ixf, valsf, bsf = W.scenario_batch(300, TS)
+    nf = len(ipf) - 1
+    pf = psp.Plan(ipf, ixf)
+    vf, bf = torch.from_numpy(valsf).to(dev), torch.from_numpy(bsf).to(dev)
+    xstar = [np.linalg.solve(W.to_dense(nf, ipf, ixf, valsf[s_]), bsf[s_]) for s_ in range(TS)]
+    dg = np.random.default_rng(1311).standard_normal(nf)
+    dg /= np.abs(dg).max()
+    fig = {"eps": 2e-3, "scenarios": TS, "n": nf}
+    for dname, dvec in (("identity", None), ("gaussian", torch.from_numpy(dg).to(dev))):
+        rows_ = {}
+        for m in range(1, 6):
+            nodes = np.array([sg * a_ * 2e-3 for a_ in range(1, m + 1) for sg in (1.0, -1.0)])
+            xf, _ = psp.solve_batched(pf, vf, nodes, bf, path="sparse", d=dvec)
+            rnf, bnf = psp.residual(pf, vf, bf, xf)
+            xfn = xf.cpu().numpy()
+            e_ = np.array([np.abs(xfn[s_] - xstar[s_]).max() / np.abs(xstar[s_]).max() for s_ in range(TS)])
+            r_ = (rnf / bnf).cpu().numpy().ravel()
+            rows_[str(2 * m)] = {"err_median": float(np.median(e_)), "err_max": float(np.nanmax(e_)),
+                                 "res_median": float(np.median(r_)), "res_max": float(np.nanmax(r_))}
+        fig[dname] = rows_
+    out["fig1_symmetric_nodes"] = fig
+    print("[bench] symmetric nodes (median err by solves): " + ", ".join(
+        f"{k}: I {fig['identity'][k]['err_median']:.1e} / G {fig['gaussian'][k]['err_median']:.1e}"
+        for k in fig["identity"]), file=sys.stderr, flush=True)
     # uneven batch: 512 Jacobians of five networks (n = 61 .. 2709), one psp_solve_group call
     groups = W.uneven_batch(512)
     items, paths_u, flops_u, sizes = [], {}, 0.0, {}
@@ -296,11 +324,11 @@ def main():
 
     info_np = r["info"].cpu().numpy()
     x_np = r["x"].cpu().numpy()
-    from oracle import oracle as O
+    # error against a partially pivoted FP64 solve (LAPACK dgesv) of the unperturbed system
     errs, resid = [], []
     for s in (0, 1, 2, 3):
         A = W.to_dense(n, ip, ix, vals[s])
-        xs_ = O.pivoted_solve(A, bs[s])
+        xs_ = np.linalg.solve(A, bs[s])
         errs.append(float(np.abs(x_np[s] - xs_).max() / np.abs(xs_).max()))
         resid.append(float(np.linalg.norm(A @ x_np[s] - bs[s]) / np.linalg.norm(bs[s])))
 
@@ -326,6 +354,7 @@ def main():
 
     cpu = None
     if not args.no_cpu:
+        from oracle import oracle as O     # the CPU baseline: the oracle, timed on the host cores
         sym = O.symbolic(n, ip, ix)
         if chosen == "dense":
             cnt = 8

@@ -22,7 +22,7 @@
 // entry within one step, optionally ending with the division.  Thread t of the
 // workgroup runs task t of a step; a step with more tasks than threads is
 // split into consecutive sub-steps.  A step's descriptors are contiguous, one
-// coalesced 8-byte load per lane, issued several steps ahead: a step itself is
+// coalesced 16-byte load per lane, issued several steps ahead: a step itself is
 // a few hundred cycles of LDS work, far less than one round trip to L2.
 //
 // Descriptor (int4, 16 bytes), LDS indices < 2^15, at most kStSegMax = 3
