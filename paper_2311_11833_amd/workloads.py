@@ -32,6 +32,7 @@ __all__ = [
     "Network", "Jacobian", "branch_count", "make_network", "make_state",
     "jacobian", "rhs", "geometric_eps", "config_eps", "seed_net",
     "seed_state", "seed_rhs", "scenario_batch", "to_dense",
+    "PowerFlowCase", "PowerFlowScenarios", "pf_case", "pf_scenarios",
 ]
 
 
@@ -239,6 +240,111 @@ def uneven_batch(total: int = 512, networks=UNEVEN_NETWORKS, seed: int = 2311):
         if count:
             out.append((N,) + scenario_batch(N, count))
     return out
+
+
+# ---------------------------------------------------------------------------
+# Newton-Raphson power flows (the setting of Sec. IV: a Jacobian solve per
+# Newton step of a distributed-slack AC power flow).
+#
+# Unknowns x = [theta (N) | |V| (N) | lambda] and equations
+#   F = [P(x) - P0 - part*lambda (N) | Q(x) - Q0 on PQ buses, |V| - V_set on
+#        PV buses (N) | theta_0 - theta_ref],
+# with the injection specification spec = [P0 | Q0 or V_set | theta_ref] laid
+# out like x.  A PV (generator) bus holds its voltage magnitude and lets its
+# reactive output float, as in the paper's reduced 531-unknown system of the
+# 300-bus case (69 generator buses: 2*300 - 69 = 531); here the reduction is
+# replaced by a unit row, so the Jacobian keeps the pattern of `jacobian`.
+# Generator buses carry the distributed slack (part > 0 only there).
+
+PV_FRACTION = 69 / 300
+
+
+@dataclass
+class PowerFlowCase:
+    net: Network
+    pv: np.ndarray          # int32 [N]: 1 = voltage-controlled bus (bus 0 always)
+    y_indptr: np.ndarray    # int32 [N+1]: bus admittance matrix, CSR, sorted, diagonal present
+    y_indices: np.ndarray   # int32 [ny]
+    g: np.ndarray           # float64 [ny]: conductance G_ij
+    b: np.ndarray           # float64 [ny]: susceptance B_ij
+    indptr: np.ndarray      # int32 [n+1]: Jacobian pattern (n = 2N+1), that of `jacobian`
+    indices: np.ndarray     # int32 [nnz]
+
+    @property
+    def N(self) -> int:
+        return self.net.N
+
+    @property
+    def n(self) -> int:
+        return 2 * self.net.N + 1
+
+
+@dataclass
+class PowerFlowScenarios:
+    x_target: np.ndarray    # [batch, n]: the state the specification was drawn from (a solution)
+    spec: np.ndarray        # [batch, n]
+    part: np.ndarray        # [batch, N]: slack participation, sums to 1, zero on PQ buses
+    x0: np.ndarray          # [batch, n]: flat start (theta = 0, |V| = 1 or V_set, lambda = 0)
+
+
+def pf_case(N: int, pv_fraction: float = PV_FRACTION, seed: int | None = None) -> PowerFlowCase:
+    net = make_network(N, seed=seed)
+    rng = np.random.default_rng(seed_net(N) + 17 if seed is None else seed + 17)
+    ng = max(1, int(round(pv_fraction * N)))
+    pv = np.zeros(N, dtype=np.int32)
+    pv[0] = 1
+    if ng > 1:
+        pv[rng.choice(np.arange(1, N), ng - 1, replace=False)] = 1
+    yr, yc, yv = _ybus_entries(net)
+    order = np.lexsort((yc, yr))
+    yr, yc, yv = yr[order], yc[order], yv[order]
+    if np.any((yr[1:] == yr[:-1]) & (yc[1:] == yc[:-1])):
+        raise RuntimeError("duplicate admittance entry")
+    y_indptr = np.zeros(N + 1, dtype=np.int64)
+    np.add.at(y_indptr, yr + 1, 1)
+    y_indptr = np.cumsum(y_indptr).astype(np.int32)
+    J = jacobian(net, np.ones(N), np.zeros(N), np.full(N, 1.0 / N))
+    return PowerFlowCase(net, pv, y_indptr, yc.astype(np.int32), yv.real.copy(), yv.imag.copy(),
+                         J.indptr, J.indices)
+
+
+def pf_scenarios(case: PowerFlowCase, batch: int, seed: int = 3110, p_sigma: float = 0.5,
+                 v_spread: float = 0.02) -> PowerFlowScenarios:
+    """Seeded solvable scenarios: scenario s draws balanced active injections
+    p ~ N(0, p_sigma), takes the DC power-flow angles for them as its target
+    angles (bus 0 the reference), |V| ~ U[1 - v_spread, 1 + v_spread],
+    part ~ Dirichlet(1) over the generator buses and lambda ~ U[-1, 1], and
+    specifies the injections that this target implies (so the target is a
+    root of F).  Draws depend only on (seed, s)."""
+    import scipy.sparse as sps
+    import scipy.sparse.linalg as spl
+    net, N, n = case.net, case.N, case.n
+    bl = 1.0 / net.x
+    Bdc = sps.coo_matrix((np.concatenate([bl, bl, -bl, -bl]),
+                          (np.concatenate([net.fbus, net.tbus, net.fbus, net.tbus]),
+                           np.concatenate([net.fbus, net.tbus, net.tbus, net.fbus]))), shape=(N, N)).tocsc()
+    lu = spl.splu(Bdc[1:, 1:].tocsc())
+    Y = sps.csr_matrix((case.g + 1j * case.b, case.y_indices, case.y_indptr), shape=(N, N))
+    pvb = case.pv.astype(bool)
+    xt = np.zeros((batch, n))
+    spec = np.zeros((batch, n))
+    part = np.zeros((batch, N))
+    x0 = np.zeros((batch, n))
+    for s in range(batch):
+        rng = np.random.default_rng((seed, N, s))
+        p = rng.normal(0.0, p_sigma, N)
+        p -= p.mean()
+        th = np.zeros(N)
+        th[1:] = lu.solve(p[1:])
+        vm = rng.uniform(1.0 - v_spread, 1.0 + v_spread, N)
+        part[s, pvb] = rng.dirichlet(np.ones(int(pvb.sum())))
+        lam = rng.uniform(-1.0, 1.0)
+        V = vm * np.exp(1j * th)
+        S = V * np.conj(Y @ V)
+        xt[s] = np.concatenate([th, vm, [lam]])
+        spec[s] = np.concatenate([S.real - part[s] * lam, np.where(pvb, vm, S.imag), [0.0]])
+        x0[s] = np.concatenate([np.zeros(N), np.where(pvb, vm, 1.0), [0.0]])
+    return PowerFlowScenarios(xt, spec, part, x0)
 
 
 def to_dense(n: int, indptr: np.ndarray, indices: np.ndarray, data: np.ndarray) -> np.ndarray:
