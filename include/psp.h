@@ -271,6 +271,69 @@ PSP_API psp_status psp_residual(psp_plan plan, int32_t batch, const double* valu
                                 const double* B, const double* X, double* R, double* rnorm, double* bnorm,
                                 void* stream);
 
+/* ------------------------------------------------------------------------
+ * Newton-Raphson power flow around Alg. 1 (Sec. IV: the method solves the
+ * Jacobian system of every Newton step of a distributed-slack AC power flow).
+ * Network: nbus buses, bus admittance matrix Y = G + jB in CSR form (sorted
+ * columns, diagonal present in every row), and pv[i] != 0 for a
+ * voltage-controlled bus.  Per scenario, with n = 2*nbus + 1:
+ *   x    = [theta (nbus) | |V| (nbus) | lambda]
+ *   spec = [P0 (nbus) | Q0 on PQ buses, V_set on PV buses (nbus) | theta_ref]
+ *   part = slack participation (nbus)
+ *   F(x) = [P_i - P0_i - part_i lambda | Q_i - Q0_i (PQ) or |V_i| - V_set_i (PV)
+ *           | theta_0 - theta_ref],
+ *   P_i = sum_j V_i V_j (G_ij cos t_ij + B_ij sin t_ij),
+ *   Q_i = sum_j V_i V_j (G_ij sin t_ij - B_ij cos t_ij),  t_ij = theta_i - theta_j.
+ * The plan's pattern must be exactly the pattern of dF/dx: for every Y entry
+ * (i, j) the positions (i, j), (i, nbus+j), (nbus+i, j), (nbus+i, nbus+j),
+ * plus (i, 2*nbus) for every bus and (2*nbus, 0); a PV bus's Q row keeps its
+ * positions (values 0 except 1 on its |V| diagonal).
+ * ---------------------------------------------------------------------- */
+typedef struct psp_pf_s* psp_pf;
+
+enum { PSP_PF_CONVERGED = 0, PSP_PF_MAXITER = 1, PSP_PF_BREAKDOWN = 2, PSP_PF_DIVERGED = 3 };
+
+/* Checks the network against the plan's pattern (PSP_E_INVALID on any
+ * mismatch, NULL pointer, malformed Y, missing diagonal or non-finite G/B),
+ * then uploads the network and the map from Y entries to Jacobian positions
+ * to the current device.  All arrays are host, read during the call.  The
+ * plan must outlive the handle; free it with psp_pf_destroy. */
+PSP_API psp_status psp_pf_create(psp_plan plan, int32_t nbus, const int32_t* y_row_ptr, const int32_t* y_col_idx,
+                                 const double* g, const double* b, const int32_t* pv, psp_pf* out);
+PSP_API void psp_pf_destroy(psp_pf pf);
+
+/* One evaluation for `batch` scenarios (device arrays): F (batch x n), the
+ * Jacobian values J (batch x nnz in the plan's CSR order, or NULL) and
+ * fnorm[s] = max_i |F_s,i| (batch, or NULL; NaN if any entry is NaN).
+ * x, spec device batch x n; part device batch x nbus.  Asynchronous. */
+PSP_API psp_status psp_pf_eval(psp_pf pf, int32_t batch, const double* x, const double* spec, const double* part,
+                               double* F, double* J, double* fnorm, void* stream);
+
+/* Device workspace psp_pf_newton needs: psp_workspace_bytes(plan, path,
+ * batch, K, 1, 0) for the solves plus F, J, dx and info. */
+PSP_API size_t psp_pf_workspace_bytes(psp_pf pf, int32_t path, int32_t batch, int32_t K);
+
+/* Newton loop for `batch` scenarios.  Each iteration evaluates F and J; a
+ * scenario whose max|F| <= tol is converged and one whose max|F| is not
+ * finite has diverged; if any scenario is still running and fewer than
+ * max_iter updates were made, Alg. 1 (psp_solve_batched on `path` with the K
+ * nodes eps and D = diag(d), d NULL for D = I) solves J dx = F for the batch
+ * and every running scenario takes x <- x - dx, unless one of its K
+ * factorisations broke down (info != 0), which stops it.
+ *   x       device batch x n, in: start, out: last iterate
+ *   iters   device batch (int32): updates applied
+ *   status  device batch (int32): PSP_PF_* (MAXITER if still above tol)
+ *   fnorm   device batch: max|F| at the last evaluation
+ *   ws      device, psp_pf_workspace_bytes(pf, path, batch, K) bytes
+ * Blocks the calling thread: after each evaluation it copies the status
+ * array to the host and waits for `stream`.  Calls on one handle must not
+ * overlap.  Errors as for psp_solve_batched; PSP_E_INVALID also for
+ * max_iter < 0 or a negative / non-finite tol. */
+PSP_API psp_status psp_pf_newton(psp_pf pf, int32_t path, int32_t batch, int32_t K, const double* eps,
+                                 const double* d, double* x, const double* spec, const double* part, double tol,
+                                 int32_t max_iter, int32_t* iters, int32_t* status, double* fnorm, void* ws,
+                                 size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

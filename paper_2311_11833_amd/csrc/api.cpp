@@ -21,6 +21,7 @@
 #include "sparse.h"
 
 #include "dense.h"
+#include "powerflow.h"
 
 using namespace psp;
 
@@ -542,6 +543,206 @@ psp_status psp_residual(psp_plan p, int32_t batch, const double* values, int32_t
 
 psp_status psp_factors_release(psp_factors f) {
     delete f;
+    return PSP_OK;
+}
+
+}  // extern "C"
+
+struct psp_pf_s {
+    psp_plan plan = nullptr;
+    int32_t N = 0, ny = 0, pos_ref = 0;
+    int device = -1;
+    int32_t *d_yptr = nullptr, *d_ycol = nullptr, *d_pv = nullptr, *d_poslam = nullptr;
+    double *d_g = nullptr, *d_b = nullptr;
+    int4* d_pos = nullptr;
+    int32_t* h_status = nullptr;   // pinned, h_cap entries
+    int32_t h_cap = 0;
+    ~psp_pf_s() {
+        if (device >= 0) {
+            int cur = 0;
+            (void)hipGetDevice(&cur);
+            (void)hipSetDevice(device);
+            (void)hipFree(d_yptr);
+            (void)hipFree(d_ycol);
+            (void)hipFree(d_pv);
+            (void)hipFree(d_poslam);
+            (void)hipFree(d_g);
+            (void)hipFree(d_b);
+            (void)hipFree(d_pos);
+            (void)hipHostFree(h_status);
+            (void)hipSetDevice(cur);
+        }
+    }
+};
+
+namespace {
+
+struct PfLayout {
+    int64_t off_F, off_J, off_dx, off_info, total;
+    size_t solve_bytes;
+};
+
+PfLayout pf_layout(psp_pf pf, int32_t path, int32_t batch, int32_t K) {
+    const Symbolic& s = pf->plan->sym;
+    PfLayout L{};
+    L.solve_bytes = psp_workspace_bytes(pf->plan, path, batch, K, 1, 0);
+    int64_t off = align_up((int64_t)L.solve_bytes, kAlign);
+    L.off_F = off;
+    off = align_up(off + (int64_t)batch * s.n * 8, kAlign);
+    L.off_J = off;
+    off = align_up(off + (int64_t)batch * s.nnz * 8, kAlign);
+    L.off_dx = off;
+    off = align_up(off + (int64_t)batch * s.n * 8, kAlign);
+    L.off_info = off;
+    L.total = align_up(off + (int64_t)batch * K * 4, kAlign);
+    return L;
+}
+
+template <class T>
+psp_status pf_upload(T** dst, const T* src, size_t count) {
+    HIP_TRY(hipMalloc((void**)dst, sizeof(T) * std::max<size_t>(count, 1)), "hipMalloc(power flow)");
+    if (count) HIP_TRY(hipMemcpy(*dst, src, sizeof(T) * count, hipMemcpyHostToDevice), "hipMemcpy(power flow)");
+    return PSP_OK;
+}
+
+PfArgs pf_args(psp_pf pf, int32_t batch, const double* x, const double* spec, const double* part, double* F,
+               double* J, double* fnorm) {
+    PfArgs a{};
+    a.N = pf->N; a.n = 2 * pf->N + 1; a.nnz = pf->plan->sym.nnz; a.batch = batch;
+    a.yptr = pf->d_yptr; a.ycol = pf->d_ycol; a.g = pf->d_g; a.b = pf->d_b; a.pv = pf->d_pv;
+    a.pos = pf->d_pos; a.pos_lam = pf->d_poslam; a.pos_ref = pf->pos_ref;
+    a.x = x; a.spec = spec; a.part = part; a.F = F; a.J = J; a.fnorm = fnorm;
+    return a;
+}
+
+psp_status pf_device_check(psp_pf pf) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    if (dev != pf->device) return fail(PSP_E_STATE, "power-flow handle was created on another device");
+    return PSP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+psp_status psp_pf_create(psp_plan plan, int32_t nbus, const int32_t* yp, const int32_t* yc, const double* g,
+                         const double* b, const int32_t* pv, psp_pf* out) {
+    if (!out) return fail(PSP_E_INVALID, "out must not be NULL");
+    *out = nullptr;
+    if (!plan || nbus < 1 || !yp || !yc || !g || !b || !pv)
+        return fail(PSP_E_INVALID, "psp_pf_create: NULL argument or nbus < 1");
+    const Symbolic& s = plan->sym;
+    if ((int64_t)s.n != 2LL * nbus + 1) return fail(PSP_E_INVALID, "psp_pf_create: plan order must be 2*nbus + 1");
+    const std::string why = validate_csr(nbus, yp, yc);
+    if (!why.empty()) return fail(PSP_E_INVALID, "psp_pf_create: admittance matrix: " + why);
+    const int32_t N = nbus, ny = yp[N];
+    for (int32_t e = 0; e < ny; ++e)
+        if (!std::isfinite(g[e]) || !std::isfinite(b[e]))
+            return fail(PSP_E_INVALID, "psp_pf_create: non-finite admittance");
+    for (int32_t i = 0; i < N; ++i) {
+        bool diag = false;
+        for (int32_t e = yp[i]; e < yp[i + 1]; ++e) diag |= yc[e] == i;
+        if (!diag) return fail(PSP_E_INVALID, "psp_pf_create: admittance row without a diagonal entry");
+    }
+    if ((int64_t)s.nnz != 4LL * ny + N + 1)
+        return fail(PSP_E_INVALID, "psp_pf_create: plan pattern is not the power-flow Jacobian pattern of this network");
+    auto find = [&](int32_t r, int32_t c) -> int32_t {
+        const int32_t* lo = s.col_idx.data() + s.row_ptr[r];
+        const int32_t* hi = s.col_idx.data() + s.row_ptr[r + 1];
+        const int32_t* it = std::lower_bound(lo, hi, c);
+        return (it != hi && *it == c) ? (int32_t)(it - s.col_idx.data()) : -1;
+    };
+    std::vector<int4> pos(std::max(ny, 1));
+    std::vector<int32_t> poslam(N);
+    for (int32_t i = 0; i < N; ++i) {
+        for (int32_t e = yp[i]; e < yp[i + 1]; ++e) {
+            const int32_t j = yc[e];
+            pos[e] = make_int4(find(i, j), find(i, N + j), find(N + i, j), find(N + i, N + j));
+            if (pos[e].x < 0 || pos[e].y < 0 || pos[e].z < 0 || pos[e].w < 0)
+                return fail(PSP_E_INVALID, "psp_pf_create: plan pattern lacks a Jacobian entry of this network");
+        }
+        poslam[i] = find(i, 2 * N);
+        if (poslam[i] < 0) return fail(PSP_E_INVALID, "psp_pf_create: plan pattern lacks the lambda column");
+    }
+    const int32_t pref = find(2 * N, 0);
+    if (pref < 0) return fail(PSP_E_INVALID, "psp_pf_create: plan pattern lacks the angle-reference entry");
+    std::vector<int32_t> pvv(pv, pv + N);
+    if (psp_status st = check_prior_hip()) return st;
+    if (psp_status r = upload_plan(plan, 0)) return r;   // also checks the device
+    auto pf = std::make_unique<psp_pf_s>();
+    pf->plan = plan; pf->N = N; pf->ny = ny; pf->pos_ref = pref;
+    HIP_TRY(hipGetDevice(&pf->device), "hipGetDevice");
+    if (psp_status r = pf_upload(&pf->d_yptr, yp, N + 1)) return r;
+    if (psp_status r = pf_upload(&pf->d_ycol, yc, ny)) return r;
+    if (psp_status r = pf_upload(&pf->d_g, g, ny)) return r;
+    if (psp_status r = pf_upload(&pf->d_b, b, ny)) return r;
+    if (psp_status r = pf_upload(&pf->d_pv, pvv.data(), N)) return r;
+    if (psp_status r = pf_upload(&pf->d_poslam, poslam.data(), N)) return r;
+    if (psp_status r = pf_upload(&pf->d_pos, pos.data(), ny)) return r;
+    *out = pf.release();
+    return PSP_OK;
+}
+
+void psp_pf_destroy(psp_pf pf) { delete pf; }
+
+psp_status psp_pf_eval(psp_pf pf, int32_t batch, const double* x, const double* spec, const double* part, double* F,
+                       double* J, double* fnorm, void* stream) {
+    if (!pf || batch < 1 || !x || !spec || !part || !F) return fail(PSP_E_INVALID, "psp_pf_eval: NULL argument or batch < 1");
+    if (psp_status st = check_prior_hip()) return st;
+    if (psp_status st = pf_device_check(pf)) return st;
+    HIP_TRY(launch_pf_eval(pf_args(pf, batch, x, spec, part, F, J, fnorm), (hipStream_t)stream), "power-flow launch");
+    return PSP_OK;
+}
+
+size_t psp_pf_workspace_bytes(psp_pf pf, int32_t path, int32_t batch, int32_t K) {
+    if (!pf || batch < 1 || K < 1) return 0;
+    return (size_t)pf_layout(pf, path, batch, K).total;
+}
+
+psp_status psp_pf_newton(psp_pf pf, int32_t path, int32_t batch, int32_t K, const double* eps, const double* d,
+                         double* x, const double* spec, const double* part, double tol, int32_t max_iter,
+                         int32_t* iters, int32_t* status, double* fnorm, void* ws, size_t ws_bytes, void* stream) {
+    if (!pf || batch < 1 || !x || !spec || !part || !iters || !status || !fnorm || !ws)
+        return fail(PSP_E_INVALID, "psp_pf_newton: NULL argument or batch < 1");
+    if (max_iter < 0 || !(tol >= 0.0) || !std::isfinite(tol))
+        return fail(PSP_E_INVALID, "psp_pf_newton: max_iter < 0 or tol negative / not finite");
+    EpsSet es;
+    if (psp_status st = make_eps(K, eps, es)) return st;
+    if (psp_status st = check_prior_hip()) return st;
+    if (psp_status st = pf_device_check(pf)) return st;
+    if (split_path(path).base < 0 && path != PSP_PATH_AUTO) return fail(PSP_E_INVALID, "unknown path");
+    const PfLayout L = pf_layout(pf, path, batch, K);
+    if (ws_bytes < (size_t)L.total) return fail(PSP_E_NOMEM, "workspace too small: need " + std::to_string(L.total) + " bytes");
+    if (pf->h_cap < batch) {
+        if (pf->h_status) HIP_TRY(hipHostFree(pf->h_status), "hipHostFree");
+        pf->h_status = nullptr;
+        pf->h_cap = 0;
+        HIP_TRY(hipHostMalloc((void**)&pf->h_status, sizeof(int32_t) * batch), "hipHostMalloc");
+        pf->h_cap = batch;
+    }
+    char* w = (char*)ws;
+    double* F = (double*)(w + L.off_F);
+    double* J = (double*)(w + L.off_J);
+    double* dx = (double*)(w + L.off_dx);
+    int32_t* info = (int32_t*)(w + L.off_info);
+    const hipStream_t st = (hipStream_t)stream;
+    PfArgs a = pf_args(pf, batch, x, spec, part, F, J, fnorm);
+    a.status = status;
+    a.tol = tol;
+    HIP_TRY(launch_pf_status(batch, status, iters, 0, st), "power-flow status launch");
+    for (int32_t it = 0;; ++it) {
+        HIP_TRY(launch_pf_eval(a, st), "power-flow launch");
+        HIP_TRY(hipMemcpyAsync(pf->h_status, status, sizeof(int32_t) * batch, hipMemcpyDeviceToHost, st),
+                "hipMemcpyAsync(status)");
+        HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+        const bool running = std::any_of(pf->h_status, pf->h_status + batch, [](int32_t v) { return v == kPfRunning; });
+        if (!running || it == max_iter) break;
+        if (psp_status r = psp_solve_batched(pf->plan, path, batch, J, K, eps, d, 1, F, dx, info, ws, L.solve_bytes, stream))
+            return r;
+        HIP_TRY(launch_pf_update(batch, 2 * pf->N + 1, K, x, dx, info, status, iters, st), "power-flow update launch");
+    }
+    HIP_TRY(launch_pf_status(batch, status, iters, 1, st), "power-flow status launch");
     return PSP_OK;
 }
 

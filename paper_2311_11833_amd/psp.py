@@ -25,7 +25,9 @@ ORDERS = {"md": 0, "natural": 1}
 EXPORTED = ["psp_last_error", "psp_version", "psp_plan_create", "psp_plan_info", "psp_plan_export",
             "psp_plan_destroy", "psp_weights", "psp_workspace_bytes", "psp_solve_batched", "psp_tune", "psp_factor",
             "psp_solve", "psp_combine", "psp_grad_values", "psp_factors_release", "psp_residual",
-            "psp_group_workspace_bytes", "psp_solve_group"]
+            "psp_group_workspace_bytes", "psp_solve_group", "psp_pf_create", "psp_pf_destroy", "psp_pf_eval",
+            "psp_pf_workspace_bytes", "psp_pf_newton"]
+PF_STATUS = {0: "converged", 1: "max_iter", 2: "breakdown", 3: "diverged"}
 
 
 class PSPError(RuntimeError):
@@ -75,9 +77,16 @@ def lib():
         L.psp_group_workspace_bytes.argtypes = [i32, vp, i32, i32]
         L.psp_group_workspace_bytes.restype = C.c_size_t
         L.psp_solve_group.argtypes = [i32, vp, i32, vp, i32, vp, C.c_size_t, vp]
+        L.psp_pf_create.argtypes = [vp, i32, vp, vp, vp, vp, vp, C.POINTER(vp)]
+        L.psp_pf_destroy.argtypes = [vp]
+        L.psp_pf_destroy.restype = None
+        L.psp_pf_eval.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
+        L.psp_pf_workspace_bytes.argtypes = [vp, i32, i32, i32]
+        L.psp_pf_workspace_bytes.restype = C.c_size_t
+        L.psp_pf_newton.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, vp, d, i32, vp, vp, vp, vp, C.c_size_t, vp]
         for f in EXPORTED:
             if f not in ("psp_last_error", "psp_version", "psp_plan_destroy", "psp_workspace_bytes",
-                         "psp_group_workspace_bytes"):
+                         "psp_group_workspace_bytes", "psp_pf_destroy", "psp_pf_workspace_bytes"):
                 getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -332,3 +341,73 @@ class Factors:
         _check(lib().psp_grad_values(self._h, nrhs, _dptr(Lamk.contiguous()), _dptr(Xk.contiguous()), _dptr(gA),
                                      _stream(stream)))
         return gA
+
+
+class PowerFlow:
+    """Newton-Raphson power flow of one network around Alg. 1 (psp_pf_* in include/psp.h).
+
+    x and spec are (batch, n) float64 device tensors laid out [theta | |V| | lambda] and
+    [P0 | Q0 or V_set | theta_ref]; part is (batch, nbus)."""
+
+    def __init__(self, plan: Plan, y_indptr, y_indices, g, b, pv):
+        yp = np.ascontiguousarray(y_indptr, dtype=np.int32)
+        yc = np.ascontiguousarray(y_indices, dtype=np.int32)
+        gg = np.ascontiguousarray(g, dtype=np.float64)
+        bb = np.ascontiguousarray(b, dtype=np.float64)
+        pvv = np.ascontiguousarray(pv, dtype=np.int32)
+        self.plan = plan
+        self.N = len(yp) - 1
+        if len(pvv) != self.N:
+            raise ValueError("pv must have one entry per bus")
+        h = C.c_void_p()
+        _check(lib().psp_pf_create(plan.handle, self.N, _np_ptr(yp), _np_ptr(yc), _np_ptr(gg), _np_ptr(bb),
+                                   _np_ptr(pvv), C.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.psp_pf_destroy(h)
+            self._h = None
+
+    def _shapes(self, x, spec, part):
+        import torch
+        for t in (x, spec, part):
+            if t.dtype != torch.float64:
+                raise TypeError("x, spec and part must be float64")
+        batch = x.shape[0]
+        if x.shape != (batch, self.plan.n) or spec.shape != x.shape or part.shape != (batch, self.N):
+            raise ValueError("shape mismatch with the network")
+        return batch
+
+    def eval(self, x, spec, part, jacobian: bool = True, stream=None):
+        """Returns (F, J or None, fnorm) for every scenario."""
+        import torch
+        batch = self._shapes(x, spec, part)
+        F = torch.empty_like(x)
+        J = torch.empty((batch, self.plan.nnz), dtype=torch.float64, device=x.device) if jacobian else None
+        fn = torch.empty(batch, dtype=torch.float64, device=x.device)
+        _check(lib().psp_pf_eval(self._h, batch, _dptr(x.contiguous()), _dptr(spec.contiguous()),
+                                 _dptr(part.contiguous()), _dptr(F), _dptr(J), _dptr(fn), _stream(stream)))
+        return F, J, fn
+
+    def workspace_bytes(self, path="auto", batch=1, K=1) -> int:
+        return int(lib().psp_pf_workspace_bytes(self._h, PATHS[path], batch, K))
+
+    def newton(self, x0, spec, part, eps, tol: float = 1e-9, max_iter: int = 10, d=None, path: str = "auto",
+               workspace=None, stream=None):
+        """Returns (x, iters, status, fnorm); status codes in PF_STATUS.  Blocks once per iteration."""
+        import torch
+        batch = self._shapes(x0, spec, part)
+        eps_h = np.ascontiguousarray(eps, dtype=np.float64)
+        K = len(eps_h)
+        x = x0.clone().contiguous()
+        iters = torch.empty(batch, dtype=torch.int32, device=x.device)
+        status = torch.empty(batch, dtype=torch.int32, device=x.device)
+        fn = torch.empty(batch, dtype=torch.float64, device=x.device)
+        need = self.workspace_bytes(path, batch, K)
+        ws = self.plan.workspace(need, x.device) if workspace is None else workspace
+        _check(lib().psp_pf_newton(self._h, PATHS[path], batch, K, _np_ptr(eps_h), _dptr(d), _dptr(x),
+                                   _dptr(spec.contiguous()), _dptr(part.contiguous()), float(tol), int(max_iter),
+                                   _dptr(iters), _dptr(status), _dptr(fn), _dptr(ws), ws.numel(), _stream(stream)))
+        return x, iters, status, fn

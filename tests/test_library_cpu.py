@@ -133,3 +133,43 @@ def test_group_rejects_bad_items_on_the_host(psp):
     arr[1] = psp.GroupItem(plan.handle, 0, 0, None, None, None, None, None)
     assert L.psp_solve_group(2, C.byref(arr), 2, eps.ctypes.data_as(C.c_void_p), 1, dummy, 1 << 30, None) == psp.PSP_E_INVALID
     assert L.psp_solve_group(0, None, 2, eps.ctypes.data_as(C.c_void_p), 1, dummy, 1 << 30, None) == psp.PSP_E_INVALID
+
+
+def test_power_flow_create_rejects_mismatched_networks_on_the_host(psp, W):
+    """psp_pf_create checks the network against the plan's pattern before any device call."""
+    import ctypes as C
+    L = psp.lib()
+    c = W.pf_case(14)
+    plan = psp.Plan(c.indptr, c.indices)
+
+    def create(plan_h, nbus, yp, yc, g, b, pv):
+        h = C.c_void_p()
+        arrs = [np.ascontiguousarray(a) for a in (yp, yc, g, b, pv)]
+        st = L.psp_pf_create(plan_h, nbus, *[a.ctypes.data_as(C.c_void_p) for a in arrs], C.byref(h))
+        return st, L.psp_last_error()
+
+    good = (c.y_indptr, c.y_indices, c.g, c.b, c.pv)
+    assert create(None, 14, *good)[0] == psp.PSP_E_INVALID
+    st, msg = create(plan.handle, 13, *good)
+    assert st == psp.PSP_E_INVALID and b"2*nbus + 1" in msg
+    g = c.g.copy()
+    g[3] = np.nan
+    st, msg = create(plan.handle, 14, c.y_indptr, c.y_indices, g, c.b, c.pv)
+    assert st == psp.PSP_E_INVALID and b"non-finite" in msg
+    # a network with one branch fewer than the plan's pattern
+    c2 = W.pf_case(14)
+    net = c2.net
+    keep = np.arange(len(net.fbus)) != len(net.fbus) - 1
+    net2 = W.Network(14, net.fbus[keep], net.tbus[keep], net.r[keep], net.x[keep])
+    yr, yc, yv = W._ybus_entries(net2)
+    o = np.lexsort((yc, yr))
+    yp = np.concatenate([[0], np.cumsum(np.bincount(yr[o], minlength=14))]).astype(np.int32)
+    st, msg = create(plan.handle, 14, yp, yc[o].astype(np.int32), yv.real[o], yv.imag[o], c.pv)
+    assert st == psp.PSP_E_INVALID and b"pattern" in msg
+    # unsorted admittance row
+    yc_bad = c.y_indices.copy()
+    yc_bad[[0, 1]] = yc_bad[[1, 0]]
+    st, msg = create(plan.handle, 14, c.y_indptr, yc_bad, c.g, c.b, c.pv)
+    assert st == psp.PSP_E_INVALID and b"ascending" in msg
+    assert L.psp_pf_workspace_bytes(None, 0, 1, 1) == 0
+    assert L.psp_pf_eval(None, 1, None, None, None, None, None, None, None) == psp.PSP_E_INVALID
