@@ -172,6 +172,34 @@ def extra_configs(psp, W, torch, dev):
                          "solves_per_s": 512 * len(eps) / (g_ms / 1e3),
                          "sparse_tflops": flops_u / (g_ms / 1e3) / 1e12}
     print(f"[bench] uneven 512: {g_ms:.3f} ms, paths {paths_u}", file=sys.stderr, flush=True)
+    # Newton-Raphson power flows (Sec. IV's setting): 512 scenarios of the 300-bus network with 69
+    # generator buses, flat start, at most 20 iterations, K = 5; one psp_pf_newton call
+    NS = 512
+    case = W.pf_case(300)
+    scn = W.pf_scenarios(case, NS)
+    plan_pf = psp.Plan(case.indptr, case.indices)
+    pfm = psp.PowerFlow(plan_pf, case.y_indptr, case.y_indices, case.g, case.b, case.pv)
+    x0d, spd, ptd = (torch.from_numpy(a).to(dev) for a in (scn.x0, scn.spec, scn.part))
+    pfm.newton(x0d, spd, ptd, eps, max_iter=20)
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        xn, itn, stn, fnn = pfm.newton(x0d, spd, ptd, eps, max_iter=20)
+    torch.cuda.synchronize()
+    nr_ms = (time.perf_counter() - t0) * 1e3 / reps
+    ev_ms, (Fj, Jj, _) = _events(torch, lambda: pfm.eval(x0d, spd, ptd), 20)
+    so_ms, _ = _events(torch, lambda: psp.solve_batched(plan_pf, Jj, eps, Fj), 5)
+    itn, stn = itn.cpu().numpy(), stn.cpu().numpy()
+    at_target = int(np.sum(np.abs(xn.cpu().numpy() - scn.x_target).max(axis=1) <= 1e-8))
+    out["newton_pf_512"] = {"buses": 300, "n": case.n, "generator_buses": int(case.pv.sum()), "scenarios": NS,
+                            "K": len(eps), "tol": 1e-9, "max_iter": 20, "ms_per_call": nr_ms,
+                            "power_flows_per_s": NS / (nr_ms / 1e3),
+                            "iterations_hist": {str(k): int(v) for k, v in enumerate(np.bincount(itn)) if v},
+                            "converged": int(np.sum(stn == 0)), "at_own_target": at_target,
+                            "eval_kernel_ms": ev_ms, "solve_ms": so_ms}
+    print(f"[bench] newton 512 x 300-bus: {nr_ms:.2f} ms ({int(itn.max())} iterations max), eval {ev_ms * 1e3:.1f} us, "
+          f"solve {so_ms:.3f} ms, converged {int(np.sum(stn == 0))}, at target {at_target}", file=sys.stderr, flush=True)
     # 10,000-bus network, n = 20,001, K = 4, 32 RHS
     from paper_2311_11833_amd.workloads import make_network, make_state, jacobian, seed_state
     net = make_network(10000)

@@ -556,6 +556,7 @@ struct psp_pf_s {
     double *d_g = nullptr, *d_b = nullptr;
     int4* d_pos = nullptr;
     int32_t* h_status = nullptr;   // pinned, h_cap entries
+    int32_t* h_idx = nullptr;      // pinned, h_cap entries: running scenarios
     int32_t h_cap = 0;
     ~psp_pf_s() {
         if (device >= 0) {
@@ -570,6 +571,7 @@ struct psp_pf_s {
             (void)hipFree(d_b);
             (void)hipFree(d_pos);
             (void)hipHostFree(h_status);
+            (void)hipHostFree(h_idx);
             (void)hipSetDevice(cur);
         }
     }
@@ -578,7 +580,7 @@ struct psp_pf_s {
 namespace {
 
 struct PfLayout {
-    int64_t off_F, off_J, off_dx, off_info, total;
+    int64_t off_F, off_J, off_dx, off_info, off_idx, total;
     size_t solve_bytes;
 };
 
@@ -594,7 +596,9 @@ PfLayout pf_layout(psp_pf pf, int32_t path, int32_t batch, int32_t K) {
     L.off_dx = off;
     off = align_up(off + (int64_t)batch * s.n * 8, kAlign);
     L.off_info = off;
-    L.total = align_up(off + (int64_t)batch * K * 4, kAlign);
+    off = align_up(off + (int64_t)batch * K * 4, kAlign);
+    L.off_idx = off;
+    L.total = align_up(off + (int64_t)batch * 4, kAlign);
     return L;
 }
 
@@ -716,9 +720,11 @@ psp_status psp_pf_newton(psp_pf pf, int32_t path, int32_t batch, int32_t K, cons
     if (ws_bytes < (size_t)L.total) return fail(PSP_E_NOMEM, "workspace too small: need " + std::to_string(L.total) + " bytes");
     if (pf->h_cap < batch) {
         if (pf->h_status) HIP_TRY(hipHostFree(pf->h_status), "hipHostFree");
-        pf->h_status = nullptr;
+        if (pf->h_idx) HIP_TRY(hipHostFree(pf->h_idx), "hipHostFree");
+        pf->h_status = pf->h_idx = nullptr;
         pf->h_cap = 0;
         HIP_TRY(hipHostMalloc((void**)&pf->h_status, sizeof(int32_t) * batch), "hipHostMalloc");
+        HIP_TRY(hipHostMalloc((void**)&pf->h_idx, sizeof(int32_t) * batch), "hipHostMalloc");
         pf->h_cap = batch;
     }
     char* w = (char*)ws;
@@ -726,21 +732,34 @@ psp_status psp_pf_newton(psp_pf pf, int32_t path, int32_t batch, int32_t K, cons
     double* J = (double*)(w + L.off_J);
     double* dx = (double*)(w + L.off_dx);
     int32_t* info = (int32_t*)(w + L.off_info);
+    int32_t* idx = (int32_t*)(w + L.off_idx);
     const hipStream_t st = (hipStream_t)stream;
-    PfArgs a = pf_args(pf, batch, x, spec, part, F, J, fnorm);
-    a.status = status;
-    a.tol = tol;
     HIP_TRY(launch_pf_status(batch, status, iters, 0, st), "power-flow status launch");
+    // Each iteration works on the scenarios that were running after the previous
+    // evaluation (all at first): evaluate them into rows 0..m-1, and if any is
+    // still running, solve those m systems and update.  A scenario that converges
+    // at this evaluation is solved once more but not updated (its status changed).
+    int32_t m = batch;
+    for (int32_t r = 0; r < batch; ++r) pf->h_idx[r] = r;
     for (int32_t it = 0;; ++it) {
+        HIP_TRY(hipMemcpyAsync(idx, pf->h_idx, sizeof(int32_t) * m, hipMemcpyHostToDevice, st), "hipMemcpyAsync(idx)");
+        PfArgs a = pf_args(pf, m, x, spec, part, F, J, fnorm);
+        a.idx = idx;
+        a.status = status;
+        a.tol = tol;
         HIP_TRY(launch_pf_eval(a, st), "power-flow launch");
         HIP_TRY(hipMemcpyAsync(pf->h_status, status, sizeof(int32_t) * batch, hipMemcpyDeviceToHost, st),
                 "hipMemcpyAsync(status)");
         HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
         const bool running = std::any_of(pf->h_status, pf->h_status + batch, [](int32_t v) { return v == kPfRunning; });
         if (!running || it == max_iter) break;
-        if (psp_status r = psp_solve_batched(pf->plan, path, batch, J, K, eps, d, 1, F, dx, info, ws, L.solve_bytes, stream))
+        if (psp_status r = psp_solve_batched(pf->plan, path, m, J, K, eps, d, 1, F, dx, info, ws, L.solve_bytes, stream))
             return r;
-        HIP_TRY(launch_pf_update(batch, 2 * pf->N + 1, K, x, dx, info, status, iters, st), "power-flow update launch");
+        HIP_TRY(launch_pf_update(m, 2 * pf->N + 1, K, idx, x, dx, info, status, iters, st), "power-flow update launch");
+        // the idx copy above has completed (the stream was synchronised), so the list can be rebuilt
+        m = 0;
+        for (int32_t r = 0; r < batch; ++r)
+            if (pf->h_status[r] == kPfRunning) pf->h_idx[m++] = r;
     }
     HIP_TRY(launch_pf_status(batch, status, iters, 1, st), "power-flow status launch");
     return PSP_OK;

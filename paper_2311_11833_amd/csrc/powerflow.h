@@ -19,19 +19,21 @@ struct PfArgs {
     const int4* pos;          // ny: Jacobian CSR positions of (dP/dtheta_j, dP/dV_j, dQ/dtheta_j, dQ/dV_j)
     const int32_t* pos_lam;   // N: position of dP_i/dlambda
     int32_t pos_ref;          // position of the angle-reference entry
-    const double* x;          // batch x n: [theta | |V| | lambda]
-    const double* spec;       // batch x n: [P0 | Q0 or V_set | theta_ref]
-    const double* part;       // batch x N
-    double* F;                // batch x n
-    double* J;                // batch x nnz, or NULL
-    double* fnorm;            // batch, or NULL: max |F| (NaN if any entry is NaN)
-    int32_t* status;          // batch, or NULL: running -> converged / diverged
+    const int32_t* idx;       // batch: scenario of block r, or NULL (block r is scenario r)
+    const double* x;          // scenarios x n: [theta | |V| | lambda]
+    const double* spec;       // scenarios x n: [P0 | Q0 or V_set | theta_ref]
+    const double* part;       // scenarios x N
+    double* F;                // batch x n, row r for block r
+    double* J;                // batch x nnz, row r for block r, or NULL
+    double* fnorm;            // per scenario, or NULL: max |F| (NaN if any entry is NaN)
+    int32_t* status;          // per scenario, or NULL: running -> converged / diverged
     double tol;
 };
 
 hipError_t launch_pf_eval(const PfArgs& a, hipStream_t st);
 hipError_t launch_pf_status(int32_t batch, int32_t* status, int32_t* iters, int32_t finish, hipStream_t st);
-hipError_t launch_pf_update(int32_t batch, int32_t n, int32_t K, double* x, const double* dx, const int32_t* info,
-                            int32_t* status, int32_t* iters, hipStream_t st);
+// block r updates scenario idx[r] (idx NULL: scenario r) from dx row r and info row r
+hipError_t launch_pf_update(int32_t batch, int32_t n, int32_t K, const int32_t* idx, double* x, const double* dx,
+                            const int32_t* info, int32_t* status, int32_t* iters, hipStream_t st);
 
 }  // namespace psp

@@ -16,6 +16,10 @@
 //
 // pf_update: x <- x - dx for scenarios still running whose K perturbed
 // factorisations all succeeded; a nonzero info marks a breakdown instead.
+//
+// Inside the Newton loop both kernels take a list of the scenarios still
+// running (block r works on scenario idx[r] and on row r of F, J, dx and
+// info), so evaluations and solves shrink with the set of running scenarios.
 #include "powerflow.h"
 
 namespace psp {
@@ -28,13 +32,14 @@ __device__ __forceinline__ double nanmax(double m, double a) { return (a != a ||
 
 __global__ __launch_bounds__(kPfThreads) void pf_eval_kernel(PfArgs a) {
     __shared__ double red[kPfThreads];
-    const int s = blockIdx.x;
+    const int r = blockIdx.x;
+    const int s = a.idx ? a.idx[r] : r;
     const int N = a.N;
     const double* xs = a.x + (int64_t)s * a.n;
     const double* sp = a.spec + (int64_t)s * a.n;
     const double* pt = a.part + (int64_t)s * N;
-    double* F = a.F + (int64_t)s * a.n;
-    double* J = a.J ? a.J + (int64_t)s * a.nnz : nullptr;
+    double* F = a.F + (int64_t)r * a.n;
+    double* J = a.J ? a.J + (int64_t)r * a.nnz : nullptr;
     double m = 0.0;
     for (int i = threadIdx.x; i < N; i += kPfThreads) {
         const double ti = xs[i], vi = xs[N + i];
@@ -111,15 +116,17 @@ __global__ void pf_status_kernel(int32_t batch, int32_t* status, int32_t* iters,
     }
 }
 
-__global__ __launch_bounds__(kPfThreads) void pf_update_kernel(int32_t n, int32_t K, double* x, const double* dx,
-                                                              const int32_t* info, int32_t* status, int32_t* iters) {
-    const int s = blockIdx.x;
+__global__ __launch_bounds__(kPfThreads) void pf_update_kernel(int32_t n, int32_t K, const int32_t* idx, double* x,
+                                                              const double* dx, const int32_t* info, int32_t* status,
+                                                              int32_t* iters) {
+    const int r = blockIdx.x;
+    const int s = idx ? idx[r] : r;
     __shared__ int go;
     if (threadIdx.x == 0) {
         int g = status[s] == kPfRunning ? 1 : 0;
         if (g)
             for (int k = 0; k < K; ++k)
-                if (info[(int64_t)s * K + k] != 0) g = 2;
+                if (info[(int64_t)r * K + k] != 0) g = 2;
         if (g == 2) status[s] = kPfBreakdown;
         if (g == 1) iters[s] += 1;
         go = g;
@@ -127,7 +134,7 @@ __global__ __launch_bounds__(kPfThreads) void pf_update_kernel(int32_t n, int32_
     __syncthreads();
     if (go != 1) return;
     double* xs = x + (int64_t)s * n;
-    const double* d = dx + (int64_t)s * n;
+    const double* d = dx + (int64_t)r * n;
     for (int i = threadIdx.x; i < n; i += kPfThreads) xs[i] = xs[i] - d[i];
 }
 }  // namespace
@@ -142,9 +149,9 @@ hipError_t launch_pf_status(int32_t batch, int32_t* status, int32_t* iters, int3
     return hipGetLastError();
 }
 
-hipError_t launch_pf_update(int32_t batch, int32_t n, int32_t K, double* x, const double* dx, const int32_t* info,
-                            int32_t* status, int32_t* iters, hipStream_t st) {
-    hipLaunchKernelGGL(pf_update_kernel, dim3(batch), dim3(kPfThreads), 0, st, n, K, x, dx, info, status, iters);
+hipError_t launch_pf_update(int32_t batch, int32_t n, int32_t K, const int32_t* idx, double* x, const double* dx,
+                            const int32_t* info, int32_t* status, int32_t* iters, hipStream_t st) {
+    hipLaunchKernelGGL(pf_update_kernel, dim3(batch), dim3(kPfThreads), 0, st, n, K, idx, x, dx, info, status, iters);
     return hipGetLastError();
 }
 
