@@ -78,153 +78,163 @@ def _events(torch, fn, reps):
     return e0.elapsed_time(e1) / reps, out
 
 
-def extra_configs(psp, W, torch, dev):
-    """The adjoint with 64 right-hand sides at n=601, and the 20,001-unknown system
-    with 32 right-hand sides (forward and adjoint), timed with HIP events."""
-    from paper_2311_11833_amd.autograd import perturbed_solve
+def extra_configs(psp, W, torch, dev, only=None):
+    """Secondary configurations, timed with HIP events: the adjoint with 64 right-hand
+    sides at n=601, the paper's symmetric node scheme, an uneven batch, the Newton
+    power-flow loop and the 20,001-unknown system.  `only`: names to run (all if None)."""
     out = {}
-    # 64 Jacobians of the 300-bus network, K=5, 64 RHS: forward and backward of the autograd op
-    J, R = 64, 64
-    ip, ix, vals, _ = W.scenario_batch(300, J)
-    n = len(ip) - 1
     eps = W.config_eps("n601")
-    plan = psp.Plan(ip, ix)
     rng = np.random.default_rng(4)
-    v = torch.from_numpy(vals).to(dev).requires_grad_(True)
-    B = torch.from_numpy(rng.standard_normal((J, n, R))).to(dev).requires_grad_(True)
-    G = torch.from_numpy(rng.standard_normal((J, n, R))).to(dev)
 
-    def fwd():
-        return perturbed_solve(v, B, plan, eps, path="sparse")
+    def want(name):
+        return only is None or name in only
 
-    def fwd_bwd():
-        x = perturbed_solve(v, B, plan, eps, path="sparse")
-        return torch.autograd.grad(x, (v, B), G)
+    if want("n601_adjoint_64rhs"):
+        from paper_2311_11833_amd.autograd import perturbed_solve
+        # 64 Jacobians of the 300-bus network, K=5, 64 RHS: forward and backward of the autograd op
+        J, R = 64, 64
+        ip, ix, vals, _ = W.scenario_batch(300, J)
+        n = len(ip) - 1
+        plan = psp.Plan(ip, ix)
+        v = torch.from_numpy(vals).to(dev).requires_grad_(True)
+        B = torch.from_numpy(rng.standard_normal((J, n, R))).to(dev).requires_grad_(True)
+        G = torch.from_numpy(rng.standard_normal((J, n, R))).to(dev)
 
-    fwd_bwd()
-    torch.cuda.synchronize()
-    f_ms, _ = _events(torch, fwd, 3)
-    fb_ms, _ = _events(torch, fwd_bwd, 3)
-    # the same per Jacobian, one Jacobian per call (the plain path), on the first 8
-    JP = 8
+        def fwd():
+            return perturbed_solve(v, B, plan, eps, path="sparse")
 
-    def plain_fwd_bwd():
-        for s_ in range(JP):
-            vs = v[s_:s_ + 1].detach().requires_grad_(True)
-            Bs = B[s_:s_ + 1].detach().requires_grad_(True)
-            xs = perturbed_solve(vs, Bs, plan, eps, path="sparse")
-            torch.autograd.grad(xs, (vs, Bs), G[s_:s_ + 1])
+        def fwd_bwd():
+            x = perturbed_solve(v, B, plan, eps, path="sparse")
+            return torch.autograd.grad(x, (v, B), G)
 
-    plain_fwd_bwd()
-    torch.cuda.synchronize()
-    p_ms, _ = _events(torch, plain_fwd_bwd, 2)
-    out["n601_adjoint_64rhs"] = {"jacobians": J, "K": len(eps), "nrhs": R, "path": "sparse (split steps)",
-                                 "forward_ms": f_ms, "backward_ms": fb_ms - f_ms,
-                                 "forward_rhs_solves_per_s": J * len(eps) * R / (f_ms / 1e3),
-                                 "plain_fwd_bwd_ms_per_jacobian": p_ms / JP,
-                                 "batched_fwd_bwd_ms_per_jacobian": fb_ms / J,
-                                 "batched_speedup": (p_ms / JP) / (fb_ms / J)}
-    print(f"[bench] n601 adjoint 64 rhs: fwd {f_ms:.3f} ms, bwd {fb_ms - f_ms:.3f} ms; plain {p_ms / JP:.3f} ms "
-          f"per Jacobian vs batched {fb_ms / J:.3f}", file=sys.stderr, flush=True)
-    # the paper's own scheme (Fig. 1 analogue): nodes +-alpha*eps, alpha = 1..m, eps = 2e-3, on 25
-    # scenarios of the 300-bus network, with D = I and with a Gaussian diagonal D (max |d_i| = 1);
-    # error against LAPACK's pivoted solve and the device residual, per number of solves 2m
-    TS = 25
-    ipf, ixf, valsf, bsf = W.scenario_batch(300, TS)
-    nf = len(ipf) - 1
-    pf = psp.Plan(ipf, ixf)
-    vf, bf = torch.from_numpy(valsf).to(dev), torch.from_numpy(bsf).to(dev)
-    xstar = [np.linalg.solve(W.to_dense(nf, ipf, ixf, valsf[s_]), bsf[s_]) for s_ in range(TS)]
-    dg = np.random.default_rng(1311).standard_normal(nf)
-    dg /= np.abs(dg).max()
-    fig = {"eps": 2e-3, "scenarios": TS, "n": nf}
-    for dname, dvec in (("identity", None), ("gaussian", torch.from_numpy(dg).to(dev))):
-        rows_ = {}
-        for m in range(1, 6):
-            nodes = np.array([sg * a_ * 2e-3 for a_ in range(1, m + 1) for sg in (1.0, -1.0)])
-            xf, _ = psp.solve_batched(pf, vf, nodes, bf, path="sparse", d=dvec)
-            rnf, bnf = psp.residual(pf, vf, bf, xf)
-            xfn = xf.cpu().numpy()
-            e_ = np.array([np.abs(xfn[s_] - xstar[s_]).max() / np.abs(xstar[s_]).max() for s_ in range(TS)])
-            r_ = (rnf / bnf).cpu().numpy().ravel()
-            rows_[str(2 * m)] = {"err_median": float(np.median(e_)), "err_max": float(np.nanmax(e_)),
-                                 "res_median": float(np.median(r_)), "res_max": float(np.nanmax(r_))}
-        fig[dname] = rows_
-    out["fig1_symmetric_nodes"] = fig
-    print("[bench] symmetric nodes (median err by solves): " + ", ".join(
-        f"{k}: I {fig['identity'][k]['err_median']:.1e} / G {fig['gaussian'][k]['err_median']:.1e}"
-        for k in fig["identity"]), file=sys.stderr, flush=True)
-    # uneven batch: 512 Jacobians of five networks (n = 61 .. 2709), one psp_solve_group call
-    groups = W.uneven_batch(512)
-    items, paths_u, flops_u, sizes = [], {}, 0.0, {}
-    for N, ipu, ixu, valsu, bsu in groups:
-        pu = psp.Plan(ipu, ixu)
-        vu, bu = torch.from_numpy(valsu).to(dev), torch.from_numpy(bsu).to(dev)
-        ch, _ = psp.tune(pu, vu, eps, bu)
-        paths_u[len(ipu) - 1] = ch
-        sizes[len(ipu) - 1] = int(valsu.shape[0])
-        flops_u += valsu.shape[0] * len(eps) * sparse_flops(pu.info(), len(ipu) - 1)
-        items.append((pu, vu, bu))
-    psp.solve_group(items, eps)
-    torch.cuda.synchronize()
-    g_ms, _ = _events(torch, lambda: psp.solve_group(items, eps), 3)
-    out["uneven_512"] = {"jacobians_by_n": sizes, "K": len(eps), "path_by_n": paths_u, "ms_per_call": g_ms,
-                         "solves_per_s": 512 * len(eps) / (g_ms / 1e3),
-                         "sparse_tflops": flops_u / (g_ms / 1e3) / 1e12}
-    print(f"[bench] uneven 512: {g_ms:.3f} ms, paths {paths_u}", file=sys.stderr, flush=True)
-    # Newton-Raphson power flows (Sec. IV's setting): 512 scenarios of the 300-bus network with 69
-    # generator buses, flat start, at most 20 iterations, K = 5; one psp_pf_newton call
-    NS = 512
-    case = W.pf_case(300)
-    scn = W.pf_scenarios(case, NS)
-    plan_pf = psp.Plan(case.indptr, case.indices)
-    pfm = psp.PowerFlow(plan_pf, case.y_indptr, case.y_indices, case.g, case.b, case.pv)
-    x0d, spd, ptd = (torch.from_numpy(a).to(dev) for a in (scn.x0, scn.spec, scn.part))
-    pfm.newton(x0d, spd, ptd, eps, max_iter=20)
-    torch.cuda.synchronize()
-    reps = 3
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        xn, itn, stn, fnn = pfm.newton(x0d, spd, ptd, eps, max_iter=20)
-    torch.cuda.synchronize()
-    nr_ms = (time.perf_counter() - t0) * 1e3 / reps
-    ev_ms, (Fj, Jj, _) = _events(torch, lambda: pfm.eval(x0d, spd, ptd), 20)
-    so_ms, _ = _events(torch, lambda: psp.solve_batched(plan_pf, Jj, eps, Fj), 5)
-    itn, stn = itn.cpu().numpy(), stn.cpu().numpy()
-    at_target = int(np.sum(np.abs(xn.cpu().numpy() - scn.x_target).max(axis=1) <= 1e-8))
-    out["newton_pf_512"] = {"buses": 300, "n": case.n, "generator_buses": int(case.pv.sum()), "scenarios": NS,
-                            "K": len(eps), "tol": 1e-9, "max_iter": 20, "ms_per_call": nr_ms,
-                            "power_flows_per_s": NS / (nr_ms / 1e3),
-                            "iterations_hist": {str(k): int(v) for k, v in enumerate(np.bincount(itn)) if v},
-                            "converged": int(np.sum(stn == 0)), "at_own_target": at_target,
-                            "eval_kernel_ms": ev_ms, "solve_ms": so_ms}
-    print(f"[bench] newton 512 x 300-bus: {nr_ms:.2f} ms ({int(itn.max())} iterations max), eval {ev_ms * 1e3:.1f} us, "
-          f"solve {so_ms:.3f} ms, converged {int(np.sum(stn == 0))}, at target {at_target}", file=sys.stderr, flush=True)
-    # 10,000-bus network, n = 20,001, K = 4, 32 RHS
-    from paper_2311_11833_amd.workloads import make_network, make_state, jacobian, seed_state
-    net = make_network(10000)
-    vm, va, p = make_state(10000, seed_state(10000, 0))
-    Jc = jacobian(net, vm, va, p)
-    eps4 = W.large_eps()
-    plan4 = psp.Plan(Jc.indptr, Jc.indices)
-    v4 = torch.from_numpy(Jc.data[None]).to(dev)
-    B4 = torch.from_numpy(rng.standard_normal((1, Jc.n, 32))).to(dev)
-    F = psp.Factors(plan4, v4, eps4, path="sparse", nrhs_cap=32)
-    torch.cuda.synchronize()
-    fac_ms, F = _events(torch, lambda: psp.Factors(plan4, v4, eps4, path="sparse", nrhs_cap=32), 2)
-    sol_ms, Xk = _events(torch, lambda: F.solve(B4), 3)
-    tr_ms, Lk = _events(torch, lambda: F.solve(B4, transpose=True), 3)
-    gr_ms, _ = _events(torch, lambda: F.grad_values(Lk, Xk), 3)
-    X = F.combine(Xk)
-    rn, bn = psp.residual(plan4, v4, B4, X, keep_r=True)[:2]
-    info = plan4.info()
-    out["n20001_32rhs"] = {"n": Jc.n, "nnz": int(info.nnz), "nnz_l": int(info.nnz_l), "K": len(eps4), "nrhs": 32,
-                           "eps": [float(e) for e in eps4], "factor_ms": fac_ms, "solve_ms": sol_ms,
-                           "transposed_solve_ms": tr_ms, "grad_values_ms": gr_ms,
-                           "factor_tflops": len(eps4) * info.flops_sparse_factor / (fac_ms / 1e3) / 1e12,
-                           "residual_rel_max": float((rn / bn).max())}
-    print(f"[bench] n20001: factor {fac_ms:.2f} ms, solve {sol_ms:.2f} ms, trans {tr_ms:.2f} ms, grad {gr_ms:.2f} ms",
-          file=sys.stderr, flush=True)
+        fwd_bwd()
+        torch.cuda.synchronize()
+        f_ms, _ = _events(torch, fwd, 3)
+        fb_ms, _ = _events(torch, fwd_bwd, 3)
+        # the same per Jacobian, one Jacobian per call (the plain path), on the first 8
+        JP = 8
+
+        def plain_fwd_bwd():
+            for s_ in range(JP):
+                vs = v[s_:s_ + 1].detach().requires_grad_(True)
+                Bs = B[s_:s_ + 1].detach().requires_grad_(True)
+                xs = perturbed_solve(vs, Bs, plan, eps, path="sparse")
+                torch.autograd.grad(xs, (vs, Bs), G[s_:s_ + 1])
+
+        plain_fwd_bwd()
+        torch.cuda.synchronize()
+        p_ms, _ = _events(torch, plain_fwd_bwd, 2)
+        out["n601_adjoint_64rhs"] = {"jacobians": J, "K": len(eps), "nrhs": R, "path": "sparse (split steps)",
+                                     "forward_ms": f_ms, "backward_ms": fb_ms - f_ms,
+                                     "forward_rhs_solves_per_s": J * len(eps) * R / (f_ms / 1e3),
+                                     "plain_fwd_bwd_ms_per_jacobian": p_ms / JP,
+                                     "batched_fwd_bwd_ms_per_jacobian": fb_ms / J,
+                                     "batched_speedup": (p_ms / JP) / (fb_ms / J)}
+        print(f"[bench] n601 adjoint 64 rhs: fwd {f_ms:.3f} ms, bwd {fb_ms - f_ms:.3f} ms; plain {p_ms / JP:.3f} ms "
+              f"per Jacobian vs batched {fb_ms / J:.3f}", file=sys.stderr, flush=True)
+    if want("fig1_symmetric_nodes"):
+        # the paper's own scheme (Fig. 1 analogue): nodes +-alpha*eps, alpha = 1..m, eps = 2e-3, on 25
+        # scenarios of the 300-bus network, with D = I and with a Gaussian diagonal D (max |d_i| = 1);
+        # error against LAPACK's pivoted solve and the device residual, per number of solves 2m
+        TS = 25
+        ipf, ixf, valsf, bsf = W.scenario_batch(300, TS)
+        nf = len(ipf) - 1
+        pf = psp.Plan(ipf, ixf)
+        vf, bf = torch.from_numpy(valsf).to(dev), torch.from_numpy(bsf).to(dev)
+        xstar = [np.linalg.solve(W.to_dense(nf, ipf, ixf, valsf[s_]), bsf[s_]) for s_ in range(TS)]
+        dg = np.random.default_rng(1311).standard_normal(nf)
+        dg /= np.abs(dg).max()
+        fig = {"eps": 2e-3, "scenarios": TS, "n": nf}
+        for dname, dvec in (("identity", None), ("gaussian", torch.from_numpy(dg).to(dev))):
+            rows_ = {}
+            for m in range(1, 6):
+                nodes = np.array([sg * a_ * 2e-3 for a_ in range(1, m + 1) for sg in (1.0, -1.0)])
+                xf, _ = psp.solve_batched(pf, vf, nodes, bf, path="sparse", d=dvec)
+                rnf, bnf = psp.residual(pf, vf, bf, xf)
+                xfn = xf.cpu().numpy()
+                e_ = np.array([np.abs(xfn[s_] - xstar[s_]).max() / np.abs(xstar[s_]).max() for s_ in range(TS)])
+                r_ = (rnf / bnf).cpu().numpy().ravel()
+                rows_[str(2 * m)] = {"err_median": float(np.median(e_)), "err_max": float(np.nanmax(e_)),
+                                     "res_median": float(np.median(r_)), "res_max": float(np.nanmax(r_))}
+            fig[dname] = rows_
+        out["fig1_symmetric_nodes"] = fig
+        print("[bench] symmetric nodes (median err by solves): " + ", ".join(
+            f"{k}: I {fig['identity'][k]['err_median']:.1e} / G {fig['gaussian'][k]['err_median']:.1e}"
+            for k in fig["identity"]), file=sys.stderr, flush=True)
+    if want("uneven_512"):
+        # uneven batch: 512 Jacobians of five networks (n = 61 .. 2709), one psp_solve_group call
+        groups = W.uneven_batch(512)
+        items, paths_u, flops_u, sizes = [], {}, 0.0, {}
+        for N, ipu, ixu, valsu, bsu in groups:
+            pu = psp.Plan(ipu, ixu)
+            vu, bu = torch.from_numpy(valsu).to(dev), torch.from_numpy(bsu).to(dev)
+            ch, _ = psp.tune(pu, vu, eps, bu)
+            paths_u[len(ipu) - 1] = ch
+            sizes[len(ipu) - 1] = int(valsu.shape[0])
+            flops_u += valsu.shape[0] * len(eps) * sparse_flops(pu.info(), len(ipu) - 1)
+            items.append((pu, vu, bu))
+        psp.solve_group(items, eps)
+        torch.cuda.synchronize()
+        g_ms, _ = _events(torch, lambda: psp.solve_group(items, eps), 3)
+        out["uneven_512"] = {"jacobians_by_n": sizes, "K": len(eps), "path_by_n": paths_u, "ms_per_call": g_ms,
+                             "solves_per_s": 512 * len(eps) / (g_ms / 1e3),
+                             "sparse_tflops": flops_u / (g_ms / 1e3) / 1e12}
+        print(f"[bench] uneven 512: {g_ms:.3f} ms, paths {paths_u}", file=sys.stderr, flush=True)
+    if want("newton_pf_512"):
+        # Newton-Raphson power flows (Sec. IV's setting): 512 scenarios of the 300-bus network with 69
+        # generator buses, flat start, at most 20 iterations, K = 5; one psp_pf_newton call
+        NS = 512
+        case = W.pf_case(300)
+        scn = W.pf_scenarios(case, NS)
+        plan_pf = psp.Plan(case.indptr, case.indices)
+        pfm = psp.PowerFlow(plan_pf, case.y_indptr, case.y_indices, case.g, case.b, case.pv)
+        x0d, spd, ptd = (torch.from_numpy(a).to(dev) for a in (scn.x0, scn.spec, scn.part))
+        pfm.newton(x0d, spd, ptd, eps, max_iter=20)
+        torch.cuda.synchronize()
+        reps = 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            xn, itn, stn, fnn = pfm.newton(x0d, spd, ptd, eps, max_iter=20)
+        torch.cuda.synchronize()
+        nr_ms = (time.perf_counter() - t0) * 1e3 / reps
+        ev_ms, (Fj, Jj, _) = _events(torch, lambda: pfm.eval(x0d, spd, ptd), 20)
+        so_ms, _ = _events(torch, lambda: psp.solve_batched(plan_pf, Jj, eps, Fj), 5)
+        itn, stn = itn.cpu().numpy(), stn.cpu().numpy()
+        at_target = int(np.sum(np.abs(xn.cpu().numpy() - scn.x_target).max(axis=1) <= 1e-8))
+        out["newton_pf_512"] = {"buses": 300, "n": case.n, "generator_buses": int(case.pv.sum()), "scenarios": NS,
+                                "K": len(eps), "tol": 1e-9, "max_iter": 20, "ms_per_call": nr_ms,
+                                "power_flows_per_s": NS / (nr_ms / 1e3),
+                                "iterations_hist": {str(k): int(v) for k, v in enumerate(np.bincount(itn)) if v},
+                                "converged": int(np.sum(stn == 0)), "at_own_target": at_target,
+                                "eval_kernel_ms": ev_ms, "solve_ms": so_ms}
+        print(f"[bench] newton 512 x 300-bus: {nr_ms:.2f} ms ({int(itn.max())} iterations max), eval {ev_ms * 1e3:.1f} us, "
+              f"solve {so_ms:.3f} ms, converged {int(np.sum(stn == 0))}, at target {at_target}", file=sys.stderr, flush=True)
+    if want("n20001_32rhs"):
+        # 10,000-bus network, n = 20,001, K = 4, 32 RHS
+        from paper_2311_11833_amd.workloads import make_network, make_state, jacobian, seed_state
+        net = make_network(10000)
+        vm, va, p = make_state(10000, seed_state(10000, 0))
+        Jc = jacobian(net, vm, va, p)
+        eps4 = W.large_eps()
+        plan4 = psp.Plan(Jc.indptr, Jc.indices)
+        v4 = torch.from_numpy(Jc.data[None]).to(dev)
+        B4 = torch.from_numpy(rng.standard_normal((1, Jc.n, 32))).to(dev)
+        F = psp.Factors(plan4, v4, eps4, path="sparse", nrhs_cap=32)
+        torch.cuda.synchronize()
+        fac_ms, F = _events(torch, lambda: psp.Factors(plan4, v4, eps4, path="sparse", nrhs_cap=32), 2)
+        sol_ms, Xk = _events(torch, lambda: F.solve(B4), 3)
+        tr_ms, Lk = _events(torch, lambda: F.solve(B4, transpose=True), 3)
+        gr_ms, _ = _events(torch, lambda: F.grad_values(Lk, Xk), 3)
+        X = F.combine(Xk)
+        rn, bn = psp.residual(plan4, v4, B4, X, keep_r=True)[:2]
+        info = plan4.info()
+        out["n20001_32rhs"] = {"n": Jc.n, "nnz": int(info.nnz), "nnz_l": int(info.nnz_l), "K": len(eps4), "nrhs": 32,
+                               "eps": [float(e) for e in eps4], "factor_ms": fac_ms, "solve_ms": sol_ms,
+                               "transposed_solve_ms": tr_ms, "grad_values_ms": gr_ms,
+                               "factor_tflops": len(eps4) * info.flops_sparse_factor / (fac_ms / 1e3) / 1e12,
+                               "residual_rel_max": float((rn / bn).max())}
+        print(f"[bench] n20001: factor {fac_ms:.2f} ms, solve {sol_ms:.2f} ms, trans {tr_ms:.2f} ms, grad {gr_ms:.2f} ms",
+              file=sys.stderr, flush=True)
     return out
 
 
@@ -243,7 +253,11 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with three 256 MiB device copies (the reference kernel for HBM counters)")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the 64-RHS adjoint and the 20,001-unknown timings")
+                    help="skip the secondary configurations (adjoint, node schemes, uneven batch, Newton loop, "
+                         "20,001 unknowns, adaptive eps)")
+    ap.add_argument("--extras", default=None,
+                    help="comma-separated secondary configurations to run (n601_adjoint_64rhs, "
+                         "fig1_symmetric_nodes, uneven_512, newton_pf_512, n20001_32rhs, adaptive_eps); default all")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only (this build has no multi-GPU path); run with --gpus 1", file=sys.stderr)
@@ -378,8 +392,9 @@ def main():
         plain = {"solves_per_s": J * K / (pms / 1e3), "systems": J * K, "ms": pms, "path": chosen,
                  "batched_speedup": value / (J * K / (pms / 1e3))}
 
-    extra = None if args.no_extra else extra_configs(psp, W, torch, dev)
-    if extra is not None:
+    only = None if args.extras is None else set(args.extras.split(","))
+    extra = None if args.no_extra else extra_configs(psp, W, torch, dev, only)
+    if extra is not None and (only is None or "adaptive_eps" in only):
         # per-Jacobian perturbation size (the adaptive layer) on the same 512 scenarios, against
         # LAPACK's pivoted solve of every unperturbed system
         from paper_2311_11833_amd.adaptive import estimate_rho, solve_adaptive

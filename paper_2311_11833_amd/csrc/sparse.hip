@@ -1001,9 +1001,10 @@ hipError_t sparse_solve_batched(const Symbolic& s, const SparseDevice& d, int32_
     a.Xk = (double*)(w + L.off_xk);
     int var = variant_of(s, ntasks, nrhs, forced);
     if (var < 0) return hipErrorInvalidValue;
-    if (forced < 0 && var == kVarBatched && nrhs == 1 && steps_ready(d)) {
-        // the step schedule beats the per-level launches whenever it exists; its
-        // Xk (when not fused) fits in the interleaved layout reserved above
+    if (forced < 0 && (var == kVarBatched || var == kVarLds) && nrhs == 1 && steps_ready(d)) {
+        // the step schedule beats the per-level launches and the level-scheduled LDS
+        // kernel whenever it exists; its Xk (when not fused) fits in the interleaved
+        // layout or the LDS variant's Xk reserved above
         var = kVarSteps;
         a.Xk = (double*)w;
     }
