@@ -272,6 +272,27 @@ PSP_API psp_status psp_residual(psp_plan plan, int32_t batch, const double* valu
                                 void* stream);
 
 /* ------------------------------------------------------------------------
+ * psp_estimate_rho -- rho(A_s^{-1} D) for every Jacobian s of a batch, the
+ * radius that decides convergence of the expansion behind the method
+ * (|eps_k| rho < 1, Sec. II-B) and the size of its truncation error (about
+ * prod_k |eps_k| rho^K); used to choose the perturbation size per Jacobian.
+ * Power iteration with M = (A_s + probe D)^{-1} D, one pivot-free factorisation
+ * per Jacobian (psp_factor, sparse path, K = 1):
+ *     v = v0 / ||v0||;  repeat iters times: x = M v, g = ||x||_2, v = x / g;
+ *     rho = exp(mean of log g over the last iters - iters/2 steps).
+ *   values  device batch x nnz;  d device n (NULL: D = I);  probe nonzero, small
+ *   v0      device batch x n start vectors (the caller draws them)
+ *   rho     device batch output (NaN if a factorisation broke down or x = 0)
+ *   ws      device, psp_estimate_rho_workspace_bytes(plan, batch) bytes
+ * Asynchronous on `stream`.  PSP_E_INVALID for NULL pointers, batch < 1 or
+ * iters outside 1..100000; PSP_E_EPS for a zero or non-finite probe.
+ * ---------------------------------------------------------------------- */
+PSP_API size_t psp_estimate_rho_workspace_bytes(psp_plan plan, int32_t batch);
+PSP_API psp_status psp_estimate_rho(psp_plan plan, int32_t batch, const double* values, const double* d, double probe,
+                                    int32_t iters, const double* v0, double* rho, void* ws, size_t ws_bytes,
+                                    void* stream);
+
+/* ------------------------------------------------------------------------
  * Newton-Raphson power flow around Alg. 1 (Sec. IV: the method solves the
  * Jacobian system of every Newton step of a distributed-slack AC power flow).
  * Network: nbus buses, bus admittance matrix Y = G + jB in CSR form (sorted

@@ -58,6 +58,8 @@ def lib():
         L.oracle_combine.restype = None
         L.oracle_residual.argtypes = [C.c_int, _ip, _ip, _dp, C.c_int, _dp, _dp, C.c_void_p, _dp, C.c_void_p]
         L.oracle_residual.restype = None
+        L.oracle_norm2.argtypes = [C.c_int, _dp]
+        L.oracle_norm2.restype = C.c_double
         L.oracle_lu_partial.argtypes = [C.c_int, _dp, C.c_int, _ip]
         L.oracle_lu_partial_solve.argtypes = [C.c_int, _dp, C.c_int, _ip, _dp]
         L.oracle_lu_partial_solve.restype = None
@@ -156,6 +158,12 @@ def residual(n, indptr, indices, values, b, x):
     bn = np.zeros(nrhs)
     lib().oracle_residual(n, _i32(indptr), _i32(indices), _f64(values), nrhs, b, x, _ptr(r), rn, _ptr(bn))
     return r, rn, bn
+
+
+def norm2(x) -> float:
+    """sqrt of the fma sum of squares in ascending order."""
+    x = _f64(np.ravel(x))
+    return float(lib().oracle_norm2(len(x), x))
 
 
 def pivoted_solve(A: np.ndarray, b: np.ndarray) -> np.ndarray:
@@ -311,6 +319,42 @@ def grad_values(n, indptr, indices, c, xk, lamk):
 
 
 # ---------------------------------------------------------------- diagnostics
+def power_rho(A: np.ndarray, d, probe: float, v0: np.ndarray, iters: int) -> float:
+    """The power iteration for rho(A^{-1} D) as the library defines it: M = (A + probe D)^{-1} D,
+    v = v0/||v0||, then iters times x = M v (pivoted solve), g = ||x||_2, v = x/g;
+    rho = exp(mean log g over the last iters - iters//2 steps)."""
+    n = A.shape[0]
+    dd = np.ones(n) if d is None else np.asarray(d, dtype=np.float64)
+    Ap = A + probe * np.diag(dd)
+    v = np.asarray(v0, dtype=np.float64) / np.linalg.norm(v0)
+    logs = []
+    for _ in range(iters):
+        x = pivoted_solve(Ap, dd * v)
+        g = np.linalg.norm(x)
+        logs.append(np.log(g))
+        v = x / g
+    return float(np.exp(np.mean(logs[iters // 2:])))
+
+
+def power_rho_pivot_free(n, indptr, indices, values, sym: Symbolic, d, probe: float, v0, iters: int) -> float:
+    """power_rho with the method's own solve: each x = (A + probe D)^{-1} D v comes from the
+    pivot-free perturbed sparse factorisation (sparse_system, one node), and every norm is
+    norm2.  With a tiny probe the pivot-free solve is only as accurate as its element growth
+    allows, so this differs from power_rho by more than rounding; it is the sequence the
+    library runs."""
+    dd = None if d is None else np.asarray(d, dtype=np.float64)
+    v = _f64(v0) / norm2(v0)
+    logs = []
+    for _ in range(iters):
+        x, info = sparse_system(n, indptr, indices, values, sym, probe, v if dd is None else dd * v, d=dd)
+        if info != 0:
+            return float("nan")
+        g = norm2(x)
+        logs.append(np.log(g))
+        v = x / g
+    return float(np.exp(np.mean(logs[iters // 2:])))
+
+
 def spectral_radius_AinvD(A: np.ndarray, d=None, iters: int = 200, seed: int = 0) -> float:
     """rho(A^{-1} D), the Neumann radius of Sec. II-B, from the growth rate of
     ||(A^{-1} D)^k v|| (pivoted solves).  The mean log growth over the second

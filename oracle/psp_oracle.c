@@ -164,6 +164,14 @@ EXPORT void oracle_residual(int n, const int* rowptr, const int* colidx, const d
     }
 }
 
+/* 2-norm as the square root of the fma sum of squares in ascending order
+ * (the norm used by the error test and the rho power iteration). */
+EXPORT double oracle_norm2(int n, const double* x) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s = fma(x[i], x[i], s);
+    return sqrt(s);
+}
+
 /* ------------------------------------------------------------------ */
 /* Ground truth: LU with partial pivoting (largest |a_ik| in the column, */
 /* ties to the smallest row index), then the two substitutions.          */

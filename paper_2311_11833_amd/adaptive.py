@@ -8,9 +8,9 @@ This module estimates rho for every Jacobian of a batch with a few power
 iterations on a slightly perturbed factorisation, picks
     eps_0 = 10^-(ceil(log10 rho) + 2),   eps_k = eps_0 ratio^k,
 so that eps_0 rho <= 0.01, and solves each group of Jacobians that share an
-eps_0 with one batched call.  Every factorisation and solve runs in the
-library's kernels; only the vector scaling and norms of the power iteration
-are torch operations on the device.
+eps_0 with one batched call.  The power iteration and every factorisation
+and solve run in the library's kernels; this module draws the start vectors
+and groups the Jacobians by eps_0 on the host.
 """
 from __future__ import annotations
 
@@ -24,24 +24,15 @@ from . import psp
 def estimate_rho(plan: psp.Plan, values, d=None, probe: float = 1e-8, iters: int = 24, seed: int = 0):
     """rho(A_s^{-1} D) for every Jacobian s of `values` (batch, nnz), as a float64 numpy array.
 
-    Power iteration with M = (A + probe D)^{-1} D (the same factors for every iteration);
-    the estimate is the mean growth factor over the second half of the iterations, which
-    is robust when the dominant eigenvalues are a complex pair."""
+    Power iteration with M = (A + probe D)^{-1} D on the library's factors
+    (psp_estimate_rho); the estimate is the mean growth factor over the second
+    half of the iterations, which is robust when the dominant eigenvalues are a
+    complex pair.  The start vectors are standard normal draws from `seed`."""
     import torch
     batch, n = values.shape[0], plan.n
-    F = psp.Factors(plan, values, np.array([probe]), path="sparse", d=d, nrhs_cap=1)
     gen = torch.Generator(device="cpu").manual_seed(seed)
-    v = torch.randn((batch, n, 1), generator=gen, dtype=torch.float64).to(values.device)
-    v = v / torch.linalg.vector_norm(v, dim=1, keepdim=True)
-    dcol = None if d is None else d.reshape(1, n, 1)
-    logs = []
-    for _ in range(iters):
-        w = F.solve(v if dcol is None else v * dcol)[:, 0]          # (batch, n, 1)
-        g = torch.linalg.vector_norm(w, dim=1, keepdim=True)
-        logs.append(torch.log(g).reshape(batch))
-        v = w / g
-    tail = torch.stack(logs[iters // 2:]).mean(dim=0)
-    return torch.exp(tail).cpu().numpy()
+    v0 = torch.randn((batch, n), generator=gen, dtype=torch.float64).to(values.device)
+    return psp.estimate_rho(plan, values, v0, d=d, probe=probe, iters=iters).cpu().numpy()
 
 
 def choose_eps0(rho, offset: int = 2):

@@ -22,6 +22,7 @@
 
 #include "dense.h"
 #include "powerflow.h"
+#include "estimate.h"
 
 using namespace psp;
 
@@ -543,6 +544,73 @@ psp_status psp_residual(psp_plan p, int32_t batch, const double* values, int32_t
 
 psp_status psp_factors_release(psp_factors f) {
     delete f;
+    return PSP_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+struct RhoLayout {
+    int64_t fac_bytes, off_B, off_X, off_v, off_acc, off_info, total;
+};
+
+RhoLayout rho_layout(psp_plan p, int32_t batch) {
+    const int64_t n = p->sym.n;
+    RhoLayout L{};
+    L.fac_bytes = (int64_t)psp_workspace_bytes(p, PSP_PATH_SPARSE, batch, 1, 1, 1);
+    int64_t off = align_up(L.fac_bytes, kAlign);
+    L.off_B = off;
+    off = align_up(off + (int64_t)batch * n * 8, kAlign);
+    L.off_X = off;
+    off = align_up(off + (int64_t)batch * n * 8, kAlign);
+    L.off_v = off;
+    off = align_up(off + (int64_t)batch * n * 8, kAlign);
+    L.off_acc = off;
+    off = align_up(off + (int64_t)batch * 8, kAlign);
+    L.off_info = off;
+    L.total = align_up(off + (int64_t)batch * 4, kAlign);
+    return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t psp_estimate_rho_workspace_bytes(psp_plan p, int32_t batch) {
+    if (!p || batch < 1) return 0;
+    return (size_t)rho_layout(p, batch).total;
+}
+
+psp_status psp_estimate_rho(psp_plan p, int32_t batch, const double* values, const double* d, double probe,
+                            int32_t iters, const double* v0, double* rho, void* ws, size_t ws_bytes, void* stream) {
+    if (!p || batch < 1 || !values || !v0 || !rho || !ws)
+        return fail(PSP_E_INVALID, "psp_estimate_rho: NULL argument or batch < 1");
+    if (iters < 1 || iters > 100000) return fail(PSP_E_INVALID, "psp_estimate_rho: iters must be in 1..100000");
+    const RhoLayout L = rho_layout(p, batch);
+    if (ws_bytes < (size_t)L.total) return fail(PSP_E_NOMEM, "workspace too small: need " + std::to_string(L.total) + " bytes");
+    char* w = (char*)ws;
+    psp_factors f = nullptr;
+    if (psp_status st = psp_factor(p, PSP_PATH_SPARSE, batch, values, 1, &probe, d, (int32_t*)(w + L.off_info), ws,
+                                   (size_t)L.fac_bytes, stream, &f))
+        return st;
+    std::unique_ptr<psp_factors_s> hold(f);
+    const hipStream_t st = (hipStream_t)stream;
+    RhoArgs a{};
+    a.n = p->sym.n; a.batch = batch; a.d = d;
+    a.v = (double*)(w + L.off_v); a.B = (double*)(w + L.off_B); a.acc = (double*)(w + L.off_acc); a.rho = rho;
+    const int32_t half = iters / 2;
+    a.inv_count = 1.0 / (double)(iters - half);
+    a.mode = 0;
+    a.src = v0;
+    HIP_TRY(launch_rho_step(a, st), "rho launch");
+    double* X = (double*)(w + L.off_X);
+    for (int32_t it = 0; it < iters; ++it) {
+        if (psp_status r = psp_solve(f, 1, a.B, X, 0, stream)) return r;
+        a.src = X;
+        a.mode = it < half ? 1 : (it == iters - 1 ? 3 : 2);
+        HIP_TRY(launch_rho_step(a, st), "rho launch");
+    }
     return PSP_OK;
 }
 

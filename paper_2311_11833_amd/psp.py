@@ -26,7 +26,7 @@ EXPORTED = ["psp_last_error", "psp_version", "psp_plan_create", "psp_plan_info",
             "psp_plan_destroy", "psp_weights", "psp_workspace_bytes", "psp_solve_batched", "psp_tune", "psp_factor",
             "psp_solve", "psp_combine", "psp_grad_values", "psp_factors_release", "psp_residual",
             "psp_group_workspace_bytes", "psp_solve_group", "psp_pf_create", "psp_pf_destroy", "psp_pf_eval",
-            "psp_pf_workspace_bytes", "psp_pf_newton"]
+            "psp_pf_workspace_bytes", "psp_pf_newton", "psp_estimate_rho_workspace_bytes", "psp_estimate_rho"]
 PF_STATUS = {0: "converged", 1: "max_iter", 2: "breakdown", 3: "diverged"}
 
 
@@ -84,9 +84,13 @@ def lib():
         L.psp_pf_workspace_bytes.argtypes = [vp, i32, i32, i32]
         L.psp_pf_workspace_bytes.restype = C.c_size_t
         L.psp_pf_newton.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, vp, d, i32, vp, vp, vp, vp, C.c_size_t, vp]
+        L.psp_estimate_rho_workspace_bytes.argtypes = [vp, i32]
+        L.psp_estimate_rho_workspace_bytes.restype = C.c_size_t
+        L.psp_estimate_rho.argtypes = [vp, i32, vp, vp, d, i32, vp, vp, vp, C.c_size_t, vp]
         for f in EXPORTED:
             if f not in ("psp_last_error", "psp_version", "psp_plan_destroy", "psp_workspace_bytes",
-                         "psp_group_workspace_bytes", "psp_pf_destroy", "psp_pf_workspace_bytes"):
+                         "psp_group_workspace_bytes", "psp_pf_destroy", "psp_pf_workspace_bytes",
+                         "psp_estimate_rho_workspace_bytes"):
                 getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -341,6 +345,23 @@ class Factors:
         _check(lib().psp_grad_values(self._h, nrhs, _dptr(Lamk.contiguous()), _dptr(Xk.contiguous()), _dptr(gA),
                                      _stream(stream)))
         return gA
+
+
+def estimate_rho(plan: Plan, values, v0, d=None, probe: float = 1e-8, iters: int = 24, stream=None):
+    """rho(A_s^{-1} D) per Jacobian by power iteration on (A_s + probe D)^{-1} D (psp_estimate_rho).
+    values (batch, nnz), v0 (batch, n) start vectors, float64 device tensors; returns (batch,)."""
+    import torch
+    batch = values.shape[0]
+    if values.dtype != torch.float64 or v0.dtype != torch.float64:
+        raise TypeError("values and v0 must be float64")
+    if values.shape[1] != plan.nnz or tuple(v0.shape) != (batch, plan.n):
+        raise ValueError("shape mismatch with the plan")
+    rho = torch.empty(batch, dtype=torch.float64, device=values.device)
+    need = int(lib().psp_estimate_rho_workspace_bytes(plan.handle, batch))
+    ws = plan.workspace(need, values.device)
+    _check(lib().psp_estimate_rho(plan.handle, batch, _dptr(values.contiguous()), _dptr(d), float(probe), int(iters),
+                                  _dptr(v0.contiguous()), _dptr(rho), _dptr(ws), ws.numel(), _stream(stream)))
+    return rho
 
 
 class PowerFlow:

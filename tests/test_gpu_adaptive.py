@@ -39,6 +39,38 @@ def test_rho_estimate_matches_eigenvalues(dev, W, batch):
         assert 0.5 < rho[s] / ref < 2.0, (HARD[s], rho[s], ref)
 
 
+@pytest.mark.parametrize("gaussian_d", [False, True])
+def test_rho_iteration_matches_oracle(dev, O, W, batch, gaussian_d):
+    """psp_estimate_rho runs the oracle's pivot-free power iteration: the same start
+    vectors, the same perturbed solves (bitwise), the same ascending fma norms and IEEE
+    divisions, so every iterate is identical and only log/exp may differ in the last bits."""
+    from paper_2311_11833_amd import psp
+    ip, ix, vals, bs = batch
+    n = len(ip) - 1
+    plan = psp.Plan(ip, ix)
+    d = None
+    if gaussian_d:
+        d = np.random.default_rng(1311).standard_normal(n)
+        d /= np.abs(d).max()
+    v0 = np.random.default_rng(9).standard_normal((len(HARD), n))
+    sym = O.symbolic(n, ip, ix)
+    print(f"[gpu adaptive] rho iteration vs oracle, gaussian d {gaussian_d}", flush=True)
+    for probe, iters in ((1e-8, 24), (1e-6, 7)):
+        rho = psp.estimate_rho(plan, torch.from_numpy(vals).to(dev), torch.from_numpy(v0).to(dev),
+                               d=None if d is None else torch.from_numpy(d).to(dev), probe=probe,
+                               iters=iters).cpu().numpy()
+        for s in range(len(HARD)):
+            ref = O.power_rho_pivot_free(n, ip, ix, vals[s], sym, d, probe, v0[s], iters)
+            assert abs(rho[s] - ref) <= 1e-13 * ref, (HARD[s], probe, rho[s], ref)
+    one = psp.estimate_rho(plan, torch.from_numpy(vals[:1]).to(dev), torch.from_numpy(v0[:1]).to(dev), iters=1)
+    ref = O.power_rho_pivot_free(n, ip, ix, vals[0], sym, None, 1e-8, v0[0], 1)
+    assert abs(float(one[0]) - ref) <= 1e-13 * ref
+    with pytest.raises(psp.PSPError):
+        psp.estimate_rho(plan, torch.from_numpy(vals).to(dev), torch.from_numpy(v0).to(dev), probe=0.0)
+    with pytest.raises(psp.PSPError):
+        psp.estimate_rho(plan, torch.from_numpy(vals).to(dev), torch.from_numpy(v0).to(dev), iters=0)
+
+
 def test_adaptive_solve_recovers_hard_scenarios(dev, O, W, batch):
     from paper_2311_11833_amd import psp
     from paper_2311_11833_amd.adaptive import solve_adaptive

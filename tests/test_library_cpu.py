@@ -173,3 +173,19 @@ def test_power_flow_create_rejects_mismatched_networks_on_the_host(psp, W):
     assert st == psp.PSP_E_INVALID and b"ascending" in msg
     assert L.psp_pf_workspace_bytes(None, 0, 1, 1) == 0
     assert L.psp_pf_eval(None, 1, None, None, None, None, None, None, None) == psp.PSP_E_INVALID
+
+
+def test_estimate_rho_argument_errors_before_any_device_call(psp):
+    import ctypes as C
+    L = psp.lib()
+    ip = np.array([0, 1, 2], np.int32)
+    ix = np.array([0, 1], np.int32)
+    plan = psp.Plan(ip, ix)
+    dummy = C.c_void_p(16)
+    assert L.psp_estimate_rho_workspace_bytes(None, 1) == 0
+    assert L.psp_estimate_rho_workspace_bytes(plan.handle, 0) == 0
+    assert L.psp_estimate_rho_workspace_bytes(plan.handle, 4) > 0
+    assert L.psp_estimate_rho(None, 1, dummy, None, 1e-8, 4, dummy, dummy, dummy, 1 << 30, None) == psp.PSP_E_INVALID
+    assert L.psp_estimate_rho(plan.handle, 1, dummy, None, 1e-8, 0, dummy, dummy, dummy, 1 << 30, None) == psp.PSP_E_INVALID
+    st = L.psp_estimate_rho(plan.handle, 1, dummy, None, 1e-8, 4, dummy, dummy, dummy, 16, None)
+    assert st == psp.PSP_E_NOMEM
