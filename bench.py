@@ -402,17 +402,21 @@ def main():
         def rel_errs(xx):
             return np.abs(xx - xstar).max(axis=1) / np.abs(xstar).max(axis=1)
         e_fixed = rel_errs(x_np)
+        rho = estimate_rho(plan, vals_d)                      # untimed: first use loads torch's indexing
+        solve_adaptive(plan, vals_d, b_d, K=K, rho=rho)       # kernels, which takes tens of ms once
         torch.cuda.synchronize()
         a0 = time.perf_counter()
         rho = estimate_rho(plan, vals_d)
+        a1 = time.perf_counter()
         xa, ia, eps0 = solve_adaptive(plan, vals_d, b_d, K=K, rho=rho)
         torch.cuda.synchronize()
-        a_ms = (time.perf_counter() - a0) * 1e3
+        a2 = time.perf_counter()
+        a_ms = (a2 - a0) * 1e3
         e_ad = rel_errs(xa.cpu().numpy())
         rna, bna = psp.residual(plan, vals_d, b_d, xa)
         extra["adaptive_eps"] = {
             "rule": "eps_0 = 10^-(ceil(log10 rho) + 2), ratio 1/2, K = 5; rho from 24 power iterations",
-            "ms_per_call_incl_estimate": a_ms, "eps0_values": sorted(float(e) for e in set(eps0)),
+            "ms_per_call_incl_estimate": a_ms, "estimate_ms": (a1 - a0) * 1e3, "grouped_solves_ms": (a2 - a1) * 1e3, "eps0_values": sorted(float(e) for e in set(eps0)),
             "fixed_nodes": {"err_above_1e-9": int(np.sum(e_fixed > 1e-9)), "err_max": float(e_fixed.max()),
                             "err_median": float(np.median(e_fixed))},
             "adaptive": {"err_above_1e-9": int(np.sum(e_ad > 1e-9)), "err_max": float(e_ad.max()),

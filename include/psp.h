@@ -276,8 +276,9 @@ PSP_API psp_status psp_residual(psp_plan plan, int32_t batch, const double* valu
  * radius that decides convergence of the expansion behind the method
  * (|eps_k| rho < 1, Sec. II-B) and the size of its truncation error (about
  * prod_k |eps_k| rho^K); used to choose the perturbation size per Jacobian.
- * Power iteration with M = (A_s + probe D)^{-1} D, one pivot-free factorisation
- * per Jacobian (psp_factor, sparse path, K = 1):
+ * Power iteration with M = (A_s + probe D)^{-1} D, pivot-free (K = 1, sparse
+ * path: a fused factor-and-solve per step when the step schedule fits, else one
+ * kept factorisation and psp_solve per step; the same bits either way):
  *     v = v0 / ||v0||;  repeat iters times: x = M v, g = ||x||_2, v = x / g;
  *     rho = exp(mean of log g over the last iters - iters/2 steps).
  *   values  device batch x nnz;  d device n (NULL: D = I);  probe nonzero, small

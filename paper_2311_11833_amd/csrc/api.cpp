@@ -552,13 +552,18 @@ psp_status psp_factors_release(psp_factors f) {
 namespace {
 
 struct RhoLayout {
+    bool refactor;   // factor and solve afresh each step (step kernel) instead of keeping the factors
     int64_t fac_bytes, off_B, off_X, off_v, off_acc, off_info, total;
 };
 
 RhoLayout rho_layout(psp_plan p, int32_t batch) {
     const int64_t n = p->sym.n;
     RhoLayout L{};
-    L.fac_bytes = (int64_t)psp_workspace_bytes(p, PSP_PATH_SPARSE, batch, 1, 1, 1);
+    // When the step schedule fits, one fused factor-and-solve per step (~0.25 ms for 512
+    // Jacobians at n = 601) is far cheaper than a solve with kept factors on the per-level
+    // path (~6 ms); both give the same bits.
+    L.refactor = steps_fit(p->sym, 1);
+    L.fac_bytes = (int64_t)psp_workspace_bytes(p, PSP_PATH_SPARSE, batch, 1, 1, L.refactor ? 0 : 1);
     int64_t off = align_up(L.fac_bytes, kAlign);
     L.off_B = off;
     off = align_up(off + (int64_t)batch * n * 8, kAlign);
@@ -590,10 +595,15 @@ psp_status psp_estimate_rho(psp_plan p, int32_t batch, const double* values, con
     const RhoLayout L = rho_layout(p, batch);
     if (ws_bytes < (size_t)L.total) return fail(PSP_E_NOMEM, "workspace too small: need " + std::to_string(L.total) + " bytes");
     char* w = (char*)ws;
+    int32_t* info = (int32_t*)(w + L.off_info);
     psp_factors f = nullptr;
-    if (psp_status st = psp_factor(p, PSP_PATH_SPARSE, batch, values, 1, &probe, d, (int32_t*)(w + L.off_info), ws,
-                                   (size_t)L.fac_bytes, stream, &f))
-        return st;
+    if (!L.refactor) {
+        if (psp_status st = psp_factor(p, PSP_PATH_SPARSE, batch, values, 1, &probe, d, info, ws, (size_t)L.fac_bytes,
+                                       stream, &f))
+            return st;
+    } else if (!(probe != 0.0) || !std::isfinite(probe)) {
+        return fail(PSP_E_EPS, "psp_estimate_rho: probe must be nonzero and finite");
+    }
     std::unique_ptr<psp_factors_s> hold(f);
     const hipStream_t st = (hipStream_t)stream;
     RhoArgs a{};
@@ -606,7 +616,13 @@ psp_status psp_estimate_rho(psp_plan p, int32_t batch, const double* values, con
     HIP_TRY(launch_rho_step(a, st), "rho launch");
     double* X = (double*)(w + L.off_X);
     for (int32_t it = 0; it < iters; ++it) {
-        if (psp_status r = psp_solve(f, 1, a.B, X, 0, stream)) return r;
+        if (L.refactor) {
+            if (psp_status r = psp_solve_batched(p, PSP_PATH_SPARSE, batch, values, 1, &probe, d, 1, a.B, X, info, ws,
+                                                 (size_t)L.fac_bytes, stream))
+                return r;
+        } else if (psp_status r = psp_solve(f, 1, a.B, X, 0, stream)) {
+            return r;
+        }
         a.src = X;
         a.mode = it < half ? 1 : (it == iters - 1 ? 3 : 2);
         HIP_TRY(launch_rho_step(a, st), "rho launch");

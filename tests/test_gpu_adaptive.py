@@ -88,3 +88,19 @@ def test_adaptive_solve_recovers_hard_scenarios(dev, O, W, batch):
         assert np.abs(xg[s] - xs).max() / np.abs(xs).max() < 1e-7, (HARD[s], eps0[s])
         xo, io, _, _ = O.sparse_batch(n, ip, ix, vals[s:s + 1], sym, eps0[s] * 0.5 ** np.arange(5), bs[s:s + 1])
         assert np.array_equal(xg[s:s + 1], xo) and np.array_equal(ig[s:s + 1], io)
+
+
+def test_rho_iteration_kept_factors_branch(dev, O, W):
+    """A pattern too large for the step schedule (1354 buses, n = 2709) keeps one factorisation
+    and solves with it each step; the iteration still equals the oracle's."""
+    from paper_2311_11833_amd import psp
+    ip, ix, vals, _ = W.scenario_batch(1354, 2)
+    n = len(ip) - 1
+    plan = psp.Plan(ip, ix)
+    sym = O.symbolic(n, ip, ix)
+    v0 = np.random.default_rng(10).standard_normal((2, n))
+    print("[gpu adaptive] rho iteration, n = 2709", flush=True)
+    rho = psp.estimate_rho(plan, torch.from_numpy(vals).to(dev), torch.from_numpy(v0).to(dev), iters=12).cpu().numpy()
+    for s in range(2):
+        ref = O.power_rho_pivot_free(n, ip, ix, vals[s], sym, None, 1e-8, v0[s], 12)
+        assert abs(rho[s] - ref) <= 1e-13 * ref, (s, rho[s], ref)
