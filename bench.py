@@ -440,9 +440,9 @@ def main():
             t = time.perf_counter()
             xo, io, _, thr = O.sparse_batch(n, ip, ix, vals[:cnt], sym, eps, bs[:cnt])
         dt = time.perf_counter() - t
-        # repeat the same pass until the sample holds about args.cpu_seconds of work (at most 200 passes)
+        # repeat the same pass until the sample holds about args.cpu_seconds of work (at most 1000 passes)
         passes = 1
-        while dt < args.cpu_seconds and passes < 200:
+        while dt < args.cpu_seconds and passes < 1000:
             if chosen == "dense":
                 O.dense_batch(n, ip, ix, vals[:cnt], eps, bs[:cnt], perm=sym.perm)
             else:
