@@ -43,8 +43,12 @@ struct SpIdx {
 // per step as rows x active threads, row r of thread t at base + r*tact + t.
 struct StepIdx {
     int32_t nsteps = 0, threads = 0, ndesc = 0;
+    int32_t packed = 0;               // L and U values share LDS slots (see steps.hip)
+    int32_t pool = 0;                 // LDS doubles holding the L and U values (2 nnzL when not packed)
     const int4* meta = nullptr;       // per step: slot base, active threads, rows, 0
     const int4* desc = nullptr;       // task descriptors, 16 bytes each (see steps.hip)
+    const int32_t* slot_l = nullptr;  // nnzl: LDS index that L position t is gathered into, or -1
+    const int32_t* slot_u = nullptr;  // nnzl: the same for U
 };
 
 struct SparseDevice {

@@ -25,10 +25,11 @@
 // coalesced 16-byte load per lane, issued several steps ahead: a step itself is
 // a few hundred cycles of LDS work, far less than one round trip to L2.
 //
-// Descriptor (int4, 16 bytes), LDS indices < 2^15, at most kStSegMax = 3
+// Descriptor (int4, 16 bytes), LDS indices < 2^15 - 1, at most kStSegMax = 3
 // updates per task:
 //   x = dst | cnt << 15 | div << 17   (cnt 0..3; div = 0x7FFF: no division)
-//   y, z, w = update pairs a | b << 16, in chain order (unused: 0)
+//   y, z, w = update pairs a | b << 16, in chain order (unused: 0); in a packed
+//             schedule bit 15 of y marks a task that starts from 0, not v[dst]
 // An empty slot has x = -1.  Update of a pair: v[dst] = fma(-v[a], v[b], v[dst]).
 //
 // Device side: LDS holds [u_jj (n) | L values (nnzL) | U values (nnzL) |
@@ -36,6 +37,18 @@
 // runs its K perturbed systems one after the other and accumulates
 // sum_k c_k x_k in the order of the reference combine (ascending k, fma chain
 // from 0).
+//
+// Packed schedules, for patterns whose L and U values do not fit in LDS side by
+// side (n = 1,001 here).  An L or U value needs LDS only from its gather (an
+// entry of A, or a value never written, which reads as 0) or its first write,
+// to its last read; a fill value's first task can start from zero instead of
+// reading its slot.  The values are packed into a pool of shared slots by these
+// live intervals in executed steps (greedy by start time, which uses exactly as
+// many slots as values are live at the busiest step: 16,095 instead of 21,728
+// at n = 1,001), and a slot is reused only in a step after its previous value's
+// last read, so no step reads a slot that a task of the step writes.  The
+// layout becomes [u_jj | pool | y | combine accumulator].  Patterns that fit
+// unpacked keep the plain layout (packing cost ~6 % at n = 601).
 #include <algorithm>
 #include <climits>
 #include <queue>
@@ -56,24 +69,119 @@ constexpr int kStAhead = 8;              // steps whose descriptors are in fligh
 constexpr int kStSegMax = 3;
 constexpr int kStLdsLimit = 152 * 1024;  // bytes of LDS the kernel may use
 
+// Values in the unpacked layout (the index space the schedule is built in).
 int64_t st_lds_doubles(const Symbolic& s) { return 3 * (int64_t)s.n + 2 * (int64_t)s.l_ptr[s.n]; }
 constexpr int64_t kStLdsMax = 160 * 1024 - 64;   // values + per-step metadata (+ the static pivot flag)
-// bytes: values (rounded to 16 B) then nsteps x int4 of metadata
+// bytes: [u_jj | L and U values (pool) | y | cx] rounded to 16 B, then one int2 of metadata per
+// padded step and ring slot
 __host__ __device__ constexpr int st_padded(int S) { return (S + kStAhead - 1) / kStAhead * kStAhead; }
-int64_t st_lds_total(int64_t n, int64_t nl, int64_t S) {
-    return ((3 * n + 2 * nl + 1) & ~1LL) * 8 + 16 * ((int64_t)st_padded((int)S) + kStAhead + 1);
+int64_t st_lds_total(int64_t n, int64_t pool, int64_t S) {
+    return ((3 * n + pool + 1) & ~1LL) * 8 + 8 * ((int64_t)st_padded((int)S) + kStAhead + 1);
 }
-int64_t st_lds_total(const Symbolic& s, int64_t S) { return st_lds_total(s.n, s.l_ptr[s.n], S); }
 
 struct StTask {
     int32_t step, dst, div, off, cnt;
 };
 
+// Packs the L and U values of a built schedule (unpacked indices, see above)
+// into shared LDS slots by live interval, rewriting every descriptor.
+bool pack_slots(const Symbolic& s, const std::vector<int32_t>& meta, std::vector<int32_t>& desc, int S,
+                std::vector<int32_t>& slot_l, std::vector<int32_t>& slot_u, int32_t& pool) {
+    const int n = s.n, nl = s.l_ptr[n], P0 = 2 * nl;
+    // entries of A land in L / U positions by the gather; everything else starts unwritten
+    std::vector<char> inA(P0, 0);
+    auto pos_in_col = [&](int col, int row) {
+        const int* b0 = s.l_idx.data() + s.l_ptr[col];
+        const int* e0 = s.l_idx.data() + s.l_ptr[col + 1];
+        const int* q = std::lower_bound(b0, e0, row);
+        return (q != e0 && *q == row) ? (int)(q - s.l_idx.data()) : -1;
+    };
+    for (int r = 0; r < n; ++r)
+        for (int e = s.row_ptr[r]; e < s.row_ptr[r + 1]; ++e) {
+            const int pr = s.iperm[r], pc = s.iperm[s.col_idx[e]];
+            const int t = pr > pc ? pos_in_col(pc, pr) : (pr < pc ? pos_in_col(pr, pc) : -1);
+            if (t >= 0) inA[(pr > pc ? 0 : nl) + t] = 1;
+        }
+    auto pooled = [&](int i) { return i >= n && i < n + P0; };
+    std::vector<int> first(P0, INT_MAX), last(P0, -1);
+    for (int st = 0; st < S; ++st) {
+        const int base = meta[4 * st], tact = meta[4 * st + 1];
+        for (int t = 0; t < tact; ++t) {
+            const int32_t* d = &desc[4 * (size_t)(base + t)];
+            if (d[0] == -1) continue;
+            const int dst = d[0] & 0x7FFF, cnt = (d[0] >> 15) & 3, div = (int)((uint32_t)d[0] >> 17);
+            if (pooled(dst)) {
+                first[dst - n] = std::min(first[dst - n], st);
+                last[dst - n] = std::max(last[dst - n], st);
+            }
+            for (int c = 0; c < cnt; ++c) {
+                const uint32_t w = (uint32_t)d[1 + c];
+                const int a = (int)(w & 0xFFFF), b = (int)(w >> 16);
+                if (pooled(a)) last[a - n] = std::max(last[a - n], st);
+                if (pooled(b)) last[b - n] = std::max(last[b - n], st);
+            }
+            if (div != 0x7FFF && pooled(div)) last[div - n] = std::max(last[div - n], st);
+        }
+    }
+    // live interval [birth, last]: birth -1 for gathered values
+    std::vector<int> birth(P0), order(P0), slot(P0, -1);
+    for (int i = 0; i < P0; ++i) {
+        birth[i] = (inA[i] || first[i] == INT_MAX) ? -1 : first[i];
+        last[i] = std::max(last[i], birth[i]);
+        order[i] = i;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return birth[a] < birth[b]; });
+    std::priority_queue<std::pair<int, int>, std::vector<std::pair<int, int>>, std::greater<std::pair<int, int>>> active;
+    std::priority_queue<int, std::vector<int>, std::greater<int>> freed;
+    int used = 0;
+    for (int i : order) {
+        while (!active.empty() && active.top().first < birth[i]) {
+            freed.push(active.top().second);
+            active.pop();
+        }
+        int sl = used;
+        if (!freed.empty()) {
+            sl = freed.top();
+            freed.pop();
+        } else {
+            ++used;
+        }
+        slot[i] = sl;
+        active.push({last[i], sl});
+    }
+    if (3 * n + used >= 0x7FFF) return false;
+    auto remap = [&](int i) { return i < n ? i : (i < n + P0 ? n + slot[i - n] : i - P0 + used); };
+    for (int st = 0; st < S; ++st) {
+        const int base = meta[4 * st], tact = meta[4 * st + 1];
+        for (int t = 0; t < tact; ++t) {
+            int32_t* d = &desc[4 * (size_t)(base + t)];
+            if (d[0] == -1) continue;
+            const int dst = d[0] & 0x7FFF, cnt = (d[0] >> 15) & 3, div = (int)((uint32_t)d[0] >> 17);
+            const uint32_t zero = (pooled(dst) && birth[dst - n] == st) ? 1u : 0u;
+            const uint32_t nd = div == 0x7FFF ? 0x7FFFu : (uint32_t)remap(div);
+            d[0] = (int32_t)((uint32_t)remap(dst) | ((uint32_t)cnt << 15) | (nd << 17));
+            for (int c = 0; c < cnt; ++c) {
+                const uint32_t w = (uint32_t)d[1 + c];
+                d[1 + c] = (int32_t)((uint32_t)remap((int)(w & 0xFFFF)) | ((uint32_t)remap((int)(w >> 16)) << 16));
+            }
+            d[1] = (int32_t)((uint32_t)d[1] | (zero << 15));
+        }
+    }
+    for (int t = 0; t < nl; ++t) {
+        slot_l[t] = birth[t] < 0 ? n + slot[t] : -1;
+        slot_u[t] = birth[nl + t] < 0 ? n + slot[nl + t] : -1;
+    }
+    pool = used;
+    return true;
+}
+
 // Builds the step schedule.  Returns false when the plan does not fit.
 bool build_schedule(const Symbolic& s, const std::vector<int32_t>& r_pos, int T, std::vector<int32_t>& meta,
-                    std::vector<int32_t>& desc, int32_t& nsteps, int seg_max = kStSegMax) {
+                    std::vector<int32_t>& desc, int32_t& nsteps, bool pack, std::vector<int32_t>& slot_l,
+                    std::vector<int32_t>& slot_u, int32_t& pool, int seg_max = kStSegMax) {
     const int n = s.n, nl = s.l_ptr[n];
-    if (st_lds_doubles(s) * 8 > kStLdsLimit || st_lds_doubles(s) >= 0x7FFF) return false;
+    if (st_lds_doubles(s) >= 0x7FFF) return false;
+    if (!pack && st_lds_doubles(s) * 8 > kStLdsLimit) return false;
     const int ybase = n + 2 * nl;
     auto LX = [&](int t) { return n + t; };
     auto UX = [&](int t) { return n + nl + t; };
@@ -198,7 +306,18 @@ bool build_schedule(const Symbolic& s, const std::vector<int32_t>& r_pos, int T,
         }
     }
     S = (int)(meta.size() / 4);
-    if (st_lds_total(s, S) > kStLdsMax) return false;
+    slot_l.resize(nl);
+    slot_u.resize(nl);
+    if (!pack) {
+        for (int t = 0; t < nl; ++t) {
+            slot_l[t] = n + t;
+            slot_u[t] = n + nl + t;
+        }
+        pool = 2 * nl;
+    } else if (!pack_slots(s, meta, desc, S, slot_l, slot_u, pool)) {
+        return false;
+    }
+    if ((3 * (int64_t)n + pool) * 8 > kStLdsLimit || st_lds_total(n, pool, S) > kStLdsMax) return false;
     nsteps = S;
     return true;
 }
@@ -215,14 +334,15 @@ struct StArgs {
     int32_t* info;          // batch x K
 };
 
+template <bool PACKED>
 __device__ __forceinline__ void st_exec(double* v, int4 d) {
     if (d.x == -1) return;
     const int dst = d.x & 0x7FFF;
     const int cnt = (d.x >> 15) & 3;
     const int div = (int)((uint32_t)d.x >> 17);
     // all operands first (unused pairs read slot 0), then the chain in order
-    const double acc0 = v[dst];
-    const double l0 = v[d.y & 0xFFFF], u0 = v[(uint32_t)d.y >> 16];
+    const double acc0 = (PACKED && ((d.y >> 15) & 1)) ? 0.0 : v[dst];
+    const double l0 = v[d.y & 0x7FFF], u0 = v[(uint32_t)d.y >> 16];
     const double l1 = v[d.z & 0xFFFF], u1 = v[(uint32_t)d.z >> 16];
     const double l2 = v[d.w & 0xFFFF], u2 = v[(uint32_t)d.w >> 16];
     double acc = acc0;
@@ -246,7 +366,7 @@ __device__ __forceinline__ int4 st_desc(__amdgpu_buffer_rsrc_t r, int2 m, int ti
     return d;
 }
 
-template <int T>
+template <int T, bool PACKED>
 __global__ __launch_bounds__(T) void steps_kernel(StArgs a, EpsSet es) {
     // 16-byte aligned: the step metadata after the values is read as int4
     // (a misaligned ds_read_b128 every step costs several times the step)
@@ -254,14 +374,14 @@ __global__ __launch_bounds__(T) void steps_kernel(StArgs a, EpsSet es) {
     __shared__ int s_bad;
     const SpIdx& ix = a.ix;
     const int n = ix.n, nl = ix.nnzl, tid = threadIdx.x;
-    const int ybase = n + 2 * nl;
+    const int ybase = n + a.sx.pool;
     double* y = v + ybase;
     double* cx = y + n;
     const int S = a.sx.nsteps;
     const int Sp = st_padded(S);
     // per-step metadata, read by every step of every system: kept in LDS,
     // followed by empty steps up to a multiple of the ring depth and one ring beyond
-    int2* sm = reinterpret_cast<int2*>(v + ((3 * n + 2 * nl + 1) & ~1));
+    int2* sm = reinterpret_cast<int2*>(v + ((3 * n + a.sx.pool + 1) & ~1));
     for (int i = tid; i < Sp + kStAhead + 1; i += T) {
         const int4 mi = i < S ? a.sx.meta[i] : make_int4(0, 0, 1, 0);
         sm[i] = make_int2(mi.x, mi.y);
@@ -284,11 +404,18 @@ __global__ __launch_bounds__(T) void steps_kernel(StArgs a, EpsSet es) {
                 ring[d] = st_desc(drs, sm[d], tid);
             }
             int2 m = sm[0];
-            // A + eps_k D permuted onto the fill pattern, and P b
+            // A + eps_k D permuted onto the fill pattern, and P b (packed: only the
+            // values live from the start; fill values start from zero at their first task)
             for (int t = tid; t < nl; t += T) {
                 const int sl = ix.src_l[t], su = ix.src_u[t];
-                v[n + t] = sl >= 0 ? vals[sl] : 0.0;
-                v[n + nl + t] = su >= 0 ? vals[su] : 0.0;
+                if (!PACKED) {
+                    v[n + t] = sl >= 0 ? vals[sl] : 0.0;
+                    v[n + nl + t] = su >= 0 ? vals[su] : 0.0;
+                } else {
+                    const int dl = a.sx.slot_l[t], du = a.sx.slot_u[t];
+                    if (dl >= 0) v[dl] = sl >= 0 ? vals[sl] : 0.0;
+                    if (du >= 0) v[du] = su >= 0 ? vals[su] : 0.0;
+                }
             }
             const double ek = eps_at(es, kk);
             for (int j = tid; j < n; j += T) {
@@ -307,7 +434,7 @@ __global__ __launch_bounds__(T) void steps_kernel(StArgs a, EpsSet es) {
 #pragma unroll
                 for (int d = 0; d < kStAhead; ++d) {
                     const int st = st0 + d;
-                    if (tid < m.y) st_exec(v, ring[d]);
+                    if (tid < m.y) st_exec<PACKED>(v, ring[d]);
                     // the next steps' metadata after the task: its latency overlaps the barrier
                     const int2 m1 = sm[st + 1];
                     const int2 ma = sm[st + kStAhead];
@@ -341,21 +468,26 @@ __global__ __launch_bounds__(T) void steps_kernel(StArgs a, EpsSet es) {
 
 }  // namespace
 
-bool steps_fit(const Symbolic& s, int32_t nrhs) {
-    return nrhs == 1 && st_lds_doubles(s) * 8 <= kStLdsLimit && st_lds_doubles(s) < 0x7FFF;
-}
+// Whether a schedule may fit (it is built, packed if need be, by steps_upload;
+// steps_ready tells whether it did).
+bool steps_fit(const Symbolic& s, int32_t nrhs) { return nrhs == 1 && st_lds_doubles(s) < 0x7FFF; }
 
 bool steps_ready(const SparseDevice& d) { return d.st_buf != nullptr; }
 
 hipError_t steps_upload(const Symbolic& s, const std::vector<int32_t>& r_pos, SparseDevice& d) {
     if (d.st_buf || !steps_fit(s, 1)) return hipSuccess;
-    std::vector<int32_t> meta, desc;
-    int32_t S = 0;
-    if (!build_schedule(s, r_pos, kStThreads, meta, desc, S) || S < 1) return hipSuccess;
-    if (desc.size() / 4 * 16 > (size_t)INT32_MAX) return hipSuccess;
+    std::vector<int32_t> meta, desc, slot_l, slot_u;
+    int32_t S = 0, pool = 0;
+    bool packed = false;
+    if (!build_schedule(s, r_pos, kStThreads, meta, desc, S, false, slot_l, slot_u, pool)) {
+        packed = true;
+        if (!build_schedule(s, r_pos, kStThreads, meta, desc, S, true, slot_l, slot_u, pool)) return hipSuccess;
+    }
+    if (S < 1 || desc.size() / 4 * 16 > (size_t)INT32_MAX) return hipSuccess;
     auto up16 = [](size_t words) { return (words + 63) / 64 * 64; };
     const size_t o_meta = 0, o_desc = up16(meta.size());
-    const size_t total = o_desc + up16(desc.size());
+    const size_t o_sl = o_desc + up16(desc.size()), o_su = o_sl + up16(slot_l.size());
+    const size_t total = o_su + up16(slot_u.size());
     // Rounded up to whole 2 MiB fragments: the kernel streams this array once
     // per system from every CU, and small-page mappings make each new page a
     // translation miss.
@@ -366,6 +498,8 @@ hipError_t steps_upload(const Symbolic& s, const std::vector<int32_t>& r_pos, Sp
     std::vector<int32_t> host(total, 0);
     std::copy(meta.begin(), meta.end(), host.begin() + o_meta);
     std::copy(desc.begin(), desc.end(), host.begin() + o_desc);
+    std::copy(slot_l.begin(), slot_l.end(), host.begin() + o_sl);
+    std::copy(slot_u.begin(), slot_u.end(), host.begin() + o_su);
     e = hipMemcpy(d.st_buf, host.data(), sizeof(int32_t) * total, hipMemcpyHostToDevice);
     if (e != hipSuccess) { (void)hipFree(d.st_buf); d.st_buf = nullptr; return e; }
     d.st.nsteps = S;
@@ -373,6 +507,10 @@ hipError_t steps_upload(const Symbolic& s, const std::vector<int32_t>& r_pos, Sp
     d.st.ndesc = (int32_t)(desc.size() / 4);
     d.st.meta = (const int4*)(d.st_buf + o_meta);
     d.st.desc = (const int4*)(d.st_buf + o_desc);
+    d.st.slot_l = d.st_buf + o_sl;
+    d.st.slot_u = d.st_buf + o_su;
+    d.st.pool = pool;
+    d.st.packed = packed ? 1 : 0;
     return hipSuccess;
 }
 
@@ -391,9 +529,10 @@ hipError_t steps_run(const SparseDevice& d, int32_t nnz, int32_t batch, const do
     a.ix = d.idx;
     a.nnz = nnz; a.batch = batch; a.K = es.K; a.per_jacobian = per_jacobian ? 1 : 0;
     a.values = values; a.dvec = dvec; a.B = B; a.X = X; a.Xk = Xk; a.info = info;
-    const int lds = (int)st_lds_total(d.idx.n, d.idx.nnzl, d.st.nsteps);
-    hipError_t e = hipFuncSetAttribute((const void*)steps_kernel<kStThreads>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    const int lds = (int)st_lds_total(d.idx.n, d.st.pool, d.st.nsteps);
+    const void* kern = d.st.packed ? (const void*)steps_kernel<kStThreads, true>
+                                   : (const void*)steps_kernel<kStThreads, false>;
+    hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
     int dev = 0, cus = 256;
     (void)hipGetDevice(&dev);
@@ -401,7 +540,10 @@ hipError_t steps_run(const SparseDevice& d, int32_t nnz, int32_t batch, const do
     const int resident = cus * std::max(1, (160 * 1024) / std::max(lds, 1));
     const int64_t jobs = per_jacobian ? batch : (int64_t)batch * es.K;
     const int grid = (int)std::min<int64_t>(jobs, resident);
-    hipLaunchKernelGGL(steps_kernel<kStThreads>, dim3(grid), dim3(kStThreads), lds, st, a, es);
+    if (d.st.packed)
+        hipLaunchKernelGGL((steps_kernel<kStThreads, true>), dim3(grid), dim3(kStThreads), lds, st, a, es);
+    else
+        hipLaunchKernelGGL((steps_kernel<kStThreads, false>), dim3(grid), dim3(kStThreads), lds, st, a, es);
     return hipGetLastError();
 }
 

@@ -210,15 +210,35 @@ def test_steps_path_modes_and_breakdown(psp, O, W, dev, N, count):
     _cmp(xg[keep], xo[keep])
 
 
+@pytest.mark.parametrize("count", [3, 260])
+def test_steps_path_packed_slots(psp, O, W, dev, count):
+    """The 500-bus pattern (n = 1,001) fits in LDS only with its L and U values packed into
+    shared slots by live interval; in both launch modes the results equal the oracle bit for
+    bit (every Jacobian for 3, sampled ones for 260)."""
+    ip, ix, vals, bs = W.scenario_batch(500, count)
+    n = len(ip) - 1
+    eps = W.config_eps("n601")
+    print(f"[gpu sparse] packed steps n={n} count={count}", flush=True)
+    plan = psp.Plan(ip, ix)
+    x, info = psp.solve_batched(plan, torch.from_numpy(vals).to(dev), eps, torch.from_numpy(bs).to(dev),
+                                path="sparse_steps")
+    torch.cuda.synchronize()
+    sym = O.symbolic(n, ip, ix)
+    pick = list(range(count)) if count <= 3 else [0, 1, 129, 255, 259]
+    xo, io, _, _ = O.sparse_batch(n, ip, ix, vals[pick], sym, eps, bs[pick])
+    assert np.array_equal(info.cpu().numpy()[pick], io)
+    _cmp(x.cpu().numpy()[pick], xo)
+
+
 def test_steps_path_rejects_what_it_cannot_run(psp, W, dev):
-    """nrhs > 1, and a fill too large for LDS, are refused with PSP_E_UNSUPPORTED."""
+    """nrhs > 1, and a fill too large for LDS even packed, are refused with PSP_E_UNSUPPORTED."""
     ip, ix, vals, bs = W.scenario_batch(30, 2)
     n = len(ip) - 1
     plan = psp.Plan(ip, ix)
     b2 = torch.zeros((2, n, 2), dtype=torch.float64, device=dev)
     with pytest.raises(psp.PSPError, match="UNSUPPORTED|cannot run"):
         psp.solve_batched(plan, torch.from_numpy(vals).to(dev), W.config_eps("n601"), b2, path="sparse_steps")
-    ip, ix, vals, bs = W.scenario_batch(500, 1)
+    ip, ix, vals, bs = W.scenario_batch(1354, 1)
     plan = psp.Plan(ip, ix)
     with pytest.raises(psp.PSPError, match="UNSUPPORTED|cannot run"):
         psp.solve_batched(plan, torch.from_numpy(vals).to(dev), W.config_eps("n601"),
