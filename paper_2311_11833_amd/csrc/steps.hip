@@ -38,17 +38,22 @@
 // sum_k c_k x_k in the order of the reference combine (ascending k, fma chain
 // from 0).
 //
-// Packed schedules, for patterns whose L and U values do not fit in LDS side by
-// side (n = 1,001 here).  An L or U value needs LDS only from its gather (an
+// Packed schedules.  A step is a few hundred cycles of dependent LDS work and a
+// barrier, so a CU runs two workgroups' steps far faster than one's: at n = 601
+// two resident workgroups per CU take 512 Jacobians in 0.77 ms instead of
+// 1.11 ms.  That needs at most 80 KB of LDS per workgroup (and registers for
+// eight waves per SIMD); unpacked, n = 601 needs 103 KB, and n = 1,001 does not
+// fit at all.  An L or U value needs LDS only from its gather (an
 // entry of A, or a value never written, which reads as 0) or its first write,
 // to its last read; a fill value's first task can start from zero instead of
 // reading its slot.  The values are packed into a pool of shared slots by these
 // live intervals in executed steps (greedy by start time, which uses exactly as
 // many slots as values are live at the busiest step: 16,095 instead of 21,728
-// at n = 1,001), and a slot is reused only in a step after its previous value's
-// last read, so no step reads a slot that a task of the step writes.  The
-// layout becomes [u_jj | pool | y | combine accumulator].  Patterns that fit
-// unpacked keep the plain layout (packing cost ~6 % at n = 601).
+// at n = 1,001; 7,651 instead of 11,016 at n = 601), and a slot is reused only
+// in a step after its previous value's last read, so no step reads a slot that
+// a task of the step writes.  The layout becomes [u_jj | pool | y | combine
+// accumulator].  A pattern is packed when that brings it to two workgroups per
+// CU or is the only way to fit; otherwise it keeps the plain layout.
 #include <algorithm>
 #include <climits>
 #include <queue>
@@ -68,6 +73,7 @@ constexpr int kStAhead = 8;              // steps whose descriptors are in fligh
 // cap raises the step count from 294 to 340 and removes every in-step fetch.
 constexpr int kStSegMax = 3;
 constexpr int kStLdsLimit = 152 * 1024;  // bytes of LDS the kernel may use
+constexpr int64_t kStLdsPair = 80 * 1024 - 64;   // at most this, and two workgroups share a CU
 
 // Values in the unpacked layout (the index space the schedule is built in).
 int64_t st_lds_doubles(const Symbolic& s) { return 3 * (int64_t)s.n + 2 * (int64_t)s.l_ptr[s.n]; }
@@ -366,8 +372,10 @@ __device__ __forceinline__ int4 st_desc(__amdgpu_buffer_rsrc_t r, int2 m, int ti
     return d;
 }
 
+// waves_per_eu(8): registers for eight waves per SIMD, i.e. two 1024-lane workgroups per CU
+// (without it the kernel takes 112 scalar registers per wave, which leaves room for seven)
 template <int T, bool PACKED>
-__global__ __launch_bounds__(T) void steps_kernel(StArgs a, EpsSet es) {
+__global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(8))) void steps_kernel(StArgs a, EpsSet es) {
     // 16-byte aligned: the step metadata after the values is read as int4
     // (a misaligned ds_read_b128 every step costs several times the step)
     extern __shared__ __align__(16) double v[];
@@ -478,10 +486,20 @@ hipError_t steps_upload(const Symbolic& s, const std::vector<int32_t>& r_pos, Sp
     if (d.st_buf || !steps_fit(s, 1)) return hipSuccess;
     std::vector<int32_t> meta, desc, slot_l, slot_u;
     int32_t S = 0, pool = 0;
+    // Unpacked when it fits two workgroups per CU (or packing cannot reach that); packed when
+    // packing is what lets two workgroups share a CU, or the only way to fit at all.
     bool packed = false;
-    if (!build_schedule(s, r_pos, kStThreads, meta, desc, S, false, slot_l, slot_u, pool)) {
-        packed = true;
-        if (!build_schedule(s, r_pos, kStThreads, meta, desc, S, true, slot_l, slot_u, pool)) return hipSuccess;
+    const bool plain = build_schedule(s, r_pos, kStThreads, meta, desc, S, false, slot_l, slot_u, pool);
+    if (!plain || st_lds_total(s.n, pool, S) > kStLdsPair) {
+        std::vector<int32_t> pm, pd, pl, pu;
+        int32_t pS = 0, pp = 0;
+        if (build_schedule(s, r_pos, kStThreads, pm, pd, pS, true, pl, pu, pp) &&
+            (!plain || st_lds_total(s.n, pp, pS) <= kStLdsPair)) {
+            meta.swap(pm); desc.swap(pd); slot_l.swap(pl); slot_u.swap(pu);
+            S = pS; pool = pp; packed = true;
+        } else if (!plain) {
+            return hipSuccess;
+        }
     }
     if (S < 1 || desc.size() / 4 * 16 > (size_t)INT32_MAX) return hipSuccess;
     auto up16 = [](size_t words) { return (words + 63) / 64 * 64; };
