@@ -380,6 +380,9 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(8))) void ste
     // (a misaligned ds_read_b128 every step costs several times the step)
     extern __shared__ __align__(16) double v[];
     __shared__ int s_bad;
+    // the nodes and weights, read once per system: kept in LDS, not in scalar registers
+    // for the whole kernel (which would cost eight-wave occupancy)
+    __shared__ double s_eps[kMaxK], s_c[kMaxK];
     const SpIdx& ix = a.ix;
     const int n = ix.n, nl = ix.nnzl, tid = threadIdx.x;
     const int ybase = n + a.sx.pool;
@@ -394,6 +397,12 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(8))) void ste
         const int4 mi = i < S ? a.sx.meta[i] : make_int4(0, 0, 1, 0);
         sm[i] = make_int2(mi.x, mi.y);
     }
+#pragma unroll
+    for (int i = 0; i < kMaxK; ++i)
+        if (tid == i) {
+            s_eps[i] = es.eps[i];
+            s_c[i] = es.c[i];
+        }
     __syncthreads();
     // gfx9-family buffer resource: raw (stride 0), range = the descriptor array
     const __amdgpu_buffer_rsrc_t drs =
@@ -425,7 +434,7 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(8))) void ste
                     if (du >= 0) v[du] = su >= 0 ? vals[su] : 0.0;
                 }
             }
-            const double ek = eps_at(es, kk);
+            const double ek = s_eps[kk];
             for (int j = tid; j < n; j += T) {
                 const int sd = ix.src_d[j], pj = ix.perm[j];
                 const double ajj = sd >= 0 ? vals[sd] : 0.0;
@@ -457,7 +466,7 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(8))) void ste
             __syncthreads();
             const int bad = s_bad == INT_MAX ? 0 : s_bad;
             if (a.per_jacobian) {
-                const double c = c_at(es, kk);
+                const double c = s_c[kk];
                 for (int q = tid; q < n; q += T) {
                     const double xq = bad ? __builtin_nan("") : y[q];
                     cx[q] = fmad(c, xq, kk == 0 ? 0.0 : cx[q]);
