@@ -66,7 +66,7 @@ namespace psp {
 
 namespace {
 constexpr int kStThreads = 1024;         // workgroup size; the schedule is built for it (one task per thread and step)
-constexpr int kStAhead = 8;              // steps whose descriptors are in flight
+constexpr int kStAhead = 7;              // steps whose descriptors are in flight
 // Longest run of one chain inside a step, so that every task's updates fit in
 // its descriptor (no second, dependent load).  The long runs belong mostly to
 // the dense slack row, whose value is needed only at the end; at n = 601 the
