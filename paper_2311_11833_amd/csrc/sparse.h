@@ -72,6 +72,7 @@ bool steps_ready(const SparseDevice& d);   // schedule built (it may not fit eve
 hipError_t steps_upload(const Symbolic& s, const std::vector<int32_t>& r_pos, SparseDevice& d);
 void steps_free(SparseDevice& d);
 // one launch; X (batch x n) combined in-kernel when per_jacobian, else Xk (batch x K x n) is written
+int steps_per_cu(const SparseDevice& d);   // step-kernel workgroups resident per CU (1 or 2)
 hipError_t steps_run(const SparseDevice& d, int32_t nnz, int32_t batch, const double* values, const EpsSet& es,
                      const double* dvec, const double* B, double* X, double* Xk, int32_t* info, bool per_jacobian,
                      hipStream_t st);

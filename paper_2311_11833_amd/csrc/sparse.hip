@@ -1015,8 +1015,9 @@ hipError_t sparse_solve_batched(const Symbolic& s, const SparseDevice& d, int32_
         int dev = 0, cus = 256;
         (void)hipGetDevice(&dev);
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        // enough Jacobians to give every CU one: one workgroup per Jacobian, combine fused
-        const bool per_jacobian = batch >= cus;
+        // enough Jacobians to fill every resident workgroup slot: one workgroup per Jacobian,
+        // combine fused; fewer: one workgroup per perturbed system and a combine launch
+        const bool per_jacobian = batch >= cus * steps_per_cu(d);
         hipError_t e = steps_run(d, s.nnz, batch, values, es, dvec, B, X, a.Xk, info, per_jacobian, st);
         if (e != hipSuccess || per_jacobian) return e;
         return launch_combine((int64_t)s.n, batch, es, a.Xk, X, st);

@@ -547,6 +547,10 @@ void steps_free(SparseDevice& d) {
     d.st = StepIdx{};
 }
 
+int steps_per_cu(const SparseDevice& d) {
+    return st_lds_total(d.idx.n, d.st.pool, d.st.nsteps) <= kStLdsPair ? 2 : 1;
+}
+
 hipError_t steps_run(const SparseDevice& d, int32_t nnz, int32_t batch, const double* values, const EpsSet& es,
                      const double* dvec, const double* B, double* X, double* Xk, int32_t* info, bool per_jacobian,
                      hipStream_t st) {
