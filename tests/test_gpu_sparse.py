@@ -184,12 +184,13 @@ def test_sparse_full_size_batched_sampled(psp, O, W, dev, path):
             _cmp(xg[s:s + 1], xo)
 
 
-@pytest.mark.parametrize("N,count", [(14, 3), (30, 300), (118, 260)])
+@pytest.mark.parametrize("N,count", [(14, 3), (30, 300), (118, 260), (30, 520), (118, 600)])
 def test_steps_path_modes_and_breakdown(psp, O, W, dev, N, count):
     """Dataflow-step execution in both launch modes (one workgroup per perturbed system
-    plus a combine launch when the batch is smaller than the CU count, one workgroup per
-    Jacobian with the combine fused otherwise), with one Jacobian broken by an infinite
-    entry: info and solutions equal to the oracle, the broken Jacobian NaN."""
+    plus a combine launch when the batch is smaller than the resident workgroup slots,
+    two per CU here; one workgroup per Jacobian with the combine fused otherwise), with
+    one Jacobian broken by an infinite entry: info and solutions equal to the oracle, the
+    broken Jacobian NaN."""
     ip, ix, vals, bs = W.scenario_batch(N, count)
     vals = vals.copy()
     vals[1, 2] = np.inf
