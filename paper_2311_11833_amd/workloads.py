@@ -23,7 +23,6 @@ factorisation break down (Sec. IV, first observation).
 """
 from __future__ import annotations
 
-import math
 from dataclasses import dataclass
 
 import numpy as np
@@ -353,6 +352,3 @@ def to_dense(n: int, indptr: np.ndarray, indices: np.ndarray, data: np.ndarray) 
         A[i, indices[indptr[i]:indptr[i + 1]]] = data[indptr[i]:indptr[i + 1]]
     return A
 
-
-def dirichlet_rows_ok(J: Jacobian) -> bool:  # pragma: no cover - debugging aid
-    return math.isfinite(float(np.sum(J.data)))
