@@ -16,7 +16,11 @@
  *     CSR order.  Dense vectors with nrhs right-hand sides are row-major
  *     n x nrhs (entry (i, r) at i*nrhs + r).
  *   - Pointers documented "device" are device memory owned by the caller;
- *     the library never frees them.  Pointers documented "host" are read
+ *     the library never allocates or frees device memory.  That includes the
+ *     plan's own index arrays: psp_plan_device_bytes sizes them and
+ *     psp_plan_upload copies them into a caller buffer, once per plan, before
+ *     any numeric call (which then allocates nothing and may be captured in a
+ *     HIP graph).  Pointers documented "host" are read
  *     during the call only.  "stream" is a hipStream_t (NULL = the null
  *     stream); device work is enqueued on it and the call returns without
  *     waiting, so device outputs are valid after the caller synchronises
@@ -91,6 +95,11 @@ typedef struct {
     int32_t nlev[3];           /* levels: factor, L-solve, U-solve                  */
     int64_t flops_dense_factor;/* n(n-1)/2 divisions + 2 * sum_k (n-1-k)^2 fma flops */
     int64_t flops_sparse_factor;/* sum_j (|L(:,j)| + 2*|L(:,j)|^2) on the fill      */
+    int32_t steps;             /* barrier steps of the LDS step schedule (0: none)  */
+    int32_t steps_packed;      /* 1 if its L/U values share LDS slots               */
+    int64_t steps_lds_bytes;   /* dynamic LDS of one step-kernel workgroup          */
+    int32_t steps_per_cu;      /* step-kernel workgroups resident per CU (0, 1, 2)  */
+    int64_t device_bytes;      /* psp_plan_device_bytes                              */
 } psp_plan_info_t;
 
 PSP_API psp_status psp_plan_info(psp_plan plan, psp_plan_info_t* out);
@@ -104,6 +113,19 @@ PSP_API psp_status psp_plan_export(psp_plan plan, int32_t* perm, int32_t* iperm,
                            int32_t* l_ptr, int32_t* l_idx, int32_t* lev_ptr[3], int32_t* lev_idx[3]);
 
 PSP_API void psp_plan_destroy(psp_plan plan);
+
+/* Device copy of the plan (the static pivot sequence of Sec. II-C and
+ * everything derived from it: fill patterns, level lists, update lists, the
+ * step schedule, dense slot offsets).  psp_plan_device_bytes returns the bytes
+ * it needs (0 on host allocation failure); psp_plan_upload copies it into
+ * `dev` (device, caller-owned, 256-byte aligned, at least that many bytes) on
+ * `stream` and waits for the copy.  The plan then refers to that buffer, which
+ * must stay alive and unmodified while the plan is used; a later upload
+ * rebinds the plan to a new buffer (on the then current device).  Numeric calls
+ * on a plan that is not uploaded to the current device return PSP_E_STATE.
+ * PSP_E_UNSUPPORTED if the device is not gfx950. */
+PSP_API size_t psp_plan_device_bytes(psp_plan plan);
+PSP_API psp_status psp_plan_upload(psp_plan plan, void* dev, size_t dev_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
  * Weights (host): c_k = prod_{l != k} eps_l / (eps_l - eps_k), the unique
@@ -153,9 +175,11 @@ enum {
 };
 
 /* Bytes of device workspace psp_factor / psp_solve_batched need for `batch`
- * Jacobians, K nodes and nrhs right-hand sides on `path`.  With keep != 0
- * the factors of all batch*K systems stay resident for psp_solve and the
- * adjoint. */
+ * Jacobians, K nodes and nrhs right-hand sides on `path` (the scratch of
+ * Alg. 1 steps 2-4: factors of the perturbed systems and their solutions
+ * before the combination).  With keep != 0 the factors of all batch*K systems
+ * stay resident for psp_solve and the adjoint.  PSP_PATH_AUTO returns the
+ * maximum over the paths.  0 for an invalid plan or size. */
 PSP_API size_t psp_workspace_bytes(psp_plan plan, int32_t path, int32_t batch, int32_t K, int32_t nrhs,
                            int32_t keep);
 
@@ -177,36 +201,60 @@ PSP_API psp_status psp_solve_batched(psp_plan plan, int32_t path, int32_t batch,
                              void* stream);
 
 /* ------------------------------------------------------------------------
- * Uneven batches (Alg. 1 steps 1-4 for Jacobians of different patterns):
- * item i holds items[i].batch Jacobians that share items[i].plan's pattern.
- *   path    PSP_PATH_* for this item; PSP_PATH_AUTO takes the plan's tuned
- *           choice for (batch, K, nrhs), else the size heuristic
- *   values  device batch x nnz;  d device n (diagonal of D) or NULL (D = I)
- *   B, X    device batch x n x nrhs;  info device batch x K
- * Every item runs on `stream`, in the given order, in its own slice of one
- * device workspace of at least psp_group_workspace_bytes(...) bytes, which
- * is the sum of the items' psp_workspace_bytes (256-byte aligned).  Errors are
- * as for psp_solve_batched; the first failing item stops the call (items
- * before it are already queued).  psp_group_workspace_bytes returns 0 for an
- * invalid item list.
+ * Groups: Alg. 1 steps 1-4 for an uneven batch, i.e. several items of
+ * Jacobians of different patterns, enqueued together (Sec. IV: batched solves
+ * whose time should not grow with the number of systems).  Item i holds
+ * shapes[i].batch Jacobians sharing shapes[i].plan's pattern, solved on
+ * shapes[i].path (PSP_PATH_AUTO: the plan's tuned choice, else the size
+ * heuristic, resolved at creation).  psp_group_create (host) checks the
+ * items (every plan must be uploaded to the current device), orders them
+ * longest first by their symbolic flop count, deals them over up to four
+ * stream lanes (the caller's stream and three the group owns, each at the
+ * default priority) and lays out one workspace: psp_group_workspace_bytes.
+ *   psp_group_run      enqueues every item: the lanes fork from `stream`
+ *                      and join back into it, so the work is ordered after
+ *                      earlier work on `stream` and later work waits for all
+ *                      of it.  tasks[i] gives item i's device arrays:
+ *                      values batch x nnz, d n or NULL (D = I), B and X
+ *                      batch x n x nrhs, info batch x K.
+ *   psp_group_capture  the same sequence captured from `stream` into one HIP
+ *                      graph (thread-local capture mode); *graph_exec
+ *                      receives the instantiated graph, which
+ *                      psp_graph_launch replays on any stream and
+ *                      psp_graph_destroy frees.  The graph keeps the task
+ *                      pointers and the workspace it was captured with.
+ * Errors as for psp_solve_batched, plus PSP_E_STATE for a group used on
+ * another device.  Calls on one group must not overlap (its lanes are shared).
  * ---------------------------------------------------------------------- */
-typedef struct psp_group_item {
+typedef struct psp_group_s* psp_group;
+
+typedef struct psp_group_shape {
     psp_plan plan;
     int32_t batch;
     int32_t path;
+} psp_group_shape_t;
+
+typedef struct psp_group_task {
     const double* values;
     const double* d;
     const double* B;
     double* X;
     int32_t* info;
-} psp_group_item_t;
+} psp_group_task_t;
 
-PSP_API size_t psp_group_workspace_bytes(int32_t nitems, const psp_group_item_t* items, int32_t K, int32_t nrhs);
-PSP_API psp_status psp_solve_group(int32_t nitems, const psp_group_item_t* items, int32_t K, const double* eps,
-                                   int32_t nrhs, void* ws, size_t ws_bytes, void* stream);
+PSP_API psp_status psp_group_create(int32_t nitems, const psp_group_shape_t* shapes, int32_t K, const double* eps,
+                                    int32_t nrhs, psp_group* out);
+PSP_API size_t psp_group_workspace_bytes(psp_group g);
+PSP_API psp_status psp_group_run(psp_group g, const psp_group_task_t* tasks, void* ws, size_t ws_bytes, void* stream);
+PSP_API psp_status psp_group_capture(psp_group g, const psp_group_task_t* tasks, void* ws, size_t ws_bytes,
+                                     void* stream, void** graph_exec);
+PSP_API psp_status psp_graph_launch(void* graph_exec, void* stream);
+PSP_API void psp_graph_destroy(void* graph_exec);
+PSP_API void psp_group_destroy(psp_group g);
 
 /* ------------------------------------------------------------------------
- * psp_tune -- autotuner: runs psp_solve_batched on the caller's data with
+ * psp_tune -- autotuner for Alg. 1 steps 2-4 in batch (Sec. IV: the batched
+ * factorisation and solves are where the time goes): runs psp_solve_batched on the caller's data with
  * every path that can run this plan and fits ws_bytes (one warm-up, three
  * timed runs each, HIP events on `stream`; the call synchronises the stream),
  * and records the fastest as the PSP_PATH_AUTO choice for (batch, K, nrhs).
@@ -224,7 +272,9 @@ PSP_API psp_status psp_tune(psp_plan plan, int32_t batch, const double* values, 
 /* ------------------------------------------------------------------------
  * Split steps (plain, one call per step) -- the adjoint and the
  * one-system-at-a-time baseline use these.
- * psp_factor: factors all batch*K perturbed systems into the workspace
+ * psp_factor (Alg. 1 steps 1-2, the factorisation half; Sec. II-C: no row
+ * exchange, the plan's static order): factors all batch*K perturbed systems
+ * P (A_s + eps_k D) P^T into the workspace
  * (keep = 1 layout) and returns a host handle that refers to it.  The
  * handle is valid while the workspace memory is alive and unmodified.
  * ---------------------------------------------------------------------- */
@@ -317,11 +367,16 @@ enum { PSP_PF_CONVERGED = 0, PSP_PF_MAXITER = 1, PSP_PF_BREAKDOWN = 2, PSP_PF_DI
 
 /* Checks the network against the plan's pattern (PSP_E_INVALID on any
  * mismatch, NULL pointer, malformed Y, missing diagonal or non-finite G/B),
- * then uploads the network and the map from Y entries to Jacobian positions
- * to the current device.  All arrays are host, read during the call.  The
- * plan must outlive the handle; free it with psp_pf_destroy. */
+ * then copies the network and the map from Y entries to Jacobian positions
+ * into `dev` (device, caller-owned, 256-byte aligned, at least
+ * psp_pf_device_bytes(nbus, y_row_ptr[nbus]) bytes) on `stream` and waits for
+ * the copy.  The plan must be uploaded to the current device.  All other
+ * arrays are host, read during the call.  The plan and `dev` must outlive the
+ * handle; free it with psp_pf_destroy. */
+PSP_API size_t psp_pf_device_bytes(int32_t nbus, int32_t nnz_y);
 PSP_API psp_status psp_pf_create(psp_plan plan, int32_t nbus, const int32_t* y_row_ptr, const int32_t* y_col_idx,
-                                 const double* g, const double* b, const int32_t* pv, psp_pf* out);
+                                 const double* g, const double* b, const int32_t* pv, void* dev, size_t dev_bytes,
+                                 void* stream, psp_pf* out);
 PSP_API void psp_pf_destroy(psp_pf pf);
 
 /* One evaluation for `batch` scenarios (device arrays): F (batch x n), the

@@ -46,6 +46,7 @@ psp_status hip_fail(hipError_t e, const char* where) {
     } while (0)
 
 constexpr int64_t kAlign = 256;
+constexpr int32_t kDenseMaxN = 4096;   // largest n of the dense path
 int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
 int device_cus() {
@@ -64,31 +65,22 @@ int device_cus() {
 
 struct psp_plan_s {
     Symbolic sym;
-    // device copies of the index arrays, uploaded on first numeric use
     std::mutex mu;
-    int device = -1;
-    int32_t* d_dst = nullptr;     // dense slot offsets, keyed by ld
+    // Device metadata: built on the host as one image (image.h), copied by
+    // psp_plan_upload into caller-owned device memory; the pointers below are
+    // relocated into that copy.  The library never frees it.
+    PlanImage img;
+    bool imaged = false;
+    int device = -1;                   // device of the uploaded copy (-1: not uploaded)
+    const void* d_image = nullptr;
+    const int32_t* d_dst = nullptr;    // dense slot offset (column-major, ld = d_dst_ld) of each CSR entry
     int32_t d_dst_ld = 0;
-    int32_t* d_perm = nullptr;
-    int32_t* d_rows = nullptr;    // original row of each CSR entry
-    int32_t* d_cols = nullptr;
-    int32_t* d_rowptr = nullptr;  // user CSR row pointers
-    SparseDevice sp;              // sparse-path arrays
+    const int32_t* d_perm = nullptr;
+    const int32_t* d_rows = nullptr;   // original row of each CSR entry
+    const int32_t* d_cols = nullptr;
+    const int32_t* d_rowptr = nullptr; // user CSR row pointers
+    SparseDevice sp;                   // sparse-path arrays
     std::map<std::tuple<int32_t, int32_t, int32_t>, int32_t> tuned;   // (batch, K, nrhs) -> path id
-    ~psp_plan_s() {
-        if (device >= 0) {
-            int cur = 0;
-            (void)hipGetDevice(&cur);
-            (void)hipSetDevice(device);
-            (void)hipFree(d_dst);
-            (void)hipFree(d_perm);
-            (void)hipFree(d_rows);
-            (void)hipFree(d_cols);
-            (void)hipFree(d_rowptr);
-            sparse_free(sp);
-            (void)hipSetDevice(cur);
-        }
-    }
 };
 
 struct psp_factors_s {
@@ -136,45 +128,41 @@ DenseLayout dense_layout(const Symbolic& s, int32_t batch, int32_t K, int32_t nr
     return L;
 }
 
-psp_status upload_plan(psp_plan p, int32_t ld) {
+// Builds the plan's device image on the host (once).
+void build_image(psp_plan p) {
     std::lock_guard<std::mutex> g(p->mu);
-    int dev = 0;
-    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
-    if (p->device >= 0 && p->device != dev) return fail(PSP_E_STATE, "plan was first used on another device");
+    if (p->imaged) return;
     const Symbolic& s = p->sym;
-    if (p->device < 0) {
-        hipDeviceProp_t prop;
-        HIP_TRY(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
-        if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
-            return fail(PSP_E_UNSUPPORTED, std::string("libpsp is built for gfx950, device is ") + prop.gcnArchName);
-        std::vector<int32_t> rows(s.nnz);
-        for (int32_t i = 0; i < s.n; ++i)
-            for (int32_t e = s.row_ptr[i]; e < s.row_ptr[i + 1]; ++e) rows[e] = i;
-        HIP_TRY(hipMalloc(&p->d_perm, sizeof(int32_t) * s.n), "hipMalloc(plan)");
-        HIP_TRY(hipMalloc(&p->d_rows, sizeof(int32_t) * std::max(1, s.nnz)), "hipMalloc(plan)");
-        HIP_TRY(hipMalloc(&p->d_cols, sizeof(int32_t) * std::max(1, s.nnz)), "hipMalloc(plan)");
-        HIP_TRY(hipMemcpy(p->d_perm, s.perm.data(), sizeof(int32_t) * s.n, hipMemcpyHostToDevice), "hipMemcpy(plan)");
-        HIP_TRY(hipMemcpy(p->d_rows, rows.data(), sizeof(int32_t) * s.nnz, hipMemcpyHostToDevice), "hipMemcpy(plan)");
-        HIP_TRY(hipMemcpy(p->d_cols, s.col_idx.data(), sizeof(int32_t) * s.nnz, hipMemcpyHostToDevice), "hipMemcpy(plan)");
-        HIP_TRY(hipMalloc(&p->d_rowptr, sizeof(int32_t) * (s.n + 1)), "hipMalloc(plan)");
-        HIP_TRY(hipMemcpy(p->d_rowptr, s.row_ptr.data(), sizeof(int32_t) * (s.n + 1), hipMemcpyHostToDevice),
-                "hipMemcpy(plan)");
-        p->device = dev;
-    }
-    if (ld > 0 && p->d_dst_ld != ld) {
+    PlanImage& img = p->img;
+    std::vector<int32_t> rows(s.nnz);
+    for (int32_t i = 0; i < s.n; ++i)
+        for (int32_t e = s.row_ptr[i]; e < s.row_ptr[i + 1]; ++e) rows[e] = i;
+    img.bind(&p->d_perm, img.put(s.perm));
+    img.bind(&p->d_rows, img.put(rows));
+    img.bind(&p->d_cols, img.put(s.col_idx));
+    img.bind(&p->d_rowptr, img.put(s.row_ptr));
+    // dense slot offsets, for the dense path's padded leading dimension
+    const int nb = dense_panel();
+    const int32_t ld = (s.n + nb - 1) / nb * nb;
+    if (s.n <= kDenseMaxN) {
         std::vector<int32_t> dst(s.nnz);
         for (int32_t i = 0; i < s.n; ++i)
-            for (int32_t e = s.row_ptr[i]; e < s.row_ptr[i + 1]; ++e) {
-                const int64_t off = (int64_t)s.iperm[s.col_idx[e]] * ld + s.iperm[i];
-                if (off > INT32_MAX) return fail(PSP_E_UNSUPPORTED, "dense slot too large for int32 offsets");
-                dst[e] = (int32_t)off;
-            }
-        if (p->d_dst) HIP_TRY(hipFree(p->d_dst), "hipFree(plan)");
-        p->d_dst = nullptr;
-        HIP_TRY(hipMalloc(&p->d_dst, sizeof(int32_t) * std::max(1, s.nnz)), "hipMalloc(plan)");
-        HIP_TRY(hipMemcpy(p->d_dst, dst.data(), sizeof(int32_t) * s.nnz, hipMemcpyHostToDevice), "hipMemcpy(plan)");
+            for (int32_t e = s.row_ptr[i]; e < s.row_ptr[i + 1]; ++e)
+                dst[e] = (int32_t)((int64_t)s.iperm[s.col_idx[e]] * ld + s.iperm[i]);
+        img.bind(&p->d_dst, img.put(dst));
         p->d_dst_ld = ld;
     }
+    sparse_image(s, img, p->sp);
+    p->imaged = true;
+}
+
+// Numeric calls need the image on the current device.
+psp_status require_upload(psp_plan p) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    std::lock_guard<std::mutex> g(p->mu);
+    if (p->device < 0 || !p->d_image) return fail(PSP_E_STATE, "plan is not uploaded: call psp_plan_upload first");
+    if (p->device != dev) return fail(PSP_E_STATE, "plan was uploaded to another device");
     return PSP_OK;
 }
 
@@ -235,7 +223,7 @@ extern "C" {
 
 const char* psp_last_error(void) { return g_err.c_str(); }
 
-int32_t psp_version(void) { return 100; }
+int32_t psp_version(void) { return 200; }
 
 psp_status psp_weights(int32_t K, const double* eps, double* c) {
     if (K < 1 || !eps || !c) return fail(PSP_E_INVALID, "psp_weights: K >= 1 and non-NULL arrays required");
@@ -280,6 +268,16 @@ psp_status psp_plan_info(psp_plan p, psp_plan_info_t* o) {
     for (int t = 0; t < 3; ++t) o->nlev[t] = (int32_t)s.lev_ptr[t].size() - 1;
     o->flops_dense_factor = s.flops_dense;
     o->flops_sparse_factor = s.flops_sparse;
+    try {
+        build_image(p);
+    } catch (const std::bad_alloc&) {
+        return fail(PSP_E_NOMEM, "psp_plan_info: host allocation failed");
+    }
+    o->steps = p->sp.st.nsteps;
+    o->steps_packed = p->sp.st.packed;
+    o->steps_lds_bytes = steps_lds_bytes(p->sp);
+    o->steps_per_cu = steps_ready(p->sp) ? steps_per_cu(p->sp) : 0;
+    o->device_bytes = (int64_t)std::max<size_t>(p->img.bytes(), 256);
     return PSP_OK;
 }
 
@@ -302,12 +300,48 @@ psp_status psp_plan_export(psp_plan p, int32_t* perm, int32_t* iperm, int32_t* p
 
 void psp_plan_destroy(psp_plan p) { delete p; }
 
+size_t psp_plan_device_bytes(psp_plan p) {
+    if (!p) return 0;
+    try {
+        build_image(p);
+    } catch (const std::bad_alloc&) {
+        return 0;
+    }
+    return std::max<size_t>(p->img.bytes(), 256);
+}
+
+psp_status psp_plan_upload(psp_plan p, void* dev, size_t dev_bytes, void* stream) {
+    if (!p || !dev) return fail(PSP_E_INVALID, "psp_plan_upload: NULL argument");
+    if (((uintptr_t)dev & 255) != 0) return fail(PSP_E_INVALID, "psp_plan_upload: device buffer must be 256-byte aligned");
+    const size_t need = psp_plan_device_bytes(p);
+    if (need == 0) return fail(PSP_E_NOMEM, "psp_plan_upload: host allocation failed");
+    if (dev_bytes < need) return fail(PSP_E_NOMEM, "psp_plan_upload: device buffer too small: need " + std::to_string(need) + " bytes");
+    if (psp_status st = check_prior_hip()) return st;
+    int devid = 0;
+    HIP_TRY(hipGetDevice(&devid), "hipGetDevice");
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, devid), "hipGetDeviceProperties");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(PSP_E_UNSUPPORTED, std::string("libpsp is built for gfx950, device is ") + prop.gcnArchName);
+    const hipStream_t st = (hipStream_t)stream;
+    std::lock_guard<std::mutex> g(p->mu);
+    HIP_TRY(hipMemcpyAsync(dev, p->img.words.data(), p->img.bytes(), hipMemcpyHostToDevice, st), "hipMemcpyAsync(plan)");
+    HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize(plan)");
+    p->img.apply(dev);
+    p->d_image = dev;
+    p->device = devid;
+    // one-off kernel attributes, here rather than inside a numeric call that may be captured
+    HIP_TRY(sparse_kernel_attrs(), "kernel attributes");
+    HIP_TRY(steps_kernel_attrs(), "kernel attributes");
+    return PSP_OK;
+}
+
 size_t psp_workspace_bytes(psp_plan p, int32_t path, int32_t batch, int32_t K, int32_t nrhs, int32_t keep) {
     if (!p || batch < 1 || K < 1 || nrhs < 0) return 0;
     if (path == PSP_PATH_AUTO) {
         size_t m = 0;
         for (int32_t c = PSP_PATH_DENSE; c <= PSP_PATH_SPARSE_STEPS; ++c)
-            if (c != PSP_PATH_DENSE || p->sym.n <= 4096) m = std::max(m, path_workspace(p->sym, c, batch, K, nrhs, keep));
+            if (c != PSP_PATH_DENSE || p->sym.n <= kDenseMaxN) m = std::max(m, path_workspace(p->sym, c, batch, K, nrhs, keep));
         return m;
     }
     return path_workspace(p->sym, path, batch, K, nrhs, keep);
@@ -325,10 +359,10 @@ psp_status psp_solve_batched(psp_plan p, int32_t path, int32_t batch, const doub
     const hipStream_t st = (hipStream_t)stream;
     const PathSel ps = split_path(resolve_path(p, path, batch, K, nrhs));
     if (ps.base == PSP_PATH_DENSE) {
-        if (s.n > 4096) return fail(PSP_E_UNSUPPORTED, "dense path supports n <= 4096");
+        if (s.n > kDenseMaxN) return fail(PSP_E_UNSUPPORTED, "dense path supports n <= 4096");
         const DenseLayout L = dense_layout(s, batch, K, nrhs, 0);
         if (ws_bytes < (size_t)L.total) return fail(PSP_E_NOMEM, "workspace too small: need " + std::to_string(L.total) + " bytes");
-        if (psp_status r = upload_plan(p, L.ld)) return r;
+        if (psp_status r = require_upload(p)) return r;
         char* w = (char*)ws;
         DenseArgs a{};
         a.n = s.n; a.n_pad = L.n_pad; a.ld = L.ld; a.nrhs = nrhs; a.nnz = s.nnz; a.batch = batch;
@@ -352,48 +386,13 @@ psp_status psp_solve_batched(psp_plan p, int32_t path, int32_t batch, const doub
             return fail(PSP_E_UNSUPPORTED, "this sparse execution cannot run the plan (update lists or LDS size)");
         const size_t need = sparse_workspace_bytes(s, batch, K, nrhs, 0, ps.forced);
         if (ws_bytes < need) return fail(PSP_E_NOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
-        if (psp_status r = upload_plan(p, 0)) return r;
-        {
-            std::lock_guard<std::mutex> g(p->mu);
-            HIP_TRY(sparse_upload(s, p->sp), "sparse plan upload");
-        }
+        if (psp_status r = require_upload(p)) return r;
         if (ps.forced == kVarSteps && !steps_ready(p->sp))
             return fail(PSP_E_UNSUPPORTED, "this sparse execution cannot run the plan (step schedule does not fit in LDS)");
         HIP_TRY(sparse_solve_batched(s, p->sp, batch, values, es, d, nrhs, B, X, info, ws, st, ps.forced), "sparse launch");
         return PSP_OK;
     }
     return fail(PSP_E_INVALID, "unknown path");
-}
-
-size_t psp_group_workspace_bytes(int32_t nitems, const psp_group_item_t* items, int32_t K, int32_t nrhs) {
-    if (nitems < 1 || !items) return 0;
-    size_t total = 0;
-    for (int32_t i = 0; i < nitems; ++i) {
-        const psp_group_item_t& it = items[i];
-        if (!it.plan || it.batch < 1) return 0;
-        const size_t w = psp_workspace_bytes(it.plan, it.path, it.batch, K, nrhs, 0);
-        if (w == 0) return 0;
-        total += (w + 255) / 256 * 256;
-    }
-    return total;
-}
-
-psp_status psp_solve_group(int32_t nitems, const psp_group_item_t* items, int32_t K, const double* eps, int32_t nrhs,
-                           void* ws, size_t ws_bytes, void* stream) {
-    if (nitems < 1 || !items || !ws) return fail(PSP_E_INVALID, "psp_solve_group: no items or NULL workspace");
-    const size_t need = psp_group_workspace_bytes(nitems, items, K, nrhs);
-    if (need == 0) return fail(PSP_E_INVALID, "psp_solve_group: an item has a NULL plan, batch < 1 or bad sizes");
-    if (ws_bytes < need) return fail(PSP_E_NOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
-    char* w = (char*)ws;
-    for (int32_t i = 0; i < nitems; ++i) {
-        const psp_group_item_t& it = items[i];
-        const size_t wi = (psp_workspace_bytes(it.plan, it.path, it.batch, K, nrhs, 0) + 255) / 256 * 256;
-        psp_status st = psp_solve_batched(it.plan, it.path, it.batch, it.values, K, eps, it.d, nrhs, it.B, it.X,
-                                          it.info, w, wi, stream);
-        if (st != PSP_OK) return fail(st, "psp_solve_group: item " + std::to_string(i) + ": " + g_err);
-        w += wi;
-    }
-    return PSP_OK;
 }
 
 psp_status psp_tune(psp_plan p, int32_t batch, const double* values, int32_t K, const double* eps, const double* d,
@@ -456,13 +455,13 @@ psp_status psp_factor(psp_plan p, int32_t path, int32_t batch, const double* val
     f->plan = p; f->path = pth; f->batch = batch; f->K = K; f->es = es;
     f->ws = (char*)ws; f->ws_bytes = ws_bytes; f->info = info;
     if (pth == PSP_PATH_DENSE) {
-        if (s.n > 4096) return fail(PSP_E_UNSUPPORTED, "dense path supports n <= 4096");
+        if (s.n > kDenseMaxN) return fail(PSP_E_UNSUPPORTED, "dense path supports n <= 4096");
         // the nrhs capacity is whatever the workspace holds beyond the factors
         const DenseLayout L0 = dense_layout(s, batch, K, 0, 1);
         if (ws_bytes < (size_t)L0.total) return fail(PSP_E_NOMEM, "workspace too small for the factors");
         const int64_t per_rhs = (int64_t)batch * K * L0.ld * 8;
         f->nrhs_cap = (int32_t)std::min<int64_t>(64, ((int64_t)ws_bytes - L0.off_tmp) / per_rhs);
-        if (psp_status r = upload_plan(p, L0.ld)) return r;
+        if (psp_status r = require_upload(p)) return r;
         f->n_pad = L0.n_pad; f->ld = L0.ld; f->slot_stride = L0.slot_stride;
         f->off_slots = L0.off_slots; f->off_tmp = L0.off_tmp;
         DenseArgs a{};
@@ -477,11 +476,7 @@ psp_status psp_factor(psp_plan p, int32_t path, int32_t batch, const double* val
     } else if (pth == PSP_PATH_SPARSE) {
         const size_t need0 = sparse_workspace_bytes(s, batch, K, 0, 1);
         if (ws_bytes < need0) return fail(PSP_E_NOMEM, "workspace too small for the factors");
-        if (psp_status r = upload_plan(p, 0)) return r;
-        {
-            std::lock_guard<std::mutex> g(p->mu);
-            HIP_TRY(sparse_upload(s, p->sp), "sparse plan upload");
-        }
+        if (psp_status r = require_upload(p)) return r;
         f->nrhs_cap = sparse_nrhs_capacity(s, batch, K, ws_bytes);
         HIP_TRY(sparse_factor(s, p->sp, batch, values, es, d, info, ws, st), "sparse factor launch");
     } else {
@@ -532,7 +527,7 @@ psp_status psp_residual(psp_plan p, int32_t batch, const double* values, int32_t
     if (!R && p->sym.n > kResLds)
         return fail(PSP_E_UNSUPPORTED, "psp_residual: n > " + std::to_string(kResLds) + " needs the R output");
     if (psp_status st = check_prior_hip()) return st;
-    if (psp_status r = upload_plan(p, 0)) return r;
+    if (psp_status r = require_upload(p)) return r;
     const Symbolic& s = p->sym;
     ResArgs a{};
     a.n = s.n; a.nnz = s.nnz; a.batch = batch; a.nrhs = nrhs;
@@ -636,32 +631,34 @@ struct psp_pf_s {
     psp_plan plan = nullptr;
     int32_t N = 0, ny = 0, pos_ref = 0;
     int device = -1;
-    int32_t *d_yptr = nullptr, *d_ycol = nullptr, *d_pv = nullptr, *d_poslam = nullptr;
-    double *d_g = nullptr, *d_b = nullptr;
-    int4* d_pos = nullptr;
-    int32_t* h_status = nullptr;   // pinned, h_cap entries
-    int32_t* h_idx = nullptr;      // pinned, h_cap entries: running scenarios
-    int32_t h_cap = 0;
-    ~psp_pf_s() {
-        if (device >= 0) {
-            int cur = 0;
-            (void)hipGetDevice(&cur);
-            (void)hipSetDevice(device);
-            (void)hipFree(d_yptr);
-            (void)hipFree(d_ycol);
-            (void)hipFree(d_pv);
-            (void)hipFree(d_poslam);
-            (void)hipFree(d_g);
-            (void)hipFree(d_b);
-            (void)hipFree(d_pos);
-            (void)hipHostFree(h_status);
-            (void)hipHostFree(h_idx);
-            (void)hipSetDevice(cur);
-        }
-    }
+    // network arrays in the caller's device buffer (psp_pf_device_bytes)
+    const int32_t *d_yptr = nullptr, *d_ycol = nullptr, *d_pv = nullptr, *d_poslam = nullptr;
+    const double *d_g = nullptr, *d_b = nullptr;
+    const int4* d_pos = nullptr;
+    std::vector<int32_t> h_status, h_idx;   // host copies: statuses, running scenarios
 };
 
 namespace {
+
+// Byte offsets of the network arrays in the caller's buffer.
+struct PfNetLayout {
+    int64_t yptr, ycol, pv, poslam, pos, g, b, total;
+};
+
+PfNetLayout pf_net_layout(int64_t N, int64_t ny) {
+    PfNetLayout L{};
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) { const int64_t o = off; off = align_up(off + std::max<int64_t>(bytes, 1), kAlign); return o; };
+    L.yptr = take(4 * (N + 1));
+    L.ycol = take(4 * ny);
+    L.pv = take(4 * N);
+    L.poslam = take(4 * N);
+    L.pos = take(16 * ny);
+    L.g = take(8 * ny);
+    L.b = take(8 * ny);
+    L.total = off;
+    return L;
+}
 
 struct PfLayout {
     int64_t off_F, off_J, off_dx, off_info, off_idx, total;
@@ -686,13 +683,6 @@ PfLayout pf_layout(psp_pf pf, int32_t path, int32_t batch, int32_t K) {
     return L;
 }
 
-template <class T>
-psp_status pf_upload(T** dst, const T* src, size_t count) {
-    HIP_TRY(hipMalloc((void**)dst, sizeof(T) * std::max<size_t>(count, 1)), "hipMalloc(power flow)");
-    if (count) HIP_TRY(hipMemcpy(*dst, src, sizeof(T) * count, hipMemcpyHostToDevice), "hipMemcpy(power flow)");
-    return PSP_OK;
-}
-
 PfArgs pf_args(psp_pf pf, int32_t batch, const double* x, const double* spec, const double* part, double* F,
                double* J, double* fnorm) {
     PfArgs a{};
@@ -714,17 +704,26 @@ psp_status pf_device_check(psp_pf pf) {
 
 extern "C" {
 
+size_t psp_pf_device_bytes(int32_t nbus, int32_t nnz_y) {
+    if (nbus < 1 || nnz_y < 0) return 0;
+    return (size_t)pf_net_layout(nbus, nnz_y).total;
+}
+
 psp_status psp_pf_create(psp_plan plan, int32_t nbus, const int32_t* yp, const int32_t* yc, const double* g,
-                         const double* b, const int32_t* pv, psp_pf* out) {
+                         const double* b, const int32_t* pv, void* dev, size_t dev_bytes, void* stream, psp_pf* out) {
     if (!out) return fail(PSP_E_INVALID, "out must not be NULL");
     *out = nullptr;
-    if (!plan || nbus < 1 || !yp || !yc || !g || !b || !pv)
+    if (!plan || nbus < 1 || !yp || !yc || !g || !b || !pv || !dev)
         return fail(PSP_E_INVALID, "psp_pf_create: NULL argument or nbus < 1");
+    if (((uintptr_t)dev & 255) != 0) return fail(PSP_E_INVALID, "psp_pf_create: device buffer must be 256-byte aligned");
     const Symbolic& s = plan->sym;
     if ((int64_t)s.n != 2LL * nbus + 1) return fail(PSP_E_INVALID, "psp_pf_create: plan order must be 2*nbus + 1");
     const std::string why = validate_csr(nbus, yp, yc);
     if (!why.empty()) return fail(PSP_E_INVALID, "psp_pf_create: admittance matrix: " + why);
     const int32_t N = nbus, ny = yp[N];
+    const PfNetLayout NL = pf_net_layout(N, ny);
+    if (dev_bytes < (size_t)NL.total)
+        return fail(PSP_E_NOMEM, "psp_pf_create: device buffer too small: need " + std::to_string(NL.total) + " bytes");
     for (int32_t e = 0; e < ny; ++e)
         if (!std::isfinite(g[e]) || !std::isfinite(b[e]))
             return fail(PSP_E_INVALID, "psp_pf_create: non-finite admittance");
@@ -755,19 +754,31 @@ psp_status psp_pf_create(psp_plan plan, int32_t nbus, const int32_t* yp, const i
     }
     const int32_t pref = find(2 * N, 0);
     if (pref < 0) return fail(PSP_E_INVALID, "psp_pf_create: plan pattern lacks the angle-reference entry");
-    std::vector<int32_t> pvv(pv, pv + N);
     if (psp_status st = check_prior_hip()) return st;
-    if (psp_status r = upload_plan(plan, 0)) return r;   // also checks the device
+    if (psp_status r = require_upload(plan)) return r;   // also checks the device
+    // one host image of the network arrays, copied with one transfer
+    std::vector<char> host((size_t)NL.total, 0);
+    std::memcpy(host.data() + NL.yptr, yp, 4 * (size_t)(N + 1));
+    std::memcpy(host.data() + NL.ycol, yc, 4 * (size_t)ny);
+    std::memcpy(host.data() + NL.pv, pv, 4 * (size_t)N);
+    std::memcpy(host.data() + NL.poslam, poslam.data(), 4 * (size_t)N);
+    std::memcpy(host.data() + NL.pos, pos.data(), 16 * (size_t)ny);
+    std::memcpy(host.data() + NL.g, g, 8 * (size_t)ny);
+    std::memcpy(host.data() + NL.b, b, 8 * (size_t)ny);
+    const hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(hipMemcpyAsync(dev, host.data(), host.size(), hipMemcpyHostToDevice, st), "hipMemcpyAsync(power flow)");
+    HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize(power flow)");
     auto pf = std::make_unique<psp_pf_s>();
     pf->plan = plan; pf->N = N; pf->ny = ny; pf->pos_ref = pref;
     HIP_TRY(hipGetDevice(&pf->device), "hipGetDevice");
-    if (psp_status r = pf_upload(&pf->d_yptr, yp, N + 1)) return r;
-    if (psp_status r = pf_upload(&pf->d_ycol, yc, ny)) return r;
-    if (psp_status r = pf_upload(&pf->d_g, g, ny)) return r;
-    if (psp_status r = pf_upload(&pf->d_b, b, ny)) return r;
-    if (psp_status r = pf_upload(&pf->d_pv, pvv.data(), N)) return r;
-    if (psp_status r = pf_upload(&pf->d_poslam, poslam.data(), N)) return r;
-    if (psp_status r = pf_upload(&pf->d_pos, pos.data(), ny)) return r;
+    const char* base = (const char*)dev;
+    pf->d_yptr = (const int32_t*)(base + NL.yptr);
+    pf->d_ycol = (const int32_t*)(base + NL.ycol);
+    pf->d_pv = (const int32_t*)(base + NL.pv);
+    pf->d_poslam = (const int32_t*)(base + NL.poslam);
+    pf->d_pos = (const int4*)(base + NL.pos);
+    pf->d_g = (const double*)(base + NL.g);
+    pf->d_b = (const double*)(base + NL.b);
     *out = pf.release();
     return PSP_OK;
 }
@@ -802,15 +813,16 @@ psp_status psp_pf_newton(psp_pf pf, int32_t path, int32_t batch, int32_t K, cons
     if (split_path(path).base < 0 && path != PSP_PATH_AUTO) return fail(PSP_E_INVALID, "unknown path");
     const PfLayout L = pf_layout(pf, path, batch, K);
     if (ws_bytes < (size_t)L.total) return fail(PSP_E_NOMEM, "workspace too small: need " + std::to_string(L.total) + " bytes");
-    if (pf->h_cap < batch) {
-        if (pf->h_status) HIP_TRY(hipHostFree(pf->h_status), "hipHostFree");
-        if (pf->h_idx) HIP_TRY(hipHostFree(pf->h_idx), "hipHostFree");
-        pf->h_status = pf->h_idx = nullptr;
-        pf->h_cap = 0;
-        HIP_TRY(hipHostMalloc((void**)&pf->h_status, sizeof(int32_t) * batch), "hipHostMalloc");
-        HIP_TRY(hipHostMalloc((void**)&pf->h_idx, sizeof(int32_t) * batch), "hipHostMalloc");
-        pf->h_cap = batch;
+    try {
+        if ((int32_t)pf->h_status.size() < batch) {
+            pf->h_status.resize(batch);
+            pf->h_idx.resize(batch);
+        }
+    } catch (const std::bad_alloc&) {
+        return fail(PSP_E_NOMEM, "psp_pf_newton: host allocation failed");
     }
+    int32_t* h_status = pf->h_status.data();
+    int32_t* h_idx = pf->h_idx.data();
     char* w = (char*)ws;
     double* F = (double*)(w + L.off_F);
     double* J = (double*)(w + L.off_J);
@@ -824,18 +836,18 @@ psp_status psp_pf_newton(psp_pf pf, int32_t path, int32_t batch, int32_t K, cons
     // still running, solve those m systems and update.  A scenario that converges
     // at this evaluation is solved once more but not updated (its status changed).
     int32_t m = batch;
-    for (int32_t r = 0; r < batch; ++r) pf->h_idx[r] = r;
+    for (int32_t r = 0; r < batch; ++r) h_idx[r] = r;
     for (int32_t it = 0;; ++it) {
-        HIP_TRY(hipMemcpyAsync(idx, pf->h_idx, sizeof(int32_t) * m, hipMemcpyHostToDevice, st), "hipMemcpyAsync(idx)");
+        HIP_TRY(hipMemcpyAsync(idx, h_idx, sizeof(int32_t) * m, hipMemcpyHostToDevice, st), "hipMemcpyAsync(idx)");
         PfArgs a = pf_args(pf, m, x, spec, part, F, J, fnorm);
         a.idx = idx;
         a.status = status;
         a.tol = tol;
         HIP_TRY(launch_pf_eval(a, st), "power-flow launch");
-        HIP_TRY(hipMemcpyAsync(pf->h_status, status, sizeof(int32_t) * batch, hipMemcpyDeviceToHost, st),
+        HIP_TRY(hipMemcpyAsync(h_status, status, sizeof(int32_t) * batch, hipMemcpyDeviceToHost, st),
                 "hipMemcpyAsync(status)");
         HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
-        const bool running = std::any_of(pf->h_status, pf->h_status + batch, [](int32_t v) { return v == kPfRunning; });
+        const bool running = std::any_of(h_status, h_status + batch, [](int32_t v) { return v == kPfRunning; });
         if (!running || it == max_iter) break;
         if (psp_status r = psp_solve_batched(pf->plan, path, m, J, K, eps, d, 1, F, dx, info, ws, L.solve_bytes, stream))
             return r;
@@ -843,10 +855,189 @@ psp_status psp_pf_newton(psp_pf pf, int32_t path, int32_t batch, int32_t K, cons
         // the idx copy above has completed (the stream was synchronised), so the list can be rebuilt
         m = 0;
         for (int32_t r = 0; r < batch; ++r)
-            if (pf->h_status[r] == kPfRunning) pf->h_idx[m++] = r;
+            if (h_status[r] == kPfRunning) h_idx[m++] = r;
     }
     HIP_TRY(launch_pf_status(batch, status, iters, 1, st), "power-flow status launch");
     return PSP_OK;
 }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- groups
+struct psp_group_s {
+    std::vector<psp_group_shape_t> items;   // path resolved at creation
+    std::vector<size_t> ws_off, ws_len;     // each item's slice of the workspace
+    std::vector<int32_t> order, lane;       // LPT order; stream lane of each item (0: the caller's)
+    size_t ws_total = 0;
+    int32_t K = 0, nrhs = 0, nlanes = 1, device = -1;
+    std::vector<double> eps;
+    hipStream_t streams[4] = {};            // lanes 1..nlanes-1 (lane 0 is the caller's stream)
+    hipEvent_t fork = nullptr, join[4] = {};
+    ~psp_group_s() {
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        if (device >= 0) (void)hipSetDevice(device);
+        for (int l = 1; l < nlanes; ++l) {
+            if (join[l]) (void)hipEventDestroy(join[l]);
+            if (streams[l]) (void)hipStreamDestroy(streams[l]);
+        }
+        if (fork) (void)hipEventDestroy(fork);
+        if (device >= 0) (void)hipSetDevice(cur);
+    }
+};
+
+namespace {
+
+constexpr int kGroupLanes = 4;   // the caller's stream and three more (GPU_MAX_HW_QUEUES is 4)
+
+// Relative cost of an item for the longest-first ordering: sparse flops of one
+// factorisation plus the substitutions, times the systems of the item.
+double item_cost(const psp_group_shape_t& it, int32_t K, int32_t nrhs) {
+    const Symbolic& s = it.plan->sym;
+    const double per = (double)s.flops_sparse + 4.0 * (double)s.l_ptr[s.n] * nrhs + 64.0 * s.n;
+    return per * it.batch * K;
+}
+
+psp_status group_enqueue(psp_group g, const psp_group_task_t* tasks, char* ws, hipStream_t st) {
+    const bool forked = g->nlanes > 1;
+    if (forked) {
+        HIP_TRY(hipEventRecord(g->fork, st), "hipEventRecord(fork)");
+        for (int l = 1; l < g->nlanes; ++l) HIP_TRY(hipStreamWaitEvent(g->streams[l], g->fork, 0), "hipStreamWaitEvent");
+    }
+    psp_status bad = PSP_OK;
+    for (int32_t i : g->order) {
+        const psp_group_shape_t& it = g->items[i];
+        const psp_group_task_t& t = tasks[i];
+        const hipStream_t ls = g->lane[i] == 0 ? st : g->streams[g->lane[i]];
+        bad = psp_solve_batched(it.plan, it.path, it.batch, t.values, g->K, g->eps.data(), t.d, g->nrhs, t.B, t.X,
+                                t.info, ws + g->ws_off[i], g->ws_len[i], (void*)ls);
+        if (bad != PSP_OK) {
+            g_err = "group item " + std::to_string(i) + ": " + g_err;
+            break;
+        }
+    }
+    // join every lane back into the caller's stream, also after a failure
+    if (forked)
+        for (int l = 1; l < g->nlanes; ++l) {
+            HIP_TRY(hipEventRecord(g->join[l], g->streams[l]), "hipEventRecord(join)");
+            HIP_TRY(hipStreamWaitEvent(st, g->join[l], 0), "hipStreamWaitEvent");
+        }
+    return bad;
+}
+
+psp_status group_check(psp_group g, const psp_group_task_t* tasks, void* ws, size_t ws_bytes) {
+    if (!g || !tasks || !ws) return fail(PSP_E_INVALID, "psp_group: NULL argument");
+    if (ws_bytes < g->ws_total)
+        return fail(PSP_E_NOMEM, "workspace too small: need " + std::to_string(g->ws_total) + " bytes");
+    if (((uintptr_t)ws & 255) != 0) return fail(PSP_E_INVALID, "psp_group: workspace must be 256-byte aligned");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    if (dev != g->device) return fail(PSP_E_STATE, "group was created on another device");
+    for (size_t i = 0; i < g->items.size(); ++i)
+        if (!tasks[i].values || !tasks[i].B || !tasks[i].X || !tasks[i].info)
+            return fail(PSP_E_INVALID, "psp_group: task " + std::to_string(i) + " has a NULL pointer");
+    return PSP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+psp_status psp_group_create(int32_t nitems, const psp_group_shape_t* shapes, int32_t K, const double* eps, int32_t nrhs,
+                            psp_group* out) {
+    if (!out) return fail(PSP_E_INVALID, "out must not be NULL");
+    *out = nullptr;
+    if (nitems < 1 || !shapes) return fail(PSP_E_INVALID, "psp_group_create: no items");
+    if (nrhs < 1 || nrhs > 64) return fail(PSP_E_INVALID, "psp_group_create: nrhs must be in 1..64");
+    EpsSet es;
+    if (psp_status st = make_eps(K, eps, es)) return st;
+    for (int32_t i = 0; i < nitems; ++i)
+        if (!shapes[i].plan || shapes[i].batch < 1)
+            return fail(PSP_E_INVALID, "psp_group_create: item " + std::to_string(i) + " has no plan or batch < 1");
+    auto g = std::make_unique<psp_group_s>();
+    HIP_TRY(hipGetDevice(&g->device), "hipGetDevice");
+    g->K = K;
+    g->nrhs = nrhs;
+    g->eps.assign(eps, eps + K);
+    std::vector<double> cost(nitems);
+    for (int32_t i = 0; i < nitems; ++i) {
+        psp_group_shape_t it = shapes[i];
+        if (psp_status r = require_upload(it.plan)) return fail(r, "psp_group_create: item " + std::to_string(i) + ": " + g_err);
+        it.path = resolve_path(it.plan, it.path, it.batch, K, nrhs);
+        if (split_path(it.path).base < 0) return fail(PSP_E_INVALID, "psp_group_create: unknown path");
+        const size_t w = psp_workspace_bytes(it.plan, it.path, it.batch, K, nrhs, 0);
+        if (w == 0) return fail(PSP_E_INVALID, "psp_group_create: item " + std::to_string(i) + " cannot run on its path");
+        g->items.push_back(it);
+        g->ws_off.push_back(g->ws_total);
+        g->ws_len.push_back(w);
+        g->ws_total += (size_t)align_up((int64_t)w, kAlign);
+        cost[i] = item_cost(it, K, nrhs);
+    }
+    // longest item first, each to the least-loaded lane
+    g->order.resize(nitems);
+    for (int32_t i = 0; i < nitems; ++i) g->order[i] = i;
+    std::stable_sort(g->order.begin(), g->order.end(), [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
+    g->nlanes = std::min<int32_t>(kGroupLanes, nitems);
+    std::vector<double> load(g->nlanes, 0.0);
+    g->lane.assign(nitems, 0);
+    for (int32_t i : g->order) {
+        const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        g->lane[i] = l;
+        load[l] += cost[i];
+    }
+    if (g->nlanes > 1) {
+        HIP_TRY(hipEventCreateWithFlags(&g->fork, hipEventDisableTiming), "hipEventCreate");
+        for (int l = 1; l < g->nlanes; ++l) {
+            HIP_TRY(hipStreamCreateWithFlags(&g->streams[l], hipStreamNonBlocking), "hipStreamCreate");
+            HIP_TRY(hipEventCreateWithFlags(&g->join[l], hipEventDisableTiming), "hipEventCreate");
+        }
+    }
+    *out = g.release();
+    return PSP_OK;
+}
+
+size_t psp_group_workspace_bytes(psp_group g) { return g ? std::max<size_t>(g->ws_total, 256) : 0; }
+
+psp_status psp_group_run(psp_group g, const psp_group_task_t* tasks, void* ws, size_t ws_bytes, void* stream) {
+    if (psp_status r = group_check(g, tasks, ws, ws_bytes)) return r;
+    if (psp_status st = check_prior_hip()) return st;
+    return group_enqueue(g, tasks, (char*)ws, (hipStream_t)stream);
+}
+
+psp_status psp_group_capture(psp_group g, const psp_group_task_t* tasks, void* ws, size_t ws_bytes, void* stream,
+                             void** graph_exec) {
+    if (!graph_exec) return fail(PSP_E_INVALID, "psp_group_capture: NULL output");
+    *graph_exec = nullptr;
+    if (psp_status r = group_check(g, tasks, ws, ws_bytes)) return r;
+    if (psp_status st = check_prior_hip()) return st;
+    const hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    const psp_status r = group_enqueue(g, tasks, (char*)ws, st);
+    hipGraph_t graph = nullptr;
+    const hipError_t ee = hipStreamEndCapture(st, &graph);
+    if (r != PSP_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return r;
+    }
+    if (ee != hipSuccess) return hip_fail(ee, "hipStreamEndCapture");
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) return hip_fail(ei, "hipGraphInstantiate");
+    *graph_exec = (void*)exec;
+    return PSP_OK;
+}
+
+psp_status psp_graph_launch(void* graph_exec, void* stream) {
+    if (!graph_exec) return fail(PSP_E_INVALID, "psp_graph_launch: NULL graph");
+    HIP_TRY(hipGraphLaunch((hipGraphExec_t)graph_exec, (hipStream_t)stream), "hipGraphLaunch");
+    return PSP_OK;
+}
+
+void psp_graph_destroy(void* graph_exec) {
+    if (graph_exec) (void)hipGraphExecDestroy((hipGraphExec_t)graph_exec);
+}
+
+void psp_group_destroy(psp_group g) { delete g; }
 
 }  // extern "C"

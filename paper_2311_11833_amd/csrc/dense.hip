@@ -465,7 +465,12 @@ hipError_t launch_grad_values(int32_t n, int32_t nnz, int32_t batch, int32_t nrh
 }
 
 hipError_t dense_occupancy(int* blocks_per_cu) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, dense_factor_solve_kernel, WG, kLdsDense);
+    // queried once per process (a launch-independent property of the compiled kernel)
+    static int occ = 0;
+    static const hipError_t e =
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, dense_factor_solve_kernel, WG, kLdsDense);
+    *blocks_per_cu = occ;
+    return e;
 }
 
 }  // namespace psp

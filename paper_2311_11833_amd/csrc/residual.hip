@@ -51,7 +51,9 @@ hipError_t launch_residual(ResArgs a, hipStream_t st) {
     a.stage = a.n <= kResLds ? 1 : 0;
     const int lds = a.stage ? a.n * 8 : 0;
     if (lds > 48 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void*)residual_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        // once per process, for the largest staged size
+        static const hipError_t e = hipFuncSetAttribute((const void*)residual_kernel,
+                                                         hipFuncAttributeMaxDynamicSharedMemorySize, kResLds * 8);
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(residual_kernel, dim3(a.batch * a.nrhs), dim3(kResThreads), lds, st, a);

@@ -2,6 +2,7 @@
 #pragma once
 
 #include "common.h"
+#include "image.h"
 #include "plan.h"
 
 namespace psp {
@@ -51,32 +52,35 @@ struct StepIdx {
     const int32_t* slot_u = nullptr;  // nnzl: the same for U
 };
 
+// The sparse path's part of the plan: pointers into the uploaded plan image
+// (set by relocation) and host copies of the level boundaries.
 struct SparseDevice {
-    bool ready = false;
-    int32_t* buf = nullptr;
+    bool imaged = false;
     SpIdx idx{};
     std::vector<int32_t> h_lev_ptr[3];   // host copies for per-level launches
     std::vector<int32_t> h_lpos_ptr;
-    int32_t* st_buf = nullptr;           // step schedule (absent when the system does not fit in LDS)
-    StepIdx st{};
-    int32_t* pair_buf = nullptr;         // update lists built on the device (too large for the host build)
+    StepIdx st{};                        // step schedule (nsteps = 0 when it does not fit in LDS)
 };
 
 enum { kVarLds = 0, kVarGlobal = 1, kVarBatched = 2, kVarGrouped = 3, kVarSteps = 4 };
 int sparse_variant(const Symbolic& s, int64_t ntasks, int32_t nrhs, int forced);
 
-hipError_t sparse_upload(const Symbolic& s, SparseDevice& d);
-// step schedule (steps.hip): built by sparse_upload when the system fits
+// Appends the sparse path's arrays (and the step schedule, when it fits) to the
+// plan image and binds d's pointers to them.
+void sparse_image(const Symbolic& s, PlanImage& img, SparseDevice& d);
+// step schedule (steps.hip): built by sparse_image when the system fits
 bool steps_fit(const Symbolic& s, int32_t nrhs);
 bool steps_ready(const SparseDevice& d);   // schedule built (it may not fit even when steps_fit holds)
-hipError_t steps_upload(const Symbolic& s, const std::vector<int32_t>& r_pos, SparseDevice& d);
-void steps_free(SparseDevice& d);
+void steps_image(const Symbolic& s, const std::vector<int32_t>& r_pos, PlanImage& img, SparseDevice& d);
+// Set the kernels' dynamic LDS limits once per process (idempotent).
+hipError_t sparse_kernel_attrs();
+hipError_t steps_kernel_attrs();
 // one launch; X (batch x n) combined in-kernel when per_jacobian, else Xk (batch x K x n) is written
 int steps_per_cu(const SparseDevice& d);   // step-kernel workgroups resident per CU (1 or 2)
+int64_t steps_lds_bytes(const SparseDevice& d);   // dynamic LDS of one step-kernel workgroup (0: no schedule)
 hipError_t steps_run(const SparseDevice& d, int32_t nnz, int32_t batch, const double* values, const EpsSet& es,
                      const double* dvec, const double* B, double* X, double* Xk, int32_t* info, bool per_jacobian,
                      hipStream_t st);
-void sparse_free(SparseDevice& d);
 bool sparse_fits_lds(const Symbolic& s, int32_t nrhs);
 size_t sparse_workspace_bytes(const Symbolic& s, int32_t batch, int32_t K, int32_t nrhs, int32_t keep, int forced = -1);
 int32_t sparse_nrhs_capacity(const Symbolic& s, int32_t batch, int32_t K, size_t ws_bytes);

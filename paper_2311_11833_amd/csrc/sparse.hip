@@ -44,10 +44,10 @@ namespace {
 constexpr int kLdsLimit = 152 * 1024;    // bytes of LDS the in-LDS kernel may use
 constexpr int kLdsThreads = 512;
 constexpr int kThreads = 256;
-constexpr int64_t kMaxPairs = 32LL << 20;   // update pairs built on the host at most (256 MB)
-// Larger update lists are built on the device (count, prefix sum, write) up
-// to int32 offsets and this many bytes of HBM.
-constexpr int64_t kMaxDevPairBytes = 24LL << 30;
+// Update lists (precomputed pairs of every factor entry's dot product) are kept
+// for at most this many pairs (256 MB of the plan image); beyond, the dot
+// products merge the two rows on the fly.
+constexpr int64_t kMaxPairs = 32LL << 20;
 
 __device__ __forceinline__ double merge_dot(const SpIdx& ix, int a, int b, const double* lv, const double* uv,
                                             double acc) {
@@ -612,104 +612,6 @@ __global__ void il_combine_kernel(IlArgs a, EpsSet es) {
     }
 }
 
-// Update lists on the device.  Item id: diagonal j -> j, U position t -> n + t,
-// L position t -> n + nnzl + t (the order of the host build).  Entry t of
-// column j, row m: U pairs (pos(j,k), pos(m,k)), L pairs (pos(m,k), pos(j,k)),
-// k in R_j ^ R_m ascending; the U and L items of t have the same length.
-__global__ void pair_count_kernel(SpIdx ix, int32_t* cnt) {
-    const int n = ix.n, nl = ix.nnzl;
-    for (int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; id < (int64_t)n + nl;
-         id += (int64_t)gridDim.x * blockDim.x) {
-        if (id < n) {
-            cnt[id] = ix.r_ptr[id + 1] - ix.r_ptr[id];
-            continue;
-        }
-        const int t = (int)(id - n), j = ix.col_of[t], m = ix.l_idx[t];
-        int p = ix.r_ptr[j], pe = ix.r_ptr[j + 1], q = ix.r_ptr[m], qe = ix.r_ptr[m + 1], c = 0;
-        while (p < pe && q < qe) {
-            const int kp = ix.r_idx[p], kq = ix.r_idx[q];
-            c += kp == kq;
-            p += kp <= kq;
-            q += kq <= kp;
-        }
-        cnt[n + t] = c;
-        cnt[n + nl + t] = c;
-    }
-}
-
-__global__ void pair_write_kernel(SpIdx ix, const int32_t* ptr, int2* pairs) {
-    const int n = ix.n, nl = ix.nnzl;
-    for (int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; id < (int64_t)n + nl;
-         id += (int64_t)gridDim.x * blockDim.x) {
-        if (id < n) {
-            int2* out = pairs + ptr[id];
-            for (int p = ix.r_ptr[id]; p < ix.r_ptr[id + 1]; ++p) {
-                const int t = ix.r_pos[p];
-                *out++ = make_int2(t, t);
-            }
-            continue;
-        }
-        const int t = (int)(id - n), j = ix.col_of[t], m = ix.l_idx[t];
-        int2* ou = pairs + ptr[n + t];
-        int2* ol = pairs + ptr[n + nl + t];
-        int p = ix.r_ptr[j], pe = ix.r_ptr[j + 1], q = ix.r_ptr[m], qe = ix.r_ptr[m + 1];
-        while (p < pe && q < qe) {
-            const int kp = ix.r_idx[p], kq = ix.r_idx[q];
-            if (kp == kq) {
-                *ou++ = make_int2(ix.r_pos[p], ix.r_pos[q]);
-                *ol++ = make_int2(ix.r_pos[q], ix.r_pos[p]);
-            }
-            p += kp <= kq;
-            q += kq <= kp;
-        }
-    }
-}
-
-// Builds the update lists on the device when they are too large for the host
-// build; leaves ix.use_pairs = 0 when they do not fit either.
-hipError_t build_pairs_on_device(const Symbolic& s, SparseDevice& d) {
-    const int n = s.n, nl = s.l_ptr[n];
-    const int64_t items = (int64_t)n + 2 * (int64_t)nl;
-    const int64_t est = (s.flops_sparse - nl) / 2;
-    if (est <= kMaxPairs || est * 8 > kMaxDevPairBytes || est >= INT32_MAX) return hipSuccess;
-    int32_t* cnt = nullptr;
-    hipError_t e = hipMalloc(&cnt, sizeof(int32_t) * (items + 1));
-    if (e != hipSuccess) return e;
-    const int threads = 256;
-    const int grid = (int)std::min<int64_t>(((int64_t)n + nl + threads - 1) / threads, 65536);
-    hipLaunchKernelGGL(pair_count_kernel, dim3(grid), dim3(threads), 0, 0, d.idx, cnt);
-    std::vector<int32_t> h(items + 1, 0);
-    e = hipGetLastError();
-    if (e == hipSuccess) e = hipMemcpy(h.data(), cnt, sizeof(int32_t) * items, hipMemcpyDeviceToHost);
-    if (e != hipSuccess) { (void)hipFree(cnt); return e; }
-    int64_t total = 0;
-    for (int64_t i = 0; i < items; ++i) {
-        const int32_t c = h[i];
-        h[i] = (int32_t)total;
-        total += c;
-        if (total >= INT32_MAX) { (void)hipFree(cnt); return hipSuccess; }   // offsets would not fit: no lists
-    }
-    h[items] = (int32_t)total;
-    const size_t ptr_words = (size_t)(items + 1 + 63) / 64 * 64;
-    e = hipMalloc(&d.pair_buf, sizeof(int32_t) * ptr_words + sizeof(int2) * (size_t)std::max<int64_t>(total, 1));
-    if (e == hipSuccess) e = hipMemcpy(d.pair_buf, h.data(), sizeof(int32_t) * (items + 1), hipMemcpyHostToDevice);
-    (void)hipFree(cnt);
-    if (e != hipSuccess) {
-        if (d.pair_buf) (void)hipFree(d.pair_buf);
-        d.pair_buf = nullptr;
-        return e;
-    }
-    int2* pairs = (int2*)(d.pair_buf + ptr_words);
-    hipLaunchKernelGGL(pair_write_kernel, dim3(grid), dim3(threads), 0, 0, d.idx, d.pair_buf, pairs);
-    e = hipGetLastError();
-    if (e == hipSuccess) e = hipDeviceSynchronize();
-    if (e != hipSuccess) return e;
-    d.idx.pair_ptr = d.pair_buf;
-    d.idx.pairs = pairs;
-    d.idx.use_pairs = 1;
-    return hipSuccess;
-}
-
 int grid_for(int64_t items, int threads) {
     int64_t g = (items + threads - 1) / threads;
     return (int)std::max<int64_t>(1, std::min<int64_t>(g, 65536));
@@ -869,8 +771,8 @@ int sparse_variant(const Symbolic& s, int64_t ntasks, int32_t nrhs, int forced) 
     return variant_of(s, ntasks, nrhs, forced);
 }
 
-hipError_t sparse_upload(const Symbolic& s, SparseDevice& d) {
-    if (d.ready) return hipSuccess;
+void sparse_image(const Symbolic& s, PlanImage& img, SparseDevice& d) {
+    if (d.imaged) return;
     const int n = s.n, nl = s.l_ptr[n];
     std::vector<int32_t> col_of(nl), r_pos(nl), src_l(nl, -1), src_u(nl, -1), src_d(n, -1);
     for (int j = 0; j < n; ++j)
@@ -926,58 +828,41 @@ hipError_t sparse_upload(const Symbolic& s, SparseDevice& d) {
         for (int t = 0; t < nl; ++t, ++id) { pair_ptr[id] = (int32_t)(pairs.size() / 2); push_merge(s.l_idx[t], col_of[t]); }
         pair_ptr[id] = (int32_t)(pairs.size() / 2);
     }
-    std::vector<const std::vector<int32_t>*> parts = {&s.perm, &s.l_ptr, &s.l_idx, &col_of, &s.lrow_ptr, &s.lrow_idx,
-                                                      &r_pos, &src_l, &src_u, &src_d};
-    for (int t = 0; t < 3; ++t) { parts.push_back(&s.lev_ptr[t]); parts.push_back(&s.lev_idx[t]); }
-    parts.push_back(&lpos_ptr);
-    parts.push_back(&lpos);
-    parts.push_back(&pair_ptr);
-    parts.push_back(&pairs);
-    std::vector<int64_t> off;
-    int64_t total = 0;
-    for (auto* p : parts) { off.push_back(total); total += ((int64_t)p->size() + 63) / 64 * 64; }
-    std::vector<int32_t> host(std::max<int64_t>(total, 1), 0);
-    for (size_t i = 0; i < parts.size(); ++i) std::copy(parts[i]->begin(), parts[i]->end(), host.begin() + off[i]);
-    hipError_t e = hipMalloc(&d.buf, sizeof(int32_t) * host.size());
-    if (e != hipSuccess) return e;
-    e = hipMemcpy(d.buf, host.data(), sizeof(int32_t) * host.size(), hipMemcpyHostToDevice);
-    if (e != hipSuccess) return e;
-    int k = 0;
-    auto ptr = [&](void) { return (const int32_t*)(d.buf + off[k++]); };
     SpIdx& ix = d.idx;
     ix.n = n;
     ix.nnzl = nl;
-    ix.perm = ptr(); ix.l_ptr = ptr(); ix.l_idx = ptr(); ix.col_of = ptr(); ix.r_ptr = ptr(); ix.r_idx = ptr();
-    ix.r_pos = ptr(); ix.src_l = ptr(); ix.src_u = ptr(); ix.src_d = ptr();
+    img.bind(&ix.perm, img.put(s.perm));
+    img.bind(&ix.l_ptr, img.put(s.l_ptr));
+    img.bind(&ix.l_idx, img.put(s.l_idx));
+    img.bind(&ix.col_of, img.put(col_of));
+    img.bind(&ix.r_ptr, img.put(s.lrow_ptr));
+    img.bind(&ix.r_idx, img.put(s.lrow_idx));
+    img.bind(&ix.r_pos, img.put(r_pos));
+    img.bind(&ix.src_l, img.put(src_l));
+    img.bind(&ix.src_u, img.put(src_u));
+    img.bind(&ix.src_d, img.put(src_d));
     for (int t = 0; t < 3; ++t) {
-        ix.lev_ptr[t] = ptr();
-        ix.lev_idx[t] = ptr();
+        img.bind(&ix.lev_ptr[t], img.put(s.lev_ptr[t]));
+        img.bind(&ix.lev_idx[t], img.put(s.lev_idx[t]));
         ix.nlev[t] = (int32_t)s.lev_ptr[t].size() - 1;
         d.h_lev_ptr[t] = s.lev_ptr[t];
     }
-    ix.lpos_ptr = ptr();
-    ix.lpos = ptr();
+    img.bind(&ix.lpos_ptr, img.put(lpos_ptr));
+    img.bind(&ix.lpos, img.put(lpos));
     ix.use_pairs = use_pairs ? 1 : 0;
-    ix.pair_ptr = ptr();
-    ix.pairs = (const int2*)ptr();
+    img.bind(&ix.pair_ptr, img.put(pair_ptr));
+    img.bind(&ix.pairs, img.put(pairs));
     d.h_lpos_ptr = lpos_ptr;
-    if (!use_pairs) {
-        e = build_pairs_on_device(s, d);
-        if (e != hipSuccess) return e;
-    }
-    e = steps_upload(s, r_pos, d);
-    if (e != hipSuccess) return e;
-    d.ready = true;
-    return hipSuccess;
+    steps_image(s, r_pos, img, d);
+    d.imaged = true;
 }
 
-void sparse_free(SparseDevice& d) {
-    steps_free(d);
-    if (d.pair_buf) (void)hipFree(d.pair_buf);
-    d.pair_buf = nullptr;
-    if (d.buf) (void)hipFree(d.buf);
-    d.buf = nullptr;
-    d.ready = false;
+hipError_t sparse_kernel_attrs() {
+    static hipError_t e = [] {
+        return hipFuncSetAttribute((const void*)sparse_lds_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   kLdsLimit);
+    }();
+    return e;
 }
 
 size_t sparse_workspace_bytes(const Symbolic& s, int32_t batch, int32_t K, int32_t nrhs, int32_t keep, int forced) {
@@ -1024,7 +909,7 @@ hipError_t sparse_solve_batched(const Symbolic& s, const SparseDevice& d, int32_
     }
     if (var == kVarLds) {
         const int lds = (int)lds_bytes(s, nrhs);
-        hipError_t e = hipFuncSetAttribute((const void*)sparse_lds_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        hipError_t e = sparse_kernel_attrs();
         if (e != hipSuccess) return e;
         int dev = 0, cus = 256;
         (void)hipGetDevice(&dev);
@@ -1058,7 +943,7 @@ hipError_t sparse_factor(const Symbolic& s, const SparseDevice& d, int32_t batch
     a.fac = (double*)((char*)ws + L.off_fac);
     if (sparse_fits_lds(s, 0)) {
         const int lds = (int)lds_bytes(s, 0);
-        hipError_t e = hipFuncSetAttribute((const void*)sparse_lds_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        hipError_t e = sparse_kernel_attrs();
         if (e != hipSuccess) return e;
         int dev = 0, cus = 256;
         (void)hipGetDevice(&dev);

@@ -73,11 +73,15 @@ constexpr int kStAhead = 7;              // steps whose descriptors are in fligh
 // cap raises the step count from 294 to 340 and removes every in-step fetch.
 constexpr int kStSegMax = 3;
 constexpr int kStLdsLimit = 152 * 1024;  // bytes of LDS the kernel may use
-constexpr int64_t kStLdsPair = 80 * 1024 - 64;   // at most this, and two workgroups share a CU
+// Static LDS of the kernel (pivot flag, nodes and weights: 260 bytes, 272 as
+// allocated), reserved with margin; steps_run checks the compiled figure
+// against it before the first launch.
+constexpr int64_t kStStaticLds = 512;
+constexpr int64_t kStLdsPair = 80 * 1024 - kStStaticLds;   // dynamic LDS at most this: two workgroups share a CU
 
 // Values in the unpacked layout (the index space the schedule is built in).
 int64_t st_lds_doubles(const Symbolic& s) { return 3 * (int64_t)s.n + 2 * (int64_t)s.l_ptr[s.n]; }
-constexpr int64_t kStLdsMax = 160 * 1024 - 64;   // values + per-step metadata (+ the static pivot flag)
+constexpr int64_t kStLdsMax = 160 * 1024 - kStStaticLds;   // dynamic LDS: values + per-step metadata
 // bytes: [u_jj | L and U values (pool) | y | cx] rounded to 16 B, then one int2 of metadata per
 // padded step and ring slot
 __host__ __device__ constexpr int st_padded(int S) { return (S + kStAhead - 1) / kStAhead * kStAhead; }
@@ -485,14 +489,15 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(8))) void ste
 
 }  // namespace
 
-// Whether a schedule may fit (it is built, packed if need be, by steps_upload;
+// Whether a schedule may fit (it is built, packed if need be, by steps_image;
 // steps_ready tells whether it did).
 bool steps_fit(const Symbolic& s, int32_t nrhs) { return nrhs == 1 && st_lds_doubles(s) < 0x7FFF; }
 
-bool steps_ready(const SparseDevice& d) { return d.st_buf != nullptr; }
+bool steps_ready(const SparseDevice& d) { return d.st.nsteps > 0; }
 
-hipError_t steps_upload(const Symbolic& s, const std::vector<int32_t>& r_pos, SparseDevice& d) {
-    if (d.st_buf || !steps_fit(s, 1)) return hipSuccess;
+void steps_image(const Symbolic& s, const std::vector<int32_t>& r_pos, PlanImage& img, SparseDevice& d) {
+    d.st = StepIdx{};
+    if (!steps_fit(s, 1)) return;
     std::vector<int32_t> meta, desc, slot_l, slot_u;
     int32_t S = 0, pool = 0;
     // Unpacked when it fits two workgroups per CU (or packing cannot reach that); packed when
@@ -507,68 +512,63 @@ hipError_t steps_upload(const Symbolic& s, const std::vector<int32_t>& r_pos, Sp
             meta.swap(pm); desc.swap(pd); slot_l.swap(pl); slot_u.swap(pu);
             S = pS; pool = pp; packed = true;
         } else if (!plain) {
-            return hipSuccess;
+            return;
         }
     }
-    if (S < 1 || desc.size() / 4 * 16 > (size_t)INT32_MAX) return hipSuccess;
-    auto up16 = [](size_t words) { return (words + 63) / 64 * 64; };
-    const size_t o_meta = 0, o_desc = up16(meta.size());
-    const size_t o_sl = o_desc + up16(desc.size()), o_su = o_sl + up16(slot_l.size());
-    const size_t total = o_su + up16(slot_u.size());
-    // Rounded up to whole 2 MiB fragments: the kernel streams this array once
-    // per system from every CU, and small-page mappings make each new page a
-    // translation miss.
-    const size_t frag = (size_t)2 << 20;
-    const size_t bytes = (sizeof(int32_t) * total + frag - 1) / frag * frag;
-    hipError_t e = hipMalloc(&d.st_buf, std::max(bytes, (size_t)4 * frag));
-    if (e != hipSuccess) { d.st_buf = nullptr; return e; }
-    std::vector<int32_t> host(total, 0);
-    std::copy(meta.begin(), meta.end(), host.begin() + o_meta);
-    std::copy(desc.begin(), desc.end(), host.begin() + o_desc);
-    std::copy(slot_l.begin(), slot_l.end(), host.begin() + o_sl);
-    std::copy(slot_u.begin(), slot_u.end(), host.begin() + o_su);
-    e = hipMemcpy(d.st_buf, host.data(), sizeof(int32_t) * total, hipMemcpyHostToDevice);
-    if (e != hipSuccess) { (void)hipFree(d.st_buf); d.st_buf = nullptr; return e; }
+    if (S < 1 || desc.size() / 4 * 16 > (size_t)INT32_MAX) return;
     d.st.nsteps = S;
     d.st.threads = kStThreads;
     d.st.ndesc = (int32_t)(desc.size() / 4);
-    d.st.meta = (const int4*)(d.st_buf + o_meta);
-    d.st.desc = (const int4*)(d.st_buf + o_desc);
-    d.st.slot_l = d.st_buf + o_sl;
-    d.st.slot_u = d.st_buf + o_su;
+    img.bind(&d.st.meta, img.put(meta));
+    img.bind(&d.st.desc, img.put(desc));
+    img.bind(&d.st.slot_l, img.put(slot_l));
+    img.bind(&d.st.slot_u, img.put(slot_u));
     d.st.pool = pool;
     d.st.packed = packed ? 1 : 0;
-    return hipSuccess;
 }
 
-void steps_free(SparseDevice& d) {
-    if (d.st_buf) (void)hipFree(d.st_buf);
-    d.st_buf = nullptr;
-    d.st = StepIdx{};
+int64_t steps_lds_bytes(const SparseDevice& d) {
+    return steps_ready(d) ? st_lds_total(d.idx.n, d.st.pool, d.st.nsteps) : 0;
 }
 
 int steps_per_cu(const SparseDevice& d) {
     return st_lds_total(d.idx.n, d.st.pool, d.st.nsteps) <= kStLdsPair ? 2 : 1;
 }
 
+// Once per process: the dynamic LDS limit of both kernel instances, and a check that
+// the compiled static LDS stays within the headroom the schedule sizes assume.
+hipError_t steps_kernel_attrs() {
+    static hipError_t e = [] {
+        const void* ks[2] = {(const void*)steps_kernel<kStThreads, true>, (const void*)steps_kernel<kStThreads, false>};
+        for (const void* k : ks) {
+            hipFuncAttributes fa{};
+            hipError_t r = hipFuncGetAttributes(&fa, k);
+            if (r != hipSuccess) return r;
+            if ((int64_t)fa.sharedSizeBytes > kStStaticLds) return hipErrorInvalidKernelFile;
+            r = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kStLdsMax);
+            if (r != hipSuccess) return r;
+        }
+        return hipSuccess;
+    }();
+    return e;
+}
+
 hipError_t steps_run(const SparseDevice& d, int32_t nnz, int32_t batch, const double* values, const EpsSet& es,
                      const double* dvec, const double* B, double* X, double* Xk, int32_t* info, bool per_jacobian,
                      hipStream_t st) {
-    if (!d.st_buf || d.st.threads != kStThreads) return hipErrorInvalidValue;
+    if (!steps_ready(d) || d.st.threads != kStThreads) return hipErrorInvalidValue;
     StArgs a{};
     a.sx = d.st;
     a.ix = d.idx;
     a.nnz = nnz; a.batch = batch; a.K = es.K; a.per_jacobian = per_jacobian ? 1 : 0;
     a.values = values; a.dvec = dvec; a.B = B; a.X = X; a.Xk = Xk; a.info = info;
     const int lds = (int)st_lds_total(d.idx.n, d.st.pool, d.st.nsteps);
-    const void* kern = d.st.packed ? (const void*)steps_kernel<kStThreads, true>
-                                   : (const void*)steps_kernel<kStThreads, false>;
-    hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    hipError_t e = steps_kernel_attrs();
     if (e != hipSuccess) return e;
     int dev = 0, cus = 256;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    const int resident = cus * std::max(1, (160 * 1024) / std::max(lds, 1));
+    const int resident = cus * steps_per_cu(d);
     const int64_t jobs = per_jacobian ? batch : (int64_t)batch * es.K;
     const int grid = (int)std::min<int64_t>(jobs, resident);
     if (d.st.packed)

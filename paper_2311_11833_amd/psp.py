@@ -23,10 +23,12 @@ PATHS = {"auto": 0, "dense": 1, "sparse": 2, "sparse_batched": 3, "sparse_lds": 
 PATH_NAMES = {v: k for k, v in PATHS.items()}
 ORDERS = {"md": 0, "natural": 1}
 EXPORTED = ["psp_last_error", "psp_version", "psp_plan_create", "psp_plan_info", "psp_plan_export",
-            "psp_plan_destroy", "psp_weights", "psp_workspace_bytes", "psp_solve_batched", "psp_tune", "psp_factor",
-            "psp_solve", "psp_combine", "psp_grad_values", "psp_factors_release", "psp_residual",
-            "psp_group_workspace_bytes", "psp_solve_group", "psp_pf_create", "psp_pf_destroy", "psp_pf_eval",
-            "psp_pf_workspace_bytes", "psp_pf_newton", "psp_estimate_rho_workspace_bytes", "psp_estimate_rho"]
+            "psp_plan_destroy", "psp_plan_device_bytes", "psp_plan_upload", "psp_weights", "psp_workspace_bytes",
+            "psp_solve_batched", "psp_tune", "psp_factor", "psp_solve", "psp_combine", "psp_grad_values",
+            "psp_factors_release", "psp_residual", "psp_group_create", "psp_group_workspace_bytes", "psp_group_run",
+            "psp_group_capture", "psp_graph_launch", "psp_graph_destroy", "psp_group_destroy", "psp_pf_device_bytes",
+            "psp_pf_create", "psp_pf_destroy", "psp_pf_eval", "psp_pf_workspace_bytes", "psp_pf_newton",
+            "psp_estimate_rho_workspace_bytes", "psp_estimate_rho"]
 PF_STATUS = {0: "converged", 1: "max_iter", 2: "breakdown", 3: "diverged"}
 
 
@@ -38,12 +40,18 @@ class PSPError(RuntimeError):
 
 class PlanInfo(C.Structure):
     _fields_ = [("n", C.c_int32), ("nnz", C.c_int32), ("nnz_l", C.c_int64), ("ndense", C.c_int32),
-                ("nlev", C.c_int32 * 3), ("flops_dense_factor", C.c_int64), ("flops_sparse_factor", C.c_int64)]
+                ("nlev", C.c_int32 * 3), ("flops_dense_factor", C.c_int64), ("flops_sparse_factor", C.c_int64),
+                ("steps", C.c_int32), ("steps_packed", C.c_int32), ("steps_lds_bytes", C.c_int64),
+                ("steps_per_cu", C.c_int32), ("device_bytes", C.c_int64)]
 
 
-class GroupItem(C.Structure):
-    _fields_ = [("plan", C.c_void_p), ("batch", C.c_int32), ("path", C.c_int32), ("values", C.c_void_p),
-                ("d", C.c_void_p), ("B", C.c_void_p), ("X", C.c_void_p), ("info", C.c_void_p)]
+class GroupShape(C.Structure):
+    _fields_ = [("plan", C.c_void_p), ("batch", C.c_int32), ("path", C.c_int32)]
+
+
+class GroupTask(C.Structure):
+    _fields_ = [("values", C.c_void_p), ("d", C.c_void_p), ("B", C.c_void_p), ("X", C.c_void_p),
+                ("info", C.c_void_p)]
 
 
 _lib = None
@@ -63,6 +71,9 @@ def lib():
         L.psp_plan_export.argtypes = [vp, vp, vp, vp, vp, vp, C.POINTER(vp), C.POINTER(vp)]
         L.psp_plan_destroy.argtypes = [vp]
         L.psp_plan_destroy.restype = None
+        L.psp_plan_device_bytes.argtypes = [vp]
+        L.psp_plan_device_bytes.restype = C.c_size_t
+        L.psp_plan_upload.argtypes = [vp, vp, C.c_size_t, vp]
         L.psp_weights.argtypes = [i32, vp, vp]
         L.psp_workspace_bytes.argtypes = [vp, i32, i32, i32, i32, i32]
         L.psp_workspace_bytes.restype = C.c_size_t
@@ -74,10 +85,19 @@ def lib():
         L.psp_grad_values.argtypes = [vp, i32, vp, vp, vp, vp]
         L.psp_factors_release.argtypes = [vp]
         L.psp_residual.argtypes = [vp, i32, vp, i32, vp, vp, vp, vp, vp, vp]
-        L.psp_group_workspace_bytes.argtypes = [i32, vp, i32, i32]
+        L.psp_group_create.argtypes = [i32, vp, i32, vp, i32, C.POINTER(vp)]
+        L.psp_group_workspace_bytes.argtypes = [vp]
         L.psp_group_workspace_bytes.restype = C.c_size_t
-        L.psp_solve_group.argtypes = [i32, vp, i32, vp, i32, vp, C.c_size_t, vp]
-        L.psp_pf_create.argtypes = [vp, i32, vp, vp, vp, vp, vp, C.POINTER(vp)]
+        L.psp_group_run.argtypes = [vp, vp, vp, C.c_size_t, vp]
+        L.psp_group_capture.argtypes = [vp, vp, vp, C.c_size_t, vp, C.POINTER(vp)]
+        L.psp_graph_launch.argtypes = [vp, vp]
+        L.psp_graph_destroy.argtypes = [vp]
+        L.psp_graph_destroy.restype = None
+        L.psp_group_destroy.argtypes = [vp]
+        L.psp_group_destroy.restype = None
+        L.psp_pf_device_bytes.argtypes = [i32, i32]
+        L.psp_pf_device_bytes.restype = C.c_size_t
+        L.psp_pf_create.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, C.c_size_t, vp, C.POINTER(vp)]
         L.psp_pf_destroy.argtypes = [vp]
         L.psp_pf_destroy.restype = None
         L.psp_pf_eval.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
@@ -88,8 +108,9 @@ def lib():
         L.psp_estimate_rho_workspace_bytes.restype = C.c_size_t
         L.psp_estimate_rho.argtypes = [vp, i32, vp, vp, d, i32, vp, vp, vp, C.c_size_t, vp]
         for f in EXPORTED:
-            if f not in ("psp_last_error", "psp_version", "psp_plan_destroy", "psp_workspace_bytes",
-                         "psp_group_workspace_bytes", "psp_pf_destroy", "psp_pf_workspace_bytes",
+            if f not in ("psp_last_error", "psp_version", "psp_plan_destroy", "psp_plan_device_bytes",
+                         "psp_workspace_bytes", "psp_group_workspace_bytes", "psp_graph_destroy",
+                         "psp_group_destroy", "psp_pf_device_bytes", "psp_pf_destroy", "psp_pf_workspace_bytes",
                          "psp_estimate_rho_workspace_bytes"):
                 getattr(L, f).restype = C.c_int
         _lib = L
@@ -151,6 +172,7 @@ class Plan:
         _check(lib().psp_plan_create(self.n, _np_ptr(ip), _np_ptr(ix), ORDERS[order], C.byref(h)))
         self._h = h
         self._ws = {}
+        self._dev = None   # device copy of the plan (a torch uint8 tensor this object owns)
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -161,6 +183,30 @@ class Plan:
     @property
     def handle(self):
         return self._h
+
+    def device_bytes(self) -> int:
+        return int(lib().psp_plan_device_bytes(self._h))
+
+    def upload(self, device=None, stream=None):
+        """Copies the plan's device arrays into a tensor on `device` (psp_plan_upload); numeric
+        calls do this on first use.  Returns the tensor, which the plan keeps alive."""
+        import torch
+        dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        nbytes = self.device_bytes()
+        if nbytes == 0:
+            raise PSPError(PSP_E_NOMEM, "plan image could not be built")
+        with torch.cuda.device(dev):
+            buf = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+            _check(lib().psp_plan_upload(self._h, _dptr(buf), nbytes, _stream(stream)))
+        self._dev = buf
+        return buf
+
+    def ensure(self, device):
+        """Uploads the plan to `device` unless it already lives there."""
+        import torch
+        dev = torch.device(device)
+        if self._dev is None or self._dev.device != dev:
+            self.upload(dev)
 
     def info(self) -> PlanInfo:
         o = PlanInfo()
@@ -210,6 +256,7 @@ def solve_batched(plan: Plan, values, eps, b, path: str = "auto", d=None, worksp
         raise TypeError("values and b must be float64")
     if values.shape[1] != plan.nnz or b.shape[1] != plan.n or b.shape[0] != batch:
         raise ValueError("shape mismatch with the plan")
+    plan.ensure(values.device)
     x = torch.empty_like(b)
     info = torch.empty((batch, K), dtype=torch.int32, device=values.device)
     need = plan.workspace_bytes(path, batch, K, nrhs, keep=False)
@@ -220,37 +267,96 @@ def solve_batched(plan: Plan, values, eps, b, path: str = "auto", d=None, worksp
     return x, info
 
 
-def solve_group(items, eps, path: str = "auto", d=None, stream=None, workspace=None):
-    """Uneven batch: items is a list of (plan, values, b), each values (batch_i, nnz_i) and b
-    (batch_i, n_i) or (batch_i, n_i, nrhs) float64 device tensors (same nrhs everywhere).
-    All items run on one stream in one workspace.  Returns [(x_i, info_i)]."""
-    import torch
-    eps_h = np.ascontiguousarray(eps, dtype=np.float64)
-    K = len(eps_h)
+class Group:
+    """An uneven batch (psp_group_*): items of Jacobians of different patterns, solved together.
+
+    shapes: list of (plan, batch) or (plan, batch, path name).  run() enqueues every item on the
+    group's stream lanes; capture() records the same work into a HIP graph that replay() launches."""
+
+    def __init__(self, shapes, eps, nrhs: int = 1, device=None):
+        import torch
+        self.eps = np.ascontiguousarray(eps, dtype=np.float64)
+        self.K = len(self.eps)
+        self.nrhs = nrhs
+        self.plans = []
+        arr = (GroupShape * len(shapes))()
+        dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        for i, sh in enumerate(shapes):
+            plan, batch = sh[0], int(sh[1])
+            path = sh[2] if len(sh) > 2 else "auto"
+            plan.ensure(dev)
+            self.plans.append((plan, batch))
+            arr[i] = GroupShape(plan.handle.value, batch, PATHS[path])
+        h = C.c_void_p()
+        _check(lib().psp_group_create(len(shapes), C.byref(arr), self.K, _np_ptr(self.eps), nrhs, C.byref(h)))
+        self._h = h
+        self.ws = torch.empty(int(lib().psp_group_workspace_bytes(h)), dtype=torch.uint8, device=dev)
+        self._graphs = []
+
+    def __del__(self):
+        for g in getattr(self, "_graphs", []):
+            if _lib is not None:
+                _lib.psp_graph_destroy(g)
+        self._graphs = []
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.psp_group_destroy(h)
+            self._h = None
+
+    def outputs(self, items, d=None):
+        """Allocates X and info for items = [(values, b)] and returns (task array, [(x, info)], keep)."""
+        import torch
+        if len(items) != len(self.plans):
+            raise ValueError("one (values, b) pair per group item")
+        tasks = (GroupTask * len(items))()
+        outs, keep = [], []
+        for i, ((plan, batch), (values, b)) in enumerate(zip(self.plans, items)):
+            if values.dtype != torch.float64 or b.dtype != torch.float64:
+                raise TypeError("values and b must be float64")
+            if values.shape != (batch, plan.nnz) or b.shape[0] != batch or b.shape[1] != plan.n:
+                raise ValueError(f"item {i}: shape mismatch with its plan")
+            if (1 if b.dim() == 2 else b.shape[2]) != self.nrhs:
+                raise ValueError(f"item {i}: wrong number of right-hand sides")
+            vc, bc = values.contiguous(), b.contiguous()
+            x = torch.empty_like(bc)
+            info = torch.empty((batch, self.K), dtype=torch.int32, device=values.device)
+            keep += [vc, bc]
+            tasks[i] = GroupTask(_dptr(vc).value, _dptr(d).value if d is not None else None, _dptr(bc).value,
+                                 _dptr(x).value, _dptr(info).value)
+            outs.append((x, info))
+        return tasks, outs, keep
+
+    def run(self, items, d=None, stream=None):
+        """Solves every item; returns [(x_i, info_i)]."""
+        tasks, outs, keep = self.outputs(items, d)
+        _check(lib().psp_group_run(self._h, C.byref(tasks), _dptr(self.ws), self.ws.numel(), _stream(stream)))
+        self._keep = keep
+        return outs
+
+    def capture(self, items, d=None, stream=None):
+        """Captures the group's work into a HIP graph; returns (graph handle, [(x_i, info_i)]).  The
+        output tensors and inputs stay bound to the graph: replay(graph) rewrites the outputs."""
+        tasks, outs, keep = self.outputs(items, d)
+        g = C.c_void_p()
+        _check(lib().psp_group_capture(self._h, C.byref(tasks), _dptr(self.ws), self.ws.numel(), _stream(stream),
+                                       C.byref(g)))
+        self._graphs.append(g)
+        self._keep_graph = getattr(self, "_keep_graph", []) + [keep]
+        return g, outs
+
+    def replay(self, graph, stream=None):
+        _check(lib().psp_graph_launch(graph, _stream(stream)))
+
+
+def solve_group(items, eps, path: str = "auto", d=None, stream=None):
+    """Uneven batch in one call: items is a list of (plan, values, b), each values (batch_i, nnz_i)
+    and b (batch_i, n_i) or (batch_i, n_i, nrhs).  Returns [(x_i, info_i)]."""
     nrhs = 1 if items[0][2].dim() == 2 else items[0][2].shape[2]
-    arr = (GroupItem * len(items))()
-    outs, keep = [], []
-    for i, (plan, values, b) in enumerate(items):
-        if values.dtype != torch.float64 or b.dtype != torch.float64:
-            raise TypeError("values and b must be float64")
-        if values.shape[1] != plan.nnz or b.shape[1] != plan.n or b.shape[0] != values.shape[0]:
-            raise ValueError(f"item {i}: shape mismatch with its plan")
-        if (1 if b.dim() == 2 else b.shape[2]) != nrhs:
-            raise ValueError("every item needs the same number of right-hand sides")
-        bc = b.contiguous()
-        x = torch.empty_like(bc)
-        info = torch.empty((values.shape[0], K), dtype=torch.int32, device=values.device)
-        keep.append(bc)
-        arr[i] = GroupItem(plan.handle, values.shape[0], PATHS[path], _dptr(values).value, _dptr(d).value if d is not None else None,
-                           _dptr(bc).value, _dptr(x).value, _dptr(info).value)
-        outs.append((x, info))
-    need = lib().psp_group_workspace_bytes(len(items), C.byref(arr), K, nrhs)
-    if need == 0:
-        raise PSPError(PSP_E_INVALID, "invalid group item list")
-    dev = items[0][1].device
-    ws = workspace if workspace is not None else torch.empty(need, dtype=torch.uint8, device=dev)
-    _check(lib().psp_solve_group(len(items), C.byref(arr), K, _np_ptr(eps_h), nrhs, _dptr(ws), ws.numel(),
-                                 _stream(stream)))
+    g = Group([(p, v.shape[0], path) for p, v, _ in items], eps, nrhs=nrhs, device=items[0][1].device)
+    outs = g.run([(v, b) for _, v, b in items], d=d, stream=stream)
+    # keep the group (its workspace and lanes) until the caller's stream has finished with it
+    import torch
+    torch.cuda.current_stream(items[0][1].device).synchronize() if stream is None else stream.synchronize()
     return outs
 
 
@@ -267,6 +373,7 @@ def residual(plan: Plan, values, b, x, keep_r: bool = False, stream=None):
         raise TypeError("values, b and x must be float64")
     if values.shape[1] != plan.nnz or b.shape != x.shape or b.shape[0] != batch or b.shape[1] != plan.n:
         raise ValueError("shape mismatch with the plan")
+    plan.ensure(values.device)
     rn = torch.empty((batch, nrhs), dtype=torch.float64, device=values.device)
     bn = torch.empty_like(rn)
     r = torch.empty_like(b) if keep_r else None
@@ -283,6 +390,7 @@ def tune(plan: Plan, values, eps, b, d=None, stream=None):
     nrhs = 1 if b.dim() == 2 else b.shape[2]
     eps_h = np.ascontiguousarray(eps, dtype=np.float64)
     K = len(eps_h)
+    plan.ensure(values.device)
     x = torch.empty_like(b)
     info = torch.empty((batch, K), dtype=torch.int32, device=values.device)
     need = plan.workspace_bytes("auto", batch, K, nrhs, keep=False)
@@ -306,6 +414,7 @@ class Factors:
         self.K = len(self.eps)
         self.c = weights(self.eps)
         self.device = values.device
+        plan.ensure(values.device)
         need = plan.workspace_bytes(path, self.batch, self.K, nrhs_cap, keep=True)
         self.ws = torch.empty(max(need, 256), dtype=torch.uint8, device=values.device)
         self.info = torch.empty((self.batch, self.K), dtype=torch.int32, device=values.device)
@@ -356,6 +465,7 @@ def estimate_rho(plan: Plan, values, v0, d=None, probe: float = 1e-8, iters: int
         raise TypeError("values and v0 must be float64")
     if values.shape[1] != plan.nnz or tuple(v0.shape) != (batch, plan.n):
         raise ValueError("shape mismatch with the plan")
+    plan.ensure(values.device)
     rho = torch.empty(batch, dtype=torch.float64, device=values.device)
     need = int(lib().psp_estimate_rho_workspace_bytes(plan.handle, batch))
     ws = plan.workspace(need, values.device)
@@ -380,9 +490,14 @@ class PowerFlow:
         self.N = len(yp) - 1
         if len(pvv) != self.N:
             raise ValueError("pv must have one entry per bus")
+        import torch
+        dev = torch.device("cuda", torch.cuda.current_device())
+        plan.ensure(dev)
+        nbytes = int(lib().psp_pf_device_bytes(self.N, int(yp[-1])))
+        self._dev = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=dev)
         h = C.c_void_p()
         _check(lib().psp_pf_create(plan.handle, self.N, _np_ptr(yp), _np_ptr(yc), _np_ptr(gg), _np_ptr(bb),
-                                   _np_ptr(pvv), C.byref(h)))
+                                   _np_ptr(pvv), _dptr(self._dev), self._dev.numel(), _stream(None), C.byref(h)))
         self._h = h
 
     def __del__(self):

@@ -114,25 +114,63 @@ def test_residual_argument_errors_before_any_device_call(psp):
 
 
 def test_group_rejects_bad_items_on_the_host(psp):
-    """psp_group_workspace_bytes returns 0 and psp_solve_group PSP_E_INVALID for an empty
-    list, a NULL plan or batch < 1 -- before any device call."""
+    """psp_group_create returns PSP_E_INVALID for an empty list, a NULL plan, batch < 1 or a
+    bad nrhs, and PSP_E_EPS for bad nodes -- before any device call."""
     import ctypes as C
     L = psp.lib()
     ip = np.array([0, 1, 2], np.int32)
     ix = np.array([0, 1], np.int32)
     plan = psp.Plan(ip, ix)
-    arr = (psp.GroupItem * 2)()
-    arr[0] = psp.GroupItem(plan.handle, 3, 0, None, None, None, None, None)
-    arr[1] = psp.GroupItem(None, 3, 0, None, None, None, None, None)
+    arr = (psp.GroupShape * 2)()
+    arr[0] = psp.GroupShape(plan.handle.value, 3, 0)
+    arr[1] = psp.GroupShape(None, 3, 0)
     eps = np.array([1e-3, 5e-4])
-    assert L.psp_group_workspace_bytes(1, C.byref(arr), 2, 1) > 0
-    assert L.psp_group_workspace_bytes(2, C.byref(arr), 2, 1) == 0
-    assert L.psp_group_workspace_bytes(0, C.byref(arr), 2, 1) == 0
-    dummy = C.c_void_p(16)
-    assert L.psp_solve_group(2, C.byref(arr), 2, eps.ctypes.data_as(C.c_void_p), 1, dummy, 1 << 30, None) == psp.PSP_E_INVALID
-    arr[1] = psp.GroupItem(plan.handle, 0, 0, None, None, None, None, None)
-    assert L.psp_solve_group(2, C.byref(arr), 2, eps.ctypes.data_as(C.c_void_p), 1, dummy, 1 << 30, None) == psp.PSP_E_INVALID
-    assert L.psp_solve_group(0, None, 2, eps.ctypes.data_as(C.c_void_p), 1, dummy, 1 << 30, None) == psp.PSP_E_INVALID
+    ep = eps.ctypes.data_as(C.c_void_p)
+    h = C.c_void_p()
+    assert L.psp_group_create(2, C.byref(arr), 2, ep, 1, C.byref(h)) == psp.PSP_E_INVALID
+    arr[1] = psp.GroupShape(plan.handle.value, 0, 0)
+    assert L.psp_group_create(2, C.byref(arr), 2, ep, 1, C.byref(h)) == psp.PSP_E_INVALID
+    assert L.psp_group_create(0, None, 2, ep, 1, C.byref(h)) == psp.PSP_E_INVALID
+    arr[1] = psp.GroupShape(plan.handle.value, 3, 0)
+    assert L.psp_group_create(2, C.byref(arr), 2, ep, 0, C.byref(h)) == psp.PSP_E_INVALID
+    same = np.array([1e-3, 1e-3])
+    assert L.psp_group_create(2, C.byref(arr), 2, same.ctypes.data_as(C.c_void_p), 1, C.byref(h)) == psp.PSP_E_EPS
+    assert h.value is None
+    assert L.psp_group_workspace_bytes(None) == 0
+    dummy = C.c_void_p(256)
+    assert L.psp_group_run(None, dummy, dummy, 1 << 20, None) == psp.PSP_E_INVALID
+    assert L.psp_group_capture(None, dummy, dummy, 1 << 20, None, C.byref(h)) == psp.PSP_E_INVALID
+    assert L.psp_graph_launch(None, None) == psp.PSP_E_INVALID
+
+
+def test_plan_upload_checks_and_image_size_on_the_host(psp, W):
+    """The plan's device image is sized on the host; psp_plan_upload rejects NULL, misaligned
+    or short buffers before any device call, and numeric calls need an uploaded plan."""
+    import ctypes as C
+    L = psp.lib()
+    ip, ix, _, _ = W.scenario_batch(300, 1)
+    plan = psp.Plan(ip, ix)
+    nb = plan.device_bytes()
+    inf = plan.info()
+    assert nb > 0 and nb % 256 == 0 and inf.device_bytes == nb
+    assert L.psp_plan_device_bytes(None) == 0
+    assert L.psp_plan_upload(plan.handle, None, nb, None) == psp.PSP_E_INVALID
+    assert L.psp_plan_upload(plan.handle, C.c_void_p(256 + 8), nb, None) == psp.PSP_E_INVALID
+    st = L.psp_plan_upload(plan.handle, C.c_void_p(256), nb - 256, None)
+    assert st == psp.PSP_E_NOMEM and b"too small" in L.psp_last_error()
+
+
+@pytest.mark.parametrize("N", [14, 30, 118, 300, 500])
+def test_step_schedule_lds_budget(psp, W, N):
+    """The step kernel's dynamic LDS plus its static LDS (at most 512 bytes reserved) fits the
+    CU's 160 KiB, and twice that when two workgroups are counted per CU."""
+    ip, ix, _, _ = W.scenario_batch(N, 1)
+    inf = psp.Plan(ip, ix).info()
+    assert inf.steps > 0
+    assert inf.steps_per_cu in (1, 2)
+    assert inf.steps_lds_bytes + 512 <= 160 * 1024
+    if inf.steps_per_cu == 2:
+        assert 2 * (inf.steps_lds_bytes + 512) <= 160 * 1024
 
 
 def test_power_flow_create_rejects_mismatched_networks_on_the_host(psp, W):
@@ -145,7 +183,9 @@ def test_power_flow_create_rejects_mismatched_networks_on_the_host(psp, W):
     def create(plan_h, nbus, yp, yc, g, b, pv):
         h = C.c_void_p()
         arrs = [np.ascontiguousarray(a) for a in (yp, yc, g, b, pv)]
-        st = L.psp_pf_create(plan_h, nbus, *[a.ctypes.data_as(C.c_void_p) for a in arrs], C.byref(h))
+        dummy = C.c_void_p(256)   # never dereferenced: every check comes before the copy
+        st = L.psp_pf_create(plan_h, nbus, *[a.ctypes.data_as(C.c_void_p) for a in arrs], dummy, 1 << 30, None,
+                             C.byref(h))
         return st, L.psp_last_error()
 
     good = (c.y_indptr, c.y_indices, c.g, c.b, c.pv)
