@@ -223,6 +223,8 @@ PSP_API psp_status psp_solve_batched(psp_plan plan, int32_t path, int32_t batch,
  *                      psp_graph_launch replays on any stream and
  *                      psp_graph_destroy frees.  The graph keeps the task
  *                      pointers and the workspace it was captured with.
+ *                      `stream` must be a created stream: the null stream
+ *                      cannot be captured (PSP_E_INVALID).
  * Errors as for psp_solve_batched, plus PSP_E_STATE for a group used on
  * another device.  Calls on one group must not overlap (its lanes are shared).
  * ---------------------------------------------------------------------- */

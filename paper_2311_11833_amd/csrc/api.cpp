@@ -1011,6 +1011,8 @@ psp_status psp_group_capture(psp_group g, const psp_group_task_t* tasks, void* w
     if (psp_status r = group_check(g, tasks, ws, ws_bytes)) return r;
     if (psp_status st = check_prior_hip()) return st;
     const hipStream_t st = (hipStream_t)stream;
+    if (st == nullptr)
+        return fail(PSP_E_INVALID, "psp_group_capture: the null (default) stream cannot be captured; pass a created stream");
     HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
     const psp_status r = group_enqueue(g, tasks, (char*)ws, st);
     hipGraph_t graph = nullptr;

@@ -337,6 +337,12 @@ class Group:
         """Captures the group's work into a HIP graph; returns (graph handle, [(x_i, info_i)]).  The
         output tensors and inputs stay bound to the graph: replay(graph) rewrites the outputs."""
         tasks, outs, keep = self.outputs(items, d)
+        if stream is None:
+            # the default stream cannot be captured: capture on a side stream ordered after it
+            import torch
+            stream = torch.cuda.Stream(device=self.ws.device)
+            stream.wait_stream(torch.cuda.current_stream(self.ws.device))
+            self._capture_streams = getattr(self, "_capture_streams", []) + [stream]
         g = C.c_void_p()
         _check(lib().psp_group_capture(self._h, C.byref(tasks), _dptr(self.ws), self.ws.numel(), _stream(stream),
                                        C.byref(g)))
