@@ -201,6 +201,24 @@ PSP_API psp_status psp_solve_batched(psp_plan plan, int32_t path, int32_t batch,
                              void* stream);
 
 /* ------------------------------------------------------------------------
+ * psp_solve_batched_noalloc -- psp_solve_batched on PSP_PATH_SPARSE_STEPS with
+ * nrhs = 1 and no workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  The call allocates nothing: when the batch is too
+ * small for one workgroup per Jacobian, the per-system solutions (batch x K x n
+ * doubles) go to a static scratch array that the library holds on every
+ * device it runs on (16 MiB per device, kept until the process ends).
+ * Arguments and results as for psp_solve_batched (the same bits).
+ * PSP_E_UNSUPPORTED when the plan has no step schedule or the batch needs more
+ * than the 16 MiB of scratch.  Every call on a device shares that device's
+ * scratch: calls that overlap on one device (concurrent streams or threads)
+ * race and must be serialised by the caller.
+ * ---------------------------------------------------------------------- */
+PSP_API psp_status psp_solve_batched_noalloc(psp_plan plan, int32_t batch, const double* values, int32_t K,
+                                             const double* eps, const double* d, const double* B, double* X,
+                                             int32_t* info, void* stream);
+
+/* ------------------------------------------------------------------------
  * Groups: Alg. 1 steps 1-4 for an uneven batch, i.e. several items of
  * Jacobians of different patterns, enqueued together (Sec. IV: batched solves
  * whose time should not grow with the number of systems).  Item i holds

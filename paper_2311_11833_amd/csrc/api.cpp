@@ -395,6 +395,30 @@ psp_status psp_solve_batched(psp_plan p, int32_t path, int32_t batch, const doub
     return fail(PSP_E_INVALID, "unknown path");
 }
 
+psp_status psp_solve_batched_noalloc(psp_plan p, int32_t batch, const double* values, int32_t K, const double* eps,
+                                     const double* d, const double* B, double* X, int32_t* info, void* stream) {
+    if (!p || batch < 1 || !values || !B || !X || !info)
+        return fail(PSP_E_INVALID, "psp_solve_batched_noalloc: NULL argument or batch < 1");
+    EpsSet es;
+    if (psp_status st = make_eps(K, eps, es)) return st;
+    if (psp_status st = check_prior_hip()) return st;
+    if (psp_status r = require_upload(p)) return r;
+    if (!steps_ready(p->sp))
+        return fail(PSP_E_UNSUPPORTED, "psp_solve_batched_noalloc: the plan has no step schedule (it does not fit in LDS)");
+    const Symbolic& s = p->sym;
+    const bool per_jacobian = steps_per_jacobian(p->sp, batch);
+    const size_t need = per_jacobian ? 0 : (size_t)batch * K * s.n * sizeof(double);
+    if (need > noalloc_scratch_bytes())
+        return fail(PSP_E_UNSUPPORTED, "psp_solve_batched_noalloc: needs " + std::to_string(need) +
+                                           " bytes of scratch, the library's static scratch holds " +
+                                           std::to_string(noalloc_scratch_bytes()));
+    void* scratch = nullptr;
+    HIP_TRY(noalloc_scratch(&scratch), "hipGetSymbolAddress(scratch)");
+    HIP_TRY(steps_solve(p->sp, s.n, s.nnz, batch, values, es, d, B, X, info, (double*)scratch, (hipStream_t)stream),
+            "step-kernel launch");
+    return PSP_OK;
+}
+
 psp_status psp_tune(psp_plan p, int32_t batch, const double* values, int32_t K, const double* eps, const double* d,
                     int32_t nrhs, const double* B, double* X, int32_t* info, void* ws, size_t ws_bytes, void* stream,
                     int32_t* chosen, float* ms) {

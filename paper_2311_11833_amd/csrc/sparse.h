@@ -81,6 +81,16 @@ int64_t steps_lds_bytes(const SparseDevice& d);   // dynamic LDS of one step-ker
 hipError_t steps_run(const SparseDevice& d, int32_t nnz, int32_t batch, const double* values, const EpsSet& es,
                      const double* dvec, const double* B, double* X, double* Xk, int32_t* info, bool per_jacobian,
                      hipStream_t st);
+// One workgroup per Jacobian (combine fused, no workspace) once the batch fills every resident slot.
+bool steps_per_jacobian(const SparseDevice& d, int32_t batch);
+// steps_run in the mode steps_per_jacobian picks, plus the combine launch in per-system mode
+// (Xk: batch x K x n doubles of device memory, unused in per-Jacobian mode).
+hipError_t steps_solve(const SparseDevice& d, int32_t n, int32_t nnz, int32_t batch, const double* values,
+                       const EpsSet& es, const double* dvec, const double* B, double* X, int32_t* info, double* Xk,
+                       hipStream_t st);
+// The library's static device scratch (noalloc.hip): its size, and the current device's address.
+size_t noalloc_scratch_bytes();
+hipError_t noalloc_scratch(void** out);
 bool sparse_fits_lds(const Symbolic& s, int32_t nrhs);
 size_t sparse_workspace_bytes(const Symbolic& s, int32_t batch, int32_t K, int32_t nrhs, int32_t keep, int forced = -1);
 int32_t sparse_nrhs_capacity(const Symbolic& s, int32_t batch, int32_t K, size_t ws_bytes);

@@ -896,16 +896,7 @@ hipError_t sparse_solve_batched(const Symbolic& s, const SparseDevice& d, int32_
     if (var == kVarBatched || var == kVarGrouped)
         return batched_run(s, d, batch, values, es, dvec, nrhs, B, X, info, w, L, st, var == kVarGrouped);
     if (var == kVarSteps) {
-        if (!steps_ready(d)) return hipErrorInvalidValue;
-        int dev = 0, cus = 256;
-        (void)hipGetDevice(&dev);
-        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        // enough Jacobians to fill every resident workgroup slot: one workgroup per Jacobian,
-        // combine fused; fewer: one workgroup per perturbed system and a combine launch
-        const bool per_jacobian = batch >= cus * steps_per_cu(d);
-        hipError_t e = steps_run(d, s.nnz, batch, values, es, dvec, B, X, a.Xk, info, per_jacobian, st);
-        if (e != hipSuccess || per_jacobian) return e;
-        return launch_combine((int64_t)s.n, batch, es, a.Xk, X, st);
+        return steps_solve(d, s.n, s.nnz, batch, values, es, dvec, B, X, info, a.Xk, st);
     }
     if (var == kVarLds) {
         const int lds = (int)lds_bytes(s, nrhs);

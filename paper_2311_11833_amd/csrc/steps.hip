@@ -578,4 +578,23 @@ hipError_t steps_run(const SparseDevice& d, int32_t nnz, int32_t batch, const do
     return hipGetLastError();
 }
 
+bool steps_per_jacobian(const SparseDevice& d, int32_t batch) {
+    int dev = 0, cus = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    return batch >= cus * steps_per_cu(d);
+}
+
+hipError_t steps_solve(const SparseDevice& d, int32_t n, int32_t nnz, int32_t batch, const double* values,
+                       const EpsSet& es, const double* dvec, const double* B, double* X, int32_t* info, double* Xk,
+                       hipStream_t st) {
+    if (!steps_ready(d)) return hipErrorInvalidValue;
+    // enough Jacobians to fill every resident workgroup slot: one workgroup per Jacobian,
+    // combine fused; fewer: one workgroup per perturbed system and a combine launch
+    const bool per_jacobian = steps_per_jacobian(d, batch);
+    hipError_t e = steps_run(d, nnz, batch, values, es, dvec, B, X, Xk, info, per_jacobian, st);
+    if (e != hipSuccess || per_jacobian) return e;
+    return launch_combine((int64_t)n, batch, es, Xk, X, st);
+}
+
 }  // namespace psp

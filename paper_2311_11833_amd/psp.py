@@ -24,7 +24,7 @@ PATH_NAMES = {v: k for k, v in PATHS.items()}
 ORDERS = {"md": 0, "natural": 1}
 EXPORTED = ["psp_last_error", "psp_version", "psp_plan_create", "psp_plan_info", "psp_plan_export",
             "psp_plan_destroy", "psp_plan_device_bytes", "psp_plan_upload", "psp_weights", "psp_workspace_bytes",
-            "psp_solve_batched", "psp_tune", "psp_factor", "psp_solve", "psp_combine", "psp_grad_values",
+            "psp_solve_batched", "psp_solve_batched_noalloc", "psp_tune", "psp_factor", "psp_solve", "psp_combine", "psp_grad_values",
             "psp_factors_release", "psp_residual", "psp_group_create", "psp_group_workspace_bytes", "psp_group_run",
             "psp_group_capture", "psp_graph_launch", "psp_graph_destroy", "psp_group_destroy", "psp_pf_device_bytes",
             "psp_pf_create", "psp_pf_destroy", "psp_pf_eval", "psp_pf_workspace_bytes", "psp_pf_newton",
@@ -78,6 +78,7 @@ def lib():
         L.psp_workspace_bytes.argtypes = [vp, i32, i32, i32, i32, i32]
         L.psp_workspace_bytes.restype = C.c_size_t
         L.psp_solve_batched.argtypes = [vp, i32, i32, vp, i32, vp, vp, i32, vp, vp, vp, vp, C.c_size_t, vp]
+        L.psp_solve_batched_noalloc.argtypes = [vp, i32, vp, i32, vp, vp, vp, vp, vp, vp]
         L.psp_tune.argtypes = [vp, i32, vp, i32, vp, vp, i32, vp, vp, vp, vp, C.c_size_t, vp, vp, vp]
         L.psp_factor.argtypes = [vp, i32, i32, vp, i32, vp, vp, vp, vp, C.c_size_t, vp, C.POINTER(vp)]
         L.psp_solve.argtypes = [vp, i32, vp, vp, i32, vp]
