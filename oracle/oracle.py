@@ -82,6 +82,12 @@ def lib():
                                            C.c_int, C.c_int, _dp, _dp, C.c_void_p, C.c_void_p, C.c_void_p]
         L.oracle_sparse_batch.argtypes = [C.c_int, _ip, _ip, C.c_int, _dp, _ip, _ip, _ip, C.c_int, _dp,
                                           _dp, C.c_void_p, C.c_int, C.c_int, _dp, _dp, C.c_void_p, _ip]
+        L.oracle_divided_difference.argtypes = [C.c_int, _dp, C.c_int64, _dp, _dp]
+        L.oracle_divided_difference.restype = None
+        L.oracle_error_estimate.argtypes = [C.c_int, _dp, C.c_int64, _dp, _dp, C.POINTER(C.c_double),
+                                            C.POINTER(C.c_double)]
+        L.oracle_error_estimate.restype = None
+        L.oracle_scale_exponent.argtypes = [C.c_int, _dp, C.c_double, C.c_double]
         L.oracle_grad_values.argtypes = [C.c_int, _ip, _ip, C.c_int, _dp, C.c_int, _dp, _dp, _dp]
         L.oracle_grad_values.restype = None
         _lib = L
@@ -304,6 +310,58 @@ def sparse_batch(n, indptr, indices, values, sym: Symbolic, eps, b, d=None, tran
                                     eps, c, _ptr(None if d is None else _f64(d)), nrhs, 1 if trans else 0,
                                     b, x, _ptr(xk), info)
     return x, info, xk, thr
+
+
+def divided_difference(j, eps, xk) -> np.ndarray:
+    """f[eps_0..eps_j] of the perturbed solutions xk (K, ...): sum_k x_k / prod_{l != k} (eps_k - eps_l)."""
+    xk = _f64(xk)
+    out = np.zeros(xk.shape[1:])
+    lib().oracle_divided_difference(j, _f64(eps), out.size, xk.reshape(xk.shape[0], -1), out.reshape(-1))
+    return out
+
+
+def error_estimate(eps, xk, x):
+    """(est, rho_hat) of one system from its perturbed solutions xk (K, n) and combination x (n):
+    est = |prod eps| m_{K-1}^2 / m_{K-2} / ||x||_inf with m_j = ||f[eps_0..eps_j]||_inf."""
+    xk = _f64(xk)
+    est, rho = C.c_double(), C.c_double()
+    lib().oracle_error_estimate(len(eps), _f64(eps), xk[0].size, xk.reshape(xk.shape[0], -1), _f64(x).reshape(-1),
+                                C.byref(est), C.byref(rho))
+    return est.value, rho.value
+
+
+def scale_exponent(eps, est: float, rho_hat: float) -> int:
+    """j of the node scale 2^-j that balances truncation against rounding (see psp_oracle.c)."""
+    return int(lib().oracle_scale_exponent(len(eps), _f64(eps), float(est), float(rho_hat)))
+
+
+def adaptive_batch(n, indptr, indices, values, sym: Symbolic, eps, b, tol: float, d=None):
+    """Alg. 1 with the error test deciding the node size per Jacobian: solve every Jacobian at the
+    nodes eps, estimate each combination's error from its perturbed solutions, and solve again the
+    Jacobians whose estimate exceeds tol (or is NaN) at the nodes 2^-j eps, j from
+    scale_exponent.  Returns (x, info, est, scale): the final combination, its info, its estimate
+    and the scale applied (1 where the first solve was kept)."""
+    values = _f64(values)
+    b = _f64(b)
+    eps = _f64(eps)
+    batch = values.shape[0]
+    x, info, xk, _ = sparse_batch(n, indptr, indices, values, sym, eps, b, d=d, keep_xk=True)
+    est = np.zeros(batch)
+    rho = np.zeros(batch)
+    for s in range(batch):
+        est[s], rho[s] = error_estimate(eps, xk[s], x[s])
+    scale = np.ones(batch)
+    for s in range(batch):
+        if not (est[s] <= tol):
+            scale[s] = 2.0 ** -scale_exponent(eps, est[s], rho[s])
+    for sc in np.unique(scale[scale != 1.0]):
+        idx = np.nonzero(scale == sc)[0]
+        e2 = eps * sc
+        x2, i2, xk2, _ = sparse_batch(n, indptr, indices, values[idx], sym, e2, b[idx], d=d, keep_xk=True)
+        x[idx], info[idx] = x2, i2
+        for t, s in enumerate(idx):
+            est[s], _ = error_estimate(e2, xk2[t], x2[t])
+    return x, info, est, scale
 
 
 def grad_values(n, indptr, indices, c, xk, lamk):

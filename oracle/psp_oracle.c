@@ -21,6 +21,9 @@
  *   solves       Alg. 1 step 2 (factor and solve each perturbed system);
  *                transposed solves for the adjoint.
  *   combine      Alg. 1 steps 3-4, eq. (x_star): x = sum_k c_k x_k.
+ *   estimate     Alg. 1 step 5 from the perturbed solutions alone: divided
+ *                differences give the expansion's next term (Sec. II-B,
+ *                Theorem 1); node scale from truncation vs rounding (Sec. V).
  *   pivoted LU   ground truth x* = A^{-1} b of Sec. III (problem statement).
  *   symbolic     static pivot sequence computed once and reused (Sec. II-C):
  *                minimum-degree order, elimination tree, fill, level sets.
@@ -139,6 +142,116 @@ EXPORT void oracle_combine(int K, int64_t len, const double* c, const double* xk
         for (int k = 0; k < K; ++k) acc = fma(c[k], xk[(size_t)k * len + i], acc);
         x[i] = acc;
     }
+}
+
+/* ------------------------------------------------------------------ */
+/* A-posteriori error estimate of the combination (Alg. 1 step 5 done    */
+/* without the unperturbed matrix).  By the expansion of Sec. II-B the   */
+/* perturbed solutions are x(eps) = sum_j (-eps)^j M^j x*, M = A^{-1} D, */
+/* so the divided difference of x over the first j+1 nodes,               */
+/*   f[eps_0..eps_j] = sum_{k<=j} x_k / prod_{l<=j, l!=k} (eps_k - eps_l),*/
+/* is (-1)^j M^j x* up to terms of order eps, and the combination's       */
+/* leading error is -(prod_k eps_k) M^K x* (Theorem 1 for general nodes). */
+/* With m_j = ||f[eps_0..eps_j]||_inf the ratio m_{K-1} / m_{K-2} is one  */
+/* more power of M (a growth factor rho_hat), and                         */
+/*   est = |prod_k eps_k| m_{K-1} rho_hat / ||x_hat||_inf                 */
+/* estimates the relative error of x_hat.  Operation order: the weights   */
+/* multiply (eps_k - eps_l) in ascending l and take one reciprocal; each  */
+/* entry of f is an fma chain over ascending k from zero; the product of  */
+/* |eps_k| runs in ascending k; est = ((P m1) (m1 / m2)) / mx.            */
+/* ------------------------------------------------------------------ */
+
+/* f[eps_0..eps_j] of the K blocks xk (each len values) into out. */
+EXPORT void oracle_divided_difference(int j, const double* eps, int64_t len, const double* xk, double* out) {
+    double w[64];
+    for (int k = 0; k <= j; ++k) {
+        double p = 1.0;
+        for (int l = 0; l <= j; ++l)
+            if (l != k) p = p * (eps[k] - eps[l]);
+        w[k] = 1.0 / p;
+    }
+    for (int64_t i = 0; i < len; ++i) {
+        double acc = 0.0;
+        for (int k = 0; k <= j; ++k) acc = fma(w[k], xk[(size_t)k * len + i], acc);
+        out[i] = acc;
+    }
+}
+
+static double max_abs(int64_t len, const double* v) {
+    double m = 0.0;
+    for (int64_t i = 0; i < len; ++i) {
+        const double a = fabs(v[i]);
+        if (a != a) return a;          /* NaN propagates */
+        if (a > m) m = a;
+    }
+    return m;
+}
+
+/* est and rho_hat of one system from its K (>= 3) perturbed solutions xk
+ * (K blocks of len) and the combination x.  m_{K-1} = 0 gives est = 0,
+ * rho_hat = 0; a NaN anywhere gives NaN. */
+EXPORT void oracle_error_estimate(int K, const double* eps, int64_t len, const double* xk, const double* x,
+                                  double* est, double* rho_hat) {
+    double* f = (double*)malloc(sizeof(double) * (size_t)(len > 0 ? len : 1));
+    oracle_divided_difference(K - 1, eps, len, xk, f);
+    const double m1 = max_abs(len, f);
+    oracle_divided_difference(K - 2, eps, len, xk, f);
+    const double m2 = max_abs(len, f);
+    free(f);
+    const double mx = max_abs(len, x);
+    if (m1 != m1 || m2 != m2 || mx != mx) {
+        *est = *rho_hat = m1 + m2 + mx;
+        return;
+    }
+    if (m1 == 0.0) {
+        *est = *rho_hat = 0.0;
+        return;
+    }
+    double P = 1.0;
+    for (int k = 0; k < K; ++k) P = P * fabs(eps[k]);
+    const double r = m1 / m2;
+    *rho_hat = r;
+    *est = ((P * m1) * r) / mx;
+}
+
+/* ------------------------------------------------------------------ */
+/* Node scale for a system whose estimate is above the tolerance (the    */
+/* perturbation strategy Sec. V leaves open).  The nodes become s eps_k   */
+/* with s = 2^-j, j >= 1 (the weights do not change).  The error at s is  */
+/* modelled as truncation + rounding,                                     */
+/*   T(s) = a s^K   with a = est when est < 1e-2 (the series converges   */
+/*                  and est is its leading term), else                    */
+/*                  a = |prod_k eps_k| rho_hat^K (a from the growth rate) */
+/*   R(s) = b / s   with b = gamma u / max_k |eps_k|, u = 2^-53,          */
+/* the rounding of the pivot-free solves growing like 1/eps once eps      */
+/* controls the smallest pivot (gamma = 50).  T + R is smallest at        */
+/* s* = q^{1/(K+1)}, q = b / (K a); j is the smallest j >= 1 with          */
+/* 2^{-j(K+1)} <= q, i.e. s is the largest power of two <= min(s*, 1/2),  */
+/* found from the binary exponent e of q (2^e <= q < 2^{e+1}):             */
+/* j = max(1, ceil(-e / (K+1))), at most 60.  A NaN est, or q zero or not */
+/* finite, gives j = 10.                                                  */
+/* ------------------------------------------------------------------ */
+EXPORT int oracle_scale_exponent(int K, const double* eps, double est, double rho_hat) {
+    if (est != est) return 10;
+    double emax = 0.0, P = 1.0;
+    for (int k = 0; k < K; ++k) {
+        const double a = fabs(eps[k]);
+        if (a > emax) emax = a;
+        P = P * a;
+    }
+    double a = est;
+    if (!(est < 1e-2)) {
+        a = P;
+        for (int k = 0; k < K; ++k) a = a * rho_hat;
+    }
+    const double b = (50.0 * 0x1p-53) / emax;
+    const double q = b / ((double)K * a);
+    if (!(q > 0.0) || !isfinite(q)) return 10;
+    const int e = ilogb(q);
+    int j = e >= 0 ? 1 : (-e + K) / (K + 1);
+    if (j < 1) j = 1;
+    if (j > 60) j = 60;
+    return j;
 }
 
 /* ------------------------------------------------------------------ */
