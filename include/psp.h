@@ -201,6 +201,43 @@ PSP_API psp_status psp_solve_batched(psp_plan plan, int32_t path, int32_t batch,
                              void* stream);
 
 /* ------------------------------------------------------------------------
+ * psp_solve_adaptive -- Alg. 1 with its error test (step 5) deciding the
+ * perturbation size per Jacobian (Sec. V leaves the perturbation strategy
+ * open; the expansion of Sec. II-B converges only while |eps| rho(A^{-1}D) < 1
+ * and its truncation grows with the nodes, its rounding with their inverse).
+ * Step-schedule path, nrhs = 1, K >= 3 nodes eps (host, distinct, nonzero).
+ *   1. Every Jacobian is solved at the nodes eps (as psp_solve_batched).
+ *   2. Error test without A: with f_j the divided difference of the K
+ *      perturbed solutions over nodes 0..j (= (-1)^j M^j x* up to O(eps),
+ *      M = A^{-1} D) and m_j = max_i |f_j[i]|,
+ *        rho_hat = m_{K-1} / m_{K-2},
+ *        est     = |prod eps_k| m_{K-1} rho_hat / ||x_hat||_inf,
+ *      the leading term -(prod eps_k) M^K x* of the combination's error
+ *      (Theorem 1), relative.
+ *   3. A Jacobian with est > tol (or NaN) is solved again at the nodes
+ *      s eps_k, s = 2^-j (the weights do not change): j is the smallest
+ *      j >= 1 with 2^{-j(K+1)} <= q = b / (K a), i.e. s is the largest power
+ *      of two at most min(s*, 1/2) where s* minimises the error model
+ *      a s^K + b / s; a = est (est < 1e-2) or |prod eps_k| rho_hat^K
+ *      (series possibly divergent), b = 50 u / max|eps_k|, u = 2^-53 (the
+ *      rounding of the pivot-free solves grows like 1/eps); at most j = 60,
+ *      j = 10 for a NaN est.  Its est is then taken at the new nodes.
+ *   values device batch x nnz;  d device n or NULL (D = I);  B, X device
+ *   batch x n;  info device batch x K (of the nodes finally used);
+ *   est device batch (final estimate);  scale device batch (1, or 2^-j);
+ *   ws device, psp_solve_adaptive_workspace_bytes(plan, batch, K) bytes,
+ *   256-byte aligned.  Asynchronous on `stream` (no host synchronisation:
+ *   the list of rescaled Jacobians stays on the device).
+ * PSP_E_INVALID for NULL pointers, batch < 1, K < 3 or a negative or
+ * non-finite tol; PSP_E_UNSUPPORTED when the plan has no step schedule.
+ * ---------------------------------------------------------------------- */
+PSP_API size_t psp_solve_adaptive_workspace_bytes(psp_plan plan, int32_t batch, int32_t K);
+PSP_API psp_status psp_solve_adaptive(psp_plan plan, int32_t batch, const double* values, int32_t K,
+                                      const double* eps, const double* d, double tol, const double* B, double* X,
+                                      int32_t* info, double* est, double* scale, void* ws, size_t ws_bytes,
+                                      void* stream);
+
+/* ------------------------------------------------------------------------
  * psp_solve_batched_noalloc -- psp_solve_batched on PSP_PATH_SPARSE_STEPS with
  * nrhs = 1 and no workspace argument, for callers that cannot allocate
  * device memory (code under HIP graph capture, tight serving loops, harnesses

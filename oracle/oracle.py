@@ -82,6 +82,8 @@ def lib():
                                            C.c_int, C.c_int, _dp, _dp, C.c_void_p, C.c_void_p, C.c_void_p]
         L.oracle_sparse_batch.argtypes = [C.c_int, _ip, _ip, C.c_int, _dp, _ip, _ip, _ip, C.c_int, _dp,
                                           _dp, C.c_void_p, C.c_int, C.c_int, _dp, _dp, C.c_void_p, _ip]
+        L.oracle_set_threads.argtypes = [C.c_int]
+        L.oracle_set_threads.restype = None
         L.oracle_divided_difference.argtypes = [C.c_int, _dp, C.c_int64, _dp, _dp]
         L.oracle_divided_difference.restype = None
         L.oracle_error_estimate.argtypes = [C.c_int, _dp, C.c_int64, _dp, _dp, C.POINTER(C.c_double),
@@ -104,6 +106,11 @@ def _i32(a):
 
 def _ptr(a):
     return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def set_threads(t: int) -> None:
+    """OpenMP threads of the batched routines (the host's count: os.cpu_count())."""
+    lib().oracle_set_threads(int(t))
 
 
 # ---------------------------------------------------------------- weights

@@ -43,6 +43,16 @@
 
 #define EXPORT __attribute__((visibility("default")))
 
+/* Number of OpenMP threads the batched routines use from now on (the CPU
+ * baseline is timed at one thread and at all threads). */
+EXPORT void oracle_set_threads(int t) {
+#ifdef _OPENMP
+    omp_set_num_threads(t > 0 ? t : 1);
+#else
+    (void)t;
+#endif
+}
+
 /* ------------------------------------------------------------------ */
 /* Weights.  Remark 2: beta = (Gamma_m^T)^{-1} e1 makes the combination  */
 /* keep the A^{-1} term with unit coefficient and cancel the next powers */

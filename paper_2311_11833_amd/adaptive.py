@@ -1,22 +1,20 @@
-"""Per-Jacobian choice of the perturbation size, built on top of the C ABI.
+"""Per-Jacobian perturbation size on top of the C ABI.
 
 The expansion behind the method converges only while every node satisfies
-|eps_k| rho(A^{-1} D) < 1 (Sec. II-B), and its truncation error is about
-prod_k |eps_k| rho^K, so one node set for a whole batch fails on the
-scenarios whose rho is large (Sec. V names the choice of eps and D as open).
-This module estimates rho for every Jacobian of a batch with a few power
-iterations on a slightly perturbed factorisation, picks
-    eps_0 = 10^-(ceil(log10 rho) + 2),   eps_k = eps_0 ratio^k,
-so that eps_0 rho <= 0.01, and solves each group of Jacobians that share an
-eps_0 with one batched call.  The power iteration and every factorisation
-and solve run in the library's kernels; this module draws the start vectors
-and groups the Jacobians by eps_0 on the host.
+|eps_k| rho(A^{-1} D) < 1 (Sec. II-B), and its truncation error grows with
+the nodes while the rounding of the pivot-free solves grows as they shrink,
+so one node set for a whole batch fails on the Jacobians whose rho is large
+(Sec. V names the choice of eps and D as open).  Two tools, both in the
+library's kernels:
+
+* solve_adaptive: psp_solve_adaptive, the error test of Alg. 1 step 5 taken
+  from the perturbed solutions themselves, with a second, rescaled solve of the
+  Jacobians that fail it (the rule lives behind the C ABI);
+* estimate_rho: psp_estimate_rho, power iteration for rho(A^{-1} D) on a
+  slightly perturbed pivot-free factorisation (diagnostics); this module only
+  draws its start vectors.
 """
 from __future__ import annotations
-
-import math
-
-import numpy as np
 
 from . import psp
 
@@ -35,32 +33,6 @@ def estimate_rho(plan: psp.Plan, values, d=None, probe: float = 1e-8, iters: int
     return psp.estimate_rho(plan, values, v0, d=d, probe=probe, iters=iters).cpu().numpy()
 
 
-def choose_eps0(rho, offset: int = 2):
-    """eps_0 = 10^-(ceil(log10 rho) + offset) per Jacobian (rho <= 0 or non-finite: 1e-3 * 10^-offset)."""
-    rho = np.asarray(rho, dtype=np.float64)
-    out = np.empty_like(rho)
-    for i, r in enumerate(rho):
-        e = math.ceil(math.log10(r)) if (np.isfinite(r) and r > 0) else 3
-        out[i] = 10.0 ** (-(e + offset))
-    return out
-
-
-def solve_adaptive(plan: psp.Plan, values, b, K: int = 5, ratio: float = 0.5, d=None, offset: int = 2,
-                   rho=None, path: str = "auto"):
-    """Alg. 1 with eps chosen per Jacobian: returns (x, info, eps0) with x shaped like b,
-    info (batch, K) and eps0 (batch,) the first node used for each Jacobian."""
-    import torch
-    if rho is None:
-        rho = estimate_rho(plan, values, d=d)
-    eps0 = choose_eps0(rho, offset)
-    x = torch.empty_like(b)
-    info = torch.empty((values.shape[0], K), dtype=torch.int32, device=values.device)
-    for e0 in np.unique(eps0):
-        idx_np = np.nonzero(eps0 == e0)[0]
-        idx = torch.from_numpy(idx_np).to(values.device)
-        eps = e0 * ratio ** np.arange(K)
-        xs, inf = psp.solve_batched(plan, values.index_select(0, idx).contiguous(), eps,
-                                    b.index_select(0, idx).contiguous(), path=path, d=d)
-        x.index_copy_(0, idx, xs)
-        info.index_copy_(0, idx, inf)
-    return x, info, eps0
+def solve_adaptive(plan: psp.Plan, values, b, eps, tol: float = 1e-10, d=None):
+    """Alg. 1 with the error test choosing the node size per Jacobian; returns (x, info, est, scale)."""
+    return psp.solve_adaptive(plan, values, eps, b, tol=tol, d=d)

@@ -23,6 +23,7 @@
 #include "dense.h"
 #include "powerflow.h"
 #include "estimate.h"
+#include "adapt.h"
 
 using namespace psp;
 
@@ -416,6 +417,70 @@ psp_status psp_solve_batched_noalloc(psp_plan p, int32_t batch, const double* va
     HIP_TRY(noalloc_scratch(&scratch), "hipGetSymbolAddress(scratch)");
     HIP_TRY(steps_solve(p->sp, s.n, s.nnz, batch, values, es, d, B, X, info, (double*)scratch, (hipStream_t)stream),
             "step-kernel launch");
+    return PSP_OK;
+}
+
+size_t psp_solve_adaptive_workspace_bytes(psp_plan p, int32_t batch, int32_t K) {
+    if (!p || batch < 1 || K < 1 || K > kMaxK) return 0;
+    return (size_t)(align_up((int64_t)batch * K * p->sym.n * 8, kAlign) + align_up((int64_t)batch * 4, kAlign) + kAlign);
+}
+
+psp_status psp_solve_adaptive(psp_plan p, int32_t batch, const double* values, int32_t K, const double* eps,
+                              const double* d, double tol, const double* B, double* X, int32_t* info, double* est,
+                              double* scale, void* ws, size_t ws_bytes, void* stream) {
+    if (!p || batch < 1 || !values || !B || !X || !info || !est || !scale || !ws)
+        return fail(PSP_E_INVALID, "psp_solve_adaptive: NULL argument or batch < 1");
+    if (K < 3) return fail(PSP_E_INVALID, "psp_solve_adaptive: the error estimate needs K >= 3 nodes");
+    if (!std::isfinite(tol) || tol < 0.0) return fail(PSP_E_INVALID, "psp_solve_adaptive: tol must be finite and >= 0");
+    EpsSet es;
+    if (psp_status st = make_eps(K, eps, es)) return st;
+    if (psp_status st = check_prior_hip()) return st;
+    if (psp_status r = require_upload(p)) return r;
+    if (!steps_ready(p->sp))
+        return fail(PSP_E_UNSUPPORTED, "psp_solve_adaptive: the plan has no step schedule (it does not fit in LDS)");
+    const size_t need = psp_solve_adaptive_workspace_bytes(p, batch, K);
+    if (ws_bytes < need) return fail(PSP_E_NOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
+    if (((uintptr_t)ws & 255) != 0) return fail(PSP_E_INVALID, "psp_solve_adaptive: workspace must be 256-byte aligned");
+    const Symbolic& s = p->sym;
+    const hipStream_t st = (hipStream_t)stream;
+    // divided-difference weights over nodes 0..j (ascending-l products, one reciprocal), the node
+    // product and the rounding coefficient of the scale rule
+    AdaptConst c{};
+    for (int which = 0; which < 2; ++which) {
+        const int j = K - 1 - which;
+        double* w = which == 0 ? c.w1 : c.w2;
+        for (int k = 0; k <= j; ++k) {
+            double prod = 1.0;
+            for (int l = 0; l <= j; ++l)
+                if (l != k) prod = prod * (eps[k] - eps[l]);
+            w[k] = 1.0 / prod;
+        }
+    }
+    double emax = 0.0;
+    c.P = 1.0;
+    for (int k = 0; k < K; ++k) {
+        c.c[k] = es.c[k];
+        const double a = std::fabs(eps[k]);
+        emax = std::max(emax, a);
+        c.P = c.P * a;
+    }
+    c.b = (50.0 * 0x1p-53) / emax;
+    char* w = (char*)ws;
+    double* Xk = (double*)w;
+    int32_t* list = (int32_t*)(w + align_up((int64_t)batch * K * s.n * 8, kAlign));
+    int32_t* count = (int32_t*)((char*)list + align_up((int64_t)batch * 4, kAlign));
+    const bool per_jacobian = steps_per_jacobian(p->sp, batch);
+    HIP_TRY(launch_adapt_reset(count, st), "adapt reset launch");
+    HIP_TRY(steps_run(p->sp, s.nnz, batch, values, es, d, B, X, Xk, info, per_jacobian, st, true), "step-kernel launch");
+    AdaptArgs a{};
+    a.n = s.n; a.K = K; a.batch = batch; a.pass = 1; a.combine = per_jacobian ? 0 : 1; a.tol = tol;
+    a.Xk = Xk; a.X = X; a.est = est; a.scale = scale; a.list = list; a.count = count;
+    HIP_TRY(launch_adapt(a, c, st), "error-test launch");
+    HIP_TRY(steps_run_list(p->sp, s.nnz, batch, values, es, d, B, Xk, info, list, count, scale, st),
+            "step-kernel launch (rescaled nodes)");
+    a.pass = 2;
+    a.combine = 1;
+    HIP_TRY(launch_adapt(a, c, st), "error-test launch (rescaled nodes)");
     return PSP_OK;
 }
 

@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 OUT = os.path.join(PKG, "libpsp.so")
-SOURCES = ["api.cpp", "plan.cpp", "dense.hip", "sparse.hip", "steps.hip", "residual.hip", "powerflow.hip", "estimate.hip", "noalloc.hip"]
+SOURCES = ["api.cpp", "plan.cpp", "dense.hip", "sparse.hip", "steps.hip", "residual.hip", "powerflow.hip", "estimate.hip", "noalloc.hip", "adapt.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-fvisibility=hidden", "-I" + os.path.join(ROOT, "include"), "-I" + HERE]

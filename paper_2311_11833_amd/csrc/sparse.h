@@ -76,11 +76,17 @@ void steps_image(const Symbolic& s, const std::vector<int32_t>& r_pos, PlanImage
 hipError_t sparse_kernel_attrs();
 hipError_t steps_kernel_attrs();
 // one launch; X (batch x n) combined in-kernel when per_jacobian, else Xk (batch x K x n) is written
+// (per_jacobian with xk_too: both)
 int steps_per_cu(const SparseDevice& d);   // step-kernel workgroups resident per CU (1 or 2)
 int64_t steps_lds_bytes(const SparseDevice& d);   // dynamic LDS of one step-kernel workgroup (0: no schedule)
 hipError_t steps_run(const SparseDevice& d, int32_t nnz, int32_t batch, const double* values, const EpsSet& es,
                      const double* dvec, const double* B, double* X, double* Xk, int32_t* info, bool per_jacobian,
-                     hipStream_t st);
+                     hipStream_t st, bool xk_too = false);
+// Per-system launch over the Jacobians list[0 .. *count-1] (device count, at most batch) with the
+// nodes scale[s] eps_k (scale: powers of two); writes Xk[s][k] and info[s*K + k] of those only.
+hipError_t steps_run_list(const SparseDevice& d, int32_t nnz, int32_t batch, const double* values, const EpsSet& es,
+                          const double* dvec, const double* B, double* Xk, int32_t* info, const int32_t* list,
+                          const int32_t* count, const double* scale, hipStream_t st);
 // One workgroup per Jacobian (combine fused, no workspace) once the batch fills every resident slot.
 bool steps_per_jacobian(const SparseDevice& d, int32_t batch);
 // steps_run in the mode steps_per_jacobian picks, plus the combine launch in per-system mode

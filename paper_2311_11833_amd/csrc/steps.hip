@@ -340,8 +340,13 @@ struct StArgs {
     const double* dvec;
     const double* B;        // batch x n
     double* X;              // batch x n        (per_jacobian)
-    double* Xk;             // batch x K x n    (otherwise)
+    double* Xk;             // batch x K x n    (otherwise; per_jacobian: also written when xk_too)
     int32_t* info;          // batch x K
+    int32_t xk_too;
+    // list mode (per system): only the Jacobians list[0 .. *count-1], with nodes scale[s] eps_k
+    const int32_t* list;
+    const int32_t* count;
+    const double* scale;
 };
 
 template <bool PACKED>
@@ -378,7 +383,7 @@ __device__ __forceinline__ int4 st_desc(__amdgpu_buffer_rsrc_t r, int2 m, int ti
 
 // waves_per_eu(8): registers for eight waves per SIMD, i.e. two 1024-lane workgroups per CU
 // (without it the kernel takes 112 scalar registers per wave, which leaves room for seven)
-template <int T, bool PACKED>
+template <int T, bool PACKED, bool LIST>
 __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(8))) void steps_kernel(StArgs a, EpsSet es) {
     // 16-byte aligned: the step metadata after the values is read as int4
     // (a misaligned ds_read_b128 every step costs several times the step)
@@ -411,9 +416,9 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(8))) void ste
     // gfx9-family buffer resource: raw (stride 0), range = the descriptor array
     const __amdgpu_buffer_rsrc_t drs =
         __builtin_amdgcn_make_buffer_rsrc((void*)a.sx.desc, (short)0, a.sx.ndesc * 16, 0x00020000);
-    const int njobs = a.per_jacobian ? a.batch : a.batch * es.K;
+    const int njobs = LIST ? *a.count * es.K : (a.per_jacobian ? a.batch : a.batch * es.K);
     for (int job = blockIdx.x; job < njobs; job += gridDim.x) {
-        const int s = a.per_jacobian ? job : job / es.K;
+        const int s = LIST ? a.list[job / es.K] : (a.per_jacobian ? job : job / es.K);
         const int k0 = a.per_jacobian ? 0 : job % es.K, k1 = a.per_jacobian ? es.K : k0 + 1;
         const double* vals = a.values + (int64_t)s * a.nnz;
         for (int kk = k0; kk < k1; ++kk) {
@@ -438,7 +443,8 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(8))) void ste
                     if (du >= 0) v[du] = su >= 0 ? vals[su] : 0.0;
                 }
             }
-            const double ek = s_eps[kk];
+            // a power-of-two node scale (list mode) multiplies every node exactly
+            const double ek = LIST ? __dmul_rn(s_eps[kk], a.scale[s]) : s_eps[kk];
             for (int j = tid; j < n; j += T) {
                 const int sd = ix.src_d[j], pj = ix.perm[j];
                 const double ajj = sd >= 0 ? vals[sd] : 0.0;
@@ -469,11 +475,13 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(8))) void ste
                 if (bad_pivot(v[j])) atomicMin(&s_bad, j + 1);
             __syncthreads();
             const int bad = s_bad == INT_MAX ? 0 : s_bad;
-            if (a.per_jacobian) {
+            if (!LIST && a.per_jacobian) {
                 const double c = s_c[kk];
+                double* xk = a.xk_too ? a.Xk + ((int64_t)s * es.K + kk) * n : nullptr;
                 for (int q = tid; q < n; q += T) {
                     const double xq = bad ? __builtin_nan("") : y[q];
                     cx[q] = fmad(c, xq, kk == 0 ? 0.0 : cx[q]);
+                    if (xk) xk[ix.perm[q]] = xq;
                 }
             } else {
                 double* xk = a.Xk + ((int64_t)s * es.K + kk) * n;
@@ -482,7 +490,7 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(8))) void ste
             if (tid == 0) a.info[s * es.K + kk] = bad;
             __syncthreads();
         }
-        if (a.per_jacobian)
+        if (!LIST && a.per_jacobian)
             for (int q = tid; q < n; q += T) a.X[(int64_t)s * n + ix.perm[q]] = cx[q];
     }
 }
@@ -539,7 +547,10 @@ int steps_per_cu(const SparseDevice& d) {
 // the compiled static LDS stays within the headroom the schedule sizes assume.
 hipError_t steps_kernel_attrs() {
     static hipError_t e = [] {
-        const void* ks[2] = {(const void*)steps_kernel<kStThreads, true>, (const void*)steps_kernel<kStThreads, false>};
+        const void* ks[4] = {(const void*)steps_kernel<kStThreads, true, false>,
+                             (const void*)steps_kernel<kStThreads, false, false>,
+                             (const void*)steps_kernel<kStThreads, true, true>,
+                             (const void*)steps_kernel<kStThreads, false, true>};
         for (const void* k : ks) {
             hipFuncAttributes fa{};
             hipError_t r = hipFuncGetAttributes(&fa, k);
@@ -555,9 +566,10 @@ hipError_t steps_kernel_attrs() {
 
 hipError_t steps_run(const SparseDevice& d, int32_t nnz, int32_t batch, const double* values, const EpsSet& es,
                      const double* dvec, const double* B, double* X, double* Xk, int32_t* info, bool per_jacobian,
-                     hipStream_t st) {
+                     hipStream_t st, bool xk_too) {
     if (!steps_ready(d) || d.st.threads != kStThreads) return hipErrorInvalidValue;
     StArgs a{};
+    a.xk_too = per_jacobian && xk_too ? 1 : 0;
     a.sx = d.st;
     a.ix = d.idx;
     a.nnz = nnz; a.batch = batch; a.K = es.K; a.per_jacobian = per_jacobian ? 1 : 0;
@@ -572,9 +584,34 @@ hipError_t steps_run(const SparseDevice& d, int32_t nnz, int32_t batch, const do
     const int64_t jobs = per_jacobian ? batch : (int64_t)batch * es.K;
     const int grid = (int)std::min<int64_t>(jobs, resident);
     if (d.st.packed)
-        hipLaunchKernelGGL((steps_kernel<kStThreads, true>), dim3(grid), dim3(kStThreads), lds, st, a, es);
+        hipLaunchKernelGGL((steps_kernel<kStThreads, true, false>), dim3(grid), dim3(kStThreads), lds, st, a, es);
     else
-        hipLaunchKernelGGL((steps_kernel<kStThreads, false>), dim3(grid), dim3(kStThreads), lds, st, a, es);
+        hipLaunchKernelGGL((steps_kernel<kStThreads, false, false>), dim3(grid), dim3(kStThreads), lds, st, a, es);
+    return hipGetLastError();
+}
+
+hipError_t steps_run_list(const SparseDevice& d, int32_t nnz, int32_t batch, const double* values, const EpsSet& es,
+                          const double* dvec, const double* B, double* Xk, int32_t* info, const int32_t* list,
+                          const int32_t* count, const double* scale, hipStream_t st) {
+    if (!steps_ready(d) || d.st.threads != kStThreads) return hipErrorInvalidValue;
+    StArgs a{};
+    a.sx = d.st;
+    a.ix = d.idx;
+    a.nnz = nnz; a.batch = batch; a.K = es.K; a.per_jacobian = 0;
+    a.values = values; a.dvec = dvec; a.B = B; a.X = nullptr; a.Xk = Xk; a.info = info;
+    a.list = list; a.count = count; a.scale = scale;
+    const int lds = (int)st_lds_total(d.idx.n, d.st.pool, d.st.nsteps);
+    hipError_t e = steps_kernel_attrs();
+    if (e != hipSuccess) return e;
+    int dev = 0, cus = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    // the job count is on the device: every resident slot, idle ones leave at once
+    const int grid = (int)std::min<int64_t>((int64_t)batch * es.K, (int64_t)cus * steps_per_cu(d));
+    if (d.st.packed)
+        hipLaunchKernelGGL((steps_kernel<kStThreads, true, true>), dim3(grid), dim3(kStThreads), lds, st, a, es);
+    else
+        hipLaunchKernelGGL((steps_kernel<kStThreads, false, true>), dim3(grid), dim3(kStThreads), lds, st, a, es);
     return hipGetLastError();
 }
 

@@ -24,7 +24,8 @@ PATH_NAMES = {v: k for k, v in PATHS.items()}
 ORDERS = {"md": 0, "natural": 1}
 EXPORTED = ["psp_last_error", "psp_version", "psp_plan_create", "psp_plan_info", "psp_plan_export",
             "psp_plan_destroy", "psp_plan_device_bytes", "psp_plan_upload", "psp_weights", "psp_workspace_bytes",
-            "psp_solve_batched", "psp_solve_batched_noalloc", "psp_tune", "psp_factor", "psp_solve", "psp_combine", "psp_grad_values",
+            "psp_solve_batched", "psp_solve_batched_noalloc", "psp_solve_adaptive_workspace_bytes",
+            "psp_solve_adaptive", "psp_tune", "psp_factor", "psp_solve", "psp_combine", "psp_grad_values",
             "psp_factors_release", "psp_residual", "psp_group_create", "psp_group_workspace_bytes", "psp_group_run",
             "psp_group_capture", "psp_graph_launch", "psp_graph_destroy", "psp_group_destroy", "psp_pf_device_bytes",
             "psp_pf_create", "psp_pf_destroy", "psp_pf_eval", "psp_pf_workspace_bytes", "psp_pf_newton",
@@ -79,6 +80,9 @@ def lib():
         L.psp_workspace_bytes.restype = C.c_size_t
         L.psp_solve_batched.argtypes = [vp, i32, i32, vp, i32, vp, vp, i32, vp, vp, vp, vp, C.c_size_t, vp]
         L.psp_solve_batched_noalloc.argtypes = [vp, i32, vp, i32, vp, vp, vp, vp, vp, vp]
+        L.psp_solve_adaptive_workspace_bytes.argtypes = [vp, i32, i32]
+        L.psp_solve_adaptive_workspace_bytes.restype = C.c_size_t
+        L.psp_solve_adaptive.argtypes = [vp, i32, vp, i32, vp, vp, d, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]
         L.psp_tune.argtypes = [vp, i32, vp, i32, vp, vp, i32, vp, vp, vp, vp, C.c_size_t, vp, vp, vp]
         L.psp_factor.argtypes = [vp, i32, i32, vp, i32, vp, vp, vp, vp, C.c_size_t, vp, C.POINTER(vp)]
         L.psp_solve.argtypes = [vp, i32, vp, vp, i32, vp]
@@ -112,7 +116,7 @@ def lib():
             if f not in ("psp_last_error", "psp_version", "psp_plan_destroy", "psp_plan_device_bytes",
                          "psp_workspace_bytes", "psp_group_workspace_bytes", "psp_graph_destroy",
                          "psp_group_destroy", "psp_pf_device_bytes", "psp_pf_destroy", "psp_pf_workspace_bytes",
-                         "psp_estimate_rho_workspace_bytes"):
+                         "psp_estimate_rho_workspace_bytes", "psp_solve_adaptive_workspace_bytes"):
                 getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -266,6 +270,34 @@ def solve_batched(plan: Plan, values, eps, b, path: str = "auto", d=None, worksp
                                    nrhs, _dptr(b.contiguous()), _dptr(x), _dptr(info), _dptr(ws), ws.numel(),
                                    _stream(stream)))
     return x, info
+
+
+def solve_adaptive(plan: Plan, values, eps, b, tol: float = 1e-10, d=None, workspace=None, stream=None):
+    """Alg. 1 with the error test choosing the node size per Jacobian (psp_solve_adaptive).
+
+    values (batch, nnz), b (batch, n) float64 device tensors; eps the first node set (K >= 3).
+    Returns (x, info, est, scale): x (batch, n), info (batch, K), the final error estimate and
+    the node scale used per Jacobian (1, or a power of two below 1)."""
+    import torch
+    batch = values.shape[0]
+    eps_h = np.ascontiguousarray(eps, dtype=np.float64)
+    K = len(eps_h)
+    if values.dtype != torch.float64 or b.dtype != torch.float64:
+        raise TypeError("values and b must be float64")
+    if values.shape[1] != plan.nnz or b.dim() != 2 or b.shape[1] != plan.n or b.shape[0] != batch:
+        raise ValueError("shape mismatch with the plan")
+    plan.ensure(values.device)
+    dev = values.device
+    x = torch.empty_like(b)
+    info = torch.empty((batch, K), dtype=torch.int32, device=dev)
+    est = torch.empty(batch, dtype=torch.float64, device=dev)
+    scale = torch.empty(batch, dtype=torch.float64, device=dev)
+    need = lib().psp_solve_adaptive_workspace_bytes(plan.handle, batch, K)
+    ws = plan.workspace(need, dev) if workspace is None else workspace
+    _check(lib().psp_solve_adaptive(plan.handle, batch, _dptr(values), K, _np_ptr(eps_h), _dptr(d), float(tol),
+                                    _dptr(b.contiguous()), _dptr(x), _dptr(info), _dptr(est), _dptr(scale),
+                                    _dptr(ws), ws.numel(), _stream(stream)))
+    return x, info, est, scale
 
 
 class Group:
