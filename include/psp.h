@@ -100,6 +100,8 @@ typedef struct {
     int64_t steps_lds_bytes;   /* dynamic LDS of one step-kernel workgroup          */
     int32_t steps_per_cu;      /* step-kernel workgroups resident per CU (0, 1, 2)  */
     int64_t device_bytes;      /* psp_plan_device_bytes                              */
+    int32_t tail_n;            /* columns of the dense trailing block (0: none)      */
+    int32_t tail_fac_levels;   /* factor levels below it                             */
 } psp_plan_info_t;
 
 PSP_API psp_status psp_plan_info(psp_plan plan, psp_plan_info_t* out);
@@ -158,6 +160,14 @@ PSP_API psp_status psp_weights(int32_t K, const double* eps, double* c);
  *                     inputs are final, forward substitution overlapping the
  *                     factorisation; one launch per call (needs nrhs = 1 and
  *                     (3 n + 2 nnz_l) * 8 <= 152 KiB).
+ *   PSP_PATH_SPARSE_TAIL     per-level kernels for the columns before the
+ *                     plan's dense trailing block (the last columns of the
+ *                     factor when they are full and sit above every other
+ *                     column in the elimination tree: the top separator and
+ *                     the slack column), which is then factored and solved
+ *                     densely in panels on the MFMA unit, several workgroups
+ *                     per system (needs a trailing block of at least 64
+ *                     columns).
  *   PSP_PATH_AUTO     the path psp_tune chose for this (batch, K, nrhs), else
  *                     a size heuristic.
  * A path that cannot run the plan returns PSP_E_UNSUPPORTED.  Every path
@@ -171,7 +181,8 @@ enum {
     PSP_PATH_SPARSE_LDS = 4,
     PSP_PATH_SPARSE_LEVELS = 5,
     PSP_PATH_SPARSE_GROUPED = 6,
-    PSP_PATH_SPARSE_STEPS = 7
+    PSP_PATH_SPARSE_STEPS = 7,
+    PSP_PATH_SPARSE_TAIL = 8
 };
 
 /* Bytes of device workspace psp_factor / psp_solve_batched need for `batch`
@@ -317,7 +328,7 @@ PSP_API void psp_group_destroy(psp_group g);
  * and records the fastest as the PSP_PATH_AUTO choice for (batch, K, nrhs).
  * Arguments as for psp_solve_batched (X and info receive the last run's
  * results, which are the same on every path).  chosen (host, may be NULL)
- * receives the path id; ms (host, may be NULL, 8 entries indexed by path id)
+ * receives the path id; ms (host, may be NULL, 9 entries indexed by path id)
  * receives the mean time per call, -1 for a path not run.  Size the
  * workspace with psp_workspace_bytes(plan, PSP_PATH_AUTO, ...), which covers
  * every candidate.

@@ -192,6 +192,7 @@ PathSel split_path(int32_t path) {
         case PSP_PATH_SPARSE_LEVELS: return {PSP_PATH_SPARSE, kVarGlobal};
         case PSP_PATH_SPARSE_GROUPED: return {PSP_PATH_SPARSE, kVarGrouped};
         case PSP_PATH_SPARSE_STEPS: return {PSP_PATH_SPARSE, kVarSteps};
+        case PSP_PATH_SPARSE_TAIL: return {PSP_PATH_SPARSE, kVarTail};
         default: return {-1, -1};
     }
 }
@@ -279,6 +280,8 @@ psp_status psp_plan_info(psp_plan p, psp_plan_info_t* o) {
     o->steps_lds_bytes = steps_lds_bytes(p->sp);
     o->steps_per_cu = steps_ready(p->sp) ? steps_per_cu(p->sp) : 0;
     o->device_bytes = (int64_t)std::max<size_t>(p->img.bytes(), 256);
+    o->tail_n = s.tail_n;
+    o->tail_fac_levels = s.tail_n ? s.fac_lev_sp : 0;
     return PSP_OK;
 }
 
@@ -341,7 +344,7 @@ size_t psp_workspace_bytes(psp_plan p, int32_t path, int32_t batch, int32_t K, i
     if (!p || batch < 1 || K < 1 || nrhs < 0) return 0;
     if (path == PSP_PATH_AUTO) {
         size_t m = 0;
-        for (int32_t c = PSP_PATH_DENSE; c <= PSP_PATH_SPARSE_STEPS; ++c)
+        for (int32_t c = PSP_PATH_DENSE; c <= PSP_PATH_SPARSE_TAIL; ++c)
             if (c != PSP_PATH_DENSE || p->sym.n <= kDenseMaxN) m = std::max(m, path_workspace(p->sym, c, batch, K, nrhs, keep));
         return m;
     }
@@ -490,14 +493,14 @@ psp_status psp_tune(psp_plan p, int32_t batch, const double* values, int32_t K, 
     if (!p) return fail(PSP_E_INVALID, "psp_tune: NULL plan");
     const hipStream_t st = (hipStream_t)stream;
     if (ms)
-        for (int c = 0; c <= PSP_PATH_SPARSE_STEPS; ++c) ms[c] = -1.0f;
+        for (int c = 0; c <= PSP_PATH_SPARSE_TAIL; ++c) ms[c] = -1.0f;
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
     HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
     int32_t best = -1;
     float best_ms = 0.0f;
     psp_status last = PSP_OK;
-    for (int32_t c = PSP_PATH_DENSE; c <= PSP_PATH_SPARSE_STEPS; ++c) {
+    for (int32_t c = PSP_PATH_DENSE; c <= PSP_PATH_SPARSE_TAIL; ++c) {
         if (c == PSP_PATH_SPARSE) continue;   // its executions are tried one by one
         if (path_workspace(p->sym, c, batch, K, nrhs, 0) > ws_bytes) continue;
         psp_status r = psp_solve_batched(p, c, batch, values, K, eps, d, nrhs, B, X, info, ws, ws_bytes, stream);

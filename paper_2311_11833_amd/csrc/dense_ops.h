@@ -1,0 +1,291 @@
+// dense_ops.h -- the dense pivot-free LU building blocks for gfx950 (internal),
+// shared by the dense path (one workgroup per system) and the dense trailing
+// block of the sparse path (one large block per system, many workgroups).
+// Every routine runs in one workgroup of WG threads.
+//
+// Every entry receives its updates a <- fma(-l, u, a) in ascending pivot
+// order and every multiplier is an IEEE division, which is the operation
+// sequence of the reference factorisation; results are identical bit for bit.
+#pragma once
+
+#include "common.h"
+
+namespace psp {
+
+constexpr int NB = 32;        // panel width
+constexpr int TB = 64;        // trailing-update tile (TB x TB)
+constexpr int SB = 64;        // triangular-solve block
+constexpr int WG = 512;       // threads per workgroup (8 waves)
+
+// ---------------------------------------------------------------- factorisation
+// GETRF of the NB x NB diagonal block at (c0, c0) by wave 0 (lane = row); the
+// factored block is left in M and in D (row-major, LDS).  Returns the 1-based
+// position of the first bad pivot or 0 (valid in wave 0 only).
+__device__ __forceinline__ int panel_getrf(double* M, int ld, int c0, double* D) {
+    const int lane = threadIdx.x & 63;
+    double r[NB];
+    const bool act = lane < NB;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) r[j] = act ? M[(int64_t)(c0 + j) * ld + c0 + lane] : 0.0;
+    int bad = 0;
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        const double ukk = readlane_d(r[k], k);
+        if (!bad && bad_pivot(ukk)) bad = c0 + k + 1;
+        const bool below = lane > k;
+        const double l = r[k] / ukk;
+        r[k] = below ? l : r[k];
+#pragma unroll
+        for (int j = k + 1; j < NB; ++j) {
+            const double ukj = readlane_d(r[j], k);
+            r[j] = below ? fmad(-l, ukj, r[j]) : r[j];
+        }
+    }
+    if (act) {
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            M[(int64_t)(c0 + j) * ld + c0 + lane] = r[j];
+            D[lane * NB + j] = r[j];
+        }
+    }
+    return bad;
+}
+
+// Load the factored diagonal block at (c0, c0) into D.
+__device__ __forceinline__ void load_diag(const double* M, int ld, int c0, double* D) {
+    for (int t = threadIdx.x; t < NB * NB; t += WG) {
+        const int i = t % NB, j = t / NB;
+        D[i * NB + j] = M[(int64_t)(c0 + j) * ld + c0 + i];
+    }
+}
+
+// One thread per item: rows [r_lo, r_hi) get l = a U^{-1} on the panel columns
+// (TRSM from the right with the upper triangle of D, IEEE divisions), columns
+// [c_lo, c_hi) get u = L^{-1} a on the panel rows (unit lower triangle of D).
+__device__ __forceinline__ void panel_trsm(double* M, int ld, int c0, const double* D, int r_lo, int r_hi, int c_lo, int c_hi) {
+    const int nrows = max(0, r_hi - r_lo), ncolr = max(0, c_hi - c_lo);
+    for (int t = threadIdx.x; t < nrows + ncolr; t += WG) {
+        double r[NB];
+        // keep the LDS reads of D inside the loop (hoisting them all would exhaust registers)
+        int z;
+        asm volatile("v_mov_b32 %0, 0" : "=v"(z));   // opaque zero offset
+        const double* Dv = D + z;
+        if (t < nrows) {
+            const int i = r_lo + t;
+#pragma unroll
+            for (int j = 0; j < NB; ++j) r[j] = M[(int64_t)(c0 + j) * ld + i];
+#pragma unroll
+            for (int k = 0; k < NB; ++k) {
+                const double l = r[k] / Dv[k * NB + k];
+                r[k] = l;
+#pragma unroll
+                for (int j = k + 1; j < NB; ++j) r[j] = fmad(-l, Dv[k * NB + j], r[j]);
+            }
+#pragma unroll
+            for (int j = 0; j < NB; ++j) M[(int64_t)(c0 + j) * ld + i] = r[j];
+        } else {
+            const int j = c_lo + (t - nrows);
+            double* col = M + (int64_t)j * ld + c0;
+#pragma unroll
+            for (int i = 0; i < NB; ++i) r[i] = col[i];
+#pragma unroll
+            for (int k = 0; k < NB; ++k)
+#pragma unroll
+                for (int i = k + 1; i < NB; ++i) r[i] = fmad(-Dv[i * NB + k], r[k], r[i]);
+#pragma unroll
+            for (int i = 0; i < NB; ++i) col[i] = r[i];
+        }
+    }
+}
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// C[r_lo:r_hi, c_lo:c_hi] -= L[:, k_lo:k_lo+KD] * U[k_lo:k_lo+KD, :] on the
+// MFMA unit.  v_mfma_f64_16x16x4f64 accumulates each output as a chain of
+// fmas in ascending k (checked on gfx950), so feeding k in ascending order
+// keeps the reference operation sequence.  Each 16 x 16 block is computed
+// transposed (D = (-U)^T L^T + C^T) so that a lane's accumulators run down a
+// column of the column-major matrix: lane l, register q holds
+// C[row0 + l%16][col0 + 4q + l/16].  Each wave keeps its 16 rows of L
+// (the b operand) in registers for the whole sweep; the U tile (KD x 64) is
+// staged in LDS and shared by the 8 waves; the workgroup covers 128 rows x 64
+// columns per step.
+constexpr int KDMAX = 128;
+
+template <int KDM = KDMAX>
+__device__ __forceinline__ void gemm_mfma(double* M, int ld, int r_lo, int r_hi, int c_lo, int c_hi, int k_lo, int kd,
+                                          double* Us) {
+    constexpr int KS = KDM / 4;
+    constexpr int NW = WG / 64;                 // waves; each owns 16 rows of the 16*NW-row group
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int ks = kd / 4;
+    for (int rg = r_lo; rg < r_hi; rg += 16 * NW) {
+        const int wr = rg + 16 * wave;
+        const bool wact = wr < r_hi;
+        const bool rok = wact && wr + li < r_hi;
+        double bop[KS];
+        {
+            const double* lb = M + (int64_t)(k_lo + lk) * ld + wr + li;
+#pragma unroll
+            for (int s = 0; s < KS; ++s) bop[s] = (rok && s < ks) ? lb[(int64_t)(4 * s) * ld] : 0.0;
+        }
+        for (int ct = c_lo; ct < c_hi; ct += 64) {
+            __syncthreads();
+            for (int t = tid; t < kd * 64; t += WG) {
+                const int k = t % kd, c = t / kd;
+                Us[k * 64 + c] = (ct + c < c_hi) ? -M[(int64_t)(ct + c) * ld + k_lo + k] : 0.0;
+            }
+            __syncthreads();
+            if (!wact) continue;
+            double* cb0 = M + (int64_t)(ct + lk) * ld + wr + li;
+            v4d acc[4];
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const bool ok = rok && (ct + 16 * cb + 4 * q + lk < c_hi);
+                    acc[cb][q] = ok ? cb0[(int64_t)(16 * cb + 4 * q) * ld] : 0.0;
+                }
+#pragma unroll
+            for (int s = 0; s < KS; ++s) {
+                if (s < ks) {
+                    double aop[4];
+#pragma unroll
+                    for (int cb = 0; cb < 4; ++cb) aop[cb] = Us[(4 * s + lk) * 64 + 16 * cb + li];
+#pragma unroll
+                    for (int cb = 0; cb < 4; ++cb)
+                        acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[cb], bop[s], acc[cb], 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const bool ok = rok && (ct + 16 * cb + 4 * q + lk < c_hi);
+                    if (ok) cb0[(int64_t)(16 * cb + 4 * q) * ld] = acc[cb][q];
+                }
+        }
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void gemm_kd(int kd, double* M, int ld, int r_lo, int r_hi, int c_lo, int c_hi, int k_lo,
+                                        double* Us) {
+    if (r_lo >= r_hi || c_lo >= c_hi) return;
+    gemm_mfma(M, ld, r_lo, r_hi, c_lo, c_hi, k_lo, kd, Us);
+}
+
+// Right-looking factorisation with super-panels of SP = 4 NB columns:
+//   inside a super-panel, NB-wide panels are factored left to right and the
+//   rest of the super-panel is updated after each (GETRF, TRSM, rank-NB);
+//   the block row to the right is then solved panel by panel (TRSM, rank-NB
+//   update of the lower panel rows), and the trailing matrix receives one
+//   rank-SP update.  Every entry still sees its updates in ascending pivot
+//   order.  Returns 0 or the 1-based position of the first bad pivot.
+constexpr int SP = 4 * NB;
+__device__ __forceinline__ int factor_slot(double* M, int n_pad, int ld, int ncols, double* lds) {
+    double* D = lds;                // NB x NB
+    double* Us = lds + NB * NB;     // SP x 64
+    __shared__ int s_info;
+    const int tid = threadIdx.x, wave = tid >> 6;
+    for (int c0 = 0; c0 < n_pad; c0 += SP) {
+        const int ce = min(c0 + SP, n_pad);
+        for (int p = c0; p < ce; p += NB) {
+            if (wave == 0) {
+                const int bad = panel_getrf(M, ld, p, D);
+                if ((tid & 63) == 0) s_info = bad;
+            }
+            __syncthreads();
+            if (s_info) return s_info;
+            panel_trsm(M, ld, p, D, p + NB, n_pad, p + NB, ce);
+            __syncthreads();
+            gemm_kd(NB, M, ld, p + NB, n_pad, p + NB, ce, p, Us);
+        }
+        if (ce < ncols) {
+            for (int p = c0; p < ce; p += NB) {
+                load_diag(M, ld, p, D);
+                __syncthreads();
+                panel_trsm(M, ld, p, D, 0, 0, ce, ncols);
+                __syncthreads();
+                gemm_kd(NB, M, ld, p + NB, ce, ce, ncols, p, Us);
+            }
+            gemm_kd(ce - c0, M, ld, ce, n_pad, ce, ncols, c0, Us);
+        }
+    }
+    return 0;
+}
+
+// ---------------------------------------------------------------- triangular solves
+// T holds nrhs columns of length n_pad with stride ld.  Variants (reference order):
+//   LOWER=1, TRANS=0: L y = b  (unit, a_ik = M[i + k ld]), ascending
+//   LOWER=0, TRANS=0: U x = y  (a_ij = M[i + j ld], diag u_jj), descending
+//   LOWER=1, TRANS=1: U^T z = w (a_ik = M[k + i ld], diag u_kk), ascending
+//   LOWER=0, TRANS=1: L^T v = z (unit, a_ij = M[j + i ld]), descending
+template <int LOWER, int TRANS>
+__device__ __forceinline__ void tri_solve(const double* M, int n_pad, int ld, double* T, int nrhs, double* lds) {
+    constexpr bool UNIT = (LOWER && !TRANS) || (!LOWER && TRANS);
+    double* Tri = lds;                 // SB x SB, Tri[i*SB + j] = a(b0+i, b0+j)
+    double* Xs = lds + SB * SB;        // SB x nrhs (nrhs <= 64)
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nblk = (n_pad + SB - 1) / SB;
+    for (int bb = 0; bb < nblk; ++bb) {
+        const int blk = LOWER ? bb : nblk - 1 - bb;
+        const int b0 = blk * SB, bs = min(SB, n_pad - b0);
+        for (int t = tid; t < SB * SB; t += WG) {
+            const int i = t % SB, j = t / SB;
+            double v = 0.0;
+            if (i < bs && j < bs) v = TRANS ? M[(int64_t)(b0 + i) * ld + b0 + j] : M[(int64_t)(b0 + j) * ld + b0 + i];
+            Tri[i * SB + j] = v;
+        }
+        __syncthreads();
+        for (int r = wave; r < nrhs; r += WG / 64) {
+            double* tc = T + (int64_t)r * ld + b0;
+            double t = lane < bs ? tc[lane] : 0.0;
+            if (LOWER) {
+                for (int k = 0; k < bs; ++k) {
+                    double xk = readlane_d(t, k);
+                    if (!UNIT) xk = xk / Tri[k * SB + k];
+                    if (lane == k) t = xk;
+                    if (lane > k) t = fmad(-Tri[lane * SB + k], xk, t);
+                    if (lane == 0) Xs[k * 64 + r] = xk;
+                }
+            } else {
+                for (int k = bs - 1; k >= 0; --k) {
+                    double xk = readlane_d(t, k);
+                    if (!UNIT) xk = xk / Tri[k * SB + k];
+                    if (lane == k) t = xk;
+                    if (lane < k) t = fmad(-Tri[lane * SB + k], xk, t);
+                    if (lane == 0) Xs[k * 64 + r] = xk;
+                }
+            }
+            if (lane < bs) tc[lane] = t;
+        }
+        __syncthreads();
+        // rows outside the block
+        const int lo = LOWER ? b0 + bs : 0, hi = LOWER ? n_pad : b0;
+        for (int t = tid; t < (hi - lo) * nrhs; t += WG) {
+            const int i = lo + t % (hi - lo), r = t / (hi - lo);
+            double v = T[(int64_t)r * ld + i];
+            if (LOWER) {
+                for (int k = 0; k < bs; ++k) {
+                    const double a = TRANS ? M[(int64_t)i * ld + b0 + k] : M[(int64_t)(b0 + k) * ld + i];
+                    v = fmad(-a, Xs[k * 64 + r], v);
+                }
+            } else {
+                for (int k = bs - 1; k >= 0; --k) {
+                    const double a = TRANS ? M[(int64_t)i * ld + b0 + k] : M[(int64_t)(b0 + k) * ld + i];
+                    v = fmad(-a, Xs[k * 64 + r], v);
+                }
+            }
+            T[(int64_t)r * ld + i] = v;
+        }
+        __syncthreads();
+    }
+}
+
+constexpr int kLdsFactor = (NB * NB + SP * 64) * 8;
+constexpr int kLdsSolve = (SB * SB + SB * 64) * 8;
+constexpr int kLdsDense = kLdsFactor > kLdsSolve ? kLdsFactor : kLdsSolve;
+
+}  // namespace psp

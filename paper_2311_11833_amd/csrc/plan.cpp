@@ -4,6 +4,7 @@
 #include "plan.h"
 
 #include <algorithm>
+#include <cstdint>
 #include <set>
 #include <utility>
 
@@ -224,6 +225,39 @@ void analyse(int32_t n, const int32_t* rp, const int32_t* ci, bool natural, Symb
         lev[i] = m;
     }
     levels_from(lev, n, s.lev_ptr[2], s.lev_idx[2]);
+
+    // dense trailing block (see plan.h)
+    int32_t t = 0;
+    while (t < n && s.l_ptr[n - t] - s.l_ptr[n - t - 1] == t) ++t;
+    s.tail_n = 0;
+    if (t >= kTailMin) {
+        std::vector<int32_t> flev(n);
+        for (size_t l = 0; l + 1 < s.lev_ptr[0].size(); ++l)
+            for (int32_t q = s.lev_ptr[0][l]; q < s.lev_ptr[0][l + 1]; ++q) flev[s.lev_idx[0][q]] = (int32_t)l;
+        const int32_t b0 = n - t;
+        int32_t max_sp = -1, min_tail = INT32_MAX;
+        for (int32_t j = 0; j < b0; ++j) max_sp = std::max(max_sp, flev[j]);
+        for (int32_t j = b0; j < n; ++j) min_tail = std::min(min_tail, flev[j]);
+        if (max_sp < min_tail) {
+            s.tail_n = t;
+            s.tail_b0 = b0;
+            s.fac_lev_sp = max_sp + 1;
+            // solve levels of the rows < b0 among themselves (the block's rows are solved densely
+            // in between: after every L-solve dependency of theirs, before every U-solve one)
+            std::vector<int32_t> lv(b0, 0);
+            for (int32_t j = 0; j < b0; ++j)
+                for (int32_t q = s.l_ptr[j]; q < s.l_ptr[j + 1]; ++q)
+                    if (s.l_idx[q] < b0) lv[s.l_idx[q]] = std::max(lv[s.l_idx[q]], lv[j] + 1);
+            levels_from(lv, b0, s.lev_sp_ptr[0], s.lev_sp_idx[0]);
+            for (int32_t i = b0 - 1; i >= 0; --i) {
+                int32_t m = 0;
+                for (int32_t q = s.l_ptr[i]; q < s.l_ptr[i + 1]; ++q)
+                    if (s.l_idx[q] < b0) m = std::max(m, lv[s.l_idx[q]] + 1);
+                lv[i] = m;
+            }
+            levels_from(lv, b0, s.lev_sp_ptr[1], s.lev_sp_idx[1]);
+        }
+    }
 
     const int64_t N = n;
     s.flops_dense = N * (N - 1) / 2 + (N - 1) * N * (2 * N - 1) / 3;

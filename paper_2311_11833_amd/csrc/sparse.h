@@ -34,6 +34,13 @@ struct SpIdx {
     int32_t use_pairs;
     const int32_t* pair_ptr;    // n + 2 nnzl + 1
     const int2* pairs;
+    // Dense trailing block (plan.h; tail_n = 0: none): columns >= tail_b0 are factored as one
+    // column-major tail_ld x tail_ld block (identity padding) at offset tail_off (doubles) of each
+    // system's factors, followed by tail_ld x 64 doubles of right-hand-side scratch.
+    int32_t tail_n, tail_b0, tail_ld, fac_lev_sp, nlev_sp[2];
+    int64_t tail_off;
+    const int32_t* lev_sp_ptr[2];   // L-solve / U-solve levels of the rows < tail_b0
+    const int32_t* lev_sp_idx[2];
 };
 
 // Dataflow step schedule of one perturbed system (factor, forward and
@@ -59,10 +66,11 @@ struct SparseDevice {
     SpIdx idx{};
     std::vector<int32_t> h_lev_ptr[3];   // host copies for per-level launches
     std::vector<int32_t> h_lpos_ptr;
+    std::vector<int32_t> h_lev_sp_ptr[2];
     StepIdx st{};                        // step schedule (nsteps = 0 when it does not fit in LDS)
 };
 
-enum { kVarLds = 0, kVarGlobal = 1, kVarBatched = 2, kVarGrouped = 3, kVarSteps = 4 };
+enum { kVarLds = 0, kVarGlobal = 1, kVarBatched = 2, kVarGrouped = 3, kVarSteps = 4, kVarTail = 5 };
 int sparse_variant(const Symbolic& s, int64_t ntasks, int32_t nrhs, int forced);
 
 // Appends the sparse path's arrays (and the step schedule, when it fits) to the

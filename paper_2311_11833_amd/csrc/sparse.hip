@@ -35,6 +35,7 @@
 
 #include "dense.h"
 #include "sparse.h"
+#include "dense_ops.h"
 
 namespace psp {
 
@@ -49,13 +50,50 @@ constexpr int kThreads = 256;
 // products merge the two rows on the fly.
 constexpr int64_t kMaxPairs = 32LL << 20;
 
-__device__ __forceinline__ double merge_dot(const SpIdx& ix, int a, int b, const double* lv, const double* uv,
-                                            double acc) {
-    // acc - sum_{k in R_a ^ R_b} lv[pos(a,k)] * uv[pos(b,k)], ascending k
+// acc - sum_{k in R_a ^ R_b, k < bound} lv[pos(a,k)] * uv[pos(b,k)], ascending k.  Rows of
+// similar length are merged; when one row is much longer (the dense slack row has an entry in
+// every column) the shorter one is walked and each of its k is found in the longer one by
+// galloping search, so the cost follows the shorter row.  Either way the matches are taken in
+// ascending k.
+__device__ __forceinline__ double merge_dot_below(const SpIdx& ix, int a, int b, int bound, const double* lv,
+                                                  const double* uv, double acc) {
     int p = ix.r_ptr[a], pe = ix.r_ptr[a + 1];
     int q = ix.r_ptr[b], qe = ix.r_ptr[b + 1];
+    const int la = pe - p, lb = qe - q;
+    if (la > 8 * lb || lb > 8 * la) {
+        const bool a_short = la <= lb;
+        int s = a_short ? p : q;
+        const int se = a_short ? pe : qe;
+        int l = a_short ? q : p;
+        const int le = a_short ? qe : pe;
+        for (; s < se && l < le; ++s) {
+            const int k = ix.r_idx[s];
+            if (k >= bound) break;
+            // first index in [l, le) with r_idx >= k
+            int lo = l, hi = l, step = 1;
+            while (hi < le && ix.r_idx[hi] < k) {
+                lo = hi + 1;
+                hi += step;
+                step <<= 1;
+            }
+            if (hi > le) hi = le;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (ix.r_idx[mid] < k) lo = mid + 1;
+                else hi = mid;
+            }
+            l = lo;
+            if (l < le && ix.r_idx[l] == k) {
+                const int pa = a_short ? s : l, pb = a_short ? l : s;
+                acc = fmad(-lv[ix.r_pos[pa]], uv[ix.r_pos[pb]], acc);
+                ++l;
+            }
+        }
+        return acc;
+    }
     while (p < pe && q < qe) {
         const int ka = ix.r_idx[p], kb = ix.r_idx[q];
+        if (ka >= bound || kb >= bound) break;
         if (ka == kb) {
             acc = fmad(-lv[ix.r_pos[p]], uv[ix.r_pos[q]], acc);
             ++p;
@@ -67,6 +105,11 @@ __device__ __forceinline__ double merge_dot(const SpIdx& ix, int a, int b, const
         }
     }
     return acc;
+}
+
+__device__ __forceinline__ double merge_dot(const SpIdx& ix, int a, int b, const double* lv, const double* uv,
+                                            double acc) {
+    return merge_dot_below(ix, a, b, INT_MAX, lv, uv, acc);
 }
 
 // acc - sum lv[pl] * uv[pu] over the precomputed pairs of item id, in order
@@ -325,16 +368,15 @@ __global__ void sp_rhs_in_kernel(SpArgs a) {
 }
 
 template <int UPPER_PASS>
-__global__ void sp_solve_level_kernel(SpArgs a, int c0, int cnt) {
+__global__ void sp_solve_level_kernel(SpArgs a, const int32_t* lev_idx, int c0, int cnt) {
     const SpIdx& ix = a.ix;
     const int n = ix.n, nl = ix.nnzl, nrhs = a.nrhs;
     const int64_t per = (int64_t)cnt * nrhs, total = per * a.ntasks;
     // pass 0: L (or U^T when transposed), ascending schedule; pass 1: U (or L^T), descending schedule
-    const int sched = UPPER_PASS ? 2 : 1;
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
         const int task = (int)(g / per), t = (int)(g % per);
         if (a.info[task]) continue;
-        const int i = ix.lev_idx[sched][c0 + t / nrhs], r = t % nrhs;
+        const int i = lev_idx[c0 + t / nrhs], r = t % nrhs;
         const double* ud = a.fac + (int64_t)task * a.fstride;
         double* y = a.y + (int64_t)task * n * nrhs;
         double v;
@@ -356,6 +398,212 @@ __global__ void sp_rhs_out_kernel(SpArgs a) {
         a.Xk[(int64_t)task * per + (int64_t)ix.perm[q] * nrhs + r] = a.info[task] ? __builtin_nan("") : a.y[g];
     }
 }
+
+// ---------------------------------------------------------------- dense trailing block
+// The last tail_n columns of the factors are full, and their factor levels lie above every other
+// column's (plan.h), so the sparse part (columns < b0) is factored first on its own levels.  Each
+// entry (i, j) of the trailing block then starts from a_ij (+ eps d on the diagonal), takes the
+// updates of the sparse part, l_ik u_kj for k < b0 in ascending k (one thread per entry, the two
+// rows merged), and the block is factored densely in panels of NB columns on the MFMA unit, which
+// continues every entry's chain over k >= b0 in ascending order: the reference sequence.
+
+__global__ void tail_assemble_kernel(SpArgs a) {
+    const SpIdx& ix = a.ix;
+    const int n = ix.n, nl = ix.nnzl, b0 = ix.tail_b0, nt = ix.tail_n, ld = ix.tail_ld;
+    const int64_t per = (int64_t)ld * ld, total = per * a.ntasks;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+        const int task = (int)(g / per);
+        const int64_t t = g % per;
+        const int i = (int)(t % ld), j = (int)(t / ld);
+        double* ud = a.fac + (int64_t)task * a.fstride;
+        double v;
+        if (i >= nt || j >= nt) {
+            v = i == j ? 1.0 : 0.0;
+        } else {
+            const int gi = b0 + i, gj = b0 + j;
+            const double* lv = ud + n;
+            const double* uv = ud + n + nl;
+            // the block's columns are full: (gi, gj) sits at l_ptr[min] + |gi - gj| - 1
+            v = gi == gj ? ud[gj] : (gi > gj ? lv[ix.l_ptr[gj] + (gi - gj - 1)] : uv[ix.l_ptr[gi] + (gj - gi - 1)]);
+            v = merge_dot_below(ix, gi, gj, b0, lv, uv, v);
+        }
+        ud[ix.tail_off + t] = v;
+    }
+}
+
+// Panel p0 of every system's block: GETRF of the NB x NB diagonal block (wave 0), then the
+// multipliers below it and the rows of U to its right (one workgroup per system).
+__global__ __launch_bounds__(WG) void tail_panel_kernel(SpArgs a, int p0) {
+    __shared__ double D[NB * NB];
+    __shared__ int s_bad;
+    const int ld = a.ix.tail_ld;
+    for (int task = blockIdx.x; task < a.ntasks; task += gridDim.x) {
+        double* T = a.fac + (int64_t)task * a.fstride + a.ix.tail_off;
+        if (threadIdx.x < 64) {
+            const int bad = panel_getrf(T, ld, p0, D);
+            if (threadIdx.x == 0) s_bad = bad;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0 && s_bad) atomicMin(&a.info[task], a.ix.tail_b0 + s_bad);
+        panel_trsm(T, ld, p0, D, p0 + NB, ld, p0 + NB, ld);
+        __syncthreads();
+    }
+}
+
+// Rank-NB update of the trailing matrix after panel p0: one workgroup per 128 x 64 tile.
+__global__ __launch_bounds__(WG) void tail_update_kernel(SpArgs a, int p0, int tiles_r, int tiles_c) {
+    __shared__ double Us[NB * 64];
+    const int ld = a.ix.tail_ld;
+    const int64_t per = (int64_t)tiles_r * tiles_c, total = per * a.ntasks;
+    for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
+        const int task = (int)(b / per), tt = (int)(b % per);
+        double* T = a.fac + (int64_t)task * a.fstride + a.ix.tail_off;
+        const int r0 = p0 + NB + 128 * (tt / tiles_c), c0 = p0 + NB + 64 * (tt % tiles_c);
+        gemm_mfma<NB>(T, ld, r0, min(r0 + 128, ld), c0, min(c0 + 64, ld), p0, NB, Us);
+    }
+}
+
+// Rows of the block, updates from the sparse part (k < b0, ascending): L (or U^T) without the
+// division, which the dense solve applies after the block's own updates.
+template <int TRANS>
+__global__ void tail_fwd_ext_kernel(SpArgs a) {
+    const SpIdx& ix = a.ix;
+    const int n = ix.n, nl = ix.nnzl, nrhs = a.nrhs, b0 = ix.tail_b0;
+    const int64_t per = (int64_t)ix.tail_n * nrhs, total = per * a.ntasks;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+        const int task = (int)(g / per), t = (int)(g % per);
+        if (a.info[task]) continue;
+        const int i = b0 + t / nrhs, r = t % nrhs;
+        const double* ud = a.fac + (int64_t)task * a.fstride;
+        const double* m = TRANS ? ud + n + nl : ud + n;
+        double* y = a.y + (int64_t)task * n * nrhs;
+        double acc = y[(int64_t)i * nrhs + r];
+        for (int p = ix.r_ptr[i]; p < ix.r_ptr[i + 1]; ++p) {
+            const int k = ix.r_idx[p];
+            if (k >= b0) break;
+            acc = fmad(-m[ix.r_pos[p]], y[(int64_t)k * nrhs + r], acc);
+        }
+        y[(int64_t)i * nrhs + r] = acc;
+    }
+}
+
+// The block's own triangular solves (forward then backward, or the transposed pair) on a
+// column-major copy R of its right-hand sides (nrhs columns of stride tail_ld), by blocks of SB
+// rows: the diagonal block of every system in one workgroup (one wave per right-hand side, the
+// pivot values passed by readlane), then the rows outside it on the whole device.  The updates of
+// an entry arrive block by block in the order of the reference substitution (ascending for the
+// forward pass, descending for the backward one).
+__global__ void tail_rhs_in_kernel(SpArgs a) {
+    const SpIdx& ix = a.ix;
+    const int n = ix.n, nrhs = a.nrhs, ld = ix.tail_ld;
+    const int64_t per = (int64_t)ld * nrhs, total = per * a.ntasks;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+        const int task = (int)(g / per), t = (int)(g % per);
+        const int q = t % ld, r = t / ld;
+        double* R = a.fac + (int64_t)task * a.fstride + ix.tail_off + (int64_t)ld * ld;
+        R[(int64_t)r * ld + q] = q < ix.tail_n ? a.y[((int64_t)task * n + ix.tail_b0 + q) * nrhs + r] : 0.0;
+    }
+}
+
+__global__ void tail_rhs_out_kernel(SpArgs a) {
+    const SpIdx& ix = a.ix;
+    const int n = ix.n, nrhs = a.nrhs, ld = ix.tail_ld, nt = ix.tail_n;
+    const int64_t per = (int64_t)nt * nrhs, total = per * a.ntasks;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+        const int task = (int)(g / per), t = (int)(g % per);
+        const int q = t % nt, r = t / nt;
+        const double* R = a.fac + (int64_t)task * a.fstride + ix.tail_off + (int64_t)ld * ld;
+        a.y[((int64_t)task * n + ix.tail_b0 + q) * nrhs + r] = R[(int64_t)r * ld + q];
+    }
+}
+
+template <int LOWER, int TRANS>
+__global__ __launch_bounds__(WG) void tail_tri_diag_kernel(SpArgs a, int c0) {
+    constexpr bool UNIT = (LOWER && !TRANS) || (!LOWER && TRANS);
+    __shared__ double Tri[SB * SB];
+    const int ld = a.ix.tail_ld, nrhs = a.nrhs, bs = min(SB, ld - c0);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int task = blockIdx.x; task < a.ntasks; task += gridDim.x) {
+        if (a.info[task]) continue;
+        const double* M = a.fac + (int64_t)task * a.fstride + a.ix.tail_off;
+        double* R = const_cast<double*>(M) + (int64_t)ld * ld;
+        for (int t = tid; t < SB * SB; t += WG) {
+            const int i = t % SB, j = t / SB;
+            double v = 0.0;
+            if (i < bs && j < bs) v = TRANS ? M[(int64_t)(c0 + i) * ld + c0 + j] : M[(int64_t)(c0 + j) * ld + c0 + i];
+            Tri[i * SB + j] = v;
+        }
+        __syncthreads();
+        for (int r = wave; r < nrhs; r += WG / 64) {
+            double* tc = R + (int64_t)r * ld + c0;
+            double t = lane < bs ? tc[lane] : 0.0;
+            if (LOWER) {
+                for (int k = 0; k < bs; ++k) {
+                    double xk = readlane_d(t, k);
+                    if (!UNIT) xk = xk / Tri[k * SB + k];
+                    if (lane == k) t = xk;
+                    if (lane > k) t = fmad(-Tri[lane * SB + k], xk, t);
+                }
+            } else {
+                for (int k = bs - 1; k >= 0; --k) {
+                    double xk = readlane_d(t, k);
+                    if (!UNIT) xk = xk / Tri[k * SB + k];
+                    if (lane == k) t = xk;
+                    if (lane < k) t = fmad(-Tri[lane * SB + k], xk, t);
+                }
+            }
+            if (lane < bs) tc[lane] = t;
+        }
+        __syncthreads();
+    }
+}
+
+template <int LOWER, int TRANS>
+__global__ void tail_tri_rest_kernel(SpArgs a, int c0) {
+    const int ld = a.ix.tail_ld, nrhs = a.nrhs, bs = min(SB, ld - c0);
+    const int lo = LOWER ? c0 + bs : 0, hi = LOWER ? ld : c0;
+    if (hi <= lo) return;
+    const int64_t per = (int64_t)(hi - lo) * nrhs, total = per * a.ntasks;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+        const int task = (int)(g / per), t = (int)(g % per);
+        if (a.info[task]) continue;
+        const int i = lo + t % (hi - lo), r = t / (hi - lo);
+        const double* M = a.fac + (int64_t)task * a.fstride + a.ix.tail_off;
+        double* R = const_cast<double*>(M) + (int64_t)ld * ld;
+        const double* xb = R + (int64_t)r * ld + c0;
+        double v = R[(int64_t)r * ld + i];
+        if (LOWER) {
+            for (int k = 0; k < bs; ++k) {
+                const double m = TRANS ? M[(int64_t)i * ld + c0 + k] : M[(int64_t)(c0 + k) * ld + i];
+                v = fmad(-m, xb[k], v);
+            }
+        } else {
+            for (int k = bs - 1; k >= 0; --k) {
+                const double m = TRANS ? M[(int64_t)i * ld + c0 + k] : M[(int64_t)(c0 + k) * ld + i];
+                v = fmad(-m, xb[k], v);
+            }
+        }
+        R[(int64_t)r * ld + i] = v;
+    }
+}
+
+int grid_for(int64_t items, int threads);
+
+template <int LOWER, int TRANS>
+hipError_t tail_tri(SpArgs a, hipStream_t st) {
+    const int ld = a.ix.tail_ld, nblk = (ld + SB - 1) / SB;
+    const int tgrid = std::min(a.ntasks, 65535);
+    for (int bb = 0; bb < nblk; ++bb) {
+        const int blk = LOWER ? bb : nblk - 1 - bb, c0 = blk * SB, bs = std::min(SB, ld - c0);
+        hipLaunchKernelGGL((tail_tri_diag_kernel<LOWER, TRANS>), dim3(tgrid), dim3(WG), 0, st, a, c0);
+        const int rows = LOWER ? ld - c0 - bs : c0;
+        if (rows > 0)
+            hipLaunchKernelGGL((tail_tri_rest_kernel<LOWER, TRANS>),
+                               dim3(grid_for((int64_t)rows * a.nrhs * a.ntasks, kThreads)), dim3(kThreads), 0, st, a, c0);
+    }
+    return hipGetLastError();
+}
+
 
 // ---------------------------------------------------------------- batched, systems interleaved
 // Many systems share one pattern, so the index data of an item is the same for
@@ -623,7 +871,15 @@ int64_t lds_bytes(const Symbolic& s, int nrhs) {
 
 int64_t align256(int64_t v) { return (v + 255) / 256 * 256; }
 
-int64_t fstride_of(const Symbolic& s) { return (s.n + 2 * (int64_t)s.l_ptr[s.n] + 31) / 32 * 32; }
+int64_t tail_ld_of(const Symbolic& s) { return s.tail_n ? (s.tail_n + NB - 1) / NB * NB : 0; }
+
+// doubles of one system's factors: [u_jj | L | U] rounded to 32, then (dense trailing block) the
+// block and its right-hand-side scratch (tail_ld x 64)
+int64_t fbase_of(const Symbolic& s) { return (s.n + 2 * (int64_t)s.l_ptr[s.n] + 31) / 32 * 32; }
+int64_t fstride_of(const Symbolic& s) {
+    const int64_t ld = tail_ld_of(s);
+    return fbase_of(s) + ld * ld + ld * 64;
+}
 
 int64_t tp_of(int64_t ntasks) { return (ntasks + 63) / 64 * 64; }
 
@@ -639,9 +895,10 @@ int variant_of(const Symbolic& s, int64_t ntasks, int32_t nrhs, int forced) {
     if (forced == kVarGrouped) return pairs_ok(s) ? kVarGrouped : -1;
     if (forced == kVarGlobal) return kVarGlobal;
     if (forced == kVarSteps) return steps_fit(s, nrhs) ? kVarSteps : -1;
-    if (ntasks >= 256 && pairs_ok(s)) return kVarBatched;
+    if (forced == kVarTail) return s.tail_n > 0 ? kVarTail : -1;
+    if (ntasks >= 256 && pairs_ok(s) && s.tail_n == 0) return kVarBatched;
     if (sparse_fits_lds(s, nrhs)) return kVarLds;
-    return kVarGlobal;
+    return s.tail_n > 0 ? kVarTail : kVarGlobal;
 }
 
 // workspace, keep = 0:
@@ -745,6 +1002,64 @@ hipError_t factor_global(const SparseDevice& d, SpArgs a, const EpsSet& es, hipS
     return hipGetLastError();
 }
 
+hipError_t factor_tail(const SparseDevice& d, SpArgs a, const EpsSet& es, hipStream_t st) {
+    hipLaunchKernelGGL(sp_gather_kernel, dim3(grid_for((int64_t)(a.ix.n + a.ix.nnzl) * a.ntasks, kThreads)),
+                       dim3(kThreads), 0, st, a, es);
+    for (int l = 0; l < a.ix.fac_lev_sp; ++l) {
+        const int c0 = d.h_lev_ptr[0][l], cnt = d.h_lev_ptr[0][l + 1] - c0;
+        hipLaunchKernelGGL(sp_diag_kernel, dim3(grid_for((int64_t)cnt * a.ntasks, kThreads)), dim3(kThreads), 0, st,
+                           a, c0, cnt);
+        const int p0 = d.h_lpos_ptr[l], np = d.h_lpos_ptr[l + 1] - p0;
+        if (np > 0)
+            hipLaunchKernelGGL(sp_offdiag_kernel, dim3(grid_for((int64_t)2 * np * a.ntasks, kThreads)), dim3(kThreads),
+                               0, st, a, p0, np);
+    }
+    const int ld = a.ix.tail_ld;
+    hipLaunchKernelGGL(tail_assemble_kernel, dim3(grid_for((int64_t)ld * ld * a.ntasks, kThreads)), dim3(kThreads), 0,
+                       st, a);
+    for (int p0 = 0; p0 < ld; p0 += NB) {
+        hipLaunchKernelGGL(tail_panel_kernel, dim3(std::min(a.ntasks, 65535)), dim3(WG), 0, st, a, p0);
+        const int rem = ld - p0 - NB;
+        if (rem > 0) {
+            const int tr = (rem + 127) / 128, tc = (rem + 63) / 64;
+            const int64_t blocks = (int64_t)tr * tc * a.ntasks;
+            hipLaunchKernelGGL(tail_update_kernel, dim3((int)std::min<int64_t>(blocks, 65535)), dim3(WG), 0, st, a, p0,
+                               tr, tc);
+        }
+    }
+    hipLaunchKernelGGL(sp_info_kernel, dim3((a.ntasks + 255) / 256), dim3(256), 0, st, a.info, a.ntasks);
+    return hipGetLastError();
+}
+
+hipError_t solve_tail(const SparseDevice& d, SpArgs a, hipStream_t st) {
+    const int64_t items = (int64_t)a.ix.n * a.nrhs * a.ntasks;
+    hipLaunchKernelGGL(sp_rhs_in_kernel, dim3(grid_for(items, kThreads)), dim3(kThreads), 0, st, a);
+    for (int l = 0; l < a.ix.nlev_sp[0]; ++l) {
+        const int c0 = d.h_lev_sp_ptr[0][l], cnt = d.h_lev_sp_ptr[0][l + 1] - c0;
+        hipLaunchKernelGGL(sp_solve_level_kernel<0>, dim3(grid_for((int64_t)cnt * a.nrhs * a.ntasks, kThreads)),
+                           dim3(kThreads), 0, st, a, a.ix.lev_sp_idx[0], c0, cnt);
+    }
+    const int64_t trows = (int64_t)a.ix.tail_n * a.nrhs * a.ntasks;
+    const int64_t tpad = (int64_t)a.ix.tail_ld * a.nrhs * a.ntasks;
+    if (a.trans)
+        hipLaunchKernelGGL(tail_fwd_ext_kernel<1>, dim3(grid_for(trows, kThreads)), dim3(kThreads), 0, st, a);
+    else
+        hipLaunchKernelGGL(tail_fwd_ext_kernel<0>, dim3(grid_for(trows, kThreads)), dim3(kThreads), 0, st, a);
+    hipLaunchKernelGGL(tail_rhs_in_kernel, dim3(grid_for(tpad, kThreads)), dim3(kThreads), 0, st, a);
+    hipError_t e = a.trans ? tail_tri<1, 1>(a, st) : tail_tri<1, 0>(a, st);
+    if (e != hipSuccess) return e;
+    e = a.trans ? tail_tri<0, 1>(a, st) : tail_tri<0, 0>(a, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(tail_rhs_out_kernel, dim3(grid_for(trows, kThreads)), dim3(kThreads), 0, st, a);
+    for (int l = 0; l < a.ix.nlev_sp[1]; ++l) {
+        const int c0 = d.h_lev_sp_ptr[1][l], cnt = d.h_lev_sp_ptr[1][l + 1] - c0;
+        hipLaunchKernelGGL(sp_solve_level_kernel<1>, dim3(grid_for((int64_t)cnt * a.nrhs * a.ntasks, kThreads)),
+                           dim3(kThreads), 0, st, a, a.ix.lev_sp_idx[1], c0, cnt);
+    }
+    hipLaunchKernelGGL(sp_rhs_out_kernel, dim3(grid_for(items, kThreads)), dim3(kThreads), 0, st, a);
+    return hipGetLastError();
+}
+
 hipError_t solve_global(const SparseDevice& d, SpArgs a, hipStream_t st) {
     const int64_t items = (int64_t)a.ix.n * a.nrhs * a.ntasks;
     hipLaunchKernelGGL(sp_rhs_in_kernel, dim3(grid_for(items, kThreads)), dim3(kThreads), 0, st, a);
@@ -752,12 +1067,12 @@ hipError_t solve_global(const SparseDevice& d, SpArgs a, hipStream_t st) {
     for (int l = 0; l < a.ix.nlev[1]; ++l) {
         const int c0 = d.h_lev_ptr[1][l], cnt = d.h_lev_ptr[1][l + 1] - c0;
         hipLaunchKernelGGL(sp_solve_level_kernel<0>, dim3(grid_for((int64_t)cnt * a.nrhs * a.ntasks, kThreads)),
-                           dim3(kThreads), 0, st, a, c0, cnt);
+                           dim3(kThreads), 0, st, a, a.ix.lev_idx[1], c0, cnt);
     }
     for (int l = 0; l < a.ix.nlev[2]; ++l) {
         const int c0 = d.h_lev_ptr[2][l], cnt = d.h_lev_ptr[2][l + 1] - c0;
         hipLaunchKernelGGL(sp_solve_level_kernel<1>, dim3(grid_for((int64_t)cnt * a.nrhs * a.ntasks, kThreads)),
-                           dim3(kThreads), 0, st, a, c0, cnt);
+                           dim3(kThreads), 0, st, a, a.ix.lev_idx[2], c0, cnt);
     }
     hipLaunchKernelGGL(sp_rhs_out_kernel, dim3(grid_for(items, kThreads)), dim3(kThreads), 0, st, a);
     return hipGetLastError();
@@ -853,14 +1168,26 @@ void sparse_image(const Symbolic& s, PlanImage& img, SparseDevice& d) {
     img.bind(&ix.pair_ptr, img.put(pair_ptr));
     img.bind(&ix.pairs, img.put(pairs));
     d.h_lpos_ptr = lpos_ptr;
+    ix.tail_n = s.tail_n;
+    ix.tail_b0 = s.tail_b0;
+    ix.tail_ld = (int32_t)tail_ld_of(s);
+    ix.fac_lev_sp = s.fac_lev_sp;
+    ix.tail_off = fbase_of(s);
+    for (int w = 0; w < 2; ++w) {
+        ix.nlev_sp[w] = s.tail_n ? (int32_t)s.lev_sp_ptr[w].size() - 1 : 0;
+        img.bind(&ix.lev_sp_ptr[w], img.put(s.lev_sp_ptr[w]));
+        img.bind(&ix.lev_sp_idx[w], img.put(s.lev_sp_idx[w]));
+        d.h_lev_sp_ptr[w] = s.lev_sp_ptr[w];
+    }
     steps_image(s, r_pos, img, d);
     d.imaged = true;
 }
 
 hipError_t sparse_kernel_attrs() {
     static hipError_t e = [] {
-        return hipFuncSetAttribute((const void*)sparse_lds_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   kLdsLimit);
+        hipError_t r = hipFuncSetAttribute((const void*)sparse_lds_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           kLdsLimit);
+        return r;
     }();
     return e;
 }
@@ -886,7 +1213,7 @@ hipError_t sparse_solve_batched(const Symbolic& s, const SparseDevice& d, int32_
     a.Xk = (double*)(w + L.off_xk);
     int var = variant_of(s, ntasks, nrhs, forced);
     if (var < 0) return hipErrorInvalidValue;
-    if (forced < 0 && (var == kVarBatched || var == kVarLds) && nrhs == 1 && steps_ready(d)) {
+    if (forced < 0 && var != kVarGrouped && nrhs == 1 && steps_ready(d)) {
         // the step schedule beats the per-level launches and the level-scheduled LDS
         // kernel whenever it exists; its Xk (when not fused) fits in the interleaved
         // layout or the LDS variant's Xk reserved above
@@ -917,9 +1244,10 @@ hipError_t sparse_solve_batched(const Symbolic& s, const SparseDevice& d, int32_
     } else {
         a.fac = (double*)(w + L.off_fac);
         a.y = (double*)(w + L.off_y);
-        hipError_t e = factor_global(d, a, es, st);
+        const bool tail = var == kVarTail;
+        hipError_t e = tail ? factor_tail(d, a, es, st) : factor_global(d, a, es, st);
         if (e != hipSuccess) return e;
-        e = solve_global(d, a, st);
+        e = tail ? solve_tail(d, a, st) : solve_global(d, a, st);
         if (e != hipSuccess) return e;
     }
     return launch_combine((int64_t)s.n * nrhs, batch, es, a.Xk, X, st);
@@ -932,6 +1260,7 @@ hipError_t sparse_factor(const Symbolic& s, const SparseDevice& d, int32_t batch
     SpArgs a = make_args(d, s, ntasks, es.K, 0);
     a.values = values; a.dvec = dvec; a.info = info;
     a.fac = (double*)((char*)ws + L.off_fac);
+    if (s.tail_n > 0) return factor_tail(d, a, es, st);
     if (sparse_fits_lds(s, 0)) {
         const int lds = (int)lds_bytes(s, 0);
         hipError_t e = sparse_kernel_attrs();
@@ -955,7 +1284,7 @@ hipError_t sparse_solve(const Symbolic& s, const SparseDevice& d, int32_t batch,
     a.B = B; a.Xk = Xk; a.info = const_cast<int32_t*>(info); a.trans = transpose ? 1 : 0;
     a.fac = (double*)((char*)ws + L.off_fac);
     a.y = (double*)((char*)ws + L.off_y);
-    return solve_global(d, a, st);
+    return s.tail_n > 0 ? solve_tail(d, a, st) : solve_global(d, a, st);
 }
 
 }  // namespace psp

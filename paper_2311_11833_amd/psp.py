@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libpsp.so")
 
 PSP_OK, PSP_E_INVALID, PSP_E_EPS, PSP_E_NOMEM, PSP_E_HIP, PSP_E_STATE, PSP_E_UNSUPPORTED = range(7)
 PATHS = {"auto": 0, "dense": 1, "sparse": 2, "sparse_batched": 3, "sparse_lds": 4, "sparse_levels": 5, "sparse_grouped": 6,
-         "sparse_steps": 7}
+         "sparse_steps": 7, "sparse_tail": 8}
 PATH_NAMES = {v: k for k, v in PATHS.items()}
 ORDERS = {"md": 0, "natural": 1}
 EXPORTED = ["psp_last_error", "psp_version", "psp_plan_create", "psp_plan_info", "psp_plan_export",
@@ -43,7 +43,8 @@ class PlanInfo(C.Structure):
     _fields_ = [("n", C.c_int32), ("nnz", C.c_int32), ("nnz_l", C.c_int64), ("ndense", C.c_int32),
                 ("nlev", C.c_int32 * 3), ("flops_dense_factor", C.c_int64), ("flops_sparse_factor", C.c_int64),
                 ("steps", C.c_int32), ("steps_packed", C.c_int32), ("steps_lds_bytes", C.c_int64),
-                ("steps_per_cu", C.c_int32), ("device_bytes", C.c_int64)]
+                ("steps_per_cu", C.c_int32), ("device_bytes", C.c_int64), ("tail_n", C.c_int32),
+                ("tail_fac_levels", C.c_int32)]
 
 
 class GroupShape(C.Structure):

@@ -98,8 +98,10 @@ def test_sparse_breakdown_info(psp, O, W, dev, N):
 
 def test_large_sparse_sampled(psp, O, W, dev):
     """20,001 unknowns (10,000-bus network), K = 4, 32 right-hand sides, forward and
-    transposed solves in the launch configuration of the benchmark; one perturbed
-    system and four RHS columns recomputed by the oracle."""
+    transposed solves in the launch configuration of the benchmark (the dense trailing
+    block of 1,521 columns on the MFMA unit); one perturbed system and four RHS columns
+    recomputed by the oracle, and the gradient on the whole pattern equal to the oracle's
+    on the same perturbed solutions and adjoints."""
     from paper_2311_11833_amd.workloads import make_network, make_state, jacobian, seed_state
     net = make_network(10000)
     vm, va, p = make_state(10000, seed_state(10000, 0))
@@ -121,6 +123,11 @@ def test_large_sparse_sampled(psp, O, W, dev):
     _cmp(Xk[0, 0, :, :4].cpu().numpy(), xo)
     _cmp(Lk[0, 0, :, :4].cpu().numpy(), lo)
     assert np.all(np.isfinite(Xk.cpu().numpy()))
+    # the gradient on A's pattern from these K perturbed solutions and adjoints, all 154,001 entries
+    gA = F.grad_values(Lk, Xk)
+    torch.cuda.synchronize()
+    go = O.grad_values(n, J.indptr, J.indices, O.weights(eps), Xk[0].cpu().numpy(), Lk[0].cpu().numpy())
+    _cmp(gA[0].cpu().numpy(), go)
 
 
 @pytest.mark.parametrize("variant", ["sparse_batched", "sparse_grouped", "sparse_lds", "sparse_levels", "sparse_steps"])
@@ -294,3 +301,46 @@ def test_gaussian_diagonal_split_steps_and_adjoint(psp, O, W, dev):
         _cmp(Lk[s].cpu().numpy(), lko[0])
         _cmp(X[s].cpu().numpy(), xo[0])
         _cmp(gA[s].cpu().numpy(), O.grad_values(n, ip, ix, c, xko[0], lko[0]))
+
+
+@pytest.mark.parametrize("N,count,nrhs", [(500, 3, 1), (1354, 4, 3), (3000, 2, 1)])
+def test_dense_tail_path_matches_oracle(psp, O, W, dev, N, count, nrhs):
+    """The dense trailing block (top separator and slack column, 87 / 231 / 547 columns at
+    n = 1001 / 2709 / 6001): sparse levels below it, the block's external updates, its
+    panel factorisation on the MFMA unit and its dense solves, bitwise equal to the oracle."""
+    ip, ix, vals, bs = W.scenario_batch(N, count)
+    n = len(ip) - 1
+    if nrhs > 1:
+        bs = np.random.default_rng(N).standard_normal((count, n, nrhs))
+    eps = W.config_eps("n601")
+    plan = psp.Plan(ip, ix)
+    print(f"[gpu sparse] dense tail N={N} n={n} count={count} nrhs={nrhs}", flush=True)
+    x, info = psp.solve_batched(plan, torch.from_numpy(vals).to(dev), eps, torch.from_numpy(bs).to(dev),
+                                path="sparse_tail")
+    torch.cuda.synchronize()
+    sym = O.symbolic(n, ip, ix)
+    xo, io, _, _ = O.sparse_batch(n, ip, ix, vals, sym, eps, bs)
+    assert np.array_equal(info.cpu().numpy(), io)
+    _cmp(x.cpu().numpy(), xo)
+
+
+def test_dense_tail_breakdown_inside_block(psp, O, W, dev):
+    """A NaN entry in the slack column (inside the dense block) breaks that Jacobian's K systems at
+    the same pivot as the oracle's; the other Jacobian is untouched."""
+    ip, ix, vals, bs = W.scenario_batch(1354, 2)
+    n = len(ip) - 1
+    vals = vals.copy()
+    lam_entries = np.nonzero(ix == n - 1)[0]          # column of lambda, the last unknown
+    vals[0, lam_entries[len(lam_entries) // 2]] = np.nan
+    eps = W.config_eps("n601")
+    plan = psp.Plan(ip, ix)
+    print("[gpu sparse] dense tail breakdown", flush=True)
+    x, info = psp.solve_batched(plan, torch.from_numpy(vals).to(dev), eps, torch.from_numpy(bs).to(dev),
+                                path="sparse_tail")
+    torch.cuda.synchronize()
+    sym = O.symbolic(n, ip, ix)
+    xo, io, _, _ = O.sparse_batch(n, ip, ix, vals, sym, eps, bs)
+    ig = info.cpu().numpy()
+    assert np.array_equal(ig, io) and np.all(ig[0] > 0) and np.all(ig[1] == 0)
+    assert np.all(np.isnan(x.cpu().numpy()[0]))
+    _cmp(x.cpu().numpy()[1], xo[1])
