@@ -230,7 +230,7 @@ void analyse(int32_t n, const int32_t* rp, const int32_t* ci, bool natural, Symb
     int32_t t = 0;
     while (t < n && s.l_ptr[n - t] - s.l_ptr[n - t - 1] == t) ++t;
     s.tail_n = 0;
-    if (t >= kTailMin) {
+    if (t >= kTailMin && n - t <= kTailAsmMaxB0) {
         std::vector<int32_t> flev(n);
         for (size_t l = 0; l + 1 < s.lev_ptr[0].size(); ++l)
             for (int32_t q = s.lev_ptr[0][l]; q < s.lev_ptr[0][l + 1]; ++q) flev[s.lev_idx[0][q]] = (int32_t)l;

@@ -29,6 +29,7 @@ struct Symbolic {
 };
 
 constexpr int32_t kTailMin = 64;
+constexpr int32_t kTailAsmMaxB0 = 60000;   // columns before the block at most (an LDS map over them)
 
 // Returns an empty string on success, else the reason the pattern was rejected.
 std::string validate_csr(int32_t n, const int32_t* row_ptr, const int32_t* col_idx);

@@ -32,6 +32,7 @@ struct SpIdx {
     // U position) pairs of its dot product in ascending k, items
     // [pair_ptr[id], pair_ptr[id+1]) of pairs (two int32 each).
     int32_t use_pairs;
+    int32_t pairs_below;        // lists exist for the items of the columns before this one
     const int32_t* pair_ptr;    // n + 2 nnzl + 1
     const int2* pairs;
     // Dense trailing block (plan.h; tail_n = 0: none): columns >= tail_b0 are factored as one
@@ -39,6 +40,7 @@ struct SpIdx {
     // system's factors, followed by tail_ld x 64 doubles of right-hand-side scratch.
     int32_t tail_n, tail_b0, tail_ld, fac_lev_sp, nlev_sp[2];
     int64_t tail_off;
+    const int32_t* tail_rcnt;       // tail_n: entries below tail_b0 in each row of the block
     const int32_t* lev_sp_ptr[2];   // L-solve / U-solve levels of the rows < tail_b0
     const int32_t* lev_sp_idx[2];
 };

@@ -139,7 +139,7 @@ __device__ __forceinline__ double pair_dot(const SpIdx& ix, int id, const double
 }
 
 __device__ __forceinline__ double diag_dot(const SpIdx& ix, int j, const double* lv, const double* uv, double acc) {
-    if (ix.use_pairs) return pair_dot(ix, j, lv, uv, acc);
+    if (ix.use_pairs && j < ix.pairs_below) return pair_dot(ix, j, lv, uv, acc);
     for (int p = ix.r_ptr[j]; p < ix.r_ptr[j + 1]; ++p) {
         const int t = ix.r_pos[p];
         acc = fmad(-lv[t], uv[t], acc);
@@ -164,7 +164,7 @@ __device__ __forceinline__ double gather_diag(const SpIdx& ix, int j, const doub
 // phase B item: it < npos -> U entry at position t, else L entry at position t
 __device__ __forceinline__ void factor_item(const SpIdx& ix, int t, bool is_l, double* ud, double* lv, double* uv) {
     const int j = ix.col_of[t], m = ix.l_idx[t];
-    if (ix.use_pairs) {
+    if (ix.use_pairs && j < ix.pairs_below) {
         if (!is_l) uv[t] = pair_dot(ix, ix.n + t, lv, uv, uv[t]);
         else lv[t] = pair_dot(ix, ix.n + ix.nnzl + t, lv, uv, lv[t]) / ud[j];
         return;
@@ -407,29 +407,140 @@ __global__ void sp_rhs_out_kernel(SpArgs a) {
 // rows merged), and the block is factored densely in panels of NB columns on the MFMA unit, which
 // continues every entry's chain over k >= b0 in ascending order: the reference sequence.
 
-__global__ void tail_assemble_kernel(SpArgs a) {
+// One workgroup per (system, column j of the block): the U values of column j's external
+// updates (row j of the factor pattern below b0, at most kAsmList entries) are staged in LDS with
+// a map k -> slot over the b0 sparse columns, and each thread walks one block row i below b0 in
+// ascending k, taking the matches: entry (i, j) receives l_ik u_kj in the reference order.  The
+// last unknown's row and column (the slack column, ordered last) are full below b0; their factor
+// entries sit last in every column, so they are read directly instead of staged.  Columns that fit
+// neither form fall back to merging the two rows per entry.
+constexpr int kAsmThreads = 256;
+constexpr int kAsmList = 2048;
+
+__global__ __launch_bounds__(kAsmThreads) void tail_assemble_kernel(SpArgs a) {
+    extern __shared__ __align__(16) double smem[];
+    double* uval = smem;                                     // kAsmList
+    int32_t* kidx = reinterpret_cast<int32_t*>(smem + kAsmList);   // kAsmList
+    int16_t* kmap = reinterpret_cast<int16_t*>(kidx + kAsmList);   // b0
     const SpIdx& ix = a.ix;
-    const int n = ix.n, nl = ix.nnzl, b0 = ix.tail_b0, nt = ix.tail_n, ld = ix.tail_ld;
-    const int64_t per = (int64_t)ld * ld, total = per * a.ntasks;
-    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
-        const int task = (int)(g / per);
-        const int64_t t = g % per;
-        const int i = (int)(t % ld), j = (int)(t / ld);
+    const int n = ix.n, nl = ix.nnzl, b0 = ix.tail_b0, nt = ix.tail_n, ld = ix.tail_ld, tid = threadIdx.x;
+    const int last = n - 1;
+    const bool last_full = ix.tail_rcnt[nt - 1] == b0;
+    const int64_t total = (int64_t)ld * a.ntasks;
+    for (int64_t wg = blockIdx.x; wg < total; wg += gridDim.x) {
+        const int task = (int)(wg / ld), j = (int)(wg % ld);
         double* ud = a.fac + (int64_t)task * a.fstride;
-        double v;
-        if (i >= nt || j >= nt) {
-            v = i == j ? 1.0 : 0.0;
-        } else {
-            const int gi = b0 + i, gj = b0 + j;
-            const double* lv = ud + n;
-            const double* uv = ud + n + nl;
-            // the block's columns are full: (gi, gj) sits at l_ptr[min] + |gi - gj| - 1
-            v = gi == gj ? ud[gj] : (gi > gj ? lv[ix.l_ptr[gj] + (gi - gj - 1)] : uv[ix.l_ptr[gi] + (gj - gi - 1)]);
-            v = merge_dot_below(ix, gi, gj, b0, lv, uv, v);
+        double* T = ud + ix.tail_off + (int64_t)j * ld;
+        if (j >= nt) {                                       // identity padding column
+            for (int i = tid; i < ld; i += kAsmThreads) T[i] = i == j ? 1.0 : 0.0;
+            continue;
         }
-        ud[ix.tail_off + t] = v;
+        const double* lv = ud + n;
+        const double* uv = ud + n + nl;
+        const int gj = b0 + j;
+        const int lenj = ix.tail_rcnt[j];
+        const bool owner_last = gj == last && last_full;
+        const bool staged = !owner_last && lenj <= kAsmList;
+        const int pj = ix.r_ptr[gj];
+        if (staged) {
+            for (int k = tid; k < b0; k += kAsmThreads) kmap[k] = -1;
+            __syncthreads();
+            for (int q = tid; q < lenj; q += kAsmThreads) {
+                const int k = ix.r_idx[pj + q];
+                kmap[k] = (int16_t)q;
+                kidx[q] = k;
+                uval[q] = uv[ix.r_pos[pj + q]];
+            }
+            __syncthreads();
+        }
+        for (int i = tid; i < ld; i += kAsmThreads) {
+            if (i >= nt) {
+                T[i] = 0.0;
+                continue;
+            }
+            const int gi = b0 + i;
+            double v = gi == gj ? ud[gj] : (gi > gj ? lv[ix.l_ptr[gj] + (gi - gj - 1)] : uv[ix.l_ptr[gi] + (gj - gi - 1)]);
+            const bool row_last = gi == last && last_full;
+            constexpr int UN = 8;
+            if (staged && row_last) {
+                // l_{last,k} is the last entry of column k
+                int q = 0;
+                for (; q + UN <= lenj; q += UN) {
+                    double l[UN];
+#pragma unroll
+                    for (int w = 0; w < UN; ++w) l[w] = lv[ix.l_ptr[kidx[q + w] + 1] - 1];
+#pragma unroll
+                    for (int w = 0; w < UN; ++w) v = fmad(-l[w], uval[q + w], v);
+                }
+                for (; q < lenj; ++q) v = fmad(-lv[ix.l_ptr[kidx[q] + 1] - 1], uval[q], v);
+            } else if (staged) {
+                // row gi below b0, UN entries at a time: indices, then map lookups and values, then the chain
+                const int p0 = ix.r_ptr[gi], pe = p0 + ix.tail_rcnt[i];
+                int p = p0;
+                for (; p + UN <= pe; p += UN) {
+                    int qq[UN], tt[UN];
+                    double l[UN];
+#pragma unroll
+                    for (int w = 0; w < UN; ++w) {
+                        qq[w] = ix.r_idx[p + w];
+                        tt[w] = ix.r_pos[p + w];
+                    }
+#pragma unroll
+                    for (int w = 0; w < UN; ++w) {
+                        qq[w] = kmap[qq[w]];
+                        l[w] = qq[w] >= 0 ? lv[tt[w]] : 0.0;
+                    }
+#pragma unroll
+                    for (int w = 0; w < UN; ++w)
+                        if (qq[w] >= 0) v = fmad(-l[w], uval[qq[w]], v);
+                }
+                for (; p < pe; ++p) {
+                    const int q = kmap[ix.r_idx[p]];
+                    if (q >= 0) v = fmad(-lv[ix.r_pos[p]], uval[q], v);
+                }
+            } else if (owner_last && row_last) {
+                // every k below b0, both factors last in column k
+                int k = 0;
+                for (; k + UN <= b0; k += UN) {
+                    double l[UN], u[UN];
+#pragma unroll
+                    for (int w = 0; w < UN; ++w) {
+                        const int t = ix.l_ptr[k + w + 1] - 1;
+                        l[w] = lv[t];
+                        u[w] = uv[t];
+                    }
+#pragma unroll
+                    for (int w = 0; w < UN; ++w) v = fmad(-l[w], u[w], v);
+                }
+                for (; k < b0; ++k) {
+                    const int t = ix.l_ptr[k + 1] - 1;
+                    v = fmad(-lv[t], uv[t], v);
+                }
+            } else if (owner_last) {
+                // u_{k,last} is the last entry of column k
+                const int p0 = ix.r_ptr[gi], pe = p0 + ix.tail_rcnt[i];
+                int p = p0;
+                for (; p + UN <= pe; p += UN) {
+                    double l[UN], u[UN];
+#pragma unroll
+                    for (int w = 0; w < UN; ++w) {
+                        l[w] = lv[ix.r_pos[p + w]];
+                        u[w] = uv[ix.l_ptr[ix.r_idx[p + w] + 1] - 1];
+                    }
+#pragma unroll
+                    for (int w = 0; w < UN; ++w) v = fmad(-l[w], u[w], v);
+                }
+                for (; p < pe; ++p) v = fmad(-lv[ix.r_pos[p]], uv[ix.l_ptr[ix.r_idx[p] + 1] - 1], v);
+            } else {
+                v = merge_dot_below(ix, gi, gj, b0, lv, uv, v);
+            }
+            T[i] = v;
+        }
+        __syncthreads();
     }
 }
+
+int64_t tail_asm_lds(int32_t b0) { return (int64_t)kAsmList * 12 + ((int64_t)b0 * 2 + 15) / 16 * 16; }
 
 // Panel p0 of every system's block: GETRF of the NB x NB diagonal block (wave 0), then the
 // multipliers below it and the rows of U to its right (one workgroup per system).
@@ -478,11 +589,19 @@ __global__ void tail_fwd_ext_kernel(SpArgs a) {
         const double* m = TRANS ? ud + n + nl : ud + n;
         double* y = a.y + (int64_t)task * n * nrhs;
         double acc = y[(int64_t)i * nrhs + r];
-        for (int p = ix.r_ptr[i]; p < ix.r_ptr[i + 1]; ++p) {
-            const int k = ix.r_idx[p];
-            if (k >= b0) break;
-            acc = fmad(-m[ix.r_pos[p]], y[(int64_t)k * nrhs + r], acc);
+        const int p0 = ix.r_ptr[i], pe = p0 + ix.tail_rcnt[i - b0];
+        int p = p0;
+        for (; p + U8 <= pe; p += U8) {
+            double mv[U8], yv[U8];
+#pragma unroll
+            for (int w = 0; w < U8; ++w) {
+                mv[w] = m[ix.r_pos[p + w]];
+                yv[w] = y[(int64_t)ix.r_idx[p + w] * nrhs + r];
+            }
+#pragma unroll
+            for (int w = 0; w < U8; ++w) acc = fmad(-mv[w], yv[w], acc);
         }
+        for (; p < pe; ++p) acc = fmad(-m[ix.r_pos[p]], y[(int64_t)ix.r_idx[p] * nrhs + r], acc);
         y[(int64_t)i * nrhs + r] = acc;
     }
 }
@@ -1015,8 +1134,8 @@ hipError_t factor_tail(const SparseDevice& d, SpArgs a, const EpsSet& es, hipStr
                                0, st, a, p0, np);
     }
     const int ld = a.ix.tail_ld;
-    hipLaunchKernelGGL(tail_assemble_kernel, dim3(grid_for((int64_t)ld * ld * a.ntasks, kThreads)), dim3(kThreads), 0,
-                       st, a);
+    hipLaunchKernelGGL(tail_assemble_kernel, dim3((int)std::min<int64_t>((int64_t)ld * a.ntasks, 1 << 20)),
+                       dim3(kAsmThreads), (int)tail_asm_lds(a.ix.tail_b0), st, a);
     for (int p0 = 0; p0 < ld; p0 += NB) {
         hipLaunchKernelGGL(tail_panel_kernel, dim3(std::min(a.ntasks, 65535)), dim3(WG), 0, st, a, p0);
         const int rem = ld - p0 - NB;
@@ -1118,15 +1237,34 @@ void sparse_image(const Symbolic& s, PlanImage& img, SparseDevice& d) {
         }
         lpos_ptr[l + 1] = (int32_t)lpos.size();
     }
-    // update lists, when the total stays modest
+    // update lists, when the total stays modest: for every item, or (a plan with a dense
+    // trailing block whose full lists are too long) for the items of the columns before the block,
+    // the only ones its per-level kernels evaluate
     const int64_t npairs_est = (s.flops_sparse - nl) / 2;
     std::vector<int32_t> pair_ptr, pairs;
-    const bool use_pairs = npairs_est <= kMaxPairs;
-    if (use_pairs) {
+    int32_t below = npairs_est <= kMaxPairs ? n : (s.tail_n > 0 ? s.tail_b0 : 0);
+    if (below > 0) {
         pair_ptr.assign((size_t)n + 2 * (size_t)nl + 1, 0);
-        pairs.reserve(2 * (size_t)std::max<int64_t>(npairs_est, 1));
+        pairs.reserve(2 * (size_t)std::min<int64_t>(std::max<int64_t>(npairs_est, 1), kMaxPairs));
         auto push_merge = [&](int a, int b) {   // pairs (pos(a,k), pos(b,k)) for k in R_a ^ R_b
             int p = s.lrow_ptr[a], pe = s.lrow_ptr[a + 1], q = s.lrow_ptr[b], qe = s.lrow_ptr[b + 1];
+            if (pe - p > 8 * (qe - q) || qe - q > 8 * (pe - p)) {
+                // very different lengths: look the shorter row's columns up in the longer one
+                const bool a_short = pe - p <= qe - q;
+                const int* lb = s.lrow_idx.data() + (a_short ? q : p);
+                const int* le = s.lrow_idx.data() + (a_short ? qe : pe);
+                for (int x = a_short ? p : q; x < (a_short ? pe : qe); ++x) {
+                    const int* f = std::lower_bound(lb, le, s.lrow_idx[x]);
+                    if (f == le) break;
+                    if (*f == s.lrow_idx[x]) {
+                        const int y = (int)(f - s.lrow_idx.data());
+                        pairs.push_back(r_pos[a_short ? x : y]);
+                        pairs.push_back(r_pos[a_short ? y : x]);
+                    }
+                    lb = f;
+                }
+                return;
+            }
             while (p < pe && q < qe) {
                 const int ka = s.lrow_idx[p], kb = s.lrow_idx[q];
                 if (ka == kb) { pairs.push_back(r_pos[p]); pairs.push_back(r_pos[q]); ++p; ++q; }
@@ -1137,12 +1275,25 @@ void sparse_image(const Symbolic& s, PlanImage& img, SparseDevice& d) {
         int64_t id = 0;
         for (int j = 0; j < n; ++j, ++id) {
             pair_ptr[id] = (int32_t)(pairs.size() / 2);
-            for (int p = s.lrow_ptr[j]; p < s.lrow_ptr[j + 1]; ++p) { pairs.push_back(r_pos[p]); pairs.push_back(r_pos[p]); }
+            if (j < below)
+                for (int p = s.lrow_ptr[j]; p < s.lrow_ptr[j + 1]; ++p) { pairs.push_back(r_pos[p]); pairs.push_back(r_pos[p]); }
         }
-        for (int t = 0; t < nl; ++t, ++id) { pair_ptr[id] = (int32_t)(pairs.size() / 2); push_merge(col_of[t], s.l_idx[t]); }
-        for (int t = 0; t < nl; ++t, ++id) { pair_ptr[id] = (int32_t)(pairs.size() / 2); push_merge(s.l_idx[t], col_of[t]); }
+        for (int t = 0; t < nl; ++t, ++id) {
+            pair_ptr[id] = (int32_t)(pairs.size() / 2);
+            if (col_of[t] < below) push_merge(col_of[t], s.l_idx[t]);
+        }
+        for (int t = 0; t < nl; ++t, ++id) {
+            pair_ptr[id] = (int32_t)(pairs.size() / 2);
+            if (col_of[t] < below) push_merge(s.l_idx[t], col_of[t]);
+        }
         pair_ptr[id] = (int32_t)(pairs.size() / 2);
+        if ((int64_t)pairs.size() / 2 > kMaxPairs) {
+            below = 0;
+            pair_ptr.clear();
+            pairs.clear();
+        }
     }
+    const bool use_pairs = below > 0;
     SpIdx& ix = d.idx;
     ix.n = n;
     ix.nnzl = nl;
@@ -1165,6 +1316,7 @@ void sparse_image(const Symbolic& s, PlanImage& img, SparseDevice& d) {
     img.bind(&ix.lpos_ptr, img.put(lpos_ptr));
     img.bind(&ix.lpos, img.put(lpos));
     ix.use_pairs = use_pairs ? 1 : 0;
+    ix.pairs_below = below;
     img.bind(&ix.pair_ptr, img.put(pair_ptr));
     img.bind(&ix.pairs, img.put(pairs));
     d.h_lpos_ptr = lpos_ptr;
@@ -1173,6 +1325,15 @@ void sparse_image(const Symbolic& s, PlanImage& img, SparseDevice& d) {
     ix.tail_ld = (int32_t)tail_ld_of(s);
     ix.fac_lev_sp = s.fac_lev_sp;
     ix.tail_off = fbase_of(s);
+    {
+        std::vector<int32_t> rc(std::max(s.tail_n, 1), 0);
+        for (int i = 0; i < s.tail_n; ++i) {
+            const int r = s.tail_b0 + i;
+            rc[i] = (int32_t)(std::lower_bound(s.lrow_idx.begin() + s.lrow_ptr[r], s.lrow_idx.begin() + s.lrow_ptr[r + 1],
+                                               s.tail_b0) - (s.lrow_idx.begin() + s.lrow_ptr[r]));
+        }
+        img.bind(&ix.tail_rcnt, img.put(rc));
+    }
     for (int w = 0; w < 2; ++w) {
         ix.nlev_sp[w] = s.tail_n ? (int32_t)s.lev_sp_ptr[w].size() - 1 : 0;
         img.bind(&ix.lev_sp_ptr[w], img.put(s.lev_sp_ptr[w]));
@@ -1187,6 +1348,9 @@ hipError_t sparse_kernel_attrs() {
     static hipError_t e = [] {
         hipError_t r = hipFuncSetAttribute((const void*)sparse_lds_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            kLdsLimit);
+        if (r == hipSuccess)
+            r = hipFuncSetAttribute((const void*)tail_assemble_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)tail_asm_lds(kTailAsmMaxB0));
         return r;
     }();
     return e;
