@@ -407,74 +407,266 @@ __global__ void sp_rhs_out_kernel(SpArgs a) {
 // rows merged), and the block is factored densely in panels of NB columns on the MFMA unit, which
 // continues every entry's chain over k >= b0 in ascending order: the reference sequence.
 
-// One workgroup per (system, column j of the block): the U values of column j's external
-// updates (row j of the factor pattern below b0, at most kAsmList entries) are staged in LDS with
-// a map k -> slot over the b0 sparse columns, and each thread walks one block row i below b0 in
-// ascending k, taking the matches: entry (i, j) receives l_ik u_kj in the reference order.  The
-// last unknown's row and column (the slack column, ordered last) are full below b0; their factor
-// entries sit last in every column, so they are read directly instead of staged.  Columns that fit
-// neither form fall back to merging the two rows per entry.
+// Each entry (i, j) of the block takes l_ik u_kj for k < b0 in ascending k.  One workgroup per
+// (system, tile of kAsmCols block columns): the U values of the tile's columns below b0 (row j of the
+// factor pattern, at most kAsmUnion distinct k over the tile) are staged in LDS with a map
+// k -> slot over the b0 sparse columns and a mask of the columns present at each slot; each thread
+// then walks one block row i below b0 in ascending k (indices prefetched kAsmUnroll at a time) and
+// applies every match to the tile's columns that have it.  The last unknown (the slack column,
+// ordered last) has a full row and column below b0 whose factor entries sit last in every column:
+// they are read directly.  A tile that holds the slack column, or whose staged values would not
+// fit, is assembled one column at a time (staged, or by merging the two rows per entry).
 constexpr int kAsmThreads = 256;
-constexpr int kAsmList = 2048;
+constexpr int kAsmCols = 4;
+constexpr int kAsmUnion = 1024;
+constexpr int kAsmUnroll = 8;
+
+struct AsmLds {
+    double* u4;        // kAsmUnion x kAsmCols (one column: kAsmUnion values)
+    int32_t* kidx;     // kAsmUnion
+    uint8_t* mask;     // kAsmUnion
+    int16_t* kmap;     // b0
+};
+
+__device__ __forceinline__ AsmLds asm_lds(double* smem) {
+    AsmLds L;
+    L.u4 = smem;
+    L.kidx = reinterpret_cast<int32_t*>(smem + kAsmUnion * kAsmCols);
+    L.mask = reinterpret_cast<uint8_t*>(L.kidx + kAsmUnion);
+    L.kmap = reinterpret_cast<int16_t*>(L.mask + kAsmUnion);
+    return L;
+}
+
+// Initial value of block entry (gi, gj): a_ij (+ eps d on the diagonal) as gathered.
+__device__ __forceinline__ double block_a(const SpIdx& ix, const double* ud, const double* lv, const double* uv,
+                                          int gi, int gj) {
+    return gi == gj ? ud[gj] : (gi > gj ? lv[ix.l_ptr[gj] + (gi - gj - 1)] : uv[ix.l_ptr[gi] + (gj - gi - 1)]);
+}
+
+// Column j of the block, alone.
+__device__ void assemble_column(const SpIdx& ix, double* ud, int j, const AsmLds& L) {
+    const int n = ix.n, nl = ix.nnzl, b0 = ix.tail_b0, nt = ix.tail_n, ld = ix.tail_ld, tid = threadIdx.x;
+    const int last = n - 1;
+    double* T = ud + ix.tail_off + (int64_t)j * ld;
+    if (j >= nt) {                                       // identity padding column
+        for (int i = tid; i < ld; i += kAsmThreads) T[i] = i == j ? 1.0 : 0.0;
+        return;
+    }
+    const double* lv = ud + n;
+    const double* uv = ud + n + nl;
+    double* uval = L.u4;
+    const int gj = b0 + j, lenj = ix.tail_rcnt[j], pj = ix.r_ptr[gj];
+    const int32_t* lpos = ix.tail_lastpos;
+    const bool owner_last = gj == last;
+    const bool staged = !owner_last && lenj <= kAsmUnion;
+    if (staged) {
+        for (int k = tid; k < b0; k += kAsmThreads) L.kmap[k] = -1;
+        __syncthreads();
+        for (int q = tid; q < lenj; q += kAsmThreads) {
+            const int k = ix.r_idx[pj + q];
+            L.kmap[k] = (int16_t)q;
+            L.kidx[q] = k;
+            uval[q] = uv[ix.r_pos[pj + q]];
+        }
+        __syncthreads();
+    }
+    constexpr int UN = kAsmUnroll;
+    for (int i = tid; i < ld; i += kAsmThreads) {
+        if (i >= nt) {
+            T[i] = 0.0;
+            continue;
+        }
+        const int gi = b0 + i;
+        double v = block_a(ix, ud, lv, uv, gi, gj);
+        const bool row_last = gi == last;
+        if (staged && row_last) {
+            // l_{last,k} at lastpos[k] (no entry: -1)
+            int q = 0;
+            for (; q + UN <= lenj; q += UN) {
+                int tt[UN];
+                double l[UN];
+#pragma unroll
+                for (int w = 0; w < UN; ++w) tt[w] = lpos[L.kidx[q + w]];
+#pragma unroll
+                for (int w = 0; w < UN; ++w) l[w] = tt[w] >= 0 ? lv[tt[w]] : 0.0;
+#pragma unroll
+                for (int w = 0; w < UN; ++w)
+                    if (tt[w] >= 0) v = fmad(-l[w], uval[q + w], v);
+            }
+            for (; q < lenj; ++q) {
+                const int t = lpos[L.kidx[q]];
+                if (t >= 0) v = fmad(-lv[t], uval[q], v);
+            }
+        } else if (staged) {
+            const int p0 = ix.r_ptr[gi], pe = p0 + ix.tail_rcnt[i];
+            int p = p0;
+            for (; p + UN <= pe; p += UN) {
+                int qq[UN], tt[UN];
+                double l[UN];
+#pragma unroll
+                for (int w = 0; w < UN; ++w) {
+                    qq[w] = ix.r_idx[p + w];
+                    tt[w] = ix.r_pos[p + w];
+                }
+#pragma unroll
+                for (int w = 0; w < UN; ++w) {
+                    qq[w] = L.kmap[qq[w]];
+                    l[w] = qq[w] >= 0 ? lv[tt[w]] : 0.0;
+                }
+#pragma unroll
+                for (int w = 0; w < UN; ++w)
+                    if (qq[w] >= 0) v = fmad(-l[w], uval[qq[w]], v);
+            }
+            for (; p < pe; ++p) {
+                const int q = L.kmap[ix.r_idx[p]];
+                if (q >= 0) v = fmad(-lv[ix.r_pos[p]], uval[q], v);
+            }
+        } else if (owner_last && row_last) {
+            // (last, last): every k below b0 with both factors at lastpos[k]
+            int k = 0;
+            for (; k + UN <= b0; k += UN) {
+                int tt[UN];
+                double l[UN], u[UN];
+#pragma unroll
+                for (int w = 0; w < UN; ++w) tt[w] = lpos[k + w];
+#pragma unroll
+                for (int w = 0; w < UN; ++w) {
+                    l[w] = tt[w] >= 0 ? lv[tt[w]] : 0.0;
+                    u[w] = tt[w] >= 0 ? uv[tt[w]] : 0.0;
+                }
+#pragma unroll
+                for (int w = 0; w < UN; ++w)
+                    if (tt[w] >= 0) v = fmad(-l[w], u[w], v);
+            }
+            for (; k < b0; ++k) {
+                const int t = lpos[k];
+                if (t >= 0) v = fmad(-lv[t], uv[t], v);
+            }
+        } else if (owner_last) {
+            // u_{k,last} at lastpos[k]
+            const int p0 = ix.r_ptr[gi], pe = p0 + ix.tail_rcnt[i];
+            int p = p0;
+            for (; p + UN <= pe; p += UN) {
+                int tt[UN], pp[UN];
+                double l[UN], u[UN];
+#pragma unroll
+                for (int w = 0; w < UN; ++w) {
+                    tt[w] = ix.r_idx[p + w];
+                    pp[w] = ix.r_pos[p + w];
+                }
+#pragma unroll
+                for (int w = 0; w < UN; ++w) tt[w] = lpos[tt[w]];
+#pragma unroll
+                for (int w = 0; w < UN; ++w) {
+                    l[w] = tt[w] >= 0 ? lv[pp[w]] : 0.0;
+                    u[w] = tt[w] >= 0 ? uv[tt[w]] : 0.0;
+                }
+#pragma unroll
+                for (int w = 0; w < UN; ++w)
+                    if (tt[w] >= 0) v = fmad(-l[w], u[w], v);
+            }
+            for (; p < pe; ++p) {
+                const int t = lpos[ix.r_idx[p]];
+                if (t >= 0) v = fmad(-lv[ix.r_pos[p]], uv[t], v);
+            }
+        } else {
+            v = merge_dot_below(ix, gi, gj, b0, lv, uv, v);
+        }
+        T[i] = v;
+    }
+    __syncthreads();
+}
 
 __global__ __launch_bounds__(kAsmThreads) void tail_assemble_kernel(SpArgs a) {
     extern __shared__ __align__(16) double smem[];
-    double* uval = smem;                                     // kAsmList
-    int32_t* kidx = reinterpret_cast<int32_t*>(smem + kAsmList);   // kAsmList
-    int16_t* kmap = reinterpret_cast<int16_t*>(kidx + kAsmList);   // b0
+    __shared__ int s_cnt;
+    const AsmLds L = asm_lds(smem);
     const SpIdx& ix = a.ix;
     const int n = ix.n, nl = ix.nnzl, b0 = ix.tail_b0, nt = ix.tail_n, ld = ix.tail_ld, tid = threadIdx.x;
     const int last = n - 1;
-    const bool last_full = ix.tail_rcnt[nt - 1] == b0;
-    const int64_t total = (int64_t)ld * a.ntasks;
+    const int32_t* lpos = ix.tail_lastpos;
+    const int ntile = ld / kAsmCols;
+    const int64_t total = (int64_t)ntile * a.ntasks;
+    constexpr int UN = kAsmUnroll;
     for (int64_t wg = blockIdx.x; wg < total; wg += gridDim.x) {
-        const int task = (int)(wg / ld), j = (int)(wg % ld);
+        const int task = (int)(wg / ntile), j0 = (int)(wg % ntile) * kAsmCols;
         double* ud = a.fac + (int64_t)task * a.fstride;
-        double* T = ud + ix.tail_off + (int64_t)j * ld;
-        if (j >= nt) {                                       // identity padding column
-            for (int i = tid; i < ld; i += kAsmThreads) T[i] = i == j ? 1.0 : 0.0;
+        int lens = 0;
+        bool has_last = false;
+        for (int c = 0; c < kAsmCols; ++c)
+            if (j0 + c < nt) {
+                lens += ix.tail_rcnt[j0 + c];
+                has_last |= b0 + j0 + c == last;
+            }
+        if (has_last || lens > kAsmUnion) {
+            for (int c = 0; c < kAsmCols; ++c) assemble_column(ix, ud, j0 + c, L);
             continue;
         }
         const double* lv = ud + n;
         const double* uv = ud + n + nl;
-        const int gj = b0 + j;
-        const int lenj = ix.tail_rcnt[j];
-        const bool owner_last = gj == last && last_full;
-        const bool staged = !owner_last && lenj <= kAsmList;
-        const int pj = ix.r_ptr[gj];
-        if (staged) {
-            for (int k = tid; k < b0; k += kAsmThreads) kmap[k] = -1;
-            __syncthreads();
-            for (int q = tid; q < lenj; q += kAsmThreads) {
-                const int k = ix.r_idx[pj + q];
-                kmap[k] = (int16_t)q;
-                kidx[q] = k;
-                uval[q] = uv[ix.r_pos[pj + q]];
+        // stage: slots for the distinct k of the tile's columns, their U values and presence mask
+        if (tid == 0) s_cnt = 0;
+        for (int k = tid; k < b0; k += kAsmThreads) L.kmap[k] = -1;
+        __syncthreads();
+        for (int c = 0; c < kAsmCols; ++c) {
+            if (j0 + c < nt) {
+                const int gj = b0 + j0 + c, pj = ix.r_ptr[gj], len = ix.tail_rcnt[j0 + c];
+                for (int q = tid; q < len; q += kAsmThreads) {
+                    const int k = ix.r_idx[pj + q];
+                    int sl = L.kmap[k];
+                    if (sl < 0) {
+                        sl = atomicAdd(&s_cnt, 1);
+                        L.kmap[k] = (int16_t)sl;
+                        L.mask[sl] = 0;
+#pragma unroll
+                        for (int w = 0; w < kAsmCols; ++w) L.u4[sl * kAsmCols + w] = 0.0;
+                    }
+                    L.u4[sl * kAsmCols + c] = uv[ix.r_pos[pj + q]];
+                    L.mask[sl] |= (uint8_t)(1u << c);
+                }
             }
             __syncthreads();
         }
         for (int i = tid; i < ld; i += kAsmThreads) {
-            if (i >= nt) {
-                T[i] = 0.0;
-                continue;
-            }
+            double acc[kAsmCols];
             const int gi = b0 + i;
-            double v = gi == gj ? ud[gj] : (gi > gj ? lv[ix.l_ptr[gj] + (gi - gj - 1)] : uv[ix.l_ptr[gi] + (gj - gi - 1)]);
-            const bool row_last = gi == last && last_full;
-            constexpr int UN = 8;
-            if (staged && row_last) {
-                // l_{last,k} is the last entry of column k
-                int q = 0;
-                for (; q + UN <= lenj; q += UN) {
-                    double l[UN];
 #pragma unroll
-                    for (int w = 0; w < UN; ++w) l[w] = lv[ix.l_ptr[kidx[q + w] + 1] - 1];
+            for (int c = 0; c < kAsmCols; ++c)
+                acc[c] = (i < nt && j0 + c < nt) ? block_a(ix, ud, lv, uv, gi, b0 + j0 + c) : 0.0;
+            if (i < nt && gi == last) {
+                // the slack row: each column's own list, l_{last,k} at lastpos[k]
+                for (int c = 0; c < kAsmCols; ++c) {
+                    if (j0 + c >= nt) continue;
+                    const int gj = b0 + j0 + c, pj = ix.r_ptr[gj], len = ix.tail_rcnt[j0 + c];
+                    double v = acc[c];
+                    int q = 0;
+                    for (; q + UN <= len; q += UN) {
+                        // indices, then the column ends, then the values: three round trips per UN entries
+                        int kk[UN], tt[UN];
+                        double l[UN], u[UN];
 #pragma unroll
-                    for (int w = 0; w < UN; ++w) v = fmad(-l[w], uval[q + w], v);
+                        for (int w = 0; w < UN; ++w) {
+                            kk[w] = ix.r_idx[pj + q + w];
+                            tt[w] = ix.r_pos[pj + q + w];
+                        }
+#pragma unroll
+                        for (int w = 0; w < UN; ++w) kk[w] = lpos[kk[w]];
+#pragma unroll
+                        for (int w = 0; w < UN; ++w) {
+                            l[w] = kk[w] >= 0 ? lv[kk[w]] : 0.0;
+                            u[w] = kk[w] >= 0 ? uv[tt[w]] : 0.0;
+                        }
+#pragma unroll
+                        for (int w = 0; w < UN; ++w)
+                            if (kk[w] >= 0) v = fmad(-l[w], u[w], v);
+                    }
+                    for (; q < len; ++q) {
+                        const int t = lpos[ix.r_idx[pj + q]];
+                        if (t >= 0) v = fmad(-lv[t], uv[ix.r_pos[pj + q]], v);
+                    }
+                    acc[c] = v;
                 }
-                for (; q < lenj; ++q) v = fmad(-lv[ix.l_ptr[kidx[q] + 1] - 1], uval[q], v);
-            } else if (staged) {
-                // row gi below b0, UN entries at a time: indices, then map lookups and values, then the chain
+            } else if (i < nt) {
                 const int p0 = ix.r_ptr[gi], pe = p0 + ix.tail_rcnt[i];
                 int p = p0;
                 for (; p + UN <= pe; p += UN) {
@@ -487,60 +679,41 @@ __global__ __launch_bounds__(kAsmThreads) void tail_assemble_kernel(SpArgs a) {
                     }
 #pragma unroll
                     for (int w = 0; w < UN; ++w) {
-                        qq[w] = kmap[qq[w]];
+                        qq[w] = L.kmap[qq[w]];
                         l[w] = qq[w] >= 0 ? lv[tt[w]] : 0.0;
                     }
 #pragma unroll
-                    for (int w = 0; w < UN; ++w)
-                        if (qq[w] >= 0) v = fmad(-l[w], uval[qq[w]], v);
+                    for (int w = 0; w < UN; ++w) {
+                        if (qq[w] < 0) continue;
+                        const int m = L.mask[qq[w]];
+#pragma unroll
+                        for (int c = 0; c < kAsmCols; ++c)
+                            if ((m >> c) & 1) acc[c] = fmad(-l[w], L.u4[qq[w] * kAsmCols + c], acc[c]);
+                    }
                 }
                 for (; p < pe; ++p) {
-                    const int q = kmap[ix.r_idx[p]];
-                    if (q >= 0) v = fmad(-lv[ix.r_pos[p]], uval[q], v);
-                }
-            } else if (owner_last && row_last) {
-                // every k below b0, both factors last in column k
-                int k = 0;
-                for (; k + UN <= b0; k += UN) {
-                    double l[UN], u[UN];
+                    const int q = L.kmap[ix.r_idx[p]];
+                    if (q < 0) continue;
+                    const double l = lv[ix.r_pos[p]];
+                    const int m = L.mask[q];
 #pragma unroll
-                    for (int w = 0; w < UN; ++w) {
-                        const int t = ix.l_ptr[k + w + 1] - 1;
-                        l[w] = lv[t];
-                        u[w] = uv[t];
-                    }
-#pragma unroll
-                    for (int w = 0; w < UN; ++w) v = fmad(-l[w], u[w], v);
+                    for (int c = 0; c < kAsmCols; ++c)
+                        if ((m >> c) & 1) acc[c] = fmad(-l, L.u4[q * kAsmCols + c], acc[c]);
                 }
-                for (; k < b0; ++k) {
-                    const int t = ix.l_ptr[k + 1] - 1;
-                    v = fmad(-lv[t], uv[t], v);
-                }
-            } else if (owner_last) {
-                // u_{k,last} is the last entry of column k
-                const int p0 = ix.r_ptr[gi], pe = p0 + ix.tail_rcnt[i];
-                int p = p0;
-                for (; p + UN <= pe; p += UN) {
-                    double l[UN], u[UN];
-#pragma unroll
-                    for (int w = 0; w < UN; ++w) {
-                        l[w] = lv[ix.r_pos[p + w]];
-                        u[w] = uv[ix.l_ptr[ix.r_idx[p + w] + 1] - 1];
-                    }
-#pragma unroll
-                    for (int w = 0; w < UN; ++w) v = fmad(-l[w], u[w], v);
-                }
-                for (; p < pe; ++p) v = fmad(-lv[ix.r_pos[p]], uv[ix.l_ptr[ix.r_idx[p] + 1] - 1], v);
-            } else {
-                v = merge_dot_below(ix, gi, gj, b0, lv, uv, v);
             }
-            T[i] = v;
+#pragma unroll
+            for (int c = 0; c < kAsmCols; ++c) {
+                const int j = j0 + c;
+                ud[ix.tail_off + (int64_t)j * ld + i] = j < nt ? (i < nt ? acc[c] : 0.0) : (i == j ? 1.0 : 0.0);
+            }
         }
         __syncthreads();
     }
 }
 
-int64_t tail_asm_lds(int32_t b0) { return (int64_t)kAsmList * 12 + ((int64_t)b0 * 2 + 15) / 16 * 16; }
+int64_t tail_asm_lds(int32_t b0) {
+    return (int64_t)kAsmUnion * (kAsmCols * 8 + 4 + 1) + ((int64_t)b0 * 2 + 15) / 16 * 16;
+}
 
 // Panel p0 of every system's block: GETRF of the NB x NB diagonal block (wave 0), then the
 // multipliers below it and the rows of U to its right (one workgroup per system).
@@ -1134,7 +1307,7 @@ hipError_t factor_tail(const SparseDevice& d, SpArgs a, const EpsSet& es, hipStr
                                0, st, a, p0, np);
     }
     const int ld = a.ix.tail_ld;
-    hipLaunchKernelGGL(tail_assemble_kernel, dim3((int)std::min<int64_t>((int64_t)ld * a.ntasks, 1 << 20)),
+    hipLaunchKernelGGL(tail_assemble_kernel, dim3((int)std::min<int64_t>((int64_t)(ld / kAsmCols) * a.ntasks, 1 << 20)),
                        dim3(kAsmThreads), (int)tail_asm_lds(a.ix.tail_b0), st, a);
     for (int p0 = 0; p0 < ld; p0 += NB) {
         hipLaunchKernelGGL(tail_panel_kernel, dim3(std::min(a.ntasks, 65535)), dim3(WG), 0, st, a, p0);
@@ -1333,6 +1506,10 @@ void sparse_image(const Symbolic& s, PlanImage& img, SparseDevice& d) {
                                                s.tail_b0) - (s.lrow_idx.begin() + s.lrow_ptr[r]));
         }
         img.bind(&ix.tail_rcnt, img.put(rc));
+        std::vector<int32_t> lp(std::max(s.tail_b0, 1), -1);
+        for (int k = 0; k < s.tail_b0; ++k)
+            if (s.l_ptr[k + 1] > s.l_ptr[k] && s.l_idx[s.l_ptr[k + 1] - 1] == n - 1) lp[k] = s.l_ptr[k + 1] - 1;
+        img.bind(&ix.tail_lastpos, img.put(lp));
     }
     for (int w = 0; w < 2; ++w) {
         ix.nlev_sp[w] = s.tail_n ? (int32_t)s.lev_sp_ptr[w].size() - 1 : 0;
