@@ -171,8 +171,8 @@ def extra_configs(psp, W, torch, dev, only=None):
         for N, ipu, ixu, valsu, bsu in groups:
             pu = psp.Plan(ipu, ixu)
             vu, bu = torch.from_numpy(valsu).to(dev), torch.from_numpy(bsu).to(dev)
-            ch, _ = psp.tune(pu, vu, eps, bu)
-            paths_u[len(ipu) - 1] = ch
+            psp.tune(pu, vu, eps, bu)
+            paths_u[len(ipu) - 1] = psp.tune_choice(pu, int(valsu.shape[0]), len(eps), 1)
             sizes[len(ipu) - 1] = int(valsu.shape[0])
             flops_u += valsu.shape[0] * len(eps) * sparse_flops(pu.info(), len(ipu) - 1)
             items.append((pu, vu, bu))
@@ -352,7 +352,8 @@ def main():
     # ---- the fixed nodes 1e-3 * 2^-k on every numeric path (one fused call each; the autotuner's timing)
     chosen, tuner_ms = psp.tune(plan, vals_d, eps, b_d)
     torch.cuda.synchronize()
-    print(f"[bench] tuner: {tuner_ms} -> {chosen}", file=sys.stderr, flush=True)
+    tuned = psp.tune_choice(plan, S, K, 1)
+    print(f"[bench] tuner: {tuner_ms} -> {tuned}", file=sys.stderr, flush=True)
     results = {}
     for p in (["sparse_steps"] if args.no_paths else
               ["dense", "sparse_batched", "sparse_grouped", "sparse_lds", "sparse_steps"]):
@@ -503,6 +504,7 @@ def main():
         "plain": plain,
         "paths": paths,
         "tuner_ms": tuner_ms,
+        "tuned_choice": tuned,
         "info_nonzero": int(np.count_nonzero(ia)),
         "residual_rel_all": {"max": float(rel_res.max()), "median": float(np.median(rel_res)),
                              "jacobians": int(rel_res.size), "above_1e-9": int(np.sum(rel_res > 1e-9)),

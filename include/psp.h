@@ -337,6 +337,41 @@ PSP_API psp_status psp_tune(psp_plan plan, int32_t batch, const double* values, 
                             const double* d, int32_t nrhs, const double* B, double* X, int32_t* info, void* ws,
                             size_t ws_bytes, void* stream, int32_t* chosen, float* ms);
 
+/* The tuner's choice for (batch, K, nrhs): the path and, for it, the launch
+ * choices searched besides the path (Sec. IV: batched factorisation and
+ * solves are where the time goes, so their launch shape is tuned per
+ * workload):
+ *   steps_mode  step schedule: -1 by batch size, 0 one workgroup per perturbed
+ *               system, 1 one workgroup per Jacobian (combine fused);
+ *   steps_wgcu  step schedule: 0 as many workgroups per CU as LDS allows,
+ *               1 one per CU;
+ *   ring        step schedule: descriptors in flight, 7 or 4;
+ *   tail_cols   dense trailing block: block columns assembled per
+ *               workgroup, 4 or 1;
+ *   ms          measured time per call (-1 when set by hand);
+ *   source      0 none (the size heuristic applies), 1 tuned or set in this
+ *               process, 2 read from the tuning cache file.
+ * psp_tune records its choice in the plan and in the tuning cache file
+ * ($PSP_TUNE_CACHE, else $HOME/.cache/psp/tune.txt; PSP_TUNE_CACHE set to ""
+ * disables it), one line per (device, pattern hash, n, nnz, batch, K, nrhs),
+ * so that PSP_PATH_AUTO in a later process uses it without tuning again.
+ * psp_tune_choice reports the choice AUTO would use; psp_set_tune_choice
+ * pins one by hand (PSP_E_INVALID for an unknown path or a launch choice
+ * outside the values above).  All choices return the same bits. */
+typedef struct {
+    int32_t path;
+    int32_t steps_mode;
+    int32_t steps_wgcu;
+    int32_t ring;
+    int32_t tail_cols;
+    float ms;
+    int32_t source;
+} psp_tune_choice_t;
+
+PSP_API psp_status psp_tune_choice(psp_plan plan, int32_t batch, int32_t K, int32_t nrhs, psp_tune_choice_t* out);
+PSP_API psp_status psp_set_tune_choice(psp_plan plan, int32_t batch, int32_t K, int32_t nrhs,
+                                       const psp_tune_choice_t* choice);
+
 /* ------------------------------------------------------------------------
  * Split steps (plain, one call per step) -- the adjoint and the
  * one-system-at-a-time baseline use these.

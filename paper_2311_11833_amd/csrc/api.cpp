@@ -5,11 +5,18 @@
 
 #include <hip/hip_runtime.h>
 
+#include <sys/stat.h>
+#include <unistd.h>
+
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <memory>
 #include <map>
+#include <sstream>
 #include <mutex>
 #include <tuple>
 #include <new>
@@ -81,7 +88,8 @@ struct psp_plan_s {
     const int32_t* d_cols = nullptr;
     const int32_t* d_rowptr = nullptr; // user CSR row pointers
     SparseDevice sp;                   // sparse-path arrays
-    std::map<std::tuple<int32_t, int32_t, int32_t>, int32_t> tuned;   // (batch, K, nrhs) -> path id
+    uint64_t hash = 0;                 // FNV-1a of the pattern (key of the tuning cache file)
+    std::map<std::tuple<int32_t, int32_t, int32_t>, psp_tune_choice_t> tuned;   // (batch, K, nrhs) -> choice
 };
 
 struct psp_factors_s {
@@ -205,11 +213,117 @@ psp_status check_prior_hip() {
     return PSP_OK;
 }
 
-int32_t resolve_path(psp_plan p, int32_t path, int32_t batch, int32_t K, int32_t nrhs) {
-    if (path != PSP_PATH_AUTO) return path;
+// ---- tuning cache: the tuner's choices, persisted to a text file (one line per
+// (device, pattern, batch, K, nrhs)) so that a later process finds them without tuning again.
+// File: $PSP_TUNE_CACHE, else $HOME/.cache/psp/tune.txt; PSP_TUNE_CACHE set but empty disables it.
+std::mutex g_cache_mu;
+bool g_cache_loaded = false;
+std::map<std::string, psp_tune_choice_t> g_cache;
+
+std::string cache_path() {
+    if (const char* e = std::getenv("PSP_TUNE_CACHE")) return e;
+    const char* h = std::getenv("HOME");
+    return h && *h ? std::string(h) + "/.cache/psp/tune.txt" : std::string();
+}
+
+std::string cache_key(psp_plan p, int32_t batch, int32_t K, int32_t nrhs) {
+    char buf[160];
+    std::snprintf(buf, sizeof(buf), "gfx950|n=%d|nnz=%d|h=%016llx|batch=%d|K=%d|nrhs=%d", p->sym.n, p->sym.nnz,
+                  (unsigned long long)p->hash, batch, K, nrhs);
+    return buf;
+}
+
+void cache_load_locked() {
+    if (g_cache_loaded) return;
+    g_cache_loaded = true;
+    const std::string path = cache_path();
+    if (path.empty()) return;
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+        std::istringstream is(line);
+        std::string key;
+        psp_tune_choice_t c{};
+        if (is >> key >> c.path >> c.steps_mode >> c.steps_wgcu >> c.ring >> c.tail_cols >> c.ms) {
+            c.source = 2;
+            g_cache[key] = c;
+        }
+    }
+}
+
+void cache_store(const std::string& key, const psp_tune_choice_t& c) {
+    std::lock_guard<std::mutex> g(g_cache_mu);
+    cache_load_locked();
+    g_cache[key] = c;
+    const std::string path = cache_path();
+    if (path.empty()) return;
+    const size_t slash = path.find_last_of('/');
+    if (slash != std::string::npos) {
+        // create the directory and its parent when missing (errors surface as a failed open below)
+        const std::string dir = path.substr(0, slash);
+        const size_t up = dir.find_last_of('/');
+        if (up != std::string::npos && up > 0) ::mkdir(dir.substr(0, up).c_str(), 0755);
+        ::mkdir(dir.c_str(), 0755);
+    }
+    const std::string tmp = path + ".tmp" + std::to_string((long long)::getpid());
+    {
+        std::ofstream f(tmp);
+        if (!f) return;
+        for (const auto& kv : g_cache)
+            f << kv.first << ' ' << kv.second.path << ' ' << kv.second.steps_mode << ' ' << kv.second.steps_wgcu << ' '
+              << kv.second.ring << ' ' << kv.second.tail_cols << ' ' << kv.second.ms << '\n';
+    }
+    std::rename(tmp.c_str(), path.c_str());
+}
+
+psp_tune_choice_t default_choice(int32_t path) {
+    psp_tune_choice_t c{};
+    const Knobs kn;
+    c.path = path;
+    c.steps_mode = kn.steps_mode;
+    c.steps_wgcu = kn.steps_wgcu;
+    c.ring = kn.ring;
+    c.tail_cols = kn.tail_cols;
+    c.ms = -1.0f;
+    c.source = 0;
+    return c;
+}
+
+Knobs knobs_of(const psp_tune_choice_t& c) {
+    Knobs kn;
+    kn.steps_mode = c.steps_mode;
+    kn.steps_wgcu = c.steps_wgcu;
+    kn.ring = c.ring;
+    kn.tail_cols = c.tail_cols;
+    return kn;
+}
+
+// The choice for this call: an explicit path with the default launch choices, or for AUTO the
+// tuner's choice (this process, else the cache file), else the size heuristic.
+psp_tune_choice_t resolve_choice(psp_plan p, int32_t path, int32_t batch, int32_t K, int32_t nrhs) {
+    if (path != PSP_PATH_AUTO) return default_choice(path);
+    const auto key = std::make_tuple(batch, K, nrhs);
+    {
+        std::lock_guard<std::mutex> g(p->mu);
+        auto it = p->tuned.find(key);
+        if (it != p->tuned.end()) return it->second;
+    }
+    psp_tune_choice_t c = default_choice(heuristic_path(p->sym));
+    {
+        std::lock_guard<std::mutex> g(g_cache_mu);
+        cache_load_locked();
+        auto it = g_cache.find(cache_key(p, batch, K, nrhs));
+        if (it == g_cache.end()) return c;
+        c = it->second;
+        c.source = 2;
+    }
     std::lock_guard<std::mutex> g(p->mu);
-    auto it = p->tuned.find(std::make_tuple(batch, K, nrhs));
-    return it != p->tuned.end() ? it->second : heuristic_path(p->sym);
+    p->tuned[key] = c;
+    return c;
+}
+
+int32_t resolve_path(psp_plan p, int32_t path, int32_t batch, int32_t K, int32_t nrhs) {
+    return resolve_choice(p, path, batch, K, nrhs).path;
 }
 
 size_t path_workspace(const Symbolic& s, int32_t path, int32_t batch, int32_t K, int32_t nrhs, int32_t keep) {
@@ -253,6 +367,18 @@ psp_status psp_plan_create(int32_t n, const int32_t* row_ptr, const int32_t* col
     try {
         auto p = std::make_unique<psp_plan_s>();
         analyse(n, row_ptr, col_idx, (flags & PSP_ORDER_NATURAL) != 0, p->sym);
+        uint64_t h = 1469598103934665603ULL;
+        auto mix = [&](uint32_t v) {
+            for (int b = 0; b < 4; ++b) {
+                h ^= (v >> (8 * b)) & 0xFF;
+                h *= 1099511628211ULL;
+            }
+        };
+        mix((uint32_t)n);
+        mix(flags);
+        for (int32_t i = 0; i <= n; ++i) mix((uint32_t)row_ptr[i]);
+        for (int32_t e = 0; e < row_ptr[n]; ++e) mix((uint32_t)col_idx[e]);
+        p->hash = h;
         *out = p.release();
     } catch (const std::bad_alloc&) {
         return fail(PSP_E_NOMEM, "psp_plan_create: host allocation failed");
@@ -351,9 +477,14 @@ size_t psp_workspace_bytes(psp_plan p, int32_t path, int32_t batch, int32_t K, i
     return path_workspace(p->sym, path, batch, K, nrhs, keep);
 }
 
-psp_status psp_solve_batched(psp_plan p, int32_t path, int32_t batch, const double* values, int32_t K,
-                             const double* eps, const double* d, int32_t nrhs, const double* B, double* X,
-                             int32_t* info, void* ws, size_t ws_bytes, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// psp_solve_batched with the path and launch choices given (path != AUTO).
+psp_status solve_choice(psp_plan p, const psp_tune_choice_t& ch, int32_t batch, const double* values, int32_t K,
+                        const double* eps, const double* d, int32_t nrhs, const double* B, double* X, int32_t* info,
+                        void* ws, size_t ws_bytes, void* stream) {
     if (!p || batch < 1 || !values || !B || !X || !info || !ws) return fail(PSP_E_INVALID, "psp_solve_batched: NULL argument or batch < 1");
     if (nrhs < 1 || nrhs > 64) return fail(PSP_E_INVALID, "psp_solve_batched: nrhs must be in 1..64");
     EpsSet es;
@@ -361,7 +492,8 @@ psp_status psp_solve_batched(psp_plan p, int32_t path, int32_t batch, const doub
     if (psp_status st = check_prior_hip()) return st;
     const Symbolic& s = p->sym;
     const hipStream_t st = (hipStream_t)stream;
-    const PathSel ps = split_path(resolve_path(p, path, batch, K, nrhs));
+    const PathSel ps = split_path(ch.path);
+    const Knobs kn = knobs_of(ch);
     if (ps.base == PSP_PATH_DENSE) {
         if (s.n > kDenseMaxN) return fail(PSP_E_UNSUPPORTED, "dense path supports n <= 4096");
         const DenseLayout L = dense_layout(s, batch, K, nrhs, 0);
@@ -393,10 +525,42 @@ psp_status psp_solve_batched(psp_plan p, int32_t path, int32_t batch, const doub
         if (psp_status r = require_upload(p)) return r;
         if (ps.forced == kVarSteps && !steps_ready(p->sp))
             return fail(PSP_E_UNSUPPORTED, "this sparse execution cannot run the plan (step schedule does not fit in LDS)");
-        HIP_TRY(sparse_solve_batched(s, p->sp, batch, values, es, d, nrhs, B, X, info, ws, st, ps.forced), "sparse launch");
+        HIP_TRY(sparse_solve_batched(s, p->sp, batch, values, es, d, nrhs, B, X, info, ws, st, ps.forced, kn),
+                "sparse launch");
         return PSP_OK;
     }
     return fail(PSP_E_INVALID, "unknown path");
+}
+
+}  // namespace
+
+extern "C" {
+
+psp_status psp_solve_batched(psp_plan p, int32_t path, int32_t batch, const double* values, int32_t K,
+                             const double* eps, const double* d, int32_t nrhs, const double* B, double* X,
+                             int32_t* info, void* ws, size_t ws_bytes, void* stream) {
+    if (!p) return fail(PSP_E_INVALID, "psp_solve_batched: NULL plan");
+    return solve_choice(p, resolve_choice(p, path, batch, K, nrhs), batch, values, K, eps, d, nrhs, B, X, info, ws,
+                        ws_bytes, stream);
+}
+
+psp_status psp_tune_choice(psp_plan p, int32_t batch, int32_t K, int32_t nrhs, psp_tune_choice_t* out) {
+    if (!p || !out) return fail(PSP_E_INVALID, "psp_tune_choice: NULL argument");
+    *out = resolve_choice(p, PSP_PATH_AUTO, batch, K, nrhs);
+    return PSP_OK;
+}
+
+psp_status psp_set_tune_choice(psp_plan p, int32_t batch, int32_t K, int32_t nrhs, const psp_tune_choice_t* c) {
+    if (!p || !c) return fail(PSP_E_INVALID, "psp_set_tune_choice: NULL argument");
+    if (split_path(c->path).base < 0) return fail(PSP_E_INVALID, "psp_set_tune_choice: unknown path");
+    if (c->steps_mode < -1 || c->steps_mode > 1 || c->steps_wgcu < 0 || c->steps_wgcu > 1 ||
+        (c->ring != 7 && c->ring != 4) || (c->tail_cols != 4 && c->tail_cols != 1))
+        return fail(PSP_E_INVALID, "psp_set_tune_choice: a launch choice is out of range");
+    psp_tune_choice_t v = *c;
+    v.source = 1;
+    std::lock_guard<std::mutex> g(p->mu);
+    p->tuned[std::make_tuple(batch, K, nrhs)] = v;
+    return PSP_OK;
 }
 
 psp_status psp_solve_batched_noalloc(psp_plan p, int32_t batch, const double* values, int32_t K, const double* eps,
@@ -497,38 +661,69 @@ psp_status psp_tune(psp_plan p, int32_t batch, const double* values, int32_t K, 
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
     HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
-    int32_t best = -1;
-    float best_ms = 0.0f;
+    psp_tune_choice_t best{};
+    bool have = false;
     psp_status last = PSP_OK;
-    for (int32_t c = PSP_PATH_DENSE; c <= PSP_PATH_SPARSE_TAIL; ++c) {
+    for (int32_t c = PSP_PATH_DENSE; c <= PSP_PATH_SPARSE_TAIL && last == PSP_OK; ++c) {
         if (c == PSP_PATH_SPARSE) continue;   // its executions are tried one by one
         if (path_workspace(p->sym, c, batch, K, nrhs, 0) > ws_bytes) continue;
-        psp_status r = psp_solve_batched(p, c, batch, values, K, eps, d, nrhs, B, X, info, ws, ws_bytes, stream);
-        if (r == PSP_E_UNSUPPORTED) continue;
-        if (r != PSP_OK) { last = r; break; }
-        HIP_TRY(hipEventRecord(e0, st), "hipEventRecord");
-        for (int rep = 0; rep < 3 && r == PSP_OK; ++rep)
-            r = psp_solve_batched(p, c, batch, values, K, eps, d, nrhs, B, X, info, ws, ws_bytes, stream);
-        if (r != PSP_OK) { last = r; break; }
-        HIP_TRY(hipEventRecord(e1, st), "hipEventRecord");
-        HIP_TRY(hipEventSynchronize(e1), "hipEventSynchronize");
-        float t = 0.0f;
-        HIP_TRY(hipEventElapsedTime(&t, e0, e1), "hipEventElapsedTime");
-        t /= 3.0f;
-        if (ms) ms[c] = t;
-        if (best < 0 || t < best_ms) { best = c; best_ms = t; }
+        // the launch choices searched on this path
+        std::vector<psp_tune_choice_t> cand;
+        const psp_tune_choice_t base = default_choice(c);
+        if (c == PSP_PATH_SPARSE_STEPS) {
+            const bool two = steps_ready(p->sp) && steps_per_cu(p->sp) == 2;
+            for (int mode = 0; mode <= 1; ++mode)
+                for (int wgcu = 0; wgcu <= (two ? 1 : 0); ++wgcu)
+                    for (int ring : {7, 4}) {
+                        psp_tune_choice_t v = base;
+                        v.steps_mode = mode;
+                        v.steps_wgcu = wgcu;
+                        v.ring = ring;
+                        cand.push_back(v);
+                    }
+        } else if (c == PSP_PATH_SPARSE_TAIL) {
+            for (int cols : {4, 1}) {
+                psp_tune_choice_t v = base;
+                v.tail_cols = cols;
+                cand.push_back(v);
+            }
+        } else {
+            cand.push_back(base);
+        }
+        for (const psp_tune_choice_t& v : cand) {
+            psp_status r = solve_choice(p, v, batch, values, K, eps, d, nrhs, B, X, info, ws, ws_bytes, stream);
+            if (r == PSP_E_UNSUPPORTED) break;
+            if (r != PSP_OK) { last = r; break; }
+            HIP_TRY(hipEventRecord(e0, st), "hipEventRecord");
+            for (int rep = 0; rep < 3 && r == PSP_OK; ++rep)
+                r = solve_choice(p, v, batch, values, K, eps, d, nrhs, B, X, info, ws, ws_bytes, stream);
+            if (r != PSP_OK) { last = r; break; }
+            HIP_TRY(hipEventRecord(e1, st), "hipEventRecord");
+            HIP_TRY(hipEventSynchronize(e1), "hipEventSynchronize");
+            float t = 0.0f;
+            HIP_TRY(hipEventElapsedTime(&t, e0, e1), "hipEventElapsedTime");
+            t /= 3.0f;
+            if (ms && (ms[c] < 0.0f || t < ms[c])) ms[c] = t;
+            if (!have || t < best.ms) {
+                best = v;
+                best.ms = t;
+                have = true;
+            }
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (last != PSP_OK) return last;
-    if (best < 0) return fail(PSP_E_UNSUPPORTED, "psp_tune: no path fits the workspace");
+    if (!have) return fail(PSP_E_UNSUPPORTED, "psp_tune: no path fits the workspace");
+    best.source = 1;
     {
         std::lock_guard<std::mutex> g(p->mu);
         p->tuned[std::make_tuple(batch, K, nrhs)] = best;
     }
-    if (chosen) *chosen = best;
+    cache_store(cache_key(p, batch, K, nrhs), best);
+    if (chosen) *chosen = best.path;
     // leave X / info from the chosen path
-    return psp_solve_batched(p, best, batch, values, K, eps, d, nrhs, B, X, info, ws, ws_bytes, stream);
+    return solve_choice(p, best, batch, values, K, eps, d, nrhs, B, X, info, ws, ws_bytes, stream);
 }
 
 psp_status psp_factor(psp_plan p, int32_t path, int32_t batch, const double* values, int32_t K, const double* eps,
@@ -958,6 +1153,7 @@ psp_status psp_pf_newton(psp_pf pf, int32_t path, int32_t batch, int32_t K, cons
 // ---------------------------------------------------------------- groups
 struct psp_group_s {
     std::vector<psp_group_shape_t> items;   // path resolved at creation
+    std::vector<psp_tune_choice_t> choice;  // with its launch choices
     std::vector<size_t> ws_off, ws_len;     // each item's slice of the workspace
     std::vector<int32_t> order, lane;       // LPT order; stream lane of each item (0: the caller's)
     size_t ws_total = 0;
@@ -1001,8 +1197,8 @@ psp_status group_enqueue(psp_group g, const psp_group_task_t* tasks, char* ws, h
         const psp_group_shape_t& it = g->items[i];
         const psp_group_task_t& t = tasks[i];
         const hipStream_t ls = g->lane[i] == 0 ? st : g->streams[g->lane[i]];
-        bad = psp_solve_batched(it.plan, it.path, it.batch, t.values, g->K, g->eps.data(), t.d, g->nrhs, t.B, t.X,
-                                t.info, ws + g->ws_off[i], g->ws_len[i], (void*)ls);
+        bad = solve_choice(it.plan, g->choice[i], it.batch, t.values, g->K, g->eps.data(), t.d, g->nrhs, t.B, t.X,
+                           t.info, ws + g->ws_off[i], g->ws_len[i], (void*)ls);
         if (bad != PSP_OK) {
             g_err = "group item " + std::to_string(i) + ": " + g_err;
             break;
@@ -1055,8 +1251,10 @@ psp_status psp_group_create(int32_t nitems, const psp_group_shape_t* shapes, int
     for (int32_t i = 0; i < nitems; ++i) {
         psp_group_shape_t it = shapes[i];
         if (psp_status r = require_upload(it.plan)) return fail(r, "psp_group_create: item " + std::to_string(i) + ": " + g_err);
-        it.path = resolve_path(it.plan, it.path, it.batch, K, nrhs);
+        const psp_tune_choice_t ch = resolve_choice(it.plan, it.path, it.batch, K, nrhs);
+        it.path = ch.path;
         if (split_path(it.path).base < 0) return fail(PSP_E_INVALID, "psp_group_create: unknown path");
+        g->choice.push_back(ch);
         const size_t w = psp_workspace_bytes(it.plan, it.path, it.batch, K, nrhs, 0);
         if (w == 0) return fail(PSP_E_INVALID, "psp_group_create: item " + std::to_string(i) + " cannot run on its path");
         g->items.push_back(it);

@@ -74,6 +74,14 @@ struct SparseDevice {
 };
 
 enum { kVarLds = 0, kVarGlobal = 1, kVarBatched = 2, kVarGrouped = 3, kVarSteps = 4, kVarTail = 5 };
+
+// Launch choices the autotuner searches (psp_tune); the defaults are the heuristics.
+struct Knobs {
+    int32_t steps_mode = -1;   // step kernel: -1 by batch size, 0 one workgroup per system, 1 per Jacobian
+    int32_t steps_wgcu = 0;    // step kernel: 0 as many workgroups per CU as LDS allows, 1 one per CU
+    int32_t ring = 7;          // step kernel: descriptors in flight (7 or 4)
+    int32_t tail_cols = 4;     // dense-block assembly: block columns per workgroup (4 or 1)
+};
 int sparse_variant(const Symbolic& s, int64_t ntasks, int32_t nrhs, int forced);
 
 // Appends the sparse path's arrays (and the step schedule, when it fits) to the
@@ -92,7 +100,7 @@ int steps_per_cu(const SparseDevice& d);   // step-kernel workgroups resident pe
 int64_t steps_lds_bytes(const SparseDevice& d);   // dynamic LDS of one step-kernel workgroup (0: no schedule)
 hipError_t steps_run(const SparseDevice& d, int32_t nnz, int32_t batch, const double* values, const EpsSet& es,
                      const double* dvec, const double* B, double* X, double* Xk, int32_t* info, bool per_jacobian,
-                     hipStream_t st, bool xk_too = false);
+                     hipStream_t st, bool xk_too = false, const Knobs& kn = Knobs());
 // Per-system launch over the Jacobians list[0 .. *count-1] (device count, at most batch) with the
 // nodes scale[s] eps_k (scale: powers of two); writes Xk[s][k] and info[s*K + k] of those only.
 hipError_t steps_run_list(const SparseDevice& d, int32_t nnz, int32_t batch, const double* values, const EpsSet& es,
@@ -104,7 +112,7 @@ bool steps_per_jacobian(const SparseDevice& d, int32_t batch);
 // (Xk: batch x K x n doubles of device memory, unused in per-Jacobian mode).
 hipError_t steps_solve(const SparseDevice& d, int32_t n, int32_t nnz, int32_t batch, const double* values,
                        const EpsSet& es, const double* dvec, const double* B, double* X, int32_t* info, double* Xk,
-                       hipStream_t st);
+                       hipStream_t st, const Knobs& kn = Knobs());
 // The library's static device scratch (noalloc.hip): its size, and the current device's address.
 size_t noalloc_scratch_bytes();
 hipError_t noalloc_scratch(void** out);
@@ -113,7 +121,7 @@ size_t sparse_workspace_bytes(const Symbolic& s, int32_t batch, int32_t K, int32
 int32_t sparse_nrhs_capacity(const Symbolic& s, int32_t batch, int32_t K, size_t ws_bytes);
 hipError_t sparse_solve_batched(const Symbolic& s, const SparseDevice& d, int32_t batch, const double* values,
                                 const EpsSet& es, const double* dvec, int32_t nrhs, const double* B, double* X,
-                                int32_t* info, void* ws, hipStream_t st, int forced = -1);
+                                int32_t* info, void* ws, hipStream_t st, int forced = -1, const Knobs& kn = Knobs());
 hipError_t sparse_factor(const Symbolic& s, const SparseDevice& d, int32_t batch, const double* values,
                          const EpsSet& es, const double* dvec, int32_t* info, void* ws, hipStream_t st);
 hipError_t sparse_solve(const Symbolic& s, const SparseDevice& d, int32_t batch, const EpsSet& es, int32_t nrhs,

@@ -577,7 +577,7 @@ __device__ void assemble_column(const SpIdx& ix, double* ud, int j, const AsmLds
     __syncthreads();
 }
 
-__global__ __launch_bounds__(kAsmThreads) void tail_assemble_kernel(SpArgs a) {
+__global__ __launch_bounds__(kAsmThreads) void tail_assemble_kernel(SpArgs a, int cols) {
     extern __shared__ __align__(16) double smem[];
     __shared__ int s_cnt;
     const AsmLds L = asm_lds(smem);
@@ -585,21 +585,21 @@ __global__ __launch_bounds__(kAsmThreads) void tail_assemble_kernel(SpArgs a) {
     const int n = ix.n, nl = ix.nnzl, b0 = ix.tail_b0, nt = ix.tail_n, ld = ix.tail_ld, tid = threadIdx.x;
     const int last = n - 1;
     const int32_t* lpos = ix.tail_lastpos;
-    const int ntile = ld / kAsmCols;
+    const int ntile = ld / cols;
     const int64_t total = (int64_t)ntile * a.ntasks;
     constexpr int UN = kAsmUnroll;
     for (int64_t wg = blockIdx.x; wg < total; wg += gridDim.x) {
-        const int task = (int)(wg / ntile), j0 = (int)(wg % ntile) * kAsmCols;
+        const int task = (int)(wg / ntile), j0 = (int)(wg % ntile) * cols;
         double* ud = a.fac + (int64_t)task * a.fstride;
         int lens = 0;
         bool has_last = false;
-        for (int c = 0; c < kAsmCols; ++c)
+        for (int c = 0; c < cols; ++c)
             if (j0 + c < nt) {
                 lens += ix.tail_rcnt[j0 + c];
                 has_last |= b0 + j0 + c == last;
             }
-        if (has_last || lens > kAsmUnion) {
-            for (int c = 0; c < kAsmCols; ++c) assemble_column(ix, ud, j0 + c, L);
+        if (cols != kAsmCols || has_last || lens > kAsmUnion) {
+            for (int c = 0; c < cols; ++c) assemble_column(ix, ud, j0 + c, L);
             continue;
         }
         const double* lv = ud + n;
@@ -1294,7 +1294,7 @@ hipError_t factor_global(const SparseDevice& d, SpArgs a, const EpsSet& es, hipS
     return hipGetLastError();
 }
 
-hipError_t factor_tail(const SparseDevice& d, SpArgs a, const EpsSet& es, hipStream_t st) {
+hipError_t factor_tail(const SparseDevice& d, SpArgs a, const EpsSet& es, hipStream_t st, int cols = kAsmCols) {
     hipLaunchKernelGGL(sp_gather_kernel, dim3(grid_for((int64_t)(a.ix.n + a.ix.nnzl) * a.ntasks, kThreads)),
                        dim3(kThreads), 0, st, a, es);
     for (int l = 0; l < a.ix.fac_lev_sp; ++l) {
@@ -1307,8 +1307,9 @@ hipError_t factor_tail(const SparseDevice& d, SpArgs a, const EpsSet& es, hipStr
                                0, st, a, p0, np);
     }
     const int ld = a.ix.tail_ld;
-    hipLaunchKernelGGL(tail_assemble_kernel, dim3((int)std::min<int64_t>((int64_t)(ld / kAsmCols) * a.ntasks, 1 << 20)),
-                       dim3(kAsmThreads), (int)tail_asm_lds(a.ix.tail_b0), st, a);
+    cols = cols == 1 ? 1 : kAsmCols;
+    hipLaunchKernelGGL(tail_assemble_kernel, dim3((int)std::min<int64_t>((int64_t)(ld / cols) * a.ntasks, 1 << 20)),
+                       dim3(kAsmThreads), (int)tail_asm_lds(a.ix.tail_b0), st, a, cols);
     for (int p0 = 0; p0 < ld; p0 += NB) {
         hipLaunchKernelGGL(tail_panel_kernel, dim3(std::min(a.ntasks, 65535)), dim3(WG), 0, st, a, p0);
         const int rem = ld - p0 - NB;
@@ -1545,7 +1546,7 @@ int32_t sparse_nrhs_capacity(const Symbolic& s, int32_t batch, int32_t K, size_t
 
 hipError_t sparse_solve_batched(const Symbolic& s, const SparseDevice& d, int32_t batch, const double* values,
                                 const EpsSet& es, const double* dvec, int32_t nrhs, const double* B, double* X,
-                                int32_t* info, void* ws, hipStream_t st, int forced) {
+                                int32_t* info, void* ws, hipStream_t st, int forced, const Knobs& kn) {
     const int32_t ntasks = batch * es.K;
     const SpLayout L = sp_layout(s, batch, es.K, nrhs, 0, forced);
     char* w = (char*)ws;
@@ -1564,7 +1565,7 @@ hipError_t sparse_solve_batched(const Symbolic& s, const SparseDevice& d, int32_
     if (var == kVarBatched || var == kVarGrouped)
         return batched_run(s, d, batch, values, es, dvec, nrhs, B, X, info, w, L, st, var == kVarGrouped);
     if (var == kVarSteps) {
-        return steps_solve(d, s.n, s.nnz, batch, values, es, dvec, B, X, info, a.Xk, st);
+        return steps_solve(d, s.n, s.nnz, batch, values, es, dvec, B, X, info, a.Xk, st, kn);
     }
     if (var == kVarLds) {
         const int lds = (int)lds_bytes(s, nrhs);
@@ -1586,7 +1587,7 @@ hipError_t sparse_solve_batched(const Symbolic& s, const SparseDevice& d, int32_
         a.fac = (double*)(w + L.off_fac);
         a.y = (double*)(w + L.off_y);
         const bool tail = var == kVarTail;
-        hipError_t e = tail ? factor_tail(d, a, es, st) : factor_global(d, a, es, st);
+        hipError_t e = tail ? factor_tail(d, a, es, st, kn.tail_cols) : factor_global(d, a, es, st);
         if (e != hipSuccess) return e;
         e = tail ? solve_tail(d, a, st) : solve_global(d, a, st);
         if (e != hipSuccess) return e;

@@ -67,6 +67,7 @@ namespace psp {
 namespace {
 constexpr int kStThreads = 1024;         // workgroup size; the schedule is built for it (one task per thread and step)
 constexpr int kStAhead = 7;              // steps whose descriptors are in flight
+constexpr int kStRingShort = 4;          // the shallower ring the tuner may choose
 // Longest run of one chain inside a step, so that every task's updates fit in
 // its descriptor (no second, dependent load).  The long runs belong mostly to
 // the dense slack row, whose value is needed only at the end; at n = 601 the
@@ -383,7 +384,9 @@ __device__ __forceinline__ int4 st_desc(__amdgpu_buffer_rsrc_t r, int2 m, int ti
 
 // waves_per_eu(8): registers for eight waves per SIMD, i.e. two 1024-lane workgroups per CU
 // (without it the kernel takes 112 scalar registers per wave, which leaves room for seven)
-template <int T, bool PACKED, bool LIST>
+// RING: steps whose descriptors are in flight (kStAhead, or a shallower ring that the tuner may pick);
+// the metadata LDS is sized for kStAhead, which covers every shallower ring.
+template <int T, bool PACKED, bool LIST, int RING>
 __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(8))) void steps_kernel(StArgs a, EpsSet es) {
     // 16-byte aligned: the step metadata after the values is read as int4
     // (a misaligned ds_read_b128 every step costs several times the step)
@@ -398,11 +401,11 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(8))) void ste
     double* y = v + ybase;
     double* cx = y + n;
     const int S = a.sx.nsteps;
-    const int Sp = st_padded(S);
+    const int Sp = (S + RING - 1) / RING * RING;
     // per-step metadata, read by every step of every system: kept in LDS,
     // followed by empty steps up to a multiple of the ring depth and one ring beyond
     int2* sm = reinterpret_cast<int2*>(v + ((3 * n + a.sx.pool + 1) & ~1));
-    for (int i = tid; i < Sp + kStAhead + 1; i += T) {
+    for (int i = tid; i < Sp + RING + 1; i += T) {
         const int4 mi = i < S ? a.sx.meta[i] : make_int4(0, 0, 1, 0);
         sm[i] = make_int2(mi.x, mi.y);
     }
@@ -422,11 +425,11 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(8))) void ste
         const int k0 = a.per_jacobian ? 0 : job % es.K, k1 = a.per_jacobian ? es.K : k0 + 1;
         const double* vals = a.values + (int64_t)s * a.nnz;
         for (int kk = k0; kk < k1; ++kk) {
-            // descriptor ring: step st runs while steps st+1 .. st+kStAhead-1 are in
+            // descriptor ring: step st runs while steps st+1 .. st+RING-1 are in
             // flight; each step waits for its own load only.
-            int4 ring[kStAhead];
+            int4 ring[RING];
 #pragma unroll
-            for (int d = 0; d < kStAhead; ++d) {
+            for (int d = 0; d < RING; ++d) {
                 ring[d] = st_desc(drs, sm[d], tid);
             }
             int2 m = sm[0];
@@ -457,14 +460,14 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(8))) void ste
             // conditional here makes the compiler copy in-flight registers,
             // which waits for the loads.  Each slot is reloaded after its task
             // ran, so old and new descriptors share registers.
-            for (int st0 = 0; st0 < Sp; st0 += kStAhead) {
+            for (int st0 = 0; st0 < Sp; st0 += RING) {
 #pragma unroll
-                for (int d = 0; d < kStAhead; ++d) {
+                for (int d = 0; d < RING; ++d) {
                     const int st = st0 + d;
                     if (tid < m.y) st_exec<PACKED>(v, ring[d]);
                     // the next steps' metadata after the task: its latency overlaps the barrier
                     const int2 m1 = sm[st + 1];
-                    const int2 ma = sm[st + kStAhead];
+                    const int2 ma = sm[st + RING];
                     ring[d] = st_desc(drs, ma, tid);
                     __syncthreads();
                     m = m1;
@@ -547,10 +550,12 @@ int steps_per_cu(const SparseDevice& d) {
 // the compiled static LDS stays within the headroom the schedule sizes assume.
 hipError_t steps_kernel_attrs() {
     static hipError_t e = [] {
-        const void* ks[4] = {(const void*)steps_kernel<kStThreads, true, false>,
-                             (const void*)steps_kernel<kStThreads, false, false>,
-                             (const void*)steps_kernel<kStThreads, true, true>,
-                             (const void*)steps_kernel<kStThreads, false, true>};
+        const void* ks[6] = {(const void*)steps_kernel<kStThreads, true, false, kStAhead>,
+                             (const void*)steps_kernel<kStThreads, false, false, kStAhead>,
+                             (const void*)steps_kernel<kStThreads, true, false, kStRingShort>,
+                             (const void*)steps_kernel<kStThreads, false, false, kStRingShort>,
+                             (const void*)steps_kernel<kStThreads, true, true, kStAhead>,
+                             (const void*)steps_kernel<kStThreads, false, true, kStAhead>};
         for (const void* k : ks) {
             hipFuncAttributes fa{};
             hipError_t r = hipFuncGetAttributes(&fa, k);
@@ -566,7 +571,7 @@ hipError_t steps_kernel_attrs() {
 
 hipError_t steps_run(const SparseDevice& d, int32_t nnz, int32_t batch, const double* values, const EpsSet& es,
                      const double* dvec, const double* B, double* X, double* Xk, int32_t* info, bool per_jacobian,
-                     hipStream_t st, bool xk_too) {
+                     hipStream_t st, bool xk_too, const Knobs& kn) {
     if (!steps_ready(d) || d.st.threads != kStThreads) return hipErrorInvalidValue;
     StArgs a{};
     a.xk_too = per_jacobian && xk_too ? 1 : 0;
@@ -580,13 +585,18 @@ hipError_t steps_run(const SparseDevice& d, int32_t nnz, int32_t batch, const do
     int dev = 0, cus = 256;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    const int resident = cus * steps_per_cu(d);
+    const int resident = cus * (kn.steps_wgcu == 1 ? 1 : steps_per_cu(d));
     const int64_t jobs = per_jacobian ? batch : (int64_t)batch * es.K;
     const int grid = (int)std::min<int64_t>(jobs, resident);
-    if (d.st.packed)
-        hipLaunchKernelGGL((steps_kernel<kStThreads, true, false>), dim3(grid), dim3(kStThreads), lds, st, a, es);
+    const bool shortr = kn.ring == kStRingShort;
+    if (d.st.packed && shortr)
+        hipLaunchKernelGGL((steps_kernel<kStThreads, true, false, kStRingShort>), dim3(grid), dim3(kStThreads), lds, st, a, es);
+    else if (d.st.packed)
+        hipLaunchKernelGGL((steps_kernel<kStThreads, true, false, kStAhead>), dim3(grid), dim3(kStThreads), lds, st, a, es);
+    else if (shortr)
+        hipLaunchKernelGGL((steps_kernel<kStThreads, false, false, kStRingShort>), dim3(grid), dim3(kStThreads), lds, st, a, es);
     else
-        hipLaunchKernelGGL((steps_kernel<kStThreads, false, false>), dim3(grid), dim3(kStThreads), lds, st, a, es);
+        hipLaunchKernelGGL((steps_kernel<kStThreads, false, false, kStAhead>), dim3(grid), dim3(kStThreads), lds, st, a, es);
     return hipGetLastError();
 }
 
@@ -609,9 +619,9 @@ hipError_t steps_run_list(const SparseDevice& d, int32_t nnz, int32_t batch, con
     // the job count is on the device: every resident slot, idle ones leave at once
     const int grid = (int)std::min<int64_t>((int64_t)batch * es.K, (int64_t)cus * steps_per_cu(d));
     if (d.st.packed)
-        hipLaunchKernelGGL((steps_kernel<kStThreads, true, true>), dim3(grid), dim3(kStThreads), lds, st, a, es);
+        hipLaunchKernelGGL((steps_kernel<kStThreads, true, true, kStAhead>), dim3(grid), dim3(kStThreads), lds, st, a, es);
     else
-        hipLaunchKernelGGL((steps_kernel<kStThreads, false, true>), dim3(grid), dim3(kStThreads), lds, st, a, es);
+        hipLaunchKernelGGL((steps_kernel<kStThreads, false, true, kStAhead>), dim3(grid), dim3(kStThreads), lds, st, a, es);
     return hipGetLastError();
 }
 
@@ -624,12 +634,12 @@ bool steps_per_jacobian(const SparseDevice& d, int32_t batch) {
 
 hipError_t steps_solve(const SparseDevice& d, int32_t n, int32_t nnz, int32_t batch, const double* values,
                        const EpsSet& es, const double* dvec, const double* B, double* X, int32_t* info, double* Xk,
-                       hipStream_t st) {
+                       hipStream_t st, const Knobs& kn) {
     if (!steps_ready(d)) return hipErrorInvalidValue;
     // enough Jacobians to fill every resident workgroup slot: one workgroup per Jacobian,
     // combine fused; fewer: one workgroup per perturbed system and a combine launch
-    const bool per_jacobian = steps_per_jacobian(d, batch);
-    hipError_t e = steps_run(d, nnz, batch, values, es, dvec, B, X, Xk, info, per_jacobian, st);
+    const bool per_jacobian = kn.steps_mode < 0 ? steps_per_jacobian(d, batch) : kn.steps_mode == 1;
+    hipError_t e = steps_run(d, nnz, batch, values, es, dvec, B, X, Xk, info, per_jacobian, st, false, kn);
     if (e != hipSuccess || per_jacobian) return e;
     return launch_combine((int64_t)n, batch, es, Xk, X, st);
 }

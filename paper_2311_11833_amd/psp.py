@@ -25,7 +25,7 @@ ORDERS = {"md": 0, "natural": 1}
 EXPORTED = ["psp_last_error", "psp_version", "psp_plan_create", "psp_plan_info", "psp_plan_export",
             "psp_plan_destroy", "psp_plan_device_bytes", "psp_plan_upload", "psp_weights", "psp_workspace_bytes",
             "psp_solve_batched", "psp_solve_batched_noalloc", "psp_solve_adaptive_workspace_bytes",
-            "psp_solve_adaptive", "psp_tune", "psp_factor", "psp_solve", "psp_combine", "psp_grad_values",
+            "psp_solve_adaptive", "psp_tune", "psp_tune_choice", "psp_set_tune_choice", "psp_factor", "psp_solve", "psp_combine", "psp_grad_values",
             "psp_factors_release", "psp_residual", "psp_group_create", "psp_group_workspace_bytes", "psp_group_run",
             "psp_group_capture", "psp_graph_launch", "psp_graph_destroy", "psp_group_destroy", "psp_pf_device_bytes",
             "psp_pf_create", "psp_pf_destroy", "psp_pf_eval", "psp_pf_workspace_bytes", "psp_pf_newton",
@@ -45,6 +45,16 @@ class PlanInfo(C.Structure):
                 ("steps", C.c_int32), ("steps_packed", C.c_int32), ("steps_lds_bytes", C.c_int64),
                 ("steps_per_cu", C.c_int32), ("device_bytes", C.c_int64), ("tail_n", C.c_int32),
                 ("tail_fac_levels", C.c_int32)]
+
+
+class TuneChoice(C.Structure):
+    _fields_ = [("path", C.c_int32), ("steps_mode", C.c_int32), ("steps_wgcu", C.c_int32), ("ring", C.c_int32),
+                ("tail_cols", C.c_int32), ("ms", C.c_float), ("source", C.c_int32)]
+
+    def as_dict(self):
+        return {"path": PATH_NAMES.get(self.path, self.path), "steps_mode": self.steps_mode,
+                "steps_wgcu": self.steps_wgcu, "ring": self.ring, "tail_cols": self.tail_cols,
+                "ms": float(self.ms), "source": {0: "heuristic", 1: "tuned", 2: "cache file"}[self.source]}
 
 
 class GroupShape(C.Structure):
@@ -84,6 +94,8 @@ def lib():
         L.psp_solve_adaptive_workspace_bytes.argtypes = [vp, i32, i32]
         L.psp_solve_adaptive_workspace_bytes.restype = C.c_size_t
         L.psp_solve_adaptive.argtypes = [vp, i32, vp, i32, vp, vp, d, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]
+        L.psp_tune_choice.argtypes = [vp, i32, i32, i32, C.POINTER(TuneChoice)]
+        L.psp_set_tune_choice.argtypes = [vp, i32, i32, i32, C.POINTER(TuneChoice)]
         L.psp_tune.argtypes = [vp, i32, vp, i32, vp, vp, i32, vp, vp, vp, vp, C.c_size_t, vp, vp, vp]
         L.psp_factor.argtypes = [vp, i32, i32, vp, i32, vp, vp, vp, vp, C.c_size_t, vp, C.POINTER(vp)]
         L.psp_solve.argtypes = [vp, i32, vp, vp, i32, vp]
@@ -441,6 +453,20 @@ def tune(plan: Plan, values, eps, b, d=None, stream=None):
                           _dptr(x), _dptr(info), _dptr(ws), ws.numel(), _stream(stream), C.byref(chosen), ms))
     times = {PATH_NAMES[i]: float(ms[i]) for i in range(1, len(PATHS)) if ms[i] >= 0}
     return PATH_NAMES[chosen.value], times
+
+
+def tune_choice(plan: Plan, batch: int, K: int, nrhs: int = 1) -> dict:
+    """The path and launch choices PSP_PATH_AUTO uses for (batch, K, nrhs), and where they come from."""
+    c = TuneChoice()
+    _check(lib().psp_tune_choice(plan.handle, batch, K, nrhs, C.byref(c)))
+    return c.as_dict()
+
+
+def set_tune_choice(plan: Plan, batch: int, K: int, nrhs: int = 1, path: str = "sparse_steps", steps_mode: int = -1,
+                    steps_wgcu: int = 0, ring: int = 7, tail_cols: int = 4) -> None:
+    """Pins the path and launch choices of PSP_PATH_AUTO for (batch, K, nrhs)."""
+    c = TuneChoice(PATHS[path], steps_mode, steps_wgcu, ring, tail_cols, -1.0, 1)
+    _check(lib().psp_set_tune_choice(plan.handle, batch, K, nrhs, C.byref(c)))
 
 
 class Factors:
