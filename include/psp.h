@@ -102,6 +102,8 @@ typedef struct {
     int64_t device_bytes;      /* psp_plan_device_bytes                              */
     int32_t tail_n;            /* columns of the dense trailing block (0: none)      */
     int32_t tail_fac_levels;   /* factor levels below it                             */
+    int32_t tail_tiles;        /* 16-row tiles of its assembly on the MFMA unit (0: none) */
+    int64_t tail_mfma;         /* 16x16x4 FP64 MFMA steps of one system's assembly  */
 } psp_plan_info_t;
 
 PSP_API psp_status psp_plan_info(psp_plan plan, psp_plan_info_t* out);
@@ -346,8 +348,9 @@ PSP_API psp_status psp_tune(psp_plan plan, int32_t batch, const double* values, 
  *   steps_wgcu  step schedule: 0 as many workgroups per CU as LDS allows,
  *               1 one per CU;
  *   ring        step schedule: descriptors in flight, 7 or 4;
- *   tail_cols   dense trailing block: block columns assembled per
- *               workgroup, 4 or 1;
+ *   tail_cols   dense trailing block assembly: 16 by 16 x 16 tile pairs on
+ *               the MFMA unit (where every tile's column union is below
+ *               65535), else 4 or 1 block columns per workgroup;
  *   ms          measured time per call (-1 when set by hand);
  *   source      0 none (the size heuristic applies), 1 tuned or set in this
  *               process, 2 read from the tuning cache file.

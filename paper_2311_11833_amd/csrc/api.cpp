@@ -408,6 +408,8 @@ psp_status psp_plan_info(psp_plan p, psp_plan_info_t* o) {
     o->device_bytes = (int64_t)std::max<size_t>(p->img.bytes(), 256);
     o->tail_n = s.tail_n;
     o->tail_fac_levels = s.tail_n ? s.fac_lev_sp : 0;
+    o->tail_tiles = p->sp.idx.tail_tiles;
+    o->tail_mfma = p->sp.h_tail_pairs / 4;
     return PSP_OK;
 }
 
@@ -554,7 +556,7 @@ psp_status psp_set_tune_choice(psp_plan p, int32_t batch, int32_t K, int32_t nrh
     if (!p || !c) return fail(PSP_E_INVALID, "psp_set_tune_choice: NULL argument");
     if (split_path(c->path).base < 0) return fail(PSP_E_INVALID, "psp_set_tune_choice: unknown path");
     if (c->steps_mode < -1 || c->steps_mode > 1 || c->steps_wgcu < 0 || c->steps_wgcu > 1 ||
-        (c->ring != 7 && c->ring != 4) || (c->tail_cols != 4 && c->tail_cols != 1))
+        (c->ring != 7 && c->ring != 4) || (c->tail_cols != 16 && c->tail_cols != 4 && c->tail_cols != 1))
         return fail(PSP_E_INVALID, "psp_set_tune_choice: a launch choice is out of range");
     psp_tune_choice_t v = *c;
     v.source = 1;
@@ -682,7 +684,7 @@ psp_status psp_tune(psp_plan p, int32_t batch, const double* values, int32_t K, 
                         cand.push_back(v);
                     }
         } else if (c == PSP_PATH_SPARSE_TAIL) {
-            for (int cols : {4, 1}) {
+            for (int cols : {16, 4, 1}) {
                 psp_tune_choice_t v = base;
                 v.tail_cols = cols;
                 cand.push_back(v);

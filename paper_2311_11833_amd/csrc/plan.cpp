@@ -256,6 +256,98 @@ void analyse(int32_t n, const int32_t* rp, const int32_t* ci, bool natural, Symb
                 lv[i] = m;
             }
             levels_from(lv, b0, s.lev_sp_ptr[1], s.lev_sp_idx[1]);
+            // tiles of 16 block rows for the assembly on the MFMA unit (see plan.h): rows placed
+            // greedily so that a tile's rows share their columns below b0
+            const int32_t tiles = (t + 15) / 16;
+            std::vector<int32_t> rp(t + 1, 0), inv_ptr(b0 + 1, 0), inv;
+            for (int32_t r = 0; r < t; ++r) {
+                int32_t q = s.lrow_ptr[b0 + r];
+                while (q < s.lrow_ptr[b0 + r + 1] && s.lrow_idx[q] < b0) ++inv_ptr[s.lrow_idx[q++] + 1];
+                rp[r + 1] = q - s.lrow_ptr[b0 + r];
+            }
+            for (int32_t r = 0; r < t; ++r) rp[r + 1] += rp[r];
+            for (int32_t k = 0; k < b0; ++k) inv_ptr[k + 1] += inv_ptr[k];
+            inv.resize(inv_ptr[b0]);
+            {
+                std::vector<int32_t> fill(inv_ptr.begin(), inv_ptr.end() - 1);
+                for (int32_t r = 0; r < t; ++r)
+                    for (int32_t q = 0; q < rp[r + 1] - rp[r]; ++q) inv[fill[s.lrow_idx[s.lrow_ptr[b0 + r] + q]]++] = r;
+            }
+            auto row_k = [&](int32_t r, int32_t q) { return s.lrow_idx[s.lrow_ptr[b0 + r] + q]; };
+            s.tail_rord.assign((size_t)16 * tiles, -1);
+            std::vector<char> placed(t, 0), in_u(b0, 0);
+            std::vector<int32_t> newc(t), touched;
+            int32_t slot = 0;
+            for (int32_t tt = 0; tt < tiles; ++tt) {
+                for (int32_t r = 0; r < t; ++r) newc[r] = rp[r + 1] - rp[r];
+                touched.clear();
+                for (int32_t m = 0; m < 16 && slot < t; ++m, ++slot) {
+                    // seed: smallest first column; then fewest new columns; longer rows, then lower index, first
+                    int32_t best = -1;
+                    int64_t bkey = INT64_MAX;
+                    for (int32_t r = 0; r < t; ++r) {
+                        if (placed[r]) continue;
+                        const int64_t len = rp[r + 1] - rp[r];
+                        const int64_t lead = m == 0 ? (len ? row_k(r, 0) : b0) : newc[r];
+                        const int64_t key = lead * ((int64_t)1 << 32) - len;
+                        if (key < bkey) { bkey = key; best = r; }
+                    }
+                    placed[best] = 1;
+                    s.tail_rord[slot] = best;
+                    for (int32_t q = 0; q < rp[best + 1] - rp[best]; ++q) {
+                        const int32_t k = row_k(best, q);
+                        if (in_u[k]) continue;
+                        in_u[k] = 1;
+                        touched.push_back(k);
+                        for (int32_t z = inv_ptr[k]; z < inv_ptr[k + 1]; ++z) --newc[inv[z]];
+                    }
+                }
+                for (int32_t k : touched) in_u[k] = 0;
+            }
+            s.tail_kt_ptr.assign(1, 0);
+            s.tail_kt.clear();
+            bool ok = true;
+            std::vector<int32_t> uni;
+            for (int32_t tt = 0; tt < tiles && ok; ++tt) {
+                uni.clear();
+                for (int32_t m = 16 * tt; m < 16 * tt + 16; ++m) {
+                    const int32_t r = s.tail_rord[m];
+                    if (r < 0) continue;
+                    for (int32_t q = 0; q < rp[r + 1] - rp[r]; ++q) uni.push_back(row_k(r, q));
+                }
+                std::sort(uni.begin(), uni.end());
+                uni.erase(std::unique(uni.begin(), uni.end()), uni.end());
+                if (uni.size() >= 65535) ok = false;
+                s.tail_kt.insert(s.tail_kt.end(), uni.begin(), uni.end());
+                s.tail_kt_ptr.push_back((int32_t)s.tail_kt.size());
+            }
+            // the common columns of every tile pair, ascending, padded to a multiple of four with
+            // the two zero columns
+            s.tail_pp_ptr.assign(ok ? (size_t)tiles * tiles + 1 : 1, 0);
+            s.tail_pairs.clear();
+            for (int32_t a = 0; a < tiles && ok; ++a)
+                for (int32_t b = 0; b < tiles && ok; ++b) {
+                    s.tail_pp_ptr[(size_t)a * tiles + b] = (int32_t)s.tail_pairs.size();
+                    const int32_t *A = s.tail_kt.data() + s.tail_kt_ptr[a], *B = s.tail_kt.data() + s.tail_kt_ptr[b];
+                    const uint32_t na = s.tail_kt_ptr[a + 1] - s.tail_kt_ptr[a], nb = s.tail_kt_ptr[b + 1] - s.tail_kt_ptr[b];
+                    uint32_t x = 0, y = 0;
+                    while (x < na && y < nb) {
+                        if (A[x] == B[y]) s.tail_pairs.push_back((int32_t)(x++ | (y++ << 16)));
+                        else if (A[x] < B[y]) ++x;
+                        else ++y;
+                    }
+                    while (s.tail_pairs.size() % 4) s.tail_pairs.push_back((int32_t)(na | (nb << 16)));
+                    if (s.tail_pairs.size() > kTailMaxPairs) ok = false;
+                }
+            if (ok) s.tail_pp_ptr[(size_t)tiles * tiles] = (int32_t)s.tail_pairs.size();
+            else {
+                s.tail_kt_ptr.clear();
+                s.tail_kt.clear();
+                s.tail_rord.clear();
+                s.tail_pp_ptr.clear();
+                s.tail_pairs.clear();
+            }
+            s.tail_tiles = ok ? tiles : 0;
         }
     }
 

@@ -26,9 +26,19 @@ struct Symbolic {
     // the block is smaller than kTailMin or the levels do not separate.
     int32_t tail_n = 0, tail_b0 = 0, fac_lev_sp = 0;
     std::vector<int32_t> lev_sp_ptr[2], lev_sp_idx[2];
+    // Tiles of 16 block rows: slot 16 t + r of tile t holds block row tail_rord[16 t + r] (-1:
+    // padding), rows grouped so that a tile's rows share their columns below tail_b0; tile t lists
+    // K_t, the columns below tail_b0 in which any of its rows has an entry, ascending, at
+    // tail_kt[tail_kt_ptr[t] ..); tail_tiles = 0 when a tile would list 65535 columns or more.
+    // The columns common to K_t and K_u, ascending, as (index in K_t) | (index in K_u) << 16 at
+    // tail_pairs[tail_pp_ptr[t * tail_tiles + u] ..), padded to a multiple of four with
+    // |K_t| | |K_u| << 16; tail_tiles = 0 as well when the lists would exceed kTailMaxPairs.
+    int32_t tail_tiles = 0;
+    std::vector<int32_t> tail_rord, tail_kt_ptr, tail_kt, tail_pp_ptr, tail_pairs;
 };
 
 constexpr int32_t kTailMin = 64;
+constexpr size_t kTailMaxPairs = (size_t)1 << 28;
 constexpr int32_t kTailAsmMaxB0 = 60000;   // columns before the block at most (an LDS map over them)
 
 // Returns an empty string on success, else the reason the pattern was rejected.

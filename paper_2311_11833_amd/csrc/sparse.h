@@ -44,6 +44,21 @@ struct SpIdx {
     const int32_t* tail_lastpos;    // tail_b0: position of (n-1, k) in column k of L, or -1
     const int32_t* lev_sp_ptr[2];   // L-solve / U-solve levels of the rows < tail_b0
     const int32_t* lev_sp_idx[2];
+    // Assembly of the block on the MFMA unit (tail_tiles > 0): tiles of 16 block rows, slot s
+    // holding block row tail_rord[s] (-1: padding); tile t's panel holds, for each column k of K_t
+    // (plan.h) and a final zero column, its 16 slots' entries l_ik (and, in the U panel, u_ki),
+    // 16 doubles per column, from panel column tail_kt_ptr[t] + t.
+    // tail_mpos gives each panel entry's position in the L pattern (or -1: zero).  The updates of
+    // block tile (t, u) are the columns common to K_t and K_u, ascending, as pairs
+    // (column in panel t) | (column in panel u) << 16 at tail_pairs[tail_pp_ptr[t * tiles + u] ..),
+    // padded to a multiple of four with the two zero columns.
+    int32_t tail_tiles;
+    int64_t tail_panel;                 // doubles of one panel set (16 x columns, rounded to 32)
+    const int32_t* tail_rord;           // 16 x tiles
+    const int32_t* tail_kt_ptr;         // tiles + 1
+    const int32_t* tail_mpos;           // 16 x panel columns
+    const int32_t* tail_pp_ptr;         // tiles^2 + 1
+    const int32_t* tail_pairs;
 };
 
 // Dataflow step schedule of one perturbed system (factor, forward and
@@ -70,6 +85,7 @@ struct SparseDevice {
     std::vector<int32_t> h_lev_ptr[3];   // host copies for per-level launches
     std::vector<int32_t> h_lpos_ptr;
     std::vector<int32_t> h_lev_sp_ptr[2];
+    int64_t h_tail_pairs = 0;            // entries of the tile-pair lists (multiple of 4 per pair)
     StepIdx st{};                        // step schedule (nsteps = 0 when it does not fit in LDS)
 };
 
@@ -80,7 +96,8 @@ struct Knobs {
     int32_t steps_mode = -1;   // step kernel: -1 by batch size, 0 one workgroup per system, 1 per Jacobian
     int32_t steps_wgcu = 0;    // step kernel: 0 as many workgroups per CU as LDS allows, 1 one per CU
     int32_t ring = 7;          // step kernel: descriptors in flight (7 or 4)
-    int32_t tail_cols = 4;     // dense-block assembly: block columns per workgroup (4 or 1)
+    int32_t tail_cols = 16;    // dense-block assembly: 16 tile pairs on the MFMA unit, or 4 or 1
+                               // block columns per workgroup
 };
 int sparse_variant(const Symbolic& s, int64_t ntasks, int32_t nrhs, int forced);
 

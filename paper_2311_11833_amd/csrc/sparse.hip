@@ -715,6 +715,106 @@ int64_t tail_asm_lds(int32_t b0) {
     return (int64_t)kAsmUnion * (kAsmCols * 8 + 4 + 1) + ((int64_t)b0 * 2 + 15) / 16 * 16;
 }
 
+// ---- assembly by tile pairs on the MFMA unit
+// Block tile (t, u) (16 x 16) receives sum_k l_ik u_kj over the columns k < tail_b0 common to
+// K_t and K_u, ascending; a column in the union of a tile's rows contributes exact zeros to the
+// rows without it (a product with a zero factor leaves a nonzero accumulator unchanged), so the
+// chain of every entry equals the reference's.  Each system's panels are gathered once, then one
+// wave per tile pair runs the chain four columns per v_mfma_f64_16x16x4f64 (which accumulates in
+// ascending k), computed transposed like gemm_mfma: A = -U panel of u, B = L panel of t, so lane
+// l, register q holds the entry of slots (16t + l%16, 16u + 4q + l/16).  Rows and columns from
+// tail_n on are the identity (written with the panels).
+constexpr int kTpWaves = 4;
+constexpr int kTpUnroll = 16;
+
+__device__ __forceinline__ double* tail_panels(const SpIdx& ix, double* ud) {
+    return ud + ix.tail_off + (int64_t)ix.tail_ld * ix.tail_ld + (int64_t)ix.tail_ld * 64;
+}
+
+__global__ void tail_panel_gather_kernel(SpArgs a) {
+    const SpIdx& ix = a.ix;
+    const int n = ix.n, nl = ix.nnzl, ld = ix.tail_ld;
+    const int64_t P = ix.tail_panel, e = ix.tail_n;
+    const int64_t below = e * (ld - e), pad = (int64_t)ld * ld - e * e, per = P + pad;
+    const int64_t total = per * a.ntasks;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+        const int task = (int)(g / per);
+        const int64_t q = g % per;
+        double* ud = a.fac + (int64_t)task * a.fstride;
+        if (q < P) {
+            const int pos = ix.tail_mpos[q];
+            double* PL = tail_panels(ix, ud);
+            PL[q] = pos >= 0 ? ud[n + pos] : 0.0;
+            PL[P + q] = pos >= 0 ? ud[n + nl + pos] : 0.0;
+        } else {
+            // identity padding: rows and columns from tail_n on
+            const int64_t r = q - P;
+            double* T = ud + ix.tail_off;
+            if (r < below) T[(r / (ld - e)) * ld + e + r % (ld - e)] = 0.0;
+            else {
+                const int64_t j = e + (r - below) / ld, i = (r - below) % ld;
+                T[j * ld + i] = i == j ? 1.0 : 0.0;
+            }
+        }
+    }
+}
+
+// Logical workgroup w of a launch of G = 8 m workgroups runs as hardware workgroup
+// (w % m) * 8 + w / m, so consecutive logical workgroups (the tile pairs of one system, which
+// share its panels) are dispatched to the same XCD and its L2.
+__global__ __launch_bounds__(64 * kTpWaves) void tail_tile_kernel(SpArgs a, int64_t wgs) {
+    const SpIdx& ix = a.ix;
+    const int64_t m = gridDim.x / 8;
+    const int64_t lw = (int64_t)(blockIdx.x % 8) * m + blockIdx.x / 8;
+    if (lw >= wgs) return;
+    const int TT = ix.tail_tiles, pairs_per = TT * TT;
+    const int64_t wpt = (pairs_per + kTpWaves - 1) / kTpWaves;
+    const int task = (int)(lw / wpt);
+    const int pi = (int)(lw % wpt) * kTpWaves + (threadIdx.x >> 6);
+    if (pi >= pairs_per) return;                 // uniform per wave; the kernel has no barrier
+    const int t = pi / TT, u = pi % TT;
+    const int n = ix.n, nl = ix.nnzl, b0 = ix.tail_b0, ld = ix.tail_ld;
+    const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+    double* ud = a.fac + (int64_t)task * a.fstride;
+    const double* lv = ud + n;
+    const double* uv = ud + n + nl;
+    const double* PL = tail_panels(ix, ud);
+    const double* Lt = PL + 16 * (int64_t)ix.tail_kt_ptr[t] + li;
+    const double* Uu = PL + ix.tail_panel + 16 * (int64_t)ix.tail_kt_ptr[u] + li;
+    const int gi = ix.tail_rord[16 * t + li];
+    int gj[4];
+    v4d acc;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        gj[q] = ix.tail_rord[16 * u + 4 * q + lk];
+        acc[q] = (gi >= 0 && gj[q] >= 0) ? block_a(ix, ud, lv, uv, b0 + gi, b0 + gj[q]) : 0.0;
+    }
+    const int p0 = ix.tail_pp_ptr[pi], p1 = ix.tail_pp_ptr[pi + 1];
+    const int32_t* pr = ix.tail_pairs + lk;
+    constexpr int UN = kTpUnroll;
+    int w[UN];
+#pragma unroll
+    for (int x = 0; x < UN; ++x) w[x] = p0 + 4 * x < p1 ? pr[p0 + 4 * x] : 0;
+    for (int p = p0; p < p1; p += 4 * UN) {
+        double av[UN], bv[UN];
+#pragma unroll
+        for (int x = 0; x < UN; ++x) {
+            av[x] = -Uu[16 * (int)((uint32_t)w[x] >> 16)];
+            bv[x] = Lt[16 * (w[x] & 0xFFFF)];
+        }
+        const int pn = p + 4 * UN;
+#pragma unroll
+        for (int x = 0; x < UN; ++x) w[x] = pn + 4 * x < p1 ? pr[pn + 4 * x] : 0;
+#pragma unroll
+        for (int x = 0; x < UN; ++x)
+            if (p + 4 * x < p1) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[x], bv[x], acc, 0, 0, 0);
+    }
+    double* T = ud + ix.tail_off;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        if (gi >= 0 && gj[q] >= 0) T[(int64_t)gj[q] * ld + gi] = acc[q];
+}
+
 // Panel p0 of every system's block: GETRF of the NB x NB diagonal block (wave 0), then the
 // multipliers below it and the rows of U to its right (one workgroup per system).
 __global__ __launch_bounds__(WG) void tail_panel_kernel(SpArgs a, int p0) {
@@ -1166,11 +1266,16 @@ int64_t align256(int64_t v) { return (v + 255) / 256 * 256; }
 int64_t tail_ld_of(const Symbolic& s) { return s.tail_n ? (s.tail_n + NB - 1) / NB * NB : 0; }
 
 // doubles of one system's factors: [u_jj | L | U] rounded to 32, then (dense trailing block) the
-// block and its right-hand-side scratch (tail_ld x 64)
+// block, its right-hand-side scratch (tail_ld x 64) and the L and U panels of the tile-pair
+// assembly
 int64_t fbase_of(const Symbolic& s) { return (s.n + 2 * (int64_t)s.l_ptr[s.n] + 31) / 32 * 32; }
+// doubles of one panel set of the tile-pair assembly (0: none)
+int64_t tail_panel_of(const Symbolic& s) {
+    return s.tail_tiles ? (16 * ((int64_t)s.tail_kt.size() + s.tail_tiles) + 31) / 32 * 32 : 0;
+}
 int64_t fstride_of(const Symbolic& s) {
     const int64_t ld = tail_ld_of(s);
-    return fbase_of(s) + ld * ld + ld * 64;
+    return fbase_of(s) + ld * ld + ld * 64 + 2 * tail_panel_of(s);
 }
 
 int64_t tp_of(int64_t ntasks) { return (ntasks + 63) / 64 * 64; }
@@ -1294,7 +1399,7 @@ hipError_t factor_global(const SparseDevice& d, SpArgs a, const EpsSet& es, hipS
     return hipGetLastError();
 }
 
-hipError_t factor_tail(const SparseDevice& d, SpArgs a, const EpsSet& es, hipStream_t st, int cols = kAsmCols) {
+hipError_t factor_tail(const SparseDevice& d, SpArgs a, const EpsSet& es, hipStream_t st, int cols = 16) {
     hipLaunchKernelGGL(sp_gather_kernel, dim3(grid_for((int64_t)(a.ix.n + a.ix.nnzl) * a.ntasks, kThreads)),
                        dim3(kThreads), 0, st, a, es);
     for (int l = 0; l < a.ix.fac_lev_sp; ++l) {
@@ -1307,9 +1412,19 @@ hipError_t factor_tail(const SparseDevice& d, SpArgs a, const EpsSet& es, hipStr
                                0, st, a, p0, np);
     }
     const int ld = a.ix.tail_ld;
-    cols = cols == 1 ? 1 : kAsmCols;
-    hipLaunchKernelGGL(tail_assemble_kernel, dim3((int)std::min<int64_t>((int64_t)(ld / cols) * a.ntasks, 1 << 20)),
-                       dim3(kAsmThreads), (int)tail_asm_lds(a.ix.tail_b0), st, a, cols);
+    if (cols == 16 && a.ix.tail_tiles > 0) {
+        const int64_t e = a.ix.tail_n;
+        const int64_t per = a.ix.tail_panel + (int64_t)ld * ld - e * e;
+        hipLaunchKernelGGL(tail_panel_gather_kernel, dim3(grid_for(per * a.ntasks, kThreads)), dim3(kThreads), 0, st, a);
+        const int64_t pairs = (int64_t)a.ix.tail_tiles * a.ix.tail_tiles;
+        const int64_t wgs = (pairs + kTpWaves - 1) / kTpWaves * a.ntasks;
+        if ((wgs + 7) / 8 * 8 > INT32_MAX) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(tail_tile_kernel, dim3((unsigned)((wgs + 7) / 8 * 8)), dim3(64 * kTpWaves), 0, st, a, wgs);
+    } else {
+        cols = cols == 1 ? 1 : kAsmCols;
+        hipLaunchKernelGGL(tail_assemble_kernel, dim3((int)std::min<int64_t>((int64_t)(ld / cols) * a.ntasks, 1 << 20)),
+                           dim3(kAsmThreads), (int)tail_asm_lds(a.ix.tail_b0), st, a, cols);
+    }
     for (int p0 = 0; p0 < ld; p0 += NB) {
         hipLaunchKernelGGL(tail_panel_kernel, dim3(std::min(a.ntasks, 65535)), dim3(WG), 0, st, a, p0);
         const int rem = ld - p0 - NB;
@@ -1511,6 +1626,34 @@ void sparse_image(const Symbolic& s, PlanImage& img, SparseDevice& d) {
         for (int k = 0; k < s.tail_b0; ++k)
             if (s.l_ptr[k + 1] > s.l_ptr[k] && s.l_idx[s.l_ptr[k + 1] - 1] == n - 1) lp[k] = s.l_ptr[k + 1] - 1;
         img.bind(&ix.tail_lastpos, img.put(lp));
+        // tile-pair assembly: panel positions and the pair lists
+        const int TT = s.tail_tiles;
+        ix.tail_tiles = TT;
+        ix.tail_panel = tail_panel_of(s);
+        std::vector<int32_t> ktp(TT + 1, 0), mpos(std::max<int64_t>(ix.tail_panel, 1), -1), ppp(1, 0), prs;
+        if (TT > 0) {
+            for (int t = 0; t <= TT; ++t) ktp[t] = s.tail_kt_ptr[t] + t;
+            for (int slot = 0; slot < 16 * TT; ++slot) {
+                if (s.tail_rord[slot] < 0) continue;
+                const int t = slot / 16, r = slot % 16, row = s.tail_b0 + s.tail_rord[slot];
+                const int32_t* K = s.tail_kt.data() + s.tail_kt_ptr[t];
+                int c = 0;
+                for (int q = s.lrow_ptr[row]; q < s.lrow_ptr[row + 1] && s.lrow_idx[q] < s.tail_b0; ++q) {
+                    while (K[c] < s.lrow_idx[q]) ++c;
+                    mpos[16 * ((int64_t)ktp[t] + c) + r] = r_pos[q];
+                }
+            }
+            ppp = s.tail_pp_ptr;
+            prs = s.tail_pairs;
+            d.h_tail_pairs = (int64_t)prs.size();
+        }
+        if (prs.empty()) prs.push_back(0);
+        std::vector<int32_t> rord = TT ? s.tail_rord : std::vector<int32_t>(1, -1);
+        img.bind(&ix.tail_rord, img.put(rord));
+        img.bind(&ix.tail_kt_ptr, img.put(ktp));
+        img.bind(&ix.tail_mpos, img.put(mpos));
+        img.bind(&ix.tail_pp_ptr, img.put(ppp));
+        img.bind(&ix.tail_pairs, img.put(prs));
     }
     for (int w = 0; w < 2; ++w) {
         ix.nlev_sp[w] = s.tail_n ? (int32_t)s.lev_sp_ptr[w].size() - 1 : 0;

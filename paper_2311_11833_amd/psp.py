@@ -44,7 +44,7 @@ class PlanInfo(C.Structure):
                 ("nlev", C.c_int32 * 3), ("flops_dense_factor", C.c_int64), ("flops_sparse_factor", C.c_int64),
                 ("steps", C.c_int32), ("steps_packed", C.c_int32), ("steps_lds_bytes", C.c_int64),
                 ("steps_per_cu", C.c_int32), ("device_bytes", C.c_int64), ("tail_n", C.c_int32),
-                ("tail_fac_levels", C.c_int32)]
+                ("tail_fac_levels", C.c_int32), ("tail_tiles", C.c_int32), ("tail_mfma", C.c_int64)]
 
 
 class TuneChoice(C.Structure):
@@ -463,7 +463,7 @@ def tune_choice(plan: Plan, batch: int, K: int, nrhs: int = 1) -> dict:
 
 
 def set_tune_choice(plan: Plan, batch: int, K: int, nrhs: int = 1, path: str = "sparse_steps", steps_mode: int = -1,
-                    steps_wgcu: int = 0, ring: int = 7, tail_cols: int = 4) -> None:
+                    steps_wgcu: int = 0, ring: int = 7, tail_cols: int = 16) -> None:
     """Pins the path and launch choices of PSP_PATH_AUTO for (batch, K, nrhs)."""
     c = TuneChoice(PATHS[path], steps_mode, steps_wgcu, ring, tail_cols, -1.0, 1)
     _check(lib().psp_set_tune_choice(plan.handle, batch, K, nrhs, C.byref(c)))

@@ -38,7 +38,7 @@ def test_every_step_launch_choice_matches_oracle(dev, O, W, N, count):
         for wgcu in ((0, 1) if two else (0,)):
             for ring in (7, 4):
                 print(f"[gpu tune] N={N} mode={mode} wgcu={wgcu} ring={ring}", flush=True)
-                psp.set_tune_choice(plan, count, len(eps), 1, "sparse_steps", mode, wgcu, ring, 4)
+                psp.set_tune_choice(plan, count, len(eps), 1, "sparse_steps", mode, wgcu, ring, 16)
                 x, info = psp.solve_batched(plan, v, eps, b, path="auto")
                 torch.cuda.synchronize()
                 assert np.array_equal(info.cpu().numpy(), io)
@@ -54,7 +54,7 @@ def test_tail_assembly_choices_match_oracle(dev, O, W):
     sym = O.symbolic(n, ip, ix)
     xo, io, _, _ = O.sparse_batch(n, ip, ix, vals, sym, eps, bs)
     v, b = torch.from_numpy(vals).to(dev), torch.from_numpy(bs).to(dev)
-    for cols in (4, 1):
+    for cols in (16, 4, 1):
         print(f"[gpu tune] tail cols={cols}", flush=True)
         psp.set_tune_choice(plan, 3, len(eps), 1, "sparse_tail", tail_cols=cols)
         x, info = psp.solve_batched(plan, v, eps, b, path="auto")
