@@ -351,6 +351,12 @@ PSP_API psp_status psp_tune(psp_plan plan, int32_t batch, const double* values, 
  *   tail_cols   dense trailing block assembly: 16 by 16 x 16 tile pairs on
  *               the MFMA unit (where every tile's column union is below
  *               65535), else 4 or 1 block columns per workgroup;
+ *   tail_il     dense trailing block, fused call: 1 the systems' factors
+ *               below the block interleaved (a wave serves 64 systems),
+ *               0 one system after another, -1 interleaved from 64
+ *               systems on (needs tail_cols 16);
+ *   tail_lu     dense trailing block LU and solves: 1 one workgroup per
+ *               system, 0 each panel step across the device;
  *   ms          measured time per call (-1 when set by hand);
  *   source      0 none (the size heuristic applies), 1 tuned or set in this
  *               process, 2 read from the tuning cache file.
@@ -367,6 +373,8 @@ typedef struct {
     int32_t steps_wgcu;
     int32_t ring;
     int32_t tail_cols;
+    int32_t tail_il;
+    int32_t tail_lu;
     float ms;
     int32_t source;
 } psp_tune_choice_t;

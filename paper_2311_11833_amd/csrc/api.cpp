@@ -228,7 +228,7 @@ std::string cache_path() {
 
 std::string cache_key(psp_plan p, int32_t batch, int32_t K, int32_t nrhs) {
     char buf[160];
-    std::snprintf(buf, sizeof(buf), "gfx950|n=%d|nnz=%d|h=%016llx|batch=%d|K=%d|nrhs=%d", p->sym.n, p->sym.nnz,
+    std::snprintf(buf, sizeof(buf), "v2|gfx950|n=%d|nnz=%d|h=%016llx|batch=%d|K=%d|nrhs=%d", p->sym.n, p->sym.nnz,
                   (unsigned long long)p->hash, batch, K, nrhs);
     return buf;
 }
@@ -244,7 +244,7 @@ void cache_load_locked() {
         std::istringstream is(line);
         std::string key;
         psp_tune_choice_t c{};
-        if (is >> key >> c.path >> c.steps_mode >> c.steps_wgcu >> c.ring >> c.tail_cols >> c.ms) {
+        if (is >> key >> c.path >> c.steps_mode >> c.steps_wgcu >> c.ring >> c.tail_cols >> c.tail_il >> c.tail_lu >> c.ms) {
             c.source = 2;
             g_cache[key] = c;
         }
@@ -271,7 +271,8 @@ void cache_store(const std::string& key, const psp_tune_choice_t& c) {
         if (!f) return;
         for (const auto& kv : g_cache)
             f << kv.first << ' ' << kv.second.path << ' ' << kv.second.steps_mode << ' ' << kv.second.steps_wgcu << ' '
-              << kv.second.ring << ' ' << kv.second.tail_cols << ' ' << kv.second.ms << '\n';
+              << kv.second.ring << ' ' << kv.second.tail_cols << ' ' << kv.second.tail_il << ' ' << kv.second.tail_lu << ' '
+              << kv.second.ms << '\n';
     }
     std::rename(tmp.c_str(), path.c_str());
 }
@@ -284,6 +285,8 @@ psp_tune_choice_t default_choice(int32_t path) {
     c.steps_wgcu = kn.steps_wgcu;
     c.ring = kn.ring;
     c.tail_cols = kn.tail_cols;
+    c.tail_il = kn.tail_il;
+    c.tail_lu = kn.tail_lu;
     c.ms = -1.0f;
     c.source = 0;
     return c;
@@ -295,6 +298,8 @@ Knobs knobs_of(const psp_tune_choice_t& c) {
     kn.steps_wgcu = c.steps_wgcu;
     kn.ring = c.ring;
     kn.tail_cols = c.tail_cols;
+    kn.tail_il = c.tail_il;
+    kn.tail_lu = c.tail_lu;
     return kn;
 }
 
@@ -556,7 +561,8 @@ psp_status psp_set_tune_choice(psp_plan p, int32_t batch, int32_t K, int32_t nrh
     if (!p || !c) return fail(PSP_E_INVALID, "psp_set_tune_choice: NULL argument");
     if (split_path(c->path).base < 0) return fail(PSP_E_INVALID, "psp_set_tune_choice: unknown path");
     if (c->steps_mode < -1 || c->steps_mode > 1 || c->steps_wgcu < 0 || c->steps_wgcu > 1 ||
-        (c->ring != 7 && c->ring != 4) || (c->tail_cols != 16 && c->tail_cols != 4 && c->tail_cols != 1))
+        (c->ring != 7 && c->ring != 4) || (c->tail_cols != 16 && c->tail_cols != 4 && c->tail_cols != 1) ||
+        c->tail_il < -1 || c->tail_il > 1 || c->tail_lu < 0 || c->tail_lu > 1)
         return fail(PSP_E_INVALID, "psp_set_tune_choice: a launch choice is out of range");
     psp_tune_choice_t v = *c;
     v.source = 1;
@@ -684,11 +690,16 @@ psp_status psp_tune(psp_plan p, int32_t batch, const double* values, int32_t K, 
                         cand.push_back(v);
                     }
         } else if (c == PSP_PATH_SPARSE_TAIL) {
-            for (int cols : {16, 4, 1}) {
-                psp_tune_choice_t v = base;
-                v.tail_cols = cols;
-                cand.push_back(v);
-            }
+            for (int cols : {16, 4, 1})
+                for (int il : {1, 0})
+                    for (int lu : {1, 0}) {
+                        if (il && cols != 16) continue;
+                        psp_tune_choice_t v = base;
+                        v.tail_cols = cols;
+                        v.tail_il = il;
+                        v.tail_lu = lu;
+                        cand.push_back(v);
+                    }
         } else {
             cand.push_back(base);
         }

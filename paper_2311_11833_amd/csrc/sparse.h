@@ -98,6 +98,10 @@ struct Knobs {
     int32_t ring = 7;          // step kernel: descriptors in flight (7 or 4)
     int32_t tail_cols = 16;    // dense-block assembly: 16 tile pairs on the MFMA unit, or 4 or 1
                                // block columns per workgroup
+    int32_t tail_il = -1;      // dense-block path, fused call: systems interleaved below the block
+                               // (1), task-major (0), or -1 by batch size
+    int32_t tail_lu = 0;       // dense-block LU and solves: one workgroup per system (1), or each
+                               // panel step across the device (0)
 };
 int sparse_variant(const Symbolic& s, int64_t ntasks, int32_t nrhs, int forced);
 

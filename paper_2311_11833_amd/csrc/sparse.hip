@@ -117,6 +117,7 @@ __device__ __forceinline__ double merge_dot(const SpIdx& ix, int a, int b, const
 // that U index/value fetches are in flight at once; the chain itself keeps
 // the ascending order.
 constexpr int U8 = 8;
+constexpr int U16 = 16;   // the block rows' updates from the sparse part: more loads in flight per step
 
 __device__ __forceinline__ double pair_dot(const SpIdx& ix, int id, const double* lv, const double* uv, double acc) {
     const int p1 = ix.pair_ptr[id + 1];
@@ -225,6 +226,13 @@ struct SpArgs {
     double* y;              // global RHS scratch: ntasks x n x nrhs
     double* X;              // batch x n x nrhs, combined in-kernel when per_jacobian
     int32_t per_jacobian, batch;
+    // Dense trailing block kernels (tail_*): value t of system s of the [u_jj | L | U] arrays at
+    // fac[s * ts + t * vs], its block, right-hand-side scratch and panels at dense + s * dstride,
+    // entry (i, r) of its substitution vector at y[s * yt + (i * nrhs + r) * yv].  Task-major
+    // factors (vs = 1, ts = fstride, block inside each system's factors) or systems interleaved
+    // (vs = TP, ts = 1, blocks in a region of their own).
+    int64_t vs, ts, dstride, yv, yt;
+    double* dense;
 };
 
 // ---------------------------------------------------------------- in-LDS kernel
@@ -437,10 +445,11 @@ __device__ __forceinline__ AsmLds asm_lds(double* smem) {
     return L;
 }
 
-// Initial value of block entry (gi, gj): a_ij (+ eps d on the diagonal) as gathered.
+// Initial value of block entry (gi, gj): a_ij (+ eps d on the diagonal) as gathered (values vs apart).
 __device__ __forceinline__ double block_a(const SpIdx& ix, const double* ud, const double* lv, const double* uv,
-                                          int gi, int gj) {
-    return gi == gj ? ud[gj] : (gi > gj ? lv[ix.l_ptr[gj] + (gi - gj - 1)] : uv[ix.l_ptr[gi] + (gj - gi - 1)]);
+                                          int gi, int gj, int64_t vs = 1) {
+    return gi == gj ? ud[gj * vs]
+                    : (gi > gj ? lv[(ix.l_ptr[gj] + (gi - gj - 1)) * vs] : uv[(ix.l_ptr[gi] + (gj - gi - 1)) * vs]);
 }
 
 // Column j of the block, alone.
@@ -722,63 +731,105 @@ int64_t tail_asm_lds(int32_t b0) {
 // chain of every entry equals the reference's.  Each system's panels are gathered once, then one
 // wave per tile pair runs the chain four columns per v_mfma_f64_16x16x4f64 (which accumulates in
 // ascending k), computed transposed like gemm_mfma: A = -U panel of u, B = L panel of t, so lane
-// l, register q holds the entry of slots (16t + l%16, 16u + 4q + l/16).  Rows and columns from
-// tail_n on are the identity (written with the panels).
+// l, register q holds the entry of slots (16t + l%16, 16u + 4q + l/16); the chains start from the
+// block's initial values, written beforehand.
 constexpr int kTpWaves = 4;
-constexpr int kTpUnroll = 16;
+constexpr int kTpUnroll = 8;
 
-__device__ __forceinline__ double* tail_panels(const SpIdx& ix, double* ud) {
-    return ud + ix.tail_off + (int64_t)ix.tail_ld * ix.tail_ld + (int64_t)ix.tail_ld * 64;
+__device__ __forceinline__ double* tail_panels(const SpIdx& ix, double* T) {
+    return T + (int64_t)ix.tail_ld * ix.tail_ld + (int64_t)ix.tail_ld * 64;
 }
 
-__global__ void tail_panel_gather_kernel(SpArgs a) {
+// Every block entry's initial value a_ij (+ eps d on the diagonal) straight from the Jacobian's
+// values, the identity on the padding rows and columns: one thread per entry, down the columns.
+__global__ void tail_block_init_kernel(SpArgs a, EpsSet es) {
     const SpIdx& ix = a.ix;
-    const int n = ix.n, nl = ix.nnzl, ld = ix.tail_ld;
-    const int64_t P = ix.tail_panel, e = ix.tail_n;
-    const int64_t below = e * (ld - e), pad = (int64_t)ld * ld - e * e, per = P + pad;
-    const int64_t total = per * a.ntasks;
+    const int ld = ix.tail_ld, nt = ix.tail_n, b0 = ix.tail_b0;
+    const int64_t per = (int64_t)ld * ld, total = per * a.ntasks;
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
         const int task = (int)(g / per);
-        const int64_t q = g % per;
-        double* ud = a.fac + (int64_t)task * a.fstride;
-        if (q < P) {
-            const int pos = ix.tail_mpos[q];
-            double* PL = tail_panels(ix, ud);
-            PL[q] = pos >= 0 ? ud[n + pos] : 0.0;
-            PL[P + q] = pos >= 0 ? ud[n + nl + pos] : 0.0;
-        } else {
-            // identity padding: rows and columns from tail_n on
-            const int64_t r = q - P;
-            double* T = ud + ix.tail_off;
-            if (r < below) T[(r / (ld - e)) * ld + e + r % (ld - e)] = 0.0;
+        const int64_t e = g % per;
+        const int i = (int)(e % ld), j = (int)(e / ld);
+        double v;
+        if (i >= nt || j >= nt) v = i == j ? 1.0 : 0.0;
+        else {
+            const double* vals = a.values + (int64_t)(task / es.K) * a.nnz;
+            const int gi = b0 + i, gj = b0 + j;
+            if (i == j) v = gather_diag(ix, gj, vals, eps_at(es, task % es.K), a.dvec);
             else {
-                const int64_t j = e + (r - below) / ld, i = (r - below) % ld;
-                T[j * ld + i] = i == j ? 1.0 : 0.0;
+                const int src = i > j ? ix.src_l[ix.l_ptr[gj] + (gi - gj - 1)] : ix.src_u[ix.l_ptr[gi] + (gj - gi - 1)];
+                v = src >= 0 ? vals[src] : 0.0;
             }
         }
+        a.dense[(int64_t)task * a.dstride + e] = v;
     }
 }
 
-// Logical workgroup w of a launch of G = 8 m workgroups runs as hardware workgroup
-// (w % m) * 8 + w / m, so consecutive logical workgroups (the tile pairs of one system, which
-// share its panels) are dispatched to the same XCD and its L2.
-__global__ __launch_bounds__(64 * kTpWaves) void tail_tile_kernel(SpArgs a, int64_t wgs) {
+// Panels, task-major factors: one thread per panel entry.
+__global__ void tail_panel_gather_kernel(SpArgs a) {
+    const SpIdx& ix = a.ix;
+    const int n = ix.n, nl = ix.nnzl;
+    const int64_t P = ix.tail_panel, total = P * a.ntasks;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+        const int task = (int)(g / P);
+        const int64_t q = g % P;
+        const int pos = ix.tail_mpos[q];
+        const double* ud = a.fac + (int64_t)task * a.ts;
+        double* PL = tail_panels(ix, a.dense + (int64_t)task * a.dstride);
+        PL[q] = pos >= 0 ? ud[n + pos] : 0.0;
+        PL[P + q] = pos >= 0 ? ud[n + nl + pos] : 0.0;
+    }
+}
+
+// Panels, interleaved factors: 64 entries x 64 systems per workgroup, read along the systems and
+// written along the entries through LDS.
+__global__ __launch_bounds__(256) void tail_panel_gather_il_kernel(SpArgs a, int echunks) {
+    __shared__ double sv[64][65];
+    const SpIdx& ix = a.ix;
+    const int n = ix.n, nl = ix.nnzl;
+    const int64_t P = ix.tail_panel, TP = a.vs;
+    const int64_t e0 = (int64_t)(blockIdx.x % echunks) * 64;
+    const int t0 = (int)(blockIdx.x / echunks) * 64;
+    const int x = threadIdx.x & 63, y = threadIdx.x >> 6;
+    int pos[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) pos[k] = e0 + y + 4 * k < P ? ix.tail_mpos[e0 + y + 4 * k] : -1;
+    for (int side = 0; side < 2; ++side) {          // L values, then U values
+        const double* src = a.fac + (int64_t)(side ? n + nl : n) * TP + t0 + x;
+        const bool tok = t0 + x < a.ntasks;
+        double v[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) v[k] = (pos[k] >= 0 && tok) ? src[(int64_t)pos[k] * TP] : 0.0;
+        if (side) __syncthreads();                  // the L values have been written out
+#pragma unroll
+        for (int k = 0; k < 16; ++k) sv[y + 4 * k][x] = v[k];
+        __syncthreads();
+        if (e0 + x < P)
+            for (int tt = y; tt < 64 && t0 + tt < a.ntasks; tt += 4)
+                tail_panels(ix, a.dense + (int64_t)(t0 + tt) * a.dstride)[side * P + e0 + x] = sv[x][tt];
+    }
+}
+
+// Logical workgroup l of a launch of G = 8 m workgroups runs as hardware workgroup
+// (l % m) * 8 + l / m, so consecutive logical workgroups (the tile pairs of one system, which
+// share its panels) are dispatched to the same XCD and its L2.  Wave w of logical workgroup l
+// takes tile pair l * kTpWaves + w (item = system * tiles^2 + t * tiles + u).  The panel loads
+// of the next kTpUnroll steps are issued before the MFMAs of the current ones (the chain of a
+// long pair, the slack row's tile with itself, is otherwise one memory latency per step).
+__global__ __launch_bounds__(64 * kTpWaves) void tail_tile_kernel(SpArgs a, int64_t items) {
     const SpIdx& ix = a.ix;
     const int64_t m = gridDim.x / 8;
     const int64_t lw = (int64_t)(blockIdx.x % 8) * m + blockIdx.x / 8;
-    if (lw >= wgs) return;
-    const int TT = ix.tail_tiles, pairs_per = TT * TT;
-    const int64_t wpt = (pairs_per + kTpWaves - 1) / kTpWaves;
-    const int task = (int)(lw / wpt);
-    const int pi = (int)(lw % wpt) * kTpWaves + (threadIdx.x >> 6);
-    if (pi >= pairs_per) return;                 // uniform per wave; the kernel has no barrier
+    const int64_t it = lw * kTpWaves + (threadIdx.x >> 6);
+    if (it >= items) return;                     // uniform per wave; the kernel has no barrier
+    const int TT = ix.tail_tiles;
+    const int64_t pairs_per = (int64_t)TT * TT;
+    const int task = (int)(it / pairs_per), pi = (int)(it % pairs_per);
     const int t = pi / TT, u = pi % TT;
-    const int n = ix.n, nl = ix.nnzl, b0 = ix.tail_b0, ld = ix.tail_ld;
+    const int ld = ix.tail_ld;
     const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
-    double* ud = a.fac + (int64_t)task * a.fstride;
-    const double* lv = ud + n;
-    const double* uv = ud + n + nl;
-    const double* PL = tail_panels(ix, ud);
+    double* T = a.dense + (int64_t)task * a.dstride;
+    const double* PL = tail_panels(ix, T);
     const double* Lt = PL + 16 * (int64_t)ix.tail_kt_ptr[t] + li;
     const double* Uu = PL + ix.tail_panel + 16 * (int64_t)ix.tail_kt_ptr[u] + li;
     const int gi = ix.tail_rord[16 * t + li];
@@ -787,29 +838,42 @@ __global__ __launch_bounds__(64 * kTpWaves) void tail_tile_kernel(SpArgs a, int6
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         gj[q] = ix.tail_rord[16 * u + 4 * q + lk];
-        acc[q] = (gi >= 0 && gj[q] >= 0) ? block_a(ix, ud, lv, uv, b0 + gi, b0 + gj[q]) : 0.0;
+        acc[q] = (gi >= 0 && gj[q] >= 0) ? T[(int64_t)gj[q] * ld + gi] : 0.0;
     }
     const int p0 = ix.tail_pp_ptr[pi], p1 = ix.tail_pp_ptr[pi + 1];
     const int32_t* pr = ix.tail_pairs + lk;
     constexpr int UN = kTpUnroll;
+    // pair words: a | b << 16 (past the end: column 0 of both panels, never used)
+    auto word = [&](int p) { return p < p1 ? pr[p] : 0; };
     int w[UN];
+    double av[UN], bv[UN];
 #pragma unroll
-    for (int x = 0; x < UN; ++x) w[x] = p0 + 4 * x < p1 ? pr[p0 + 4 * x] : 0;
+    for (int x = 0; x < UN; ++x) w[x] = word(p0 + 4 * x);
+#pragma unroll
+    for (int x = 0; x < UN; ++x) {
+        av[x] = -Uu[16 * (int)((uint32_t)w[x] >> 16)];
+        bv[x] = Lt[16 * (w[x] & 0xFFFF)];
+    }
+#pragma unroll
+    for (int x = 0; x < UN; ++x) w[x] = word(p0 + 4 * UN + 4 * x);
     for (int p = p0; p < p1; p += 4 * UN) {
-        double av[UN], bv[UN];
+        double an[UN], bn[UN];
 #pragma unroll
         for (int x = 0; x < UN; ++x) {
-            av[x] = -Uu[16 * (int)((uint32_t)w[x] >> 16)];
-            bv[x] = Lt[16 * (w[x] & 0xFFFF)];
+            an[x] = -Uu[16 * (int)((uint32_t)w[x] >> 16)];
+            bn[x] = Lt[16 * (w[x] & 0xFFFF)];
         }
-        const int pn = p + 4 * UN;
 #pragma unroll
-        for (int x = 0; x < UN; ++x) w[x] = pn + 4 * x < p1 ? pr[pn + 4 * x] : 0;
+        for (int x = 0; x < UN; ++x) w[x] = word(p + 8 * UN + 4 * x);
 #pragma unroll
         for (int x = 0; x < UN; ++x)
             if (p + 4 * x < p1) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[x], bv[x], acc, 0, 0, 0);
+#pragma unroll
+        for (int x = 0; x < UN; ++x) {
+            av[x] = an[x];
+            bv[x] = bn[x];
+        }
     }
-    double* T = ud + ix.tail_off;
 #pragma unroll
     for (int q = 0; q < 4; ++q)
         if (gi >= 0 && gj[q] >= 0) T[(int64_t)gj[q] * ld + gi] = acc[q];
@@ -822,7 +886,7 @@ __global__ __launch_bounds__(WG) void tail_panel_kernel(SpArgs a, int p0) {
     __shared__ int s_bad;
     const int ld = a.ix.tail_ld;
     for (int task = blockIdx.x; task < a.ntasks; task += gridDim.x) {
-        double* T = a.fac + (int64_t)task * a.fstride + a.ix.tail_off;
+        double* T = a.dense + (int64_t)task * a.dstride;
         if (threadIdx.x < 64) {
             const int bad = panel_getrf(T, ld, p0, D);
             if (threadIdx.x == 0) s_bad = bad;
@@ -841,7 +905,7 @@ __global__ __launch_bounds__(WG) void tail_update_kernel(SpArgs a, int p0, int t
     const int64_t per = (int64_t)tiles_r * tiles_c, total = per * a.ntasks;
     for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
         const int task = (int)(b / per), tt = (int)(b % per);
-        double* T = a.fac + (int64_t)task * a.fstride + a.ix.tail_off;
+        double* T = a.dense + (int64_t)task * a.dstride;
         const int r0 = p0 + NB + 128 * (tt / tiles_c), c0 = p0 + NB + 64 * (tt % tiles_c);
         gemm_mfma<NB>(T, ld, r0, min(r0 + 128, ld), c0, min(c0 + 64, ld), p0, NB, Us);
     }
@@ -854,28 +918,46 @@ __global__ void tail_fwd_ext_kernel(SpArgs a) {
     const SpIdx& ix = a.ix;
     const int n = ix.n, nl = ix.nnzl, nrhs = a.nrhs, b0 = ix.tail_b0;
     const int64_t per = (int64_t)ix.tail_n * nrhs, total = per * a.ntasks;
+    const bool il = a.vs != 1;      // interleaved: consecutive threads serve consecutive systems
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
-        const int task = (int)(g / per), t = (int)(g % per);
+        const int task = il ? (int)(g % a.ntasks) : (int)(g / per);
+        const int t = il ? (int)(g / a.ntasks) : (int)(g % per);
         if (a.info[task]) continue;
         const int i = b0 + t / nrhs, r = t % nrhs;
-        const double* ud = a.fac + (int64_t)task * a.fstride;
-        const double* m = TRANS ? ud + n + nl : ud + n;
-        double* y = a.y + (int64_t)task * n * nrhs;
-        double acc = y[(int64_t)i * nrhs + r];
+        const int64_t vs = a.vs, ys = a.yv;
+        const double* m = a.fac + (int64_t)task * a.ts + (int64_t)(TRANS ? n + nl : n) * vs;
+        double* y = a.y + (int64_t)task * a.yt + (int64_t)r * ys;
+        double acc = y[(int64_t)i * nrhs * ys];
         const int p0 = ix.r_ptr[i], pe = p0 + ix.tail_rcnt[i - b0];
         int p = p0;
-        for (; p + U8 <= pe; p += U8) {
-            double mv[U8], yv[U8];
+        if (p + U16 <= pe) {
+            // the indices of the next block are fetched while this block's values are in flight
+            int ip[U16], iy[U16];
 #pragma unroll
-            for (int w = 0; w < U8; ++w) {
-                mv[w] = m[ix.r_pos[p + w]];
-                yv[w] = y[(int64_t)ix.r_idx[p + w] * nrhs + r];
+            for (int w = 0; w < U16; ++w) {
+                ip[w] = ix.r_pos[p + w];
+                iy[w] = ix.r_idx[p + w];
             }
+            for (; p + U16 <= pe; p += U16) {
+                double mv[U16], yw[U16];
 #pragma unroll
-            for (int w = 0; w < U8; ++w) acc = fmad(-mv[w], yv[w], acc);
+                for (int w = 0; w < U16; ++w) {
+                    mv[w] = m[ip[w] * vs];
+                    yw[w] = y[(int64_t)iy[w] * nrhs * ys];
+                }
+                if (p + 2 * U16 <= pe) {
+#pragma unroll
+                    for (int w = 0; w < U16; ++w) {
+                        ip[w] = ix.r_pos[p + U16 + w];
+                        iy[w] = ix.r_idx[p + U16 + w];
+                    }
+                }
+#pragma unroll
+                for (int w = 0; w < U16; ++w) acc = fmad(-mv[w], yw[w], acc);
+            }
         }
-        for (; p < pe; ++p) acc = fmad(-m[ix.r_pos[p]], y[(int64_t)ix.r_idx[p] * nrhs + r], acc);
-        y[(int64_t)i * nrhs + r] = acc;
+        for (; p < pe; ++p) acc = fmad(-m[ix.r_pos[p] * vs], y[(int64_t)ix.r_idx[p] * nrhs * ys], acc);
+        y[(int64_t)i * nrhs * ys] = acc;
     }
 }
 
@@ -892,8 +974,8 @@ __global__ void tail_rhs_in_kernel(SpArgs a) {
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
         const int task = (int)(g / per), t = (int)(g % per);
         const int q = t % ld, r = t / ld;
-        double* R = a.fac + (int64_t)task * a.fstride + ix.tail_off + (int64_t)ld * ld;
-        R[(int64_t)r * ld + q] = q < ix.tail_n ? a.y[((int64_t)task * n + ix.tail_b0 + q) * nrhs + r] : 0.0;
+        double* R = a.dense + (int64_t)task * a.dstride + (int64_t)ld * ld;
+        R[(int64_t)r * ld + q] = q < ix.tail_n ? a.y[task * a.yt + ((int64_t)(ix.tail_b0 + q) * nrhs + r) * a.yv] : 0.0;
     }
 }
 
@@ -904,8 +986,8 @@ __global__ void tail_rhs_out_kernel(SpArgs a) {
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
         const int task = (int)(g / per), t = (int)(g % per);
         const int q = t % nt, r = t / nt;
-        const double* R = a.fac + (int64_t)task * a.fstride + ix.tail_off + (int64_t)ld * ld;
-        a.y[((int64_t)task * n + ix.tail_b0 + q) * nrhs + r] = R[(int64_t)r * ld + q];
+        const double* R = a.dense + (int64_t)task * a.dstride + (int64_t)ld * ld;
+        a.y[task * a.yt + ((int64_t)(ix.tail_b0 + q) * nrhs + r) * a.yv] = R[(int64_t)r * ld + q];
     }
 }
 
@@ -917,7 +999,7 @@ __global__ __launch_bounds__(WG) void tail_tri_diag_kernel(SpArgs a, int c0) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     for (int task = blockIdx.x; task < a.ntasks; task += gridDim.x) {
         if (a.info[task]) continue;
-        const double* M = a.fac + (int64_t)task * a.fstride + a.ix.tail_off;
+        const double* M = a.dense + (int64_t)task * a.dstride;
         double* R = const_cast<double*>(M) + (int64_t)ld * ld;
         for (int t = tid; t < SB * SB; t += WG) {
             const int i = t % SB, j = t / SB;
@@ -960,7 +1042,7 @@ __global__ void tail_tri_rest_kernel(SpArgs a, int c0) {
         const int task = (int)(g / per), t = (int)(g % per);
         if (a.info[task]) continue;
         const int i = lo + t % (hi - lo), r = t / (hi - lo);
-        const double* M = a.fac + (int64_t)task * a.fstride + a.ix.tail_off;
+        const double* M = a.dense + (int64_t)task * a.dstride;
         double* R = const_cast<double*>(M) + (int64_t)ld * ld;
         const double* xb = R + (int64_t)r * ld + c0;
         double v = R[(int64_t)r * ld + i];
@@ -976,6 +1058,31 @@ __global__ void tail_tri_rest_kernel(SpArgs a, int c0) {
             }
         }
         R[(int64_t)r * ld + i] = v;
+    }
+}
+
+// One workgroup per system (large batches): the block's whole LU with super-panels and MFMA
+// updates, or one triangular solve; the same operations in the same order as the per-panel and
+// per-block kernels above, so the same bits.
+__global__ __launch_bounds__(WG) void tail_lu_slot_kernel(SpArgs a) {
+    extern __shared__ double lds[];
+    const int ld = a.ix.tail_ld;
+    for (int task = blockIdx.x; task < a.ntasks; task += gridDim.x) {
+        double* T = a.dense + (int64_t)task * a.dstride;
+        const int bad = factor_slot(T, ld, ld, ld, lds);
+        if (threadIdx.x == 0 && bad) atomicMin(&a.info[task], a.ix.tail_b0 + bad);
+        __syncthreads();
+    }
+}
+
+template <int LOWER, int TRANS>
+__global__ __launch_bounds__(WG) void tail_tri_slot_kernel(SpArgs a) {
+    extern __shared__ double lds[];
+    const int ld = a.ix.tail_ld;
+    for (int task = blockIdx.x; task < a.ntasks; task += gridDim.x) {
+        if (a.info[task]) continue;                  // uniform per workgroup
+        double* T = a.dense + (int64_t)task * a.dstride;
+        tri_solve<LOWER, TRANS>(T, ld, ld, T + (int64_t)ld * ld, a.nrhs, lds);
     }
 }
 
@@ -1145,11 +1252,14 @@ __device__ __forceinline__ void il_solve_item(const IlArgs& a, int i, int r, int
     y[((int64_t)i * nrhs + r) * TP + q] = acc;
 }
 
-__global__ void il_gather_kernel(IlArgs a, EpsSet es) {
-    const int64_t total = (int64_t)(a.ix.n + a.ix.nnzl) * a.TP;
+// Positions [0, npos) of L and U and diagonal entries [0, ndiag) (all of them: nnzl and n; below
+// a dense trailing block only its columns' positions and diagonal, the block being gathered on
+// its own).
+__global__ void il_gather_kernel(IlArgs a, EpsSet es, int npos, int ndiag) {
+    const int64_t total = (int64_t)(npos + ndiag) * a.TP;
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
-        const int q = (int)(g % a.TP);
-        if (q < a.ntasks) il_gather_item(a, es, (int)(g / a.TP), q);
+        const int q = (int)(g % a.TP), v = (int)(g / a.TP);
+        if (q < a.ntasks) il_gather_item(a, es, v < npos ? v : a.ix.nnzl + (v - npos), q);
     }
 }
 
@@ -1180,12 +1290,12 @@ __global__ void il_rhs_in_kernel(IlArgs a) {
 }
 
 template <int UPPER>
-__global__ void il_solve_level_kernel(IlArgs a, int c0, int cnt) {
+__global__ void il_solve_level_kernel(IlArgs a, const int32_t* lev_idx, int c0, int cnt) {
     const int nrhs = a.nrhs;
     const int64_t total = (int64_t)cnt * nrhs * a.TP;
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
         const int q = (int)(g % a.TP), v = (int)(g / a.TP);
-        if (q < a.ntasks) il_solve_item<UPPER>(a, a.ix.lev_idx[UPPER ? 2 : 1][c0 + v / nrhs], v % nrhs, q);
+        if (q < a.ntasks) il_solve_item<UPPER>(a, lev_idx[c0 + v / nrhs], v % nrhs, q);
     }
 }
 
@@ -1273,10 +1383,11 @@ int64_t fbase_of(const Symbolic& s) { return (s.n + 2 * (int64_t)s.l_ptr[s.n] + 
 int64_t tail_panel_of(const Symbolic& s) {
     return s.tail_tiles ? (16 * ((int64_t)s.tail_kt.size() + s.tail_tiles) + 31) / 32 * 32 : 0;
 }
-int64_t fstride_of(const Symbolic& s) {
+int64_t dstride_of(const Symbolic& s) {
     const int64_t ld = tail_ld_of(s);
-    return fbase_of(s) + ld * ld + ld * 64 + 2 * tail_panel_of(s);
+    return ld * ld + ld * 64 + 2 * tail_panel_of(s);
 }
+int64_t fstride_of(const Symbolic& s) { return fbase_of(s) + dstride_of(s); }
 
 int64_t tp_of(int64_t ntasks) { return (ntasks + 63) / 64 * 64; }
 
@@ -1322,11 +1433,18 @@ SpLayout sp_layout(const Symbolic& s, int32_t batch, int32_t K, int32_t nrhs, in
     }
     const bool lds = var == kVarLds || var == kVarSteps;
     int64_t off = lds ? 0 : align256(ntasks * fstride_of(s) * 8);
+    if (var == kVarTail && !keep) {
+        // the interleaved form of the fused call: [ factors ((n + 2 nnzl) x TP) | blocks | y ((n nrhs) x TP) ]
+        const int64_t TP = tp_of(ntasks);
+        const int64_t il = align256(align256(align256(((int64_t)s.n + 2 * (int64_t)s.l_ptr[s.n]) * TP * 8) +
+                                             ntasks * dstride_of(s) * 8) + (int64_t)s.n * nrhs * TP * 8);
+        L.total = std::max<int64_t>(il, align256(off + 2 * ntasks * (int64_t)s.n * nrhs * 8));
+    }
     L.off_y = off;
     if (!lds) off = align256(off + ntasks * (int64_t)s.n * nrhs * 8);
     L.off_xk = off;
     if (!keep) off = align256(off + ntasks * (int64_t)s.n * nrhs * 8);
-    L.total = std::max<int64_t>(off, 256);
+    L.total = std::max<int64_t>(std::max<int64_t>(off, 256), L.total);
     return L;
 }
 
@@ -1347,7 +1465,8 @@ hipError_t batched_run(const Symbolic& s, const SparseDevice& d, int32_t batch, 
                            a, es);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(il_gather_kernel, dim3(grid_for((int64_t)(n + nl) * a.TP, kThreads)), dim3(kThreads), 0, st, a, es);
+    hipLaunchKernelGGL(il_gather_kernel, dim3(grid_for((int64_t)(n + nl) * a.TP, kThreads)), dim3(kThreads), 0, st, a, es,
+                       nl, n);
     for (int l = 0; l < a.ix.nlev[0]; ++l) {
         const int c0 = d.h_lev_ptr[0][l], cnt = d.h_lev_ptr[0][l + 1] - c0;
         hipLaunchKernelGGL(il_diag_kernel, dim3(grid_for((int64_t)cnt * a.TP, kThreads)), dim3(kThreads), 0, st, a, c0, cnt);
@@ -1360,12 +1479,12 @@ hipError_t batched_run(const Symbolic& s, const SparseDevice& d, int32_t batch, 
     for (int l = 0; l < a.ix.nlev[1]; ++l) {
         const int c0 = d.h_lev_ptr[1][l], cnt = d.h_lev_ptr[1][l + 1] - c0;
         hipLaunchKernelGGL(il_solve_level_kernel<0>, dim3(grid_for((int64_t)cnt * nrhs * a.TP, kThreads)),
-                           dim3(kThreads), 0, st, a, c0, cnt);
+                           dim3(kThreads), 0, st, a, a.ix.lev_idx[1], c0, cnt);
     }
     for (int l = 0; l < a.ix.nlev[2]; ++l) {
         const int c0 = d.h_lev_ptr[2][l], cnt = d.h_lev_ptr[2][l + 1] - c0;
         hipLaunchKernelGGL(il_solve_level_kernel<1>, dim3(grid_for((int64_t)cnt * nrhs * a.TP, kThreads)),
-                           dim3(kThreads), 0, st, a, c0, cnt);
+                           dim3(kThreads), 0, st, a, a.ix.lev_idx[2], c0, cnt);
     }
     hipLaunchKernelGGL(il_combine_kernel, dim3(grid_for((int64_t)batch * n * nrhs, kThreads)), dim3(kThreads), 0, st, a,
                        es);
@@ -1399,31 +1518,49 @@ hipError_t factor_global(const SparseDevice& d, SpArgs a, const EpsSet& es, hipS
     return hipGetLastError();
 }
 
-hipError_t factor_tail(const SparseDevice& d, SpArgs a, const EpsSet& es, hipStream_t st, int cols = 16) {
-    hipLaunchKernelGGL(sp_gather_kernel, dim3(grid_for((int64_t)(a.ix.n + a.ix.nnzl) * a.ntasks, kThreads)),
-                       dim3(kThreads), 0, st, a, es);
-    for (int l = 0; l < a.ix.fac_lev_sp; ++l) {
-        const int c0 = d.h_lev_ptr[0][l], cnt = d.h_lev_ptr[0][l + 1] - c0;
-        hipLaunchKernelGGL(sp_diag_kernel, dim3(grid_for((int64_t)cnt * a.ntasks, kThreads)), dim3(kThreads), 0, st,
-                           a, c0, cnt);
-        const int p0 = d.h_lpos_ptr[l], np = d.h_lpos_ptr[l + 1] - p0;
-        if (np > 0)
-            hipLaunchKernelGGL(sp_offdiag_kernel, dim3(grid_for((int64_t)2 * np * a.ntasks, kThreads)), dim3(kThreads),
-                               0, st, a, p0, np);
-    }
+// Task-major addressing of the dense-block kernels: each system's block inside its factors.
+void tail_task_major(SpArgs& a) {
+    a.vs = 1;
+    a.ts = a.fstride;
+    a.dense = a.fac + a.ix.tail_off;
+    a.dstride = a.fstride;
+    a.yv = 1;
+    a.yt = (int64_t)a.ix.n * a.nrhs;
+}
+
+// One workgroup per system for the block's LU and solves (a tuning choice: at n = 2709 and 550
+// systems the per-panel launches across the device are faster).
+bool tail_slot(const Knobs& kn, int64_t) { return kn.tail_lu == 1; }
+
+// Assembly and LU of every system's dense block, the factors below it done (any addressing; the
+// column-wise assembly only task-major).
+hipError_t tail_dense_factor(SpArgs a, const EpsSet& es, hipStream_t st, int cols, bool slot) {
     const int ld = a.ix.tail_ld;
     if (cols == 16 && a.ix.tail_tiles > 0) {
-        const int64_t e = a.ix.tail_n;
-        const int64_t per = a.ix.tail_panel + (int64_t)ld * ld - e * e;
-        hipLaunchKernelGGL(tail_panel_gather_kernel, dim3(grid_for(per * a.ntasks, kThreads)), dim3(kThreads), 0, st, a);
-        const int64_t pairs = (int64_t)a.ix.tail_tiles * a.ix.tail_tiles;
-        const int64_t wgs = (pairs + kTpWaves - 1) / kTpWaves * a.ntasks;
+        if (!a.values) return hipErrorInvalidValue;   // the block's initial values come from the Jacobians
+        hipLaunchKernelGGL(tail_block_init_kernel, dim3(grid_for((int64_t)ld * ld * a.ntasks, kThreads)), dim3(kThreads),
+                           0, st, a, es);
+        if (a.vs == 1) {
+            hipLaunchKernelGGL(tail_panel_gather_kernel, dim3(grid_for(a.ix.tail_panel * a.ntasks, kThreads)),
+                               dim3(kThreads), 0, st, a);
+        } else {
+            const int64_t ech = (a.ix.tail_panel + 63) / 64, tch = (a.ntasks + 63) / 64;
+            if (ech * tch > INT32_MAX) return hipErrorInvalidValue;
+            hipLaunchKernelGGL(tail_panel_gather_il_kernel, dim3((unsigned)(ech * tch)), dim3(256), 0, st, a, (int)ech);
+        }
+        const int64_t items = (int64_t)a.ix.tail_tiles * a.ix.tail_tiles * a.ntasks;
+        const int64_t wgs = (items + kTpWaves - 1) / kTpWaves;
         if ((wgs + 7) / 8 * 8 > INT32_MAX) return hipErrorInvalidValue;
-        hipLaunchKernelGGL(tail_tile_kernel, dim3((unsigned)((wgs + 7) / 8 * 8)), dim3(64 * kTpWaves), 0, st, a, wgs);
+        hipLaunchKernelGGL(tail_tile_kernel, dim3((unsigned)((wgs + 7) / 8 * 8)), dim3(64 * kTpWaves), 0, st, a, items);
     } else {
+        if (a.vs != 1) return hipErrorInvalidValue;
         cols = cols == 1 ? 1 : kAsmCols;
         hipLaunchKernelGGL(tail_assemble_kernel, dim3((int)std::min<int64_t>((int64_t)(ld / cols) * a.ntasks, 1 << 20)),
                            dim3(kAsmThreads), (int)tail_asm_lds(a.ix.tail_b0), st, a, cols);
+    }
+    if (slot) {
+        hipLaunchKernelGGL(tail_lu_slot_kernel, dim3(std::min(a.ntasks, 65535)), dim3(WG), kLdsFactor, st, a);
+        return hipGetLastError();
     }
     for (int p0 = 0; p0 < ld; p0 += NB) {
         hipLaunchKernelGGL(tail_panel_kernel, dim3(std::min(a.ntasks, 65535)), dim3(WG), 0, st, a, p0);
@@ -1435,18 +1572,31 @@ hipError_t factor_tail(const SparseDevice& d, SpArgs a, const EpsSet& es, hipStr
                                tr, tc);
         }
     }
+    return hipGetLastError();
+}
+
+hipError_t factor_tail(const SparseDevice& d, SpArgs a, const EpsSet& es, hipStream_t st, const Knobs& kn = Knobs()) {
+    tail_task_major(a);
+    hipLaunchKernelGGL(sp_gather_kernel, dim3(grid_for((int64_t)(a.ix.n + a.ix.nnzl) * a.ntasks, kThreads)),
+                       dim3(kThreads), 0, st, a, es);
+    for (int l = 0; l < a.ix.fac_lev_sp; ++l) {
+        const int c0 = d.h_lev_ptr[0][l], cnt = d.h_lev_ptr[0][l + 1] - c0;
+        hipLaunchKernelGGL(sp_diag_kernel, dim3(grid_for((int64_t)cnt * a.ntasks, kThreads)), dim3(kThreads), 0, st,
+                           a, c0, cnt);
+        const int p0 = d.h_lpos_ptr[l], np = d.h_lpos_ptr[l + 1] - p0;
+        if (np > 0)
+            hipLaunchKernelGGL(sp_offdiag_kernel, dim3(grid_for((int64_t)2 * np * a.ntasks, kThreads)), dim3(kThreads),
+                               0, st, a, p0, np);
+    }
+    hipError_t e = tail_dense_factor(a, es, st, kn.tail_cols, tail_slot(kn, a.ntasks));
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(sp_info_kernel, dim3((a.ntasks + 255) / 256), dim3(256), 0, st, a.info, a.ntasks);
     return hipGetLastError();
 }
 
-hipError_t solve_tail(const SparseDevice& d, SpArgs a, hipStream_t st) {
-    const int64_t items = (int64_t)a.ix.n * a.nrhs * a.ntasks;
-    hipLaunchKernelGGL(sp_rhs_in_kernel, dim3(grid_for(items, kThreads)), dim3(kThreads), 0, st, a);
-    for (int l = 0; l < a.ix.nlev_sp[0]; ++l) {
-        const int c0 = d.h_lev_sp_ptr[0][l], cnt = d.h_lev_sp_ptr[0][l + 1] - c0;
-        hipLaunchKernelGGL(sp_solve_level_kernel<0>, dim3(grid_for((int64_t)cnt * a.nrhs * a.ntasks, kThreads)),
-                           dim3(kThreads), 0, st, a, a.ix.lev_sp_idx[0], c0, cnt);
-    }
+// The block rows of the substitutions: their updates from the sparse part, then the block's own
+// triangular solves (any addressing).
+hipError_t tail_dense_solve(SpArgs a, hipStream_t st, bool slot) {
     const int64_t trows = (int64_t)a.ix.tail_n * a.nrhs * a.ntasks;
     const int64_t tpad = (int64_t)a.ix.tail_ld * a.nrhs * a.ntasks;
     if (a.trans)
@@ -1454,17 +1604,112 @@ hipError_t solve_tail(const SparseDevice& d, SpArgs a, hipStream_t st) {
     else
         hipLaunchKernelGGL(tail_fwd_ext_kernel<0>, dim3(grid_for(trows, kThreads)), dim3(kThreads), 0, st, a);
     hipLaunchKernelGGL(tail_rhs_in_kernel, dim3(grid_for(tpad, kThreads)), dim3(kThreads), 0, st, a);
-    hipError_t e = a.trans ? tail_tri<1, 1>(a, st) : tail_tri<1, 0>(a, st);
-    if (e != hipSuccess) return e;
-    e = a.trans ? tail_tri<0, 1>(a, st) : tail_tri<0, 0>(a, st);
-    if (e != hipSuccess) return e;
+    if (slot) {
+        const dim3 g(std::min(a.ntasks, 65535));
+        if (a.trans) {
+            hipLaunchKernelGGL((tail_tri_slot_kernel<1, 1>), g, dim3(WG), kLdsSolve, st, a);
+            hipLaunchKernelGGL((tail_tri_slot_kernel<0, 1>), g, dim3(WG), kLdsSolve, st, a);
+        } else {
+            hipLaunchKernelGGL((tail_tri_slot_kernel<1, 0>), g, dim3(WG), kLdsSolve, st, a);
+            hipLaunchKernelGGL((tail_tri_slot_kernel<0, 0>), g, dim3(WG), kLdsSolve, st, a);
+        }
+    } else {
+        hipError_t e = a.trans ? tail_tri<1, 1>(a, st) : tail_tri<1, 0>(a, st);
+        if (e != hipSuccess) return e;
+        e = a.trans ? tail_tri<0, 1>(a, st) : tail_tri<0, 0>(a, st);
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(tail_rhs_out_kernel, dim3(grid_for(trows, kThreads)), dim3(kThreads), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t solve_tail(const SparseDevice& d, SpArgs a, hipStream_t st, const Knobs& kn = Knobs()) {
+    tail_task_major(a);
+    const int64_t items = (int64_t)a.ix.n * a.nrhs * a.ntasks;
+    hipLaunchKernelGGL(sp_rhs_in_kernel, dim3(grid_for(items, kThreads)), dim3(kThreads), 0, st, a);
+    for (int l = 0; l < a.ix.nlev_sp[0]; ++l) {
+        const int c0 = d.h_lev_sp_ptr[0][l], cnt = d.h_lev_sp_ptr[0][l + 1] - c0;
+        hipLaunchKernelGGL(sp_solve_level_kernel<0>, dim3(grid_for((int64_t)cnt * a.nrhs * a.ntasks, kThreads)),
+                           dim3(kThreads), 0, st, a, a.ix.lev_sp_idx[0], c0, cnt);
+    }
+    hipError_t e = tail_dense_solve(a, st, tail_slot(kn, a.ntasks));
+    if (e != hipSuccess) return e;
     for (int l = 0; l < a.ix.nlev_sp[1]; ++l) {
         const int c0 = d.h_lev_sp_ptr[1][l], cnt = d.h_lev_sp_ptr[1][l + 1] - c0;
         hipLaunchKernelGGL(sp_solve_level_kernel<1>, dim3(grid_for((int64_t)cnt * a.nrhs * a.ntasks, kThreads)),
                            dim3(kThreads), 0, st, a, a.ix.lev_sp_idx[1], c0, cnt);
     }
     hipLaunchKernelGGL(sp_rhs_out_kernel, dim3(grid_for(items, kThreads)), dim3(kThreads), 0, st, a);
+    return hipGetLastError();
+}
+
+// The fused call on the dense-block path with the systems interleaved below the block (the
+// batched kernels' layout: a wave serves one item of 64 systems, index loads uniform, value
+// loads contiguous), each system's block task-major in a region of its own.
+// The interleaved form needs the pair lists below the block and the tile-pair assembly; by
+// default it is taken for 64 systems or more.
+bool tail_il_ok(const Symbolic& s, const SparseDevice& d, int64_t ntasks, const Knobs& kn) {
+    if (!d.idx.use_pairs || d.idx.pairs_below < s.tail_b0 || d.idx.tail_tiles == 0 || kn.tail_cols != 16) return false;
+    return kn.tail_il < 0 ? ntasks >= 64 : kn.tail_il == 1;
+}
+
+hipError_t tail_il_run(const Symbolic& s, const SparseDevice& d, int32_t batch, const double* values,
+                       const EpsSet& es, const double* dvec, int32_t nrhs, const double* B, double* X, int32_t* info,
+                       char* w, hipStream_t st, const Knobs& kn) {
+    if (!d.idx.use_pairs || d.idx.pairs_below < s.tail_b0 || d.idx.tail_tiles == 0) return hipErrorInvalidValue;
+    IlArgs ia{};
+    ia.ix = d.idx;
+    ia.nnz = s.nnz; ia.nrhs = nrhs; ia.ntasks = batch * es.K; ia.TP = (int32_t)tp_of(ia.ntasks); ia.K = es.K;
+    ia.batch = batch; ia.values = values; ia.dvec = dvec; ia.B = B; ia.X = X; ia.info = info;
+    const int n = s.n, nl = s.l_ptr[n];
+    const int64_t off_dense = align256(((int64_t)n + 2 * (int64_t)nl) * ia.TP * 8);
+    const int64_t off_y = align256(off_dense + (int64_t)ia.ntasks * dstride_of(s) * 8);
+    ia.fac = (double*)w;
+    ia.y = (double*)(w + off_y);
+    const int npos = s.l_ptr[s.tail_b0];
+    hipLaunchKernelGGL(il_gather_kernel, dim3(grid_for((int64_t)(npos + s.tail_b0) * ia.TP, kThreads)), dim3(kThreads), 0,
+                       st, ia, es, npos, s.tail_b0);
+    for (int l = 0; l < ia.ix.fac_lev_sp; ++l) {
+        const int c0 = d.h_lev_ptr[0][l], cnt = d.h_lev_ptr[0][l + 1] - c0;
+        hipLaunchKernelGGL(il_diag_kernel, dim3(grid_for((int64_t)cnt * ia.TP, kThreads)), dim3(kThreads), 0, st, ia, c0,
+                           cnt);
+        const int p0 = d.h_lpos_ptr[l], np = d.h_lpos_ptr[l + 1] - p0;
+        if (np > 0)
+            hipLaunchKernelGGL(il_offdiag_kernel, dim3(grid_for((int64_t)2 * np * ia.TP, kThreads)), dim3(kThreads), 0, st,
+                               ia, p0, np);
+    }
+    SpArgs a = make_args(d, s, ia.ntasks, es.K, nrhs);
+    a.values = values;
+    a.dvec = dvec;
+    a.B = B;
+    a.info = info;
+    a.fac = ia.fac;
+    a.vs = ia.TP;
+    a.ts = 1;
+    a.dense = (double*)(w + off_dense);
+    a.dstride = dstride_of(s);
+    a.y = ia.y;
+    a.yv = ia.TP;
+    a.yt = 1;
+    const bool slot = tail_slot(kn, a.ntasks);
+    hipError_t e = tail_dense_factor(a, es, st, 16, slot);
+    if (e != hipSuccess) return e;
+    // clears the unbroken systems' info (the gather's INT_MAX) before anything reads it
+    hipLaunchKernelGGL(il_rhs_in_kernel, dim3(grid_for((int64_t)n * nrhs * ia.TP, kThreads)), dim3(kThreads), 0, st, ia);
+    for (int l = 0; l < ia.ix.nlev_sp[0]; ++l) {
+        const int c0 = d.h_lev_sp_ptr[0][l], cnt = d.h_lev_sp_ptr[0][l + 1] - c0;
+        hipLaunchKernelGGL(il_solve_level_kernel<0>, dim3(grid_for((int64_t)cnt * nrhs * ia.TP, kThreads)),
+                           dim3(kThreads), 0, st, ia, ia.ix.lev_sp_idx[0], c0, cnt);
+    }
+    e = tail_dense_solve(a, st, slot);
+    if (e != hipSuccess) return e;
+    for (int l = 0; l < ia.ix.nlev_sp[1]; ++l) {
+        const int c0 = d.h_lev_sp_ptr[1][l], cnt = d.h_lev_sp_ptr[1][l + 1] - c0;
+        hipLaunchKernelGGL(il_solve_level_kernel<1>, dim3(grid_for((int64_t)cnt * nrhs * ia.TP, kThreads)),
+                           dim3(kThreads), 0, st, ia, ia.ix.lev_sp_idx[1], c0, cnt);
+    }
+    hipLaunchKernelGGL(il_combine_kernel, dim3(grid_for((int64_t)batch * n * nrhs, kThreads)), dim3(kThreads), 0, st, ia,
+                       es);
     return hipGetLastError();
 }
 
@@ -1727,12 +1972,14 @@ hipError_t sparse_solve_batched(const Symbolic& s, const SparseDevice& d, int32_
         e = hipGetLastError();
         if (e != hipSuccess || a.per_jacobian) return e;
     } else {
+        const bool tail = var == kVarTail;
+        if (tail && tail_il_ok(s, d, ntasks, kn))
+            return tail_il_run(s, d, batch, values, es, dvec, nrhs, B, X, info, w, st, kn);
         a.fac = (double*)(w + L.off_fac);
         a.y = (double*)(w + L.off_y);
-        const bool tail = var == kVarTail;
-        hipError_t e = tail ? factor_tail(d, a, es, st, kn.tail_cols) : factor_global(d, a, es, st);
+        hipError_t e = tail ? factor_tail(d, a, es, st, kn) : factor_global(d, a, es, st);
         if (e != hipSuccess) return e;
-        e = tail ? solve_tail(d, a, st) : solve_global(d, a, st);
+        e = tail ? solve_tail(d, a, st, kn) : solve_global(d, a, st);
         if (e != hipSuccess) return e;
     }
     return launch_combine((int64_t)s.n * nrhs, batch, es, a.Xk, X, st);

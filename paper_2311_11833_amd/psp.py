@@ -49,11 +49,11 @@ class PlanInfo(C.Structure):
 
 class TuneChoice(C.Structure):
     _fields_ = [("path", C.c_int32), ("steps_mode", C.c_int32), ("steps_wgcu", C.c_int32), ("ring", C.c_int32),
-                ("tail_cols", C.c_int32), ("ms", C.c_float), ("source", C.c_int32)]
+                ("tail_cols", C.c_int32), ("tail_il", C.c_int32), ("tail_lu", C.c_int32), ("ms", C.c_float), ("source", C.c_int32)]
 
     def as_dict(self):
         return {"path": PATH_NAMES.get(self.path, self.path), "steps_mode": self.steps_mode,
-                "steps_wgcu": self.steps_wgcu, "ring": self.ring, "tail_cols": self.tail_cols,
+                "steps_wgcu": self.steps_wgcu, "ring": self.ring, "tail_cols": self.tail_cols, "tail_il": self.tail_il, "tail_lu": self.tail_lu,
                 "ms": float(self.ms), "source": {0: "heuristic", 1: "tuned", 2: "cache file"}[self.source]}
 
 
@@ -463,9 +463,10 @@ def tune_choice(plan: Plan, batch: int, K: int, nrhs: int = 1) -> dict:
 
 
 def set_tune_choice(plan: Plan, batch: int, K: int, nrhs: int = 1, path: str = "sparse_steps", steps_mode: int = -1,
-                    steps_wgcu: int = 0, ring: int = 7, tail_cols: int = 16) -> None:
+                    steps_wgcu: int = 0, ring: int = 7, tail_cols: int = 16, tail_il: int = -1,
+                    tail_lu: int = 0) -> None:
     """Pins the path and launch choices of PSP_PATH_AUTO for (batch, K, nrhs)."""
-    c = TuneChoice(PATHS[path], steps_mode, steps_wgcu, ring, tail_cols, -1.0, 1)
+    c = TuneChoice(PATHS[path], steps_mode, steps_wgcu, ring, tail_cols, tail_il, tail_lu, -1.0, 1)
     _check(lib().psp_set_tune_choice(plan.handle, batch, K, nrhs, C.byref(c)))
 
 

@@ -324,6 +324,36 @@ def test_dense_tail_path_matches_oracle(psp, O, W, dev, N, count, nrhs):
     _cmp(x.cpu().numpy(), xo)
 
 
+@pytest.mark.parametrize("count,nrhs", [(14, 1), (13, 2)])
+def test_dense_tail_interleaved_matches_oracle(psp, O, W, dev, count, nrhs):
+    """From 64 systems on, the fused call keeps the factors below the block interleaved across
+    systems (one wave serves an item of 64 systems) and each block in a region of its own: one
+    Jacobian broken below the block, one inside it; info equal to the oracle's, the broken ones
+    NaN, every other solution bitwise equal."""
+    ip, ix, vals, bs = W.scenario_batch(1354, count)
+    n = len(ip) - 1
+    vals = vals.copy()
+    vals[2, 0] = np.nan
+    lam_entries = np.nonzero(ix == n - 1)[0]
+    vals[5, lam_entries[len(lam_entries) // 3]] = np.inf
+    if nrhs > 1:
+        bs = np.random.default_rng(count).standard_normal((count, n, nrhs))
+    eps = W.config_eps("n601")
+    plan = psp.Plan(ip, ix)
+    print(f"[gpu sparse] dense tail interleaved count={count} nrhs={nrhs}", flush=True)
+    x, info = psp.solve_batched(plan, torch.from_numpy(vals).to(dev), eps, torch.from_numpy(bs).to(dev),
+                                path="sparse_tail")
+    torch.cuda.synchronize()
+    sym = O.symbolic(n, ip, ix)
+    xo, io, _, _ = O.sparse_batch(n, ip, ix, vals, sym, eps, bs)
+    ig, xg = info.cpu().numpy(), x.cpu().numpy()
+    assert np.array_equal(ig, io) and np.all(ig[2] > 0) and np.all(ig[5] > 0)
+    assert np.all(np.isnan(xg[2])) and np.all(np.isnan(xg[5]))
+    keep = np.ones(count, bool)
+    keep[[2, 5]] = False
+    _cmp(xg[keep], xo[keep])
+
+
 def test_dense_tail_breakdown_inside_block(psp, O, W, dev):
     """A NaN entry in the slack column (inside the dense block) breaks that Jacobian's K systems at
     the same pivot as the oracle's; the other Jacobian is untouched."""

@@ -54,15 +54,17 @@ def test_tail_assembly_choices_match_oracle(dev, O, W):
     sym = O.symbolic(n, ip, ix)
     xo, io, _, _ = O.sparse_batch(n, ip, ix, vals, sym, eps, bs)
     v, b = torch.from_numpy(vals).to(dev), torch.from_numpy(bs).to(dev)
-    for cols in (16, 4, 1):
-        print(f"[gpu tune] tail cols={cols}", flush=True)
-        psp.set_tune_choice(plan, 3, len(eps), 1, "sparse_tail", tail_cols=cols)
+    for cols, il, lu in ((16, 1, 1), (16, 1, 0), (16, 0, 1), (16, 0, 0), (4, 0, 1), (1, 0, 0)):
+        print(f"[gpu tune] tail cols={cols} interleaved={il} lu={lu}", flush=True)
+        psp.set_tune_choice(plan, 3, len(eps), 1, "sparse_tail", tail_cols=cols, tail_il=il, tail_lu=lu)
         x, info = psp.solve_batched(plan, v, eps, b, path="auto")
         torch.cuda.synchronize()
         assert np.array_equal(info.cpu().numpy(), io)
         assert np.array_equal(x.cpu().numpy(), xo)
     with pytest.raises(psp.PSPError):
         psp.set_tune_choice(plan, 3, len(eps), 1, "sparse_tail", tail_cols=3)
+    with pytest.raises(psp.PSPError):
+        psp.set_tune_choice(plan, 3, len(eps), 1, "sparse_tail", tail_il=2)
 
 
 _CHILD = r"""
@@ -102,6 +104,6 @@ def test_tuning_cache_is_reused_by_a_fresh_process(dev, tmp_path):
     print("[gpu tune] reading the cache in a second child process", flush=True)
     second = _child(False, cache)
     assert second["before"]["source"] == "cache file"
-    for key in ("path", "steps_mode", "steps_wgcu", "ring", "tail_cols"):
+    for key in ("path", "steps_mode", "steps_wgcu", "ring", "tail_cols", "tail_il", "tail_lu"):
         assert second["before"][key] == first["after"][key]
     assert second["x0"] == first["x0"]
