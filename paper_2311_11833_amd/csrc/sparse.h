@@ -42,6 +42,7 @@ struct SpIdx {
     int64_t tail_off;
     const int32_t* tail_rcnt;       // tail_n: entries below tail_b0 in each row of the block
     const int32_t* tail_lastpos;    // tail_b0: position of (n-1, k) in column k of L, or -1
+    const int32_t* tail_ccnt;       // tail_b0: entries of column k of L in rows before tail_b0
     const int32_t* lev_sp_ptr[2];   // L-solve / U-solve levels of the rows < tail_b0
     const int32_t* lev_sp_idx[2];
     // Assembly of the block on the MFMA unit (tail_tiles > 0): tiles of 16 block rows, slot s

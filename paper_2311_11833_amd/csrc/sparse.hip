@@ -195,13 +195,15 @@ __device__ __forceinline__ double fwd_row(const SpIdx& ix, int i, int r, int nrh
     return TRANS ? acc / ud[i] : acc;
 }
 
+// t_end: positions of column i from t_end on were applied beforehand (the dense trailing block's
+// rows, tail_bwd_ext_kernel); -1: none.
 template <int TRANS>
 __device__ __forceinline__ double bwd_row(const SpIdx& ix, int i, int r, int nrhs, const double* ud, const double* lv,
-                                          const double* uv, const double* y) {
+                                          const double* uv, const double* y, int t_end = -1) {
     double acc = y[(int64_t)i * nrhs + r];
     const double* m = TRANS ? lv : uv;
     const int t0 = ix.l_ptr[i];
-    int t = ix.l_ptr[i + 1] - 1;
+    int t = (t_end < 0 ? ix.l_ptr[i + 1] : t_end) - 1;
     for (; t - U8 + 1 >= t0; t -= U8) {
         double a[U8], b[U8];
 #pragma unroll
@@ -375,8 +377,9 @@ __global__ void sp_rhs_in_kernel(SpArgs a) {
     }
 }
 
+// sparse_only (U pass below a dense trailing block): the block rows' terms were applied beforehand.
 template <int UPPER_PASS>
-__global__ void sp_solve_level_kernel(SpArgs a, const int32_t* lev_idx, int c0, int cnt) {
+__global__ void sp_solve_level_kernel(SpArgs a, const int32_t* lev_idx, int c0, int cnt, int sparse_only) {
     const SpIdx& ix = a.ix;
     const int n = ix.n, nl = ix.nnzl, nrhs = a.nrhs;
     const int64_t per = (int64_t)cnt * nrhs, total = per * a.ntasks;
@@ -390,8 +393,11 @@ __global__ void sp_solve_level_kernel(SpArgs a, const int32_t* lev_idx, int c0, 
         double v;
         if (!UPPER_PASS) v = a.trans ? fwd_row<1>(ix, i, r, nrhs, ud, ud + n, ud + n + nl, y)
                                      : fwd_row<0>(ix, i, r, nrhs, ud, ud + n, ud + n + nl, y);
-        else v = a.trans ? bwd_row<1>(ix, i, r, nrhs, ud, ud + n, ud + n + nl, y)
-                         : bwd_row<0>(ix, i, r, nrhs, ud, ud + n, ud + n + nl, y);
+        else {
+            const int te = sparse_only ? ix.l_ptr[i] + ix.tail_ccnt[i] : -1;
+            v = a.trans ? bwd_row<1>(ix, i, r, nrhs, ud, ud + n, ud + n + nl, y, te)
+                        : bwd_row<0>(ix, i, r, nrhs, ud, ud + n, ud + n + nl, y, te);
+        }
         y[(int64_t)i * nrhs + r] = v;
     }
 }
@@ -961,6 +967,51 @@ __global__ void tail_fwd_ext_kernel(SpArgs a) {
     }
 }
 
+// Rows before the block, backward pass (U, or L^T when transposed): each row's chain starts with
+// the terms of the block's columns (its highest positions, descending); they are applied to every
+// row at once once the block is solved, and the levels run the rest of the chains.
+template <int TRANS>
+__global__ void tail_bwd_ext_kernel(SpArgs a) {
+    const SpIdx& ix = a.ix;
+    const int n = ix.n, nl = ix.nnzl, nrhs = a.nrhs, b0 = ix.tail_b0;
+    const int64_t per = (int64_t)b0 * nrhs, total = per * a.ntasks;
+    const bool il = a.vs != 1;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+        const int task = il ? (int)(g % a.ntasks) : (int)(g / per);
+        const int q = il ? (int)(g / a.ntasks) : (int)(g % per);
+        if (a.info[task]) continue;
+        const int i = q / nrhs, r = q % nrhs;
+        const int t0 = ix.l_ptr[i] + ix.tail_ccnt[i];
+        int t = ix.l_ptr[i + 1] - 1;
+        if (t < t0) continue;
+        const int64_t vs = a.vs, ys = a.yv;
+        const double* m = a.fac + (int64_t)task * a.ts + (int64_t)(TRANS ? n : n + nl) * vs;
+        double* y = a.y + (int64_t)task * a.yt + (int64_t)r * ys;
+        double acc = y[(int64_t)i * nrhs * ys];
+        if (t - U16 + 1 >= t0) {
+            int iy[U16];
+#pragma unroll
+            for (int w = 0; w < U16; ++w) iy[w] = ix.l_idx[t - w];
+            for (; t - U16 + 1 >= t0; t -= U16) {
+                double mv[U16], yw[U16];
+#pragma unroll
+                for (int w = 0; w < U16; ++w) {
+                    mv[w] = m[(int64_t)(t - w) * vs];
+                    yw[w] = y[(int64_t)iy[w] * nrhs * ys];
+                }
+                if (t - 2 * U16 + 1 >= t0) {
+#pragma unroll
+                    for (int w = 0; w < U16; ++w) iy[w] = ix.l_idx[t - U16 - w];
+                }
+#pragma unroll
+                for (int w = 0; w < U16; ++w) acc = fmad(-mv[w], yw[w], acc);
+            }
+        }
+        for (; t >= t0; --t) acc = fmad(-m[(int64_t)t * vs], y[(int64_t)ix.l_idx[t] * nrhs * ys], acc);
+        y[(int64_t)i * nrhs * ys] = acc;
+    }
+}
+
 // The block's own triangular solves (forward then backward, or the transposed pair) on a
 // column-major copy R of its right-hand sides (nrhs columns of stride tail_ld), by blocks of SB
 // rows: the diagonal block of every system in one workgroup (one wave per right-hand side, the
@@ -1209,7 +1260,7 @@ __device__ __forceinline__ void il_rhs_item(const IlArgs& a, int v, int q) {
 }
 
 template <int UPPER>
-__device__ __forceinline__ void il_solve_item(const IlArgs& a, int i, int r, int q) {
+__device__ __forceinline__ void il_solve_item(const IlArgs& a, int i, int r, int q, int sparse_only = 0) {
     const SpIdx& ix = a.ix;
     const int n = ix.n, nl = ix.nnzl, nrhs = a.nrhs, TP = a.TP;
     const double* ud = a.fac;
@@ -1234,7 +1285,7 @@ __device__ __forceinline__ void il_solve_item(const IlArgs& a, int i, int r, int
             acc = fmad(-lv[(int64_t)ix.r_pos[p] * TP + q], y[((int64_t)ix.r_idx[p] * nrhs + r) * TP + q], acc);
     } else {
         const int t0 = ix.l_ptr[i];
-        int t = ix.l_ptr[i + 1] - 1;
+        int t = (sparse_only ? t0 + ix.tail_ccnt[i] : ix.l_ptr[i + 1]) - 1;
         for (; t - U8 + 1 >= t0; t -= U8) {
             double x[U8], z[U8];
 #pragma unroll
@@ -1290,12 +1341,12 @@ __global__ void il_rhs_in_kernel(IlArgs a) {
 }
 
 template <int UPPER>
-__global__ void il_solve_level_kernel(IlArgs a, const int32_t* lev_idx, int c0, int cnt) {
+__global__ void il_solve_level_kernel(IlArgs a, const int32_t* lev_idx, int c0, int cnt, int sparse_only) {
     const int nrhs = a.nrhs;
     const int64_t total = (int64_t)cnt * nrhs * a.TP;
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
         const int q = (int)(g % a.TP), v = (int)(g / a.TP);
-        if (q < a.ntasks) il_solve_item<UPPER>(a, lev_idx[c0 + v / nrhs], v % nrhs, q);
+        if (q < a.ntasks) il_solve_item<UPPER>(a, lev_idx[c0 + v / nrhs], v % nrhs, q, sparse_only);
     }
 }
 
@@ -1479,12 +1530,12 @@ hipError_t batched_run(const Symbolic& s, const SparseDevice& d, int32_t batch, 
     for (int l = 0; l < a.ix.nlev[1]; ++l) {
         const int c0 = d.h_lev_ptr[1][l], cnt = d.h_lev_ptr[1][l + 1] - c0;
         hipLaunchKernelGGL(il_solve_level_kernel<0>, dim3(grid_for((int64_t)cnt * nrhs * a.TP, kThreads)),
-                           dim3(kThreads), 0, st, a, a.ix.lev_idx[1], c0, cnt);
+                           dim3(kThreads), 0, st, a, a.ix.lev_idx[1], c0, cnt, 0);
     }
     for (int l = 0; l < a.ix.nlev[2]; ++l) {
         const int c0 = d.h_lev_ptr[2][l], cnt = d.h_lev_ptr[2][l + 1] - c0;
         hipLaunchKernelGGL(il_solve_level_kernel<1>, dim3(grid_for((int64_t)cnt * nrhs * a.TP, kThreads)),
-                           dim3(kThreads), 0, st, a, a.ix.lev_idx[2], c0, cnt);
+                           dim3(kThreads), 0, st, a, a.ix.lev_idx[2], c0, cnt, 0);
     }
     hipLaunchKernelGGL(il_combine_kernel, dim3(grid_for((int64_t)batch * n * nrhs, kThreads)), dim3(kThreads), 0, st, a,
                        es);
@@ -1594,8 +1645,9 @@ hipError_t factor_tail(const SparseDevice& d, SpArgs a, const EpsSet& es, hipStr
     return hipGetLastError();
 }
 
-// The block rows of the substitutions: their updates from the sparse part, then the block's own
-// triangular solves (any addressing).
+// The block rows of the substitutions: their updates from the sparse part, the block's own
+// triangular solves, then the block's terms of the backward chains of the rows before it (any
+// addressing).
 hipError_t tail_dense_solve(SpArgs a, hipStream_t st, bool slot) {
     const int64_t trows = (int64_t)a.ix.tail_n * a.nrhs * a.ntasks;
     const int64_t tpad = (int64_t)a.ix.tail_ld * a.nrhs * a.ntasks;
@@ -1620,6 +1672,11 @@ hipError_t tail_dense_solve(SpArgs a, hipStream_t st, bool slot) {
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(tail_rhs_out_kernel, dim3(grid_for(trows, kThreads)), dim3(kThreads), 0, st, a);
+    const int64_t srows = (int64_t)a.ix.tail_b0 * a.nrhs * a.ntasks;
+    if (a.trans)
+        hipLaunchKernelGGL(tail_bwd_ext_kernel<1>, dim3(grid_for(srows, kThreads)), dim3(kThreads), 0, st, a);
+    else
+        hipLaunchKernelGGL(tail_bwd_ext_kernel<0>, dim3(grid_for(srows, kThreads)), dim3(kThreads), 0, st, a);
     return hipGetLastError();
 }
 
@@ -1630,14 +1687,14 @@ hipError_t solve_tail(const SparseDevice& d, SpArgs a, hipStream_t st, const Kno
     for (int l = 0; l < a.ix.nlev_sp[0]; ++l) {
         const int c0 = d.h_lev_sp_ptr[0][l], cnt = d.h_lev_sp_ptr[0][l + 1] - c0;
         hipLaunchKernelGGL(sp_solve_level_kernel<0>, dim3(grid_for((int64_t)cnt * a.nrhs * a.ntasks, kThreads)),
-                           dim3(kThreads), 0, st, a, a.ix.lev_sp_idx[0], c0, cnt);
+                           dim3(kThreads), 0, st, a, a.ix.lev_sp_idx[0], c0, cnt, 0);
     }
     hipError_t e = tail_dense_solve(a, st, tail_slot(kn, a.ntasks));
     if (e != hipSuccess) return e;
     for (int l = 0; l < a.ix.nlev_sp[1]; ++l) {
         const int c0 = d.h_lev_sp_ptr[1][l], cnt = d.h_lev_sp_ptr[1][l + 1] - c0;
         hipLaunchKernelGGL(sp_solve_level_kernel<1>, dim3(grid_for((int64_t)cnt * a.nrhs * a.ntasks, kThreads)),
-                           dim3(kThreads), 0, st, a, a.ix.lev_sp_idx[1], c0, cnt);
+                           dim3(kThreads), 0, st, a, a.ix.lev_sp_idx[1], c0, cnt, 1);
     }
     hipLaunchKernelGGL(sp_rhs_out_kernel, dim3(grid_for(items, kThreads)), dim3(kThreads), 0, st, a);
     return hipGetLastError();
@@ -1699,14 +1756,14 @@ hipError_t tail_il_run(const Symbolic& s, const SparseDevice& d, int32_t batch, 
     for (int l = 0; l < ia.ix.nlev_sp[0]; ++l) {
         const int c0 = d.h_lev_sp_ptr[0][l], cnt = d.h_lev_sp_ptr[0][l + 1] - c0;
         hipLaunchKernelGGL(il_solve_level_kernel<0>, dim3(grid_for((int64_t)cnt * nrhs * ia.TP, kThreads)),
-                           dim3(kThreads), 0, st, ia, ia.ix.lev_sp_idx[0], c0, cnt);
+                           dim3(kThreads), 0, st, ia, ia.ix.lev_sp_idx[0], c0, cnt, 0);
     }
     e = tail_dense_solve(a, st, slot);
     if (e != hipSuccess) return e;
     for (int l = 0; l < ia.ix.nlev_sp[1]; ++l) {
         const int c0 = d.h_lev_sp_ptr[1][l], cnt = d.h_lev_sp_ptr[1][l + 1] - c0;
         hipLaunchKernelGGL(il_solve_level_kernel<1>, dim3(grid_for((int64_t)cnt * nrhs * ia.TP, kThreads)),
-                           dim3(kThreads), 0, st, ia, ia.ix.lev_sp_idx[1], c0, cnt);
+                           dim3(kThreads), 0, st, ia, ia.ix.lev_sp_idx[1], c0, cnt, 1);
     }
     hipLaunchKernelGGL(il_combine_kernel, dim3(grid_for((int64_t)batch * n * nrhs, kThreads)), dim3(kThreads), 0, st, ia,
                        es);
@@ -1720,12 +1777,12 @@ hipError_t solve_global(const SparseDevice& d, SpArgs a, hipStream_t st) {
     for (int l = 0; l < a.ix.nlev[1]; ++l) {
         const int c0 = d.h_lev_ptr[1][l], cnt = d.h_lev_ptr[1][l + 1] - c0;
         hipLaunchKernelGGL(sp_solve_level_kernel<0>, dim3(grid_for((int64_t)cnt * a.nrhs * a.ntasks, kThreads)),
-                           dim3(kThreads), 0, st, a, a.ix.lev_idx[1], c0, cnt);
+                           dim3(kThreads), 0, st, a, a.ix.lev_idx[1], c0, cnt, 0);
     }
     for (int l = 0; l < a.ix.nlev[2]; ++l) {
         const int c0 = d.h_lev_ptr[2][l], cnt = d.h_lev_ptr[2][l + 1] - c0;
         hipLaunchKernelGGL(sp_solve_level_kernel<1>, dim3(grid_for((int64_t)cnt * a.nrhs * a.ntasks, kThreads)),
-                           dim3(kThreads), 0, st, a, a.ix.lev_idx[2], c0, cnt);
+                           dim3(kThreads), 0, st, a, a.ix.lev_idx[2], c0, cnt, 0);
     }
     hipLaunchKernelGGL(sp_rhs_out_kernel, dim3(grid_for(items, kThreads)), dim3(kThreads), 0, st, a);
     return hipGetLastError();
@@ -1871,6 +1928,11 @@ void sparse_image(const Symbolic& s, PlanImage& img, SparseDevice& d) {
         for (int k = 0; k < s.tail_b0; ++k)
             if (s.l_ptr[k + 1] > s.l_ptr[k] && s.l_idx[s.l_ptr[k + 1] - 1] == n - 1) lp[k] = s.l_ptr[k + 1] - 1;
         img.bind(&ix.tail_lastpos, img.put(lp));
+        std::vector<int32_t> cc(std::max(s.tail_b0, 1), 0);
+        for (int k = 0; k < s.tail_b0; ++k)
+            cc[k] = (int32_t)(std::lower_bound(s.l_idx.begin() + s.l_ptr[k], s.l_idx.begin() + s.l_ptr[k + 1], s.tail_b0) -
+                              (s.l_idx.begin() + s.l_ptr[k]));
+        img.bind(&ix.tail_ccnt, img.put(cc));
         // tile-pair assembly: panel positions and the pair lists
         const int TT = s.tail_tiles;
         ix.tail_tiles = TT;
