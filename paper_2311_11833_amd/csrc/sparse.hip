@@ -904,6 +904,35 @@ __global__ __launch_bounds__(WG) void tail_panel_kernel(SpArgs a, int p0) {
     }
 }
 
+// The same step split for a few systems: the diagonal block's GETRF (one wave per system), then
+// the multipliers and U rows in chunks of WG items (rows below, then columns to the right) over
+// many workgroups, each reloading the factored diagonal block.
+__global__ __launch_bounds__(64) void tail_getrf_kernel(SpArgs a, int p0) {
+    __shared__ double D[NB * NB];
+    const int ld = a.ix.tail_ld;
+    for (int task = blockIdx.x; task < a.ntasks; task += gridDim.x) {
+        const int bad = panel_getrf(a.dense + (int64_t)task * a.dstride, ld, p0, D);
+        if (threadIdx.x == 0 && bad) atomicMin(&a.info[task], a.ix.tail_b0 + bad);
+    }
+}
+
+__global__ __launch_bounds__(WG) void tail_trsm_kernel(SpArgs a, int p0, int chunks) {
+    __shared__ double D[NB * NB];
+    const int ld = a.ix.tail_ld, rest = ld - p0 - NB;
+    const int64_t total = (int64_t)chunks * a.ntasks;
+    for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
+        const int task = (int)(b / chunks), c = (int)(b % chunks);
+        double* T = a.dense + (int64_t)task * a.dstride;
+        load_diag(T, ld, p0, D);
+        __syncthreads();
+        const int i0 = c * WG, i1 = min(i0 + WG, 2 * rest);
+        const int r_lo = p0 + NB + min(i0, rest), r_hi = p0 + NB + min(i1, rest);
+        const int c_lo = p0 + NB + max(i0 - rest, 0), c_hi = p0 + NB + max(i1 - rest, 0);
+        panel_trsm(T, ld, p0, D, r_lo, r_hi, c_lo, c_hi);
+        __syncthreads();
+    }
+}
+
 // Rank-NB update of the trailing matrix after panel p0: one workgroup per 128 x 64 tile.
 __global__ __launch_bounds__(WG) void tail_update_kernel(SpArgs a, int p0, int tiles_r, int tiles_c) {
     __shared__ double Us[NB * 64];
@@ -1613,9 +1642,23 @@ hipError_t tail_dense_factor(SpArgs a, const EpsSet& es, hipStream_t st, int col
         hipLaunchKernelGGL(tail_lu_slot_kernel, dim3(std::min(a.ntasks, 65535)), dim3(WG), kLdsFactor, st, a);
         return hipGetLastError();
     }
+    int dev = 0, cus = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const bool split = a.ntasks < cus;      // too few systems to fill the device one per workgroup
     for (int p0 = 0; p0 < ld; p0 += NB) {
-        hipLaunchKernelGGL(tail_panel_kernel, dim3(std::min(a.ntasks, 65535)), dim3(WG), 0, st, a, p0);
-        const int rem = ld - p0 - NB;
+        const int rest = ld - p0 - NB;
+        if (split) {
+            hipLaunchKernelGGL(tail_getrf_kernel, dim3(std::min(a.ntasks, 65535)), dim3(64), 0, st, a, p0);
+            if (rest > 0) {
+                const int chunks = (2 * rest + WG - 1) / WG;
+                hipLaunchKernelGGL(tail_trsm_kernel, dim3((int)std::min<int64_t>((int64_t)chunks * a.ntasks, 65535)),
+                                   dim3(WG), 0, st, a, p0, chunks);
+            }
+        } else {
+            hipLaunchKernelGGL(tail_panel_kernel, dim3(std::min(a.ntasks, 65535)), dim3(WG), 0, st, a, p0);
+        }
+        const int rem = rest;
         if (rem > 0) {
             const int tr = (rem + 127) / 128, tc = (rem + 63) / 64;
             const int64_t blocks = (int64_t)tr * tc * a.ntasks;
