@@ -118,6 +118,7 @@ __device__ __forceinline__ double merge_dot(const SpIdx& ix, int a, int b, const
 // the ascending order.
 constexpr int U8 = 8;
 constexpr int U16 = 16;   // the block rows' updates from the sparse part: more loads in flight per step
+constexpr int U32 = 32;
 
 __device__ __forceinline__ double pair_dot(const SpIdx& ix, int id, const double* lv, const double* uv, double acc) {
     const int p1 = ix.pair_ptr[id + 1];
@@ -948,8 +949,10 @@ __global__ __launch_bounds__(WG) void tail_update_kernel(SpArgs a, int p0, int t
 
 // Rows of the block, updates from the sparse part (k < b0, ascending): L (or U^T) without the
 // division, which the dense solve applies after the block's own updates.
+constexpr int kExtThreads = 128;   // the block-row update kernel: room for 32 loads in flight per lane
+
 template <int TRANS>
-__global__ void tail_fwd_ext_kernel(SpArgs a) {
+__global__ __launch_bounds__(kExtThreads) void tail_fwd_ext_kernel(SpArgs a) {
     const SpIdx& ix = a.ix;
     const int n = ix.n, nl = ix.nnzl, nrhs = a.nrhs, b0 = ix.tail_b0;
     const int64_t per = (int64_t)ix.tail_n * nrhs, total = per * a.ntasks;
@@ -965,30 +968,30 @@ __global__ void tail_fwd_ext_kernel(SpArgs a) {
         double acc = y[(int64_t)i * nrhs * ys];
         const int p0 = ix.r_ptr[i], pe = p0 + ix.tail_rcnt[i - b0];
         int p = p0;
-        if (p + U16 <= pe) {
+        if (p + U32 <= pe) {
             // the indices of the next block are fetched while this block's values are in flight
-            int ip[U16], iy[U16];
+            int ip[U32], iy[U32];
 #pragma unroll
-            for (int w = 0; w < U16; ++w) {
+            for (int w = 0; w < U32; ++w) {
                 ip[w] = ix.r_pos[p + w];
                 iy[w] = ix.r_idx[p + w];
             }
-            for (; p + U16 <= pe; p += U16) {
-                double mv[U16], yw[U16];
+            for (; p + U32 <= pe; p += U32) {
+                double mv[U32], yw[U32];
 #pragma unroll
-                for (int w = 0; w < U16; ++w) {
+                for (int w = 0; w < U32; ++w) {
                     mv[w] = m[ip[w] * vs];
                     yw[w] = y[(int64_t)iy[w] * nrhs * ys];
                 }
-                if (p + 2 * U16 <= pe) {
+                if (p + 2 * U32 <= pe) {
 #pragma unroll
-                    for (int w = 0; w < U16; ++w) {
-                        ip[w] = ix.r_pos[p + U16 + w];
-                        iy[w] = ix.r_idx[p + U16 + w];
+                    for (int w = 0; w < U32; ++w) {
+                        ip[w] = ix.r_pos[p + U32 + w];
+                        iy[w] = ix.r_idx[p + U32 + w];
                     }
                 }
 #pragma unroll
-                for (int w = 0; w < U16; ++w) acc = fmad(-mv[w], yw[w], acc);
+                for (int w = 0; w < U32; ++w) acc = fmad(-mv[w], yw[w], acc);
             }
         }
         for (; p < pe; ++p) acc = fmad(-m[ix.r_pos[p] * vs], y[(int64_t)ix.r_idx[p] * nrhs * ys], acc);
@@ -1074,10 +1077,13 @@ __global__ void tail_rhs_out_kernel(SpArgs a) {
 template <int LOWER, int TRANS>
 __global__ __launch_bounds__(WG) void tail_tri_diag_kernel(SpArgs a, int c0) {
     constexpr bool UNIT = (LOWER && !TRANS) || (!LOWER && TRANS);
+    constexpr int NW = WG / 64;                  // right-hand sides per workgroup, one per wave
     __shared__ double Tri[SB * SB];
     const int ld = a.ix.tail_ld, nrhs = a.nrhs, bs = min(SB, ld - c0);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int task = blockIdx.x; task < a.ntasks; task += gridDim.x) {
+    const int groups = (nrhs + NW - 1) / NW;     // workgroup b: system b / groups, waves' RHS from (b % groups) * NW
+    for (int64_t b = blockIdx.x; b < (int64_t)a.ntasks * groups; b += gridDim.x) {
+        const int task = (int)(b / groups), r0 = (int)(b % groups) * NW;
         if (a.info[task]) continue;
         const double* M = a.dense + (int64_t)task * a.dstride;
         double* R = const_cast<double*>(M) + (int64_t)ld * ld;
@@ -1088,7 +1094,7 @@ __global__ __launch_bounds__(WG) void tail_tri_diag_kernel(SpArgs a, int c0) {
             Tri[i * SB + j] = v;
         }
         __syncthreads();
-        for (int r = wave; r < nrhs; r += WG / 64) {
+        for (int r = r0 + wave; r < min(nrhs, r0 + NW); r += NW) {
             double* tc = R + (int64_t)r * ld + c0;
             double t = lane < bs ? tc[lane] : 0.0;
             if (LOWER) {
@@ -1171,7 +1177,7 @@ int grid_for(int64_t items, int threads);
 template <int LOWER, int TRANS>
 hipError_t tail_tri(SpArgs a, hipStream_t st) {
     const int ld = a.ix.tail_ld, nblk = (ld + SB - 1) / SB;
-    const int tgrid = std::min(a.ntasks, 65535);
+    const int tgrid = (int)std::min<int64_t>((int64_t)a.ntasks * ((a.nrhs + WG / 64 - 1) / (WG / 64)), 65535);
     for (int bb = 0; bb < nblk; ++bb) {
         const int blk = LOWER ? bb : nblk - 1 - bb, c0 = blk * SB, bs = std::min(SB, ld - c0);
         hipLaunchKernelGGL((tail_tri_diag_kernel<LOWER, TRANS>), dim3(tgrid), dim3(WG), 0, st, a, c0);
@@ -1695,9 +1701,9 @@ hipError_t tail_dense_solve(SpArgs a, hipStream_t st, bool slot) {
     const int64_t trows = (int64_t)a.ix.tail_n * a.nrhs * a.ntasks;
     const int64_t tpad = (int64_t)a.ix.tail_ld * a.nrhs * a.ntasks;
     if (a.trans)
-        hipLaunchKernelGGL(tail_fwd_ext_kernel<1>, dim3(grid_for(trows, kThreads)), dim3(kThreads), 0, st, a);
+        hipLaunchKernelGGL(tail_fwd_ext_kernel<1>, dim3(grid_for(trows, kExtThreads)), dim3(kExtThreads), 0, st, a);
     else
-        hipLaunchKernelGGL(tail_fwd_ext_kernel<0>, dim3(grid_for(trows, kThreads)), dim3(kThreads), 0, st, a);
+        hipLaunchKernelGGL(tail_fwd_ext_kernel<0>, dim3(grid_for(trows, kExtThreads)), dim3(kExtThreads), 0, st, a);
     hipLaunchKernelGGL(tail_rhs_in_kernel, dim3(grid_for(tpad, kThreads)), dim3(kThreads), 0, st, a);
     if (slot) {
         const dim3 g(std::min(a.ntasks, 65535));
