@@ -394,6 +394,18 @@ def main():
                 "flops_per_system": flops_of("sparse_steps"), "systems_per_launch": systems,
                 "hbm_bytes_algorithmic": S * (pinfo.nnz + 2 * n) * 8,
                 "hbm_gbs_algorithmic": S * (pinfo.nnz + 2 * n) * 8 / (steps_ms / 1e3) / 1e9}
+    # the bound that applies: the schedule's dependency depth (barrier steps one after another per
+    # workgroup, K systems per workgroup, workgroups resident per CU); ns per step per workgroup
+    if pinfo.steps > 0 and pinfo.steps_per_cu > 0:
+        cus = torch.cuda.get_device_properties(dev).multi_processor_count
+        slots = cus * pinfo.steps_per_cu
+        per_jac = tuned["steps_mode"] == 1 or (tuned["steps_mode"] == -1 and S >= slots)
+        wgs, sys_wg = (S, len(eps)) if per_jac else (S * len(eps), 1)
+        rounds = -(-wgs // slots)                          # rounds of resident workgroups
+        roofline["dependency_bound"] = {
+            "barrier_steps_per_system": int(pinfo.steps), "systems_per_workgroup": sys_wg,
+            "workgroups_per_cu": int(pinfo.steps_per_cu), "workgroup_rounds": int(rounds),
+            "ns_per_step_per_workgroup": steps_ms * 1e6 / (rounds * sys_wg * pinfo.steps)}
     roofline_dense = None
     if "dense" in results:
         a_d = dense_flops(n) * systems / (results["dense"]["ms"] / 1e3)
