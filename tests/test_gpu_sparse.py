@@ -324,7 +324,7 @@ def test_dense_tail_path_matches_oracle(psp, O, W, dev, N, count, nrhs):
     _cmp(x.cpu().numpy(), xo)
 
 
-@pytest.mark.parametrize("count,nrhs", [(14, 1), (13, 2)])
+@pytest.mark.parametrize("count,nrhs", [(14, 1), (13, 2), (14, 7)])
 def test_dense_tail_interleaved_matches_oracle(psp, O, W, dev, count, nrhs):
     """From 64 systems on, the fused call keeps the factors below the block interleaved across
     systems (one wave serves an item of 64 systems) and each block in a region of its own: one
@@ -374,3 +374,26 @@ def test_dense_tail_breakdown_inside_block(psp, O, W, dev):
     assert np.array_equal(ig, io) and np.all(ig[0] > 0) and np.all(ig[1] == 0)
     assert np.all(np.isnan(x.cpu().numpy()[0]))
     _cmp(x.cpu().numpy()[1], xo[1])
+
+
+@pytest.mark.parametrize("N,count", [(1354, 13), (3000, 13)])
+def test_dense_tail_launch_choices_match_oracle(psp, O, W, dev, N, count):
+    """65 perturbed systems (one past the 64 of a wave of the interleaved layout) at n = 2,709 and
+    6,001: every combination of the layout below the block (interleaved or one system after
+    another) and of the block's LU and solves (per-panel launches across the device, split into a
+    GETRF and a many-workgroup TRSM below 256 systems, or one workgroup per system) returns the
+    oracle's bits."""
+    ip, ix, vals, bs = W.scenario_batch(N, count)
+    n = len(ip) - 1
+    eps = W.config_eps("n601")
+    plan = psp.Plan(ip, ix)
+    sym = O.symbolic(n, ip, ix)
+    xo, io, _, _ = O.sparse_batch(n, ip, ix, vals, sym, eps, bs)
+    v, b = torch.from_numpy(vals).to(dev), torch.from_numpy(bs).to(dev)
+    for il, lu in ((1, 0), (1, 1), (0, 1), (0, 0)):
+        print(f"[gpu sparse] dense tail N={N} count={count} interleaved={il} lu={lu}", flush=True)
+        psp.set_tune_choice(plan, count, len(eps), 1, "sparse_tail", tail_il=il, tail_lu=lu)
+        x, info = psp.solve_batched(plan, v, eps, b, path="auto")
+        torch.cuda.synchronize()
+        assert np.array_equal(info.cpu().numpy(), io)
+        _cmp(x.cpu().numpy(), xo)
