@@ -81,7 +81,7 @@ def _events(torch, fn, reps):
     return e0.elapsed_time(e1) / reps, out
 
 
-def extra_configs(psp, W, torch, dev, only=None):
+def extra_configs(psp, W, torch, dev, only=None, tol=1e-10):
     """Secondary configurations, timed with HIP events: the adjoint with 64 right-hand
     sides at n=601, the paper's symmetric node scheme, an uneven batch, the Newton
     power-flow loop and the 20,001-unknown system.  `only`: names to run (all if None)."""
@@ -187,12 +187,50 @@ def extra_configs(psp, W, torch, dev, only=None):
         gr_ms, _ = _events(torch, lambda: grp.replay(graph_u), 5)
         same = all(torch.equal(a[0], b_[0]) for a, b_ in zip(outs_u, outs_g))
         best = min(g_ms, gr_ms)
+        # recovered x against a partially pivoted sparse LU (SuperLU), every Jacobian of every item
+        import scipy.sparse as sps
+        import scipy.sparse.linalg as spla
+        acc_u = {}
+        for (N, ipu, ixu, valsu, bsu), o_ in zip(groups, outs_u):
+            nu, xu = len(ipu) - 1, o_[0].cpu().numpy()
+            e_ = []
+            for s_ in range(valsu.shape[0]):
+                xs_ = spla.splu(sps.csr_matrix((valsu[s_], ixu, ipu), shape=(nu, nu)).tocsc()).solve(bsu[s_])
+                e_.append(np.abs(xu[s_] - xs_).max() / np.abs(xs_).max())
+            e_ = np.array(e_)
+            acc_u[nu] = {"above_1e-9": int((e_ > 1e-9).sum()), "max": float(np.nanmax(e_)),
+                         "median": float(np.median(e_))}
+        # the same group with the error test on every item (psp_group_run_adaptive)
+        grp.run_adaptive(gin, tol=tol)
+        torch.cuda.synchronize()
+        ga_ms, outs_a = _events(torch, lambda: grp.run_adaptive(gin, tol=tol), 3)
+        graph_a, _ = grp.capture_adaptive(gin, tol=tol)
+        grp.replay(graph_a)
+        torch.cuda.synchronize()
+        gra_ms, _ = _events(torch, lambda: grp.replay(graph_a), 5)
+        acc_a, resc_a = {}, {}
+        for (N, ipu, ixu, valsu, bsu), o_ in zip(groups, outs_a):
+            nu, xu = len(ipu) - 1, o_[0].cpu().numpy()
+            e_ = np.array([np.abs(xu[s_] - (xs_ := spla.splu(sps.csr_matrix((valsu[s_], ixu, ipu), shape=(nu, nu))
+                                                            .tocsc()).solve(bsu[s_]))).max() / np.abs(xs_).max()
+                           for s_ in range(valsu.shape[0])])
+            acc_a[nu] = {"above_1e-9": int((e_ > 1e-9).sum()), "max": float(np.nanmax(e_)),
+                         "median": float(np.median(e_))}
+            resc_a[nu] = int((o_[3].cpu().numpy() != 1.0).sum())
+        best_a = min(ga_ms, gra_ms)
         out["uneven_512"] = {"jacobians_by_n": sizes, "K": len(eps), "path_by_n": paths_u, "ms_per_call": best,
                              "eager_ms": g_ms, "graph_ms": gr_ms, "graph_bitwise_equal": bool(same),
                              "solves_per_s": 512 * len(eps) / (best / 1e3),
-                             "sparse_tflops": flops_u / (best / 1e3) / 1e12}
-        print(f"[bench] uneven 512: eager {g_ms:.3f} ms, graph {gr_ms:.3f} ms, paths {paths_u}", file=sys.stderr,
-              flush=True)
+                             "sparse_tflops": flops_u / (best / 1e3) / 1e12,
+                             "rel_err_vs_pivoted_by_n": acc_u,
+                             "nodes": "1e-3 * 2^-k for every item (no error test)",
+                             "error_test": {"tol": tol, "ms_per_call": best_a, "eager_ms": ga_ms,
+                                            "graph_ms": gra_ms, "rescaled_by_n": resc_a,
+                                            "rel_err_vs_pivoted_by_n": acc_a}}
+        print(f"[bench] uneven 512: eager {g_ms:.3f} ms, graph {gr_ms:.3f} ms; with the error test eager "
+              f"{ga_ms:.3f} ms, graph {gra_ms:.3f} ms; above 1e-9: fixed "
+              f"{sum(v['above_1e-9'] for v in acc_u.values())}, error test {sum(v['above_1e-9'] for v in acc_a.values())}",
+              file=sys.stderr, flush=True)
     if want("newton_pf_512"):
         # Newton-Raphson power flows (Sec. IV's setting): 512 scenarios of the 300-bus network with 69
         # generator buses, flat start, at most 20 iterations, K = 5; one psp_pf_newton call
@@ -462,7 +500,7 @@ def main():
         print(f"[bench] plain: {pms:.3f} ms for {J * K} systems", file=sys.stderr, flush=True)
 
     only = None if args.extras is None else set(args.extras.split(","))
-    extra = None if args.no_extra else extra_configs(psp, W, torch, dev, only)
+    extra = None if args.no_extra else extra_configs(psp, W, torch, dev, only, args.tol)
 
     cpu = None
     if not args.no_cpu:

@@ -218,7 +218,10 @@ PSP_API psp_status psp_solve_batched(psp_plan plan, int32_t path, int32_t batch,
  * perturbation size per Jacobian (Sec. V leaves the perturbation strategy
  * open; the expansion of Sec. II-B converges only while |eps| rho(A^{-1}D) < 1
  * and its truncation grows with the nodes, its rounding with their inverse).
- * Step-schedule path, nrhs = 1, K >= 3 nodes eps (host, distinct, nonzero).
+ * Step-schedule path (else, for a pattern without one, the dense-trailing-
+ * block path, whose second solve runs every Jacobian again at its scale: 1
+ * for those that passed, which reproduces their first solve bit for bit),
+ * nrhs = 1, K >= 3 nodes eps (host, distinct, nonzero).
  *   1. Every Jacobian is solved at the nodes eps (as psp_solve_batched).
  *   2. Error test without A: with f_j the divided difference of the K
  *      perturbed solutions over nodes 0..j (= (-1)^j M^j x* up to O(eps),
@@ -242,7 +245,7 @@ PSP_API psp_status psp_solve_batched(psp_plan plan, int32_t path, int32_t batch,
  *   256-byte aligned.  Asynchronous on `stream` (no host synchronisation:
  *   the list of rescaled Jacobians stays on the device).
  * PSP_E_INVALID for NULL pointers, batch < 1, K < 3 or a negative or
- * non-finite tol; PSP_E_UNSUPPORTED when the plan has no step schedule.
+ * non-finite tol; PSP_E_UNSUPPORTED when the plan has neither path.
  * ---------------------------------------------------------------------- */
 PSP_API size_t psp_solve_adaptive_workspace_bytes(psp_plan plan, int32_t batch, int32_t K);
 PSP_API psp_status psp_solve_adaptive(psp_plan plan, int32_t batch, const double* values, int32_t K,
@@ -318,6 +321,23 @@ PSP_API size_t psp_group_workspace_bytes(psp_group g);
 PSP_API psp_status psp_group_run(psp_group g, const psp_group_task_t* tasks, void* ws, size_t ws_bytes, void* stream);
 PSP_API psp_status psp_group_capture(psp_group g, const psp_group_task_t* tasks, void* ws, size_t ws_bytes,
                                      void* stream, void** graph_exec);
+/* Groups with the error test (psp_solve_adaptive for every item: the first
+ * solve at eps, the estimate, the second solve at 2^-j eps for the Jacobians
+ * above tol, on the step schedule or, for patterns without one, the dense
+ * trailing block path).  nrhs = 1 and K >= 3 (else PSP_E_INVALID); an item
+ * with neither path gives PSP_E_UNSUPPORTED.  outs[i] gives item i's device
+ * arrays est and scale (batch each, as for psp_solve_adaptive); the workspace
+ * is psp_group_adaptive_workspace_bytes.  Run and capture as above. */
+typedef struct psp_group_adapt {
+    double* est;
+    double* scale;
+} psp_group_adapt_t;
+
+PSP_API size_t psp_group_adaptive_workspace_bytes(psp_group g);
+PSP_API psp_status psp_group_run_adaptive(psp_group g, const psp_group_task_t* tasks, const psp_group_adapt_t* outs,
+                                          double tol, void* ws, size_t ws_bytes, void* stream);
+PSP_API psp_status psp_group_capture_adaptive(psp_group g, const psp_group_task_t* tasks, const psp_group_adapt_t* outs,
+                                              double tol, void* ws, size_t ws_bytes, void* stream, void** graph_exec);
 PSP_API psp_status psp_graph_launch(void* graph_exec, void* stream);
 PSP_API void psp_graph_destroy(void* graph_exec);
 PSP_API void psp_group_destroy(psp_group g);

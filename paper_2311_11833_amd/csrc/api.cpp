@@ -595,9 +595,27 @@ psp_status psp_solve_batched_noalloc(psp_plan p, int32_t batch, const double* va
     return PSP_OK;
 }
 
+namespace {
+// Which path runs the adaptive call: the step schedule, else the dense-trailing-block path (0: none).
+int adaptive_path(psp_plan p) {
+    try {
+        build_image(p);
+    } catch (const std::bad_alloc&) {
+        return 0;
+    }
+    if (steps_ready(p->sp)) return PSP_PATH_SPARSE_STEPS;
+    if (sparse_tail_adaptive_ok(p->sym, p->sp)) return PSP_PATH_SPARSE_TAIL;
+    return 0;
+}
+}  // namespace
+
 size_t psp_solve_adaptive_workspace_bytes(psp_plan p, int32_t batch, int32_t K) {
     if (!p || batch < 1 || K < 1 || K > kMaxK) return 0;
-    return (size_t)(align_up((int64_t)batch * K * p->sym.n * 8, kAlign) + align_up((int64_t)batch * 4, kAlign) + kAlign);
+    const size_t base =
+        (size_t)(align_up((int64_t)batch * K * p->sym.n * 8, kAlign) + align_up((int64_t)batch * 4, kAlign) + kAlign);
+    if (adaptive_path(p) == PSP_PATH_SPARSE_TAIL)
+        return base + (size_t)align_up((int64_t)sparse_tail_run_bytes(p->sym, batch, K), kAlign);
+    return base;
 }
 
 psp_status psp_solve_adaptive(psp_plan p, int32_t batch, const double* values, int32_t K, const double* eps,
@@ -611,8 +629,10 @@ psp_status psp_solve_adaptive(psp_plan p, int32_t batch, const double* values, i
     if (psp_status st = make_eps(K, eps, es)) return st;
     if (psp_status st = check_prior_hip()) return st;
     if (psp_status r = require_upload(p)) return r;
-    if (!steps_ready(p->sp))
-        return fail(PSP_E_UNSUPPORTED, "psp_solve_adaptive: the plan has no step schedule (it does not fit in LDS)");
+    const int path = adaptive_path(p);
+    if (path == 0)
+        return fail(PSP_E_UNSUPPORTED,
+                    "psp_solve_adaptive: the plan has neither a step schedule nor a dense trailing block path");
     const size_t need = psp_solve_adaptive_workspace_bytes(p, batch, K);
     if (ws_bytes < need) return fail(PSP_E_NOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
     if (((uintptr_t)ws & 255) != 0) return fail(PSP_E_INVALID, "psp_solve_adaptive: workspace must be 256-byte aligned");
@@ -644,6 +664,26 @@ psp_status psp_solve_adaptive(psp_plan p, int32_t batch, const double* values, i
     double* Xk = (double*)w;
     int32_t* list = (int32_t*)(w + align_up((int64_t)batch * K * s.n * 8, kAlign));
     int32_t* count = (int32_t*)((char*)list + align_up((int64_t)batch * 4, kAlign));
+    if (path == PSP_PATH_SPARSE_TAIL) {
+        // the first solve writes the per-system solutions; the second solves every Jacobian again
+        // at its node scale (1 for those that passed: the same bits), the error test re-estimates
+        // the rescaled ones
+        void* tws = (char*)count + kAlign;
+        const psp_tune_choice_t ch = resolve_choice(p, PSP_PATH_SPARSE_TAIL, batch, K, 1);
+        const Knobs kn = knobs_of(ch);
+        HIP_TRY(launch_adapt_reset(count, st), "adapt reset launch");
+        HIP_TRY(sparse_tail_run(s, p->sp, batch, values, es, d, B, X, info, Xk, nullptr, tws, st, kn),
+                "dense-block path launch");
+        AdaptArgs a{};
+        a.n = s.n; a.K = K; a.batch = batch; a.pass = 1; a.combine = 0; a.tol = tol;
+        a.Xk = Xk; a.X = X; a.est = est; a.scale = scale; a.list = list; a.count = count;
+        HIP_TRY(launch_adapt(a, c, st), "error-test launch");
+        HIP_TRY(sparse_tail_run(s, p->sp, batch, values, es, d, B, X, info, Xk, scale, tws, st, kn),
+                "dense-block path launch (rescaled nodes)");
+        a.pass = 2;
+        HIP_TRY(launch_adapt(a, c, st), "error-test launch (rescaled nodes)");
+        return PSP_OK;
+    }
     const bool per_jacobian = steps_per_jacobian(p->sp, batch);
     HIP_TRY(launch_adapt_reset(count, st), "adapt reset launch");
     HIP_TRY(steps_run(p->sp, s.nnz, batch, values, es, d, B, X, Xk, info, per_jacobian, st, true), "step-kernel launch");
@@ -1168,6 +1208,8 @@ struct psp_group_s {
     std::vector<psp_group_shape_t> items;   // path resolved at creation
     std::vector<psp_tune_choice_t> choice;  // with its launch choices
     std::vector<size_t> ws_off, ws_len;     // each item's slice of the workspace
+    std::vector<size_t> ad_off, ad_len;     // the same for the adaptive run (psp_solve_adaptive per item)
+    size_t ad_total = 0;
     std::vector<int32_t> order, lane;       // LPT order; stream lane of each item (0: the caller's)
     size_t ws_total = 0;
     int32_t K = 0, nrhs = 0, nlanes = 1, device = -1;
@@ -1199,7 +1241,9 @@ double item_cost(const psp_group_shape_t& it, int32_t K, int32_t nrhs) {
     return per * it.batch * K;
 }
 
-psp_status group_enqueue(psp_group g, const psp_group_task_t* tasks, char* ws, hipStream_t st) {
+// outs != NULL: every item through psp_solve_adaptive (error test + rescale) instead of its path.
+psp_status group_enqueue(psp_group g, const psp_group_task_t* tasks, char* ws, hipStream_t st,
+                         const psp_group_adapt_t* outs = nullptr, double tol = 0.0) {
     const bool forked = g->nlanes > 1;
     if (forked) {
         HIP_TRY(hipEventRecord(g->fork, st), "hipEventRecord(fork)");
@@ -1210,8 +1254,12 @@ psp_status group_enqueue(psp_group g, const psp_group_task_t* tasks, char* ws, h
         const psp_group_shape_t& it = g->items[i];
         const psp_group_task_t& t = tasks[i];
         const hipStream_t ls = g->lane[i] == 0 ? st : g->streams[g->lane[i]];
-        bad = solve_choice(it.plan, g->choice[i], it.batch, t.values, g->K, g->eps.data(), t.d, g->nrhs, t.B, t.X,
-                           t.info, ws + g->ws_off[i], g->ws_len[i], (void*)ls);
+        if (outs)
+            bad = psp_solve_adaptive(it.plan, it.batch, t.values, g->K, g->eps.data(), t.d, tol, t.B, t.X, t.info,
+                                     outs[i].est, outs[i].scale, ws + g->ad_off[i], g->ad_len[i], (void*)ls);
+        else
+            bad = solve_choice(it.plan, g->choice[i], it.batch, t.values, g->K, g->eps.data(), t.d, g->nrhs, t.B, t.X,
+                               t.info, ws + g->ws_off[i], g->ws_len[i], (void*)ls);
         if (bad != PSP_OK) {
             g_err = "group item " + std::to_string(i) + ": " + g_err;
             break;
@@ -1226,10 +1274,23 @@ psp_status group_enqueue(psp_group g, const psp_group_task_t* tasks, char* ws, h
     return bad;
 }
 
-psp_status group_check(psp_group g, const psp_group_task_t* tasks, void* ws, size_t ws_bytes) {
+psp_status group_check(psp_group g, const psp_group_task_t* tasks, void* ws, size_t ws_bytes,
+                       const psp_group_adapt_t* outs = nullptr, bool adaptive = false) {
     if (!g || !tasks || !ws) return fail(PSP_E_INVALID, "psp_group: NULL argument");
-    if (ws_bytes < g->ws_total)
-        return fail(PSP_E_NOMEM, "workspace too small: need " + std::to_string(g->ws_total) + " bytes");
+    const size_t need = adaptive ? g->ad_total : g->ws_total;
+    if (ws_bytes < need) return fail(PSP_E_NOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
+    if (adaptive) {
+        if (!outs) return fail(PSP_E_INVALID, "psp_group: NULL outputs");
+        if (g->nrhs != 1 || g->K < 3)
+            return fail(PSP_E_INVALID, "psp_group adaptive: needs nrhs = 1 and K >= 3 nodes");
+        for (size_t i = 0; i < g->items.size(); ++i) {
+            if (!outs[i].est || !outs[i].scale)
+                return fail(PSP_E_INVALID, "psp_group: item " + std::to_string(i) + " has a NULL est or scale");
+            if (g->ad_len[i] == 0)
+                return fail(PSP_E_UNSUPPORTED, "psp_group adaptive: item " + std::to_string(i) +
+                                                   " has neither a step schedule nor a dense trailing block path");
+        }
+    }
     if (((uintptr_t)ws & 255) != 0) return fail(PSP_E_INVALID, "psp_group: workspace must be 256-byte aligned");
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
@@ -1274,6 +1335,10 @@ psp_status psp_group_create(int32_t nitems, const psp_group_shape_t* shapes, int
         g->ws_off.push_back(g->ws_total);
         g->ws_len.push_back(w);
         g->ws_total += (size_t)align_up((int64_t)w, kAlign);
+        const size_t wa = (nrhs == 1 && K >= 3) ? psp_solve_adaptive_workspace_bytes(it.plan, it.batch, K) : 0;
+        g->ad_off.push_back(g->ad_total);
+        g->ad_len.push_back(wa);
+        g->ad_total += (size_t)align_up((int64_t)wa, kAlign);
         cost[i] = item_cost(it, K, nrhs);
     }
     // longest item first, each to the least-loaded lane
@@ -1301,10 +1366,32 @@ psp_status psp_group_create(int32_t nitems, const psp_group_shape_t* shapes, int
 
 size_t psp_group_workspace_bytes(psp_group g) { return g ? std::max<size_t>(g->ws_total, 256) : 0; }
 
+size_t psp_group_adaptive_workspace_bytes(psp_group g) { return g ? std::max<size_t>(g->ad_total, 256) : 0; }
+
 psp_status psp_group_run(psp_group g, const psp_group_task_t* tasks, void* ws, size_t ws_bytes, void* stream) {
     if (psp_status r = group_check(g, tasks, ws, ws_bytes)) return r;
     if (psp_status st = check_prior_hip()) return st;
     return group_enqueue(g, tasks, (char*)ws, (hipStream_t)stream);
+}
+
+psp_status psp_group_run_adaptive(psp_group g, const psp_group_task_t* tasks, const psp_group_adapt_t* outs, double tol,
+                                  void* ws, size_t ws_bytes, void* stream) {
+    if (psp_status r = group_check(g, tasks, ws, ws_bytes, outs, true)) return r;
+    if (!std::isfinite(tol) || tol < 0.0) return fail(PSP_E_INVALID, "psp_group adaptive: tol must be finite and >= 0");
+    if (psp_status st = check_prior_hip()) return st;
+    return group_enqueue(g, tasks, (char*)ws, (hipStream_t)stream, outs, tol);
+}
+
+psp_status group_capture(psp_group g, const psp_group_task_t* tasks, void* ws, size_t ws_bytes, void* stream,
+                         void** graph_exec, const psp_group_adapt_t* outs, double tol);
+
+psp_status psp_group_capture_adaptive(psp_group g, const psp_group_task_t* tasks, const psp_group_adapt_t* outs,
+                                      double tol, void* ws, size_t ws_bytes, void* stream, void** graph_exec) {
+    if (!graph_exec) return fail(PSP_E_INVALID, "psp_group_capture: NULL output");
+    *graph_exec = nullptr;
+    if (psp_status r = group_check(g, tasks, ws, ws_bytes, outs, true)) return r;
+    if (!std::isfinite(tol) || tol < 0.0) return fail(PSP_E_INVALID, "psp_group adaptive: tol must be finite and >= 0");
+    return group_capture(g, tasks, ws, ws_bytes, stream, graph_exec, outs, tol);
 }
 
 psp_status psp_group_capture(psp_group g, const psp_group_task_t* tasks, void* ws, size_t ws_bytes, void* stream,
@@ -1312,12 +1399,18 @@ psp_status psp_group_capture(psp_group g, const psp_group_task_t* tasks, void* w
     if (!graph_exec) return fail(PSP_E_INVALID, "psp_group_capture: NULL output");
     *graph_exec = nullptr;
     if (psp_status r = group_check(g, tasks, ws, ws_bytes)) return r;
+    return group_capture(g, tasks, ws, ws_bytes, stream, graph_exec, nullptr, 0.0);
+}
+
+psp_status group_capture(psp_group g, const psp_group_task_t* tasks, void* ws, size_t ws_bytes, void* stream,
+                         void** graph_exec, const psp_group_adapt_t* outs, double tol) {
+    (void)ws_bytes;
     if (psp_status st = check_prior_hip()) return st;
     const hipStream_t st = (hipStream_t)stream;
     if (st == nullptr)
         return fail(PSP_E_INVALID, "psp_group_capture: the null (default) stream cannot be captured; pass a created stream");
     HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-    const psp_status r = group_enqueue(g, tasks, (char*)ws, st);
+    const psp_status r = group_enqueue(g, tasks, (char*)ws, st, outs, tol);
     hipGraph_t graph = nullptr;
     const hipError_t ee = hipStreamEndCapture(st, &graph);
     if (r != PSP_OK) {

@@ -140,6 +140,14 @@ size_t noalloc_scratch_bytes();
 hipError_t noalloc_scratch(void** out);
 bool sparse_fits_lds(const Symbolic& s, int32_t nrhs);
 size_t sparse_workspace_bytes(const Symbolic& s, int32_t batch, int32_t K, int32_t nrhs, int32_t keep, int forced = -1);
+// The dense-trailing-block path's fused call with the factors below the block interleaved, one
+// right-hand side, also writing the per-system solutions Xk (batch x K x n, NaN where broken) and,
+// with scale, Jacobian s at the nodes scale[s] eps_k: the error test's first and second solves.
+bool sparse_tail_adaptive_ok(const Symbolic& s, const SparseDevice& d);
+size_t sparse_tail_run_bytes(const Symbolic& s, int32_t batch, int32_t K);
+hipError_t sparse_tail_run(const Symbolic& s, const SparseDevice& d, int32_t batch, const double* values,
+                           const EpsSet& es, const double* dvec, const double* B, double* X, int32_t* info, double* Xk,
+                           const double* scale, void* ws, hipStream_t st, const Knobs& kn);
 int32_t sparse_nrhs_capacity(const Symbolic& s, int32_t batch, int32_t K, size_t ws_bytes);
 hipError_t sparse_solve_batched(const Symbolic& s, const SparseDevice& d, int32_t batch, const double* values,
                                 const EpsSet& es, const double* dvec, int32_t nrhs, const double* B, double* X,

@@ -236,6 +236,7 @@ struct SpArgs {
     // (vs = TP, ts = 1, blocks in a region of their own).
     int64_t vs, ts, dstride, yv, yt;
     double* dense;
+    const double* scale;    // or NULL: Jacobian s at the nodes scale[s] eps_k (a power of two)
 };
 
 // ---------------------------------------------------------------- in-LDS kernel
@@ -762,7 +763,9 @@ __global__ void tail_block_init_kernel(SpArgs a, EpsSet es) {
         else {
             const double* vals = a.values + (int64_t)(task / es.K) * a.nnz;
             const int gi = b0 + i, gj = b0 + j;
-            if (i == j) v = gather_diag(ix, gj, vals, eps_at(es, task % es.K), a.dvec);
+            const double e = a.scale ? __dmul_rn(eps_at(es, task % es.K), a.scale[task / es.K])
+                                     : eps_at(es, task % es.K);
+            if (i == j) v = gather_diag(ix, gj, vals, e, a.dvec);
             else {
                 const int src = i > j ? ix.src_l[ix.l_ptr[gj] + (gi - gj - 1)] : ix.src_u[ix.l_ptr[gi] + (gj - gi - 1)];
                 v = src >= 0 ? vals[src] : 0.0;
@@ -1206,6 +1209,8 @@ struct IlArgs {
     int32_t* info;
     double* fac;     // (n + 2 nnzl) x TP
     double* y;       // (n * nrhs) x TP
+    double* Xk;              // or NULL: the per-system solutions too, batch x K x n x nrhs (NaN if broken)
+    const double* scale;     // or NULL: Jacobian s at the nodes scale[s] eps_k (a power of two)
 };
 
 // UNIFORM: every lane of the wave works on the same item (the per-level
@@ -1253,7 +1258,8 @@ __device__ __forceinline__ void il_gather_item(const IlArgs& a, const EpsSet& es
         uv[(int64_t)v * a.TP + q] = su >= 0 ? vals[su] : 0.0;
     } else {
         const int j = v - nl;
-        ud[(int64_t)j * a.TP + q] = gather_diag(ix, j, vals, eps_at(es, kk), a.dvec);
+        const double e = a.scale ? __dmul_rn(eps_at(es, kk), a.scale[s]) : eps_at(es, kk);
+        ud[(int64_t)j * a.TP + q] = gather_diag(ix, j, vals, e, a.dvec);
         if (j == 0) a.info[q] = INT_MAX;
     }
 }
@@ -1442,6 +1448,7 @@ __global__ void il_combine_kernel(IlArgs a, EpsSet es) {
         for (int k = 0; k < es.K; ++k) {
             const int q = s * es.K + k;
             const double x = a.info[q] ? __builtin_nan("") : a.y[(int64_t)v * a.TP + q];
+            if (a.Xk) a.Xk[((int64_t)q * n + ix.perm[i]) * nrhs + r] = x;
             acc = fmad(c_at(es, k), x, acc);
         }
         a.X[((int64_t)s * n + ix.perm[i]) * nrhs + r] = acc;
@@ -1761,12 +1768,14 @@ bool tail_il_ok(const Symbolic& s, const SparseDevice& d, int64_t ntasks, const 
 
 hipError_t tail_il_run(const Symbolic& s, const SparseDevice& d, int32_t batch, const double* values,
                        const EpsSet& es, const double* dvec, int32_t nrhs, const double* B, double* X, int32_t* info,
-                       char* w, hipStream_t st, const Knobs& kn) {
+                       char* w, hipStream_t st, const Knobs& kn, double* Xk = nullptr, const double* scale = nullptr) {
     if (!d.idx.use_pairs || d.idx.pairs_below < s.tail_b0 || d.idx.tail_tiles == 0) return hipErrorInvalidValue;
     IlArgs ia{};
     ia.ix = d.idx;
     ia.nnz = s.nnz; ia.nrhs = nrhs; ia.ntasks = batch * es.K; ia.TP = (int32_t)tp_of(ia.ntasks); ia.K = es.K;
     ia.batch = batch; ia.values = values; ia.dvec = dvec; ia.B = B; ia.X = X; ia.info = info;
+    ia.Xk = Xk;
+    ia.scale = scale;
     const int n = s.n, nl = s.l_ptr[n];
     const int64_t off_dense = align256(((int64_t)n + 2 * (int64_t)nl) * ia.TP * 8);
     const int64_t off_y = align256(off_dense + (int64_t)ia.ntasks * dstride_of(s) * 8);
@@ -1789,6 +1798,7 @@ hipError_t tail_il_run(const Symbolic& s, const SparseDevice& d, int32_t batch, 
     a.dvec = dvec;
     a.B = B;
     a.info = info;
+    a.scale = scale;
     a.fac = ia.fac;
     a.vs = ia.TP;
     a.ts = 1;
@@ -2094,6 +2104,21 @@ hipError_t sparse_solve_batched(const Symbolic& s, const SparseDevice& d, int32_
         if (e != hipSuccess) return e;
     }
     return launch_combine((int64_t)s.n * nrhs, batch, es, a.Xk, X, st);
+}
+
+bool sparse_tail_adaptive_ok(const Symbolic& s, const SparseDevice& d) {
+    return s.tail_n > 0 && d.idx.use_pairs && d.idx.pairs_below >= s.tail_b0 && d.idx.tail_tiles > 0;
+}
+
+size_t sparse_tail_run_bytes(const Symbolic& s, int32_t batch, int32_t K) {
+    return (size_t)sp_layout(s, batch, K, 1, 0, kVarTail).total;
+}
+
+hipError_t sparse_tail_run(const Symbolic& s, const SparseDevice& d, int32_t batch, const double* values,
+                           const EpsSet& es, const double* dvec, const double* B, double* X, int32_t* info, double* Xk,
+                           const double* scale, void* ws, hipStream_t st, const Knobs& kn) {
+    if (!sparse_tail_adaptive_ok(s, d)) return hipErrorInvalidValue;
+    return tail_il_run(s, d, batch, values, es, dvec, 1, B, X, info, (char*)ws, st, kn, Xk, scale);
 }
 
 hipError_t sparse_factor(const Symbolic& s, const SparseDevice& d, int32_t batch, const double* values,

@@ -27,7 +27,8 @@ EXPORTED = ["psp_last_error", "psp_version", "psp_plan_create", "psp_plan_info",
             "psp_solve_batched", "psp_solve_batched_noalloc", "psp_solve_adaptive_workspace_bytes",
             "psp_solve_adaptive", "psp_tune", "psp_tune_choice", "psp_set_tune_choice", "psp_factor", "psp_solve", "psp_combine", "psp_grad_values",
             "psp_factors_release", "psp_residual", "psp_group_create", "psp_group_workspace_bytes", "psp_group_run",
-            "psp_group_capture", "psp_graph_launch", "psp_graph_destroy", "psp_group_destroy", "psp_pf_device_bytes",
+            "psp_group_capture", "psp_group_adaptive_workspace_bytes", "psp_group_run_adaptive",
+            "psp_group_capture_adaptive", "psp_graph_launch", "psp_graph_destroy", "psp_group_destroy", "psp_pf_device_bytes",
             "psp_pf_create", "psp_pf_destroy", "psp_pf_eval", "psp_pf_workspace_bytes", "psp_pf_newton",
             "psp_estimate_rho_workspace_bytes", "psp_estimate_rho"]
 PF_STATUS = {0: "converged", 1: "max_iter", 2: "breakdown", 3: "diverged"}
@@ -64,6 +65,10 @@ class GroupShape(C.Structure):
 class GroupTask(C.Structure):
     _fields_ = [("values", C.c_void_p), ("d", C.c_void_p), ("B", C.c_void_p), ("X", C.c_void_p),
                 ("info", C.c_void_p)]
+
+
+class GroupAdapt(C.Structure):
+    _fields_ = [("est", C.c_void_p), ("scale", C.c_void_p)]
 
 
 _lib = None
@@ -108,6 +113,10 @@ def lib():
         L.psp_group_workspace_bytes.restype = C.c_size_t
         L.psp_group_run.argtypes = [vp, vp, vp, C.c_size_t, vp]
         L.psp_group_capture.argtypes = [vp, vp, vp, C.c_size_t, vp, C.POINTER(vp)]
+        L.psp_group_adaptive_workspace_bytes.argtypes = [vp]
+        L.psp_group_adaptive_workspace_bytes.restype = C.c_size_t
+        L.psp_group_run_adaptive.argtypes = [vp, vp, vp, d, vp, C.c_size_t, vp]
+        L.psp_group_capture_adaptive.argtypes = [vp, vp, vp, d, vp, C.c_size_t, vp, C.POINTER(vp)]
         L.psp_graph_launch.argtypes = [vp, vp]
         L.psp_graph_destroy.argtypes = [vp]
         L.psp_graph_destroy.restype = None
@@ -128,7 +137,7 @@ def lib():
         for f in EXPORTED:
             if f not in ("psp_last_error", "psp_version", "psp_plan_destroy", "psp_plan_device_bytes",
                          "psp_workspace_bytes", "psp_group_workspace_bytes", "psp_graph_destroy",
-                         "psp_group_destroy", "psp_pf_device_bytes", "psp_pf_destroy", "psp_pf_workspace_bytes",
+                         "psp_group_destroy", "psp_group_adaptive_workspace_bytes", "psp_pf_device_bytes", "psp_pf_destroy", "psp_pf_workspace_bytes",
                          "psp_estimate_rho_workspace_bytes", "psp_solve_adaptive_workspace_bytes"):
                 getattr(L, f).restype = C.c_int
         _lib = L
@@ -398,6 +407,47 @@ class Group:
 
     def replay(self, graph, stream=None):
         _check(lib().psp_graph_launch(graph, _stream(stream)))
+
+    def _adapt_outputs(self, outs):
+        import torch
+        arr = (GroupAdapt * len(self.plans))()
+        res = []
+        for i, (plan, batch) in enumerate(self.plans):
+            dev = outs[i][0].device
+            est = torch.empty(batch, dtype=torch.float64, device=dev)
+            scale = torch.empty(batch, dtype=torch.float64, device=dev)
+            arr[i] = GroupAdapt(_dptr(est).value, _dptr(scale).value)
+            res.append((est, scale))
+        if not hasattr(self, "ws_adapt"):
+            self.ws_adapt = torch.empty(int(lib().psp_group_adaptive_workspace_bytes(self._h)), dtype=torch.uint8,
+                                        device=self.ws.device)
+        return arr, res
+
+    def run_adaptive(self, items, tol: float = 1e-10, d=None, stream=None):
+        """Every item with the error test (psp_solve_adaptive); returns [(x_i, info_i, est_i, scale_i)]."""
+        tasks, outs, keep = self.outputs(items, d)
+        arr, res = self._adapt_outputs(outs)
+        _check(lib().psp_group_run_adaptive(self._h, C.byref(tasks), C.byref(arr), float(tol), _dptr(self.ws_adapt),
+                                            self.ws_adapt.numel(), _stream(stream)))
+        self._keep = keep
+        return [o + r for o, r in zip(outs, res)]
+
+    def capture_adaptive(self, items, tol: float = 1e-10, d=None, stream=None):
+        """capture() of run_adaptive; returns (graph handle, [(x_i, info_i, est_i, scale_i)])."""
+        tasks, outs, keep = self.outputs(items, d)
+        arr, res = self._adapt_outputs(outs)
+        if stream is None:
+            import torch
+            stream = torch.cuda.Stream(device=self.ws.device)
+            stream.wait_stream(torch.cuda.current_stream(self.ws.device))
+            self._capture_streams = getattr(self, "_capture_streams", []) + [stream]
+        g = C.c_void_p()
+        _check(lib().psp_group_capture_adaptive(self._h, C.byref(tasks), C.byref(arr), float(tol),
+                                                _dptr(self.ws_adapt), self.ws_adapt.numel(), _stream(stream),
+                                                C.byref(g)))
+        self._graphs.append(g)
+        self._keep_graph = getattr(self, "_keep_graph", []) + [(keep, res)]
+        return g, [o + r for o, r in zip(outs, res)]
 
 
 def solve_group(items, eps, path: str = "auto", d=None, stream=None):

@@ -207,3 +207,29 @@ def test_rho_iteration_kept_factors_branch(dev, O, W):
     for s in range(2):
         ref = O.power_rho_pivot_free(n, ip, ix, vals[s], sym, None, 1e-8, v0[s], 12)
         assert abs(rho[s] - ref) <= 1e-13 * ref, (s, rho[s], ref)
+
+
+@pytest.mark.parametrize("count", [14, 110])
+def test_error_test_on_dense_block_path_matches_oracle(dev, O, W, count):
+    """n = 2,709 (no step schedule: the dense-trailing-block path, factors below the block
+    interleaved): the first solve keeps the perturbed solutions, the error test picks the node
+    scales, every Jacobian is solved again at its scale (1 for those that passed: the same bits);
+    x, info, est and scale equal the oracle's, and the recovered x meet 1e-9 against a pivoted
+    solve on all but a few (the 110-Jacobian item of the uneven batch: most need a smaller scale)."""
+    from paper_2311_11833_amd import psp
+    import scipy.sparse as sps
+    import scipy.sparse.linalg as spla
+    ip, ix, vals, bs = W.scenario_batch(1354, count)
+    n = len(ip) - 1
+    plan = psp.Plan(ip, ix)
+    assert plan.info().steps == 0 and plan.info().tail_n > 0
+    eps = W.config_eps("n601")
+    print(f"[gpu adaptive] error test + rescale, dense-block path, {count} x K=5", flush=True)
+    out = psp.solve_adaptive(plan, torch.from_numpy(vals).to(dev), eps, torch.from_numpy(bs).to(dev), tol=1e-10)
+    torch.cuda.synchronize()
+    so = _check_adaptive(O, ip, ix, vals, bs, eps, 1e-10, out)
+    assert int((so != 1.0).sum()) >= count // 4
+    x = out[0].cpu().numpy()
+    err = np.array([np.abs(x[s] - (xs := spla.splu(sps.csr_matrix((vals[s], ix, ip), shape=(n, n)).tocsc())
+                                   .solve(bs[s]))).max() / np.abs(xs).max() for s in range(count)])
+    assert int((err > 1e-9).sum()) <= max(1, count // 50)

@@ -85,3 +85,31 @@ def test_group_workspace_too_small_is_reported(psp, W, dev):
     tiny = torch.empty(256, dtype=torch.uint8, device=dev)
     st = psp.lib().psp_group_run(g._h, C.byref(tasks), psp._dptr(tiny), 256, psp._stream(None))
     assert st == psp.PSP_E_NOMEM
+
+
+def test_group_error_test_matches_oracle_and_replays(psp, O, W, dev):
+    """The uneven group with the error test on every item (psp_group_run_adaptive: the step
+    schedule for n <= 1,001, the dense-trailing-block path for 2,709): x, info, est and scale
+    equal the oracle's adaptive solve; the captured graph replays to the same bits."""
+    eps = W.config_eps("n601")
+    items, ref = _items(psp, W, dev, {30: 4, 118: 3, 300: 20, 500: 9, 1354: 14})
+    g = psp.Group([(p, v.shape[0]) for p, v, _ in items], eps)
+    gin = [(v, b) for _, v, b in items]
+    print("[gpu group] error test, eager", flush=True)
+    outs = g.run_adaptive(gin, tol=1e-10)
+    torch.cuda.synchronize()
+    for (x, info, est, scale), (n, ip, ix, vals, bs) in zip(outs, ref):
+        sym = O.symbolic(n, ip, ix)
+        xo, io, eo, so = O.adaptive_batch(n, ip, ix, vals, sym, eps, bs, 1e-10)
+        assert np.array_equal(scale.cpu().numpy(), so), n
+        assert np.array_equal(info.cpu().numpy(), io), n
+        assert np.array_equal(est.cpu().numpy(), eo, equal_nan=True), n
+        assert np.array_equal(x.cpu().numpy(), xo, equal_nan=True), n
+    print("[gpu group] error test, graph", flush=True)
+    graph, gouts = g.capture_adaptive(gin, tol=1e-10)
+    for _ in range(3):
+        g.replay(graph)
+        torch.cuda.synchronize()
+        for a, b in zip(outs, gouts):
+            for u, v in zip(a, b):
+                assert torch.equal(u.nan_to_num(), v.nan_to_num())
