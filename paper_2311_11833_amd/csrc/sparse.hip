@@ -1222,18 +1222,25 @@ __device__ __forceinline__ double il_pair_dot(const SpIdx& ix, int id, const dou
     const int p0 = UNIFORM ? __builtin_amdgcn_readfirstlane(ix.pair_ptr[id]) : ix.pair_ptr[id];
     const int p1 = UNIFORM ? __builtin_amdgcn_readfirstlane(ix.pair_ptr[id + 1]) : ix.pair_ptr[id + 1];
     int p = p0;
-    for (; p + U8 <= p1; p += U8) {
+    if (p + U8 <= p1) {
+        // the next block's pair indices are fetched while this block's values are in flight
         int2 pq[U8];
-        double a[U8], b[U8];
 #pragma unroll
         for (int u = 0; u < U8; ++u) pq[u] = ix.pairs[p + u];
+        for (; p + U8 <= p1; p += U8) {
+            double a[U8], b[U8];
 #pragma unroll
-        for (int u = 0; u < U8; ++u) {
-            a[u] = lv[(int64_t)pq[u].x * TP + q];
-            b[u] = uv[(int64_t)pq[u].y * TP + q];
+            for (int u = 0; u < U8; ++u) {
+                a[u] = lv[(int64_t)pq[u].x * TP + q];
+                b[u] = uv[(int64_t)pq[u].y * TP + q];
+            }
+            if (p + 2 * U8 <= p1) {
+#pragma unroll
+                for (int u = 0; u < U8; ++u) pq[u] = ix.pairs[p + U8 + u];
+            }
+#pragma unroll
+            for (int u = 0; u < U8; ++u) acc = fmad(-a[u], b[u], acc);
         }
-#pragma unroll
-        for (int u = 0; u < U8; ++u) acc = fmad(-a[u], b[u], acc);
     }
     for (; p < p1; ++p) {
         const int2 pq = ix.pairs[p];
