@@ -123,15 +123,22 @@ constexpr int U32 = 32;
 __device__ __forceinline__ double pair_dot(const SpIdx& ix, int id, const double* lv, const double* uv, double acc) {
     const int p1 = ix.pair_ptr[id + 1];
     int p = ix.pair_ptr[id];
-    for (; p + U8 <= p1; p += U8) {
+    if (p + U8 <= p1) {
+        // the next block's pairs are fetched while this block's values are in flight
         int2 pq[U8];
-        double a[U8], b[U8];
 #pragma unroll
         for (int u = 0; u < U8; ++u) pq[u] = ix.pairs[p + u];
+        for (; p + U8 <= p1; p += U8) {
+            double a[U8], b[U8];
 #pragma unroll
-        for (int u = 0; u < U8; ++u) { a[u] = lv[pq[u].x]; b[u] = uv[pq[u].y]; }
+            for (int u = 0; u < U8; ++u) { a[u] = lv[pq[u].x]; b[u] = uv[pq[u].y]; }
+            if (p + 2 * U8 <= p1) {
 #pragma unroll
-        for (int u = 0; u < U8; ++u) acc = fmad(-a[u], b[u], acc);
+                for (int u = 0; u < U8; ++u) pq[u] = ix.pairs[p + U8 + u];
+            }
+#pragma unroll
+            for (int u = 0; u < U8; ++u) acc = fmad(-a[u], b[u], acc);
+        }
     }
     for (; p < p1; ++p) {
         const int2 pq = ix.pairs[p];
@@ -1319,30 +1326,54 @@ __device__ __forceinline__ void il_solve_item(const IlArgs& a, int i, int r, int
     if (!UPPER) {
         const int p1 = ix.r_ptr[i + 1];
         int p = ix.r_ptr[i];
-        for (; p + U8 <= p1; p += U8) {
-            double x[U8], z[U8];
+        if (p + U8 <= p1) {
+            int ip[U8], iy[U8];
 #pragma unroll
             for (int u = 0; u < U8; ++u) {
-                x[u] = lv[(int64_t)ix.r_pos[p + u] * TP + q];
-                z[u] = y[((int64_t)ix.r_idx[p + u] * nrhs + r) * TP + q];
+                ip[u] = ix.r_pos[p + u];
+                iy[u] = ix.r_idx[p + u];
             }
+            for (; p + U8 <= p1; p += U8) {
+                double x[U8], z[U8];
 #pragma unroll
-            for (int u = 0; u < U8; ++u) acc = fmad(-x[u], z[u], acc);
+                for (int u = 0; u < U8; ++u) {
+                    x[u] = lv[(int64_t)ip[u] * TP + q];
+                    z[u] = y[((int64_t)iy[u] * nrhs + r) * TP + q];
+                }
+                if (p + 2 * U8 <= p1) {
+#pragma unroll
+                    for (int u = 0; u < U8; ++u) {
+                        ip[u] = ix.r_pos[p + U8 + u];
+                        iy[u] = ix.r_idx[p + U8 + u];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < U8; ++u) acc = fmad(-x[u], z[u], acc);
+            }
         }
         for (; p < p1; ++p)
             acc = fmad(-lv[(int64_t)ix.r_pos[p] * TP + q], y[((int64_t)ix.r_idx[p] * nrhs + r) * TP + q], acc);
     } else {
         const int t0 = ix.l_ptr[i];
         int t = (sparse_only ? t0 + ix.tail_ccnt[i] : ix.l_ptr[i + 1]) - 1;
-        for (; t - U8 + 1 >= t0; t -= U8) {
-            double x[U8], z[U8];
+        if (t - U8 + 1 >= t0) {
+            int iy[U8];
 #pragma unroll
-            for (int u = 0; u < U8; ++u) {
-                x[u] = uv[(int64_t)(t - u) * TP + q];
-                z[u] = y[((int64_t)ix.l_idx[t - u] * nrhs + r) * TP + q];
+            for (int u = 0; u < U8; ++u) iy[u] = ix.l_idx[t - u];
+            for (; t - U8 + 1 >= t0; t -= U8) {
+                double x[U8], z[U8];
+#pragma unroll
+                for (int u = 0; u < U8; ++u) {
+                    x[u] = uv[(int64_t)(t - u) * TP + q];
+                    z[u] = y[((int64_t)iy[u] * nrhs + r) * TP + q];
+                }
+                if (t - 2 * U8 + 1 >= t0) {
+#pragma unroll
+                    for (int u = 0; u < U8; ++u) iy[u] = ix.l_idx[t - U8 - u];
+                }
+#pragma unroll
+                for (int u = 0; u < U8; ++u) acc = fmad(-x[u], z[u], acc);
             }
-#pragma unroll
-            for (int u = 0; u < U8; ++u) acc = fmad(-x[u], z[u], acc);
         }
         for (; t >= t0; --t)
             acc = fmad(-uv[(int64_t)t * TP + q], y[((int64_t)ix.l_idx[t] * nrhs + r) * TP + q], acc);
