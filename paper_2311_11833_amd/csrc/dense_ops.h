@@ -53,18 +53,18 @@ __device__ __forceinline__ int panel_getrf(double* M, int ld, int c0, double* D)
 
 // Load the factored diagonal block at (c0, c0) into D.
 __device__ __forceinline__ void load_diag(const double* M, int ld, int c0, double* D) {
-    for (int t = threadIdx.x; t < NB * NB; t += WG) {
+    for (int t = threadIdx.x; t < NB * NB; t += blockDim.x) {
         const int i = t % NB, j = t / NB;
         D[i * NB + j] = M[(int64_t)(c0 + j) * ld + c0 + i];
     }
 }
 
-// One thread per item: rows [r_lo, r_hi) get l = a U^{-1} on the panel columns
+// One thread per item (any workgroup width): rows [r_lo, r_hi) get l = a U^{-1} on the panel columns
 // (TRSM from the right with the upper triangle of D, IEEE divisions), columns
 // [c_lo, c_hi) get u = L^{-1} a on the panel rows (unit lower triangle of D).
 __device__ __forceinline__ void panel_trsm(double* M, int ld, int c0, const double* D, int r_lo, int r_hi, int c_lo, int c_hi) {
     const int nrows = max(0, r_hi - r_lo), ncolr = max(0, c_hi - c_lo);
-    for (int t = threadIdx.x; t < nrows + ncolr; t += WG) {
+    for (int t = threadIdx.x; t < nrows + ncolr; t += blockDim.x) {
         double r[NB];
         // keep the LDS reads of D inside the loop (hoisting them all would exhaust registers)
         int z;

@@ -896,28 +896,11 @@ __global__ __launch_bounds__(64 * kTpWaves) void tail_tile_kernel(SpArgs a, int6
         if (gi >= 0 && gj[q] >= 0) T[(int64_t)gj[q] * ld + gi] = acc[q];
 }
 
-// Panel p0 of every system's block: GETRF of the NB x NB diagonal block (wave 0), then the
-// multipliers below it and the rows of U to its right (one workgroup per system).
-__global__ __launch_bounds__(WG) void tail_panel_kernel(SpArgs a, int p0) {
-    __shared__ double D[NB * NB];
-    __shared__ int s_bad;
-    const int ld = a.ix.tail_ld;
-    for (int task = blockIdx.x; task < a.ntasks; task += gridDim.x) {
-        double* T = a.dense + (int64_t)task * a.dstride;
-        if (threadIdx.x < 64) {
-            const int bad = panel_getrf(T, ld, p0, D);
-            if (threadIdx.x == 0) s_bad = bad;
-        }
-        __syncthreads();
-        if (threadIdx.x == 0 && s_bad) atomicMin(&a.info[task], a.ix.tail_b0 + s_bad);
-        panel_trsm(T, ld, p0, D, p0 + NB, ld, p0 + NB, ld);
-        __syncthreads();
-    }
-}
 
-// The same step split for a few systems: the diagonal block's GETRF (one wave per system), then
-// the multipliers and U rows in chunks of WG items (rows below, then columns to the right) over
-// many workgroups, each reloading the factored diagonal block.
+// Panel p0 of every system's block: the diagonal block's GETRF (one wave per system), then the
+// multipliers below it and the rows of U to its right in chunks of kTrsmThreads items (rows
+// below, then columns to the right) over many workgroups, each reloading the factored diagonal
+// block.
 __global__ __launch_bounds__(64) void tail_getrf_kernel(SpArgs a, int p0) {
     __shared__ double D[NB * NB];
     const int ld = a.ix.tail_ld;
@@ -927,7 +910,9 @@ __global__ __launch_bounds__(64) void tail_getrf_kernel(SpArgs a, int p0) {
     }
 }
 
-__global__ __launch_bounds__(WG) void tail_trsm_kernel(SpArgs a, int p0, int chunks) {
+constexpr int kTrsmThreads = 256;
+
+__global__ __launch_bounds__(kTrsmThreads) void tail_trsm_kernel(SpArgs a, int p0, int chunks) {
     __shared__ double D[NB * NB];
     const int ld = a.ix.tail_ld, rest = ld - p0 - NB;
     const int64_t total = (int64_t)chunks * a.ntasks;
@@ -936,7 +921,7 @@ __global__ __launch_bounds__(WG) void tail_trsm_kernel(SpArgs a, int p0, int chu
         double* T = a.dense + (int64_t)task * a.dstride;
         load_diag(T, ld, p0, D);
         __syncthreads();
-        const int i0 = c * WG, i1 = min(i0 + WG, 2 * rest);
+        const int i0 = c * kTrsmThreads, i1 = min(i0 + kTrsmThreads, 2 * rest);
         const int r_lo = p0 + NB + min(i0, rest), r_hi = p0 + NB + min(i1, rest);
         const int c_lo = p0 + NB + max(i0 - rest, 0), c_hi = p0 + NB + max(i1 - rest, 0);
         panel_trsm(T, ld, p0, D, r_lo, r_hi, c_lo, c_hi);
@@ -1693,21 +1678,13 @@ hipError_t tail_dense_factor(SpArgs a, const EpsSet& es, hipStream_t st, int col
         hipLaunchKernelGGL(tail_lu_slot_kernel, dim3(std::min(a.ntasks, 65535)), dim3(WG), kLdsFactor, st, a);
         return hipGetLastError();
     }
-    int dev = 0, cus = 256;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    const bool split = a.ntasks < cus;      // too few systems to fill the device one per workgroup
     for (int p0 = 0; p0 < ld; p0 += NB) {
         const int rest = ld - p0 - NB;
-        if (split) {
-            hipLaunchKernelGGL(tail_getrf_kernel, dim3(std::min(a.ntasks, 65535)), dim3(64), 0, st, a, p0);
-            if (rest > 0) {
-                const int chunks = (2 * rest + WG - 1) / WG;
-                hipLaunchKernelGGL(tail_trsm_kernel, dim3((int)std::min<int64_t>((int64_t)chunks * a.ntasks, 65535)),
-                                   dim3(WG), 0, st, a, p0, chunks);
-            }
-        } else {
-            hipLaunchKernelGGL(tail_panel_kernel, dim3(std::min(a.ntasks, 65535)), dim3(WG), 0, st, a, p0);
+        hipLaunchKernelGGL(tail_getrf_kernel, dim3(std::min(a.ntasks, 65535)), dim3(64), 0, st, a, p0);
+        if (rest > 0) {
+            const int chunks = (2 * rest + kTrsmThreads - 1) / kTrsmThreads;
+            hipLaunchKernelGGL(tail_trsm_kernel, dim3((int)std::min<int64_t>((int64_t)chunks * a.ntasks, 65535)),
+                               dim3(kTrsmThreads), 0, st, a, p0, chunks);
         }
         const int rem = rest;
         if (rem > 0) {
