@@ -50,17 +50,27 @@ def sparse_flops(info, n, nrhs=1):
     return info.flops_sparse_factor + nrhs * (4 * info.nnz_l + n)
 
 
+# counter summaries (FETCH_SIZE + WRITE_SIZE per launch) and the sources of the kernel they cover
+TRAFFIC_PROFILES = {
+    "sparse_steps": ("steps_kernel_n601_hbm_traffic.md", ["steps.hip"]),
+    "dense": ("dense_kernel_n601_hbm_traffic.md", ["dense.hip", "dense_ops.h"]),
+}
+
+
 def measured_traffic(path):
-    """HBM bytes per launch of the headline kernel from the committed counter summary,
+    """HBM bytes per launch of a path's kernel from the committed counter summary,
     or None when the summary is missing or the kernel source changed since."""
     import hashlib
-    if path != "sparse_steps":
+    if path not in TRAFFIC_PROFILES:
         return None
-    prof = os.path.join(ROOT, "profiles", "steps_kernel_n601_hbm_traffic.md")
-    src = os.path.join(ROOT, "paper_2311_11833_amd", "csrc", "steps.hip")
+    name, sources = TRAFFIC_PROFILES[path]
+    prof = os.path.join(ROOT, "profiles", name)
     try:
         text = open(prof).read()
-        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        h = hashlib.sha256()
+        for f in sources:
+            h.update(open(os.path.join(ROOT, "paper_2311_11833_amd", "csrc", f), "rb").read())
+        digest = h.hexdigest()[:16]
     except OSError:
         return None
     vals = dict(l.split(": ", 1) for l in text.splitlines() if l.startswith(("traffic_bytes", "kernel_source")))
@@ -447,9 +457,11 @@ def main():
     roofline_dense = None
     if "dense" in results:
         a_d = dense_flops(n) * systems / (results["dense"]["ms"] / 1e3)
+        tr_d = measured_traffic("dense")
         roofline_dense = {"bound": "mfma", "achieved": a_d / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
-                          "frac": a_d / PEAK_FP64, "traffic": None, "kernel": KERNELS["dense"],
-                          "flops_per_system": dense_flops(n), "solves_per_s": systems / (results["dense"]["ms"] / 1e3)}
+                          "frac": a_d / PEAK_FP64, "traffic": tr_d, "kernel": KERNELS["dense"],
+                          "flops_per_system": dense_flops(n), "solves_per_s": systems / (results["dense"]["ms"] / 1e3),
+                          "hbm_gbs_measured": tr_d / (results["dense"]["ms"] / 1e3) / 1e9 if tr_d else None}
     paths = {}
     for p, rr in results.items():
         paths[p] = {"ms_per_step": rr["ms"], "solves_per_s": systems / (rr["ms"] / 1e3),

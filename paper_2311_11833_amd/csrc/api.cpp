@@ -470,6 +470,7 @@ psp_status psp_plan_upload(psp_plan p, void* dev, size_t dev_bytes, void* stream
     // one-off kernel attributes, here rather than inside a numeric call that may be captured
     HIP_TRY(sparse_kernel_attrs(), "kernel attributes");
     HIP_TRY(steps_kernel_attrs(), "kernel attributes");
+    HIP_TRY(dense_kernel_attrs(), "kernel attributes");
     return PSP_OK;
 }
 

@@ -57,5 +57,6 @@ hipError_t launch_grad_values(int32_t n, int32_t nnz, int32_t batch, int32_t nrh
                               const int32_t* rows, const int32_t* cols, const double* Lamk, const double* Xk,
                               double* gA, hipStream_t st);
 hipError_t dense_occupancy(int* blocks_per_cu);
+hipError_t dense_kernel_attrs();   // once per process: the dense kernels' dynamic LDS limit
 
 }  // namespace psp

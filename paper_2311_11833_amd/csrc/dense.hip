@@ -1,5 +1,5 @@
 // dense.hip -- dense batched pivot-free LU, substitutions and combine for
-// gfx950, one workgroup (4 waves) per perturbed system.
+// gfx950, one workgroup per perturbed system (or per Jacobian and its K systems).
 //
 // Each perturbed system P (A_s + eps_k D) P^T is assembled from the CSR
 // values straight into a column-major n_pad x (n_pad + nrhs) slot of the
@@ -9,20 +9,28 @@
 // so the forward substitution L y = P b is performed by the factorisation
 // itself, exactly as elimination on [A | b] does.
 //
-// Factorisation: right-looking, panels of NB = 32 columns:
+// Factorisation (factor_slot): right-looking, super-panels of 128 columns
+// made of panels of NB = 32:
 //   1. GETRF of the NB x NB diagonal block by one wave (lane = row,
 //      pivot row broadcast with readlane);
 //   2. TRSM of the block column below (one thread per row) and of the block
 //      row to the right, RHS columns included (one thread per column);
-//   3. rank-NB update of the trailing matrix in 64 x 64 tiles staged in LDS.
+//   3. rank-NB updates inside the super-panel and of its block row, then one
+//      rank-128 update of the trailing matrix, all on the MFMA unit with the
+//      U tiles double-buffered in LDS (gemm_mfma_pipe).
 // Every entry receives its updates a <- fma(-l, u, a) in ascending pivot
 // order and every multiplier is an IEEE division, which is the operation
 // sequence of the reference factorisation; the results are therefore
 // identical bit for bit.
 //
-// Back substitution U x = y: blocks of 64 columns from the right; the
-// diagonal triangle is staged in LDS and solved by one wave per RHS column,
-// then the rows above are updated in descending column order.
+// Back substitution U x = y (one RHS: upper_solve_1rhs): blocks of 32 rows
+// from the bottom; wave 0 solves the diagonal triangle from registers, then
+// the rows above are updated in descending column order.
+//
+// Two 256-lane workgroups share a CU, so that one system's in-order panel
+// steps overlap the other's updates.  At n = 608 the kernel streams each
+// system's 3 MB slot from HBM several times (about 24 MB read and 13 MB
+// written per system), half the HBM bandwidth at the measured speed.
 #include "dense.h"
 #include "dense_ops.h"
 
@@ -32,12 +40,12 @@ namespace psp {
 __device__ __forceinline__ void assemble(const DenseArgs& a, double* M, int s, double eps, int ncols) {
     const int tid = threadIdx.x;
     const int64_t total = (int64_t)a.ld * ncols;
-    for (int64_t i = tid; i < total; i += WG) M[i] = 0.0;
+    for (int64_t i = tid; i < total; i += WGD) M[i] = 0.0;
     __syncthreads();
     const double* v = a.values + (int64_t)s * a.nnz;
-    for (int e = tid; e < a.nnz; e += WG) M[a.dst[e]] = v[e];
+    for (int e = tid; e < a.nnz; e += WGD) M[a.dst[e]] = v[e];
     __syncthreads();
-    for (int q = tid; q < a.n_pad; q += WG) {
+    for (int q = tid; q < a.n_pad; q += WGD) {
         const int64_t o = (int64_t)q * a.ld + q;
         if (q < a.n) {
             const double dq = a.dvec ? a.dvec[a.perm[q]] : 1.0;
@@ -48,7 +56,7 @@ __device__ __forceinline__ void assemble(const DenseArgs& a, double* M, int s, d
     }
     if (a.nrhs > 0) {
         const double* b = a.B + (int64_t)s * a.n * a.nrhs;
-        for (int t = tid; t < a.n * a.nrhs; t += WG) {
+        for (int t = tid; t < a.n * a.nrhs; t += WGD) {
             const int q = t / a.nrhs, r = t % a.nrhs;
             M[(int64_t)(a.n_pad + r) * a.ld + q] = b[(int64_t)a.perm[q] * a.nrhs + r];
         }
@@ -62,8 +70,19 @@ __device__ __forceinline__ void assemble(const DenseArgs& a, double* M, int s, d
 // Jacobians s (per_jacobian), which run their K systems one after the other
 // and accumulate x_s = sum_k c_k x_sk in ascending k straight into X, each
 // thread owning the same entries for every k.
-__global__ __launch_bounds__(WG) void dense_factor_solve_kernel(DenseArgs a, EpsSet es) {
+// 256-lane workgroups, two per CU (two waves per SIMD, at most 256 registers per wave, at
+// most 80 KB of LDS each), so that one system's in-order panel steps overlap the other's
+// MFMA updates.
+__global__ __launch_bounds__(WGD, 2) void dense_factor_solve_kernel(DenseArgs a, EpsSet es) {
     extern __shared__ double lds[];
+    // the nodes and weights in LDS: held in scalar registers for the whole kernel they
+    // crowd out the update's addresses
+    __shared__ double s_eps[kMaxK], s_c[kMaxK];
+    if (threadIdx.x < kMaxK) {
+        s_eps[threadIdx.x] = eps_at(es, threadIdx.x);
+        s_c[threadIdx.x] = c_at(es, threadIdx.x);
+    }
+    __syncthreads();
     const int K = es.K;
     const int ntask = a.per_jacobian ? a.batch : a.ntasks;
     for (int task = blockIdx.x; task < ntask; task += gridDim.x) {
@@ -73,17 +92,19 @@ __global__ __launch_bounds__(WG) void dense_factor_solve_kernel(DenseArgs a, Eps
             const int sys = s * K + k;
             double* M = a.slots + (a.keep ? (int64_t)sys : (int64_t)blockIdx.x) * a.slot_stride;
             const int ncols = a.n_pad + a.nrhs;
-            assemble(a, M, s, eps_at(es, k), ncols);
-            const int info = factor_slot(M, a.n_pad, a.ld, ncols, lds);
-            if (info == 0 && a.nrhs > 0) tri_solve<0, 0>(M, a.n_pad, a.ld, M + (int64_t)a.n_pad * a.ld, a.nrhs, lds);
+            assemble(a, M, s, s_eps[k], ncols);
+            const int info = factor_slot<WGD, kFusedBuf, kFusedCT>(M, a.n_pad, a.ld, ncols, lds);
+            if (info == 0 && a.nrhs == 1) upper_solve_1rhs<WGD>(M, a.n_pad, a.ld, M + (int64_t)a.n_pad * a.ld, lds);
+            else if (info == 0 && a.nrhs > 0)
+                tri_solve<0, 0, WGD>(M, a.n_pad, a.ld, M + (int64_t)a.n_pad * a.ld, a.nrhs, lds);
             if (threadIdx.x == 0) a.info[sys] = info;
             if (a.nrhs > 0) {
                 double* x = a.per_jacobian ? a.X + (int64_t)s * a.n * a.nrhs : a.Xk + (int64_t)sys * a.n * a.nrhs;
-                for (int t = threadIdx.x; t < a.n * a.nrhs; t += WG) {
+                for (int t = threadIdx.x; t < a.n * a.nrhs; t += WGD) {
                     const int q = t / a.nrhs, r = t % a.nrhs;
                     const double v = info ? __builtin_nan("") : M[(int64_t)(a.n_pad + r) * a.ld + q];
                     double* dst = x + (int64_t)a.perm[q] * a.nrhs + r;
-                    *dst = a.per_jacobian ? fmad(c_at(es, k), v, k == 0 ? 0.0 : *dst) : v;
+                    *dst = a.per_jacobian ? fmad(s_c[k], v, k == 0 ? 0.0 : *dst) : v;
                 }
             }
             __syncthreads();
@@ -158,16 +179,16 @@ __global__ void grad_values_kernel(int32_t n, int32_t nnz, int32_t batch, int32_
 }
 
 // ---------------------------------------------------------------- host launchers
-int dense_lds_bytes() { return kLdsDense; }
+int dense_lds_bytes() { return kLdsFused; }
 int dense_panel() { return NB; }
 
 hipError_t launch_dense_factor_solve(const DenseArgs& a, const EpsSet& es, int grid, hipStream_t st) {
-    hipLaunchKernelGGL(dense_factor_solve_kernel, dim3(grid), dim3(WG), kLdsDense, st, a, es);
+    hipLaunchKernelGGL(dense_factor_solve_kernel, dim3(grid), dim3(WGD), kLdsFused, st, a, es);
     return hipGetLastError();
 }
 
 hipError_t launch_dense_solve(const DenseSolveArgs& a, int grid, hipStream_t st) {
-    hipLaunchKernelGGL(dense_solve_kernel, dim3(grid), dim3(WG), kLdsDense, st, a);
+    hipLaunchKernelGGL(dense_solve_kernel, dim3(grid), dim3(WG), kLdsSolve, st, a);
     return hipGetLastError();
 }
 
@@ -190,11 +211,23 @@ hipError_t launch_grad_values(int32_t n, int32_t nnz, int32_t batch, int32_t nrh
     return hipGetLastError();
 }
 
+hipError_t dense_kernel_attrs() {
+    static const hipError_t e = [] {
+        hipError_t r = hipFuncSetAttribute((const void*)dense_factor_solve_kernel,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, kLdsFused);
+        if (r == hipSuccess)
+            r = hipFuncSetAttribute((const void*)dense_solve_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    kLdsSolve);
+        return r;
+    }();
+    return e;
+}
+
 hipError_t dense_occupancy(int* blocks_per_cu) {
     // queried once per process (a launch-independent property of the compiled kernel)
     static int occ = 0;
     static const hipError_t e =
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, dense_factor_solve_kernel, WG, kLdsDense);
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, dense_factor_solve_kernel, WGD, kLdsFused);
     *blocks_per_cu = occ;
     return e;
 }

@@ -2053,6 +2053,9 @@ hipError_t sparse_kernel_attrs() {
         if (r == hipSuccess)
             r = hipFuncSetAttribute((const void*)tail_assemble_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)tail_asm_lds(kTailAsmMaxB0));
+        if (r == hipSuccess)
+            r = hipFuncSetAttribute((const void*)tail_lu_slot_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    kLdsFactor);
         return r;
     }();
     return e;
