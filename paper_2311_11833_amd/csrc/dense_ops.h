@@ -386,8 +386,11 @@ __device__ __forceinline__ int factor_slot(double* M, int n_pad, int ld, int nco
 template <int LOWER, int TRANS, int W = WG>
 __device__ __forceinline__ void tri_solve(const double* M, int n_pad, int ld, double* T, int nrhs, double* lds) {
     constexpr bool UNIT = (LOWER && !TRANS) || (!LOWER && TRANS);
-    double* Tri = lds;                 // SB x SB, Tri[i*SB + j] = a(b0+i, b0+j)
-    double* Xs = lds + SB * SB;        // SB x nrhs (nrhs <= 64)
+    // SB x SB, Tri[i*(SB+1) + j] = a(b0+i, b0+j): the padded row stride puts the column reads of
+    // the diagonal solve (one row per lane) on distinct banks
+    constexpr int TP = SB + 1;
+    double* Tri = lds;
+    double* Xs = lds + SB * TP;        // SB x nrhs (nrhs <= 64)
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nblk = (n_pad + SB - 1) / SB;
     for (int bb = 0; bb < nblk; ++bb) {
@@ -397,7 +400,7 @@ __device__ __forceinline__ void tri_solve(const double* M, int n_pad, int ld, do
             const int i = t % SB, j = t / SB;
             double v = 0.0;
             if (i < bs && j < bs) v = TRANS ? M[(int64_t)(b0 + i) * ld + b0 + j] : M[(int64_t)(b0 + j) * ld + b0 + i];
-            Tri[i * SB + j] = v;
+            Tri[i * TP + j] = v;
         }
         __syncthreads();
         for (int r = wave; r < nrhs; r += W / 64) {
@@ -406,17 +409,17 @@ __device__ __forceinline__ void tri_solve(const double* M, int n_pad, int ld, do
             if (LOWER) {
                 for (int k = 0; k < bs; ++k) {
                     double xk = readlane_d(t, k);
-                    if (!UNIT) xk = xk / Tri[k * SB + k];
+                    if (!UNIT) xk = xk / Tri[k * TP + k];
                     if (lane == k) t = xk;
-                    if (lane > k) t = fmad(-Tri[lane * SB + k], xk, t);
+                    if (lane > k) t = fmad(-Tri[lane * TP + k], xk, t);
                     if (lane == 0) Xs[k * 64 + r] = xk;
                 }
             } else {
                 for (int k = bs - 1; k >= 0; --k) {
                     double xk = readlane_d(t, k);
-                    if (!UNIT) xk = xk / Tri[k * SB + k];
+                    if (!UNIT) xk = xk / Tri[k * TP + k];
                     if (lane == k) t = xk;
-                    if (lane < k) t = fmad(-Tri[lane * SB + k], xk, t);
+                    if (lane < k) t = fmad(-Tri[lane * TP + k], xk, t);
                     if (lane == 0) Xs[k * 64 + r] = xk;
                 }
             }
@@ -496,7 +499,7 @@ __device__ __forceinline__ void upper_solve_1rhs(const double* M, int n_pad, int
 template <int NBUF, int CT = 64>
 constexpr int lds_factor_bytes() { return (NB * NB + gemm_pipe_lds_doubles<SP, NBUF, CT>()) * 8; }
 constexpr int kLdsFactor = lds_factor_bytes<2>();
-constexpr int kLdsSolve = (SB * SB + SB * 64) * 8;
+constexpr int kLdsSolve = (SB * (SB + 1) + SB * 64) * 8;
 constexpr int kLdsDense = kLdsFactor > kLdsSolve ? kLdsFactor : kLdsSolve;
 // the fused dense kernel: two 256-lane workgroups per CU, whose updates double-buffer
 // U tiles of 32 columns (74.75 KB of LDS with the diagonal block)

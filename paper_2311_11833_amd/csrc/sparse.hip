@@ -1073,7 +1073,8 @@ template <int LOWER, int TRANS>
 __global__ __launch_bounds__(WG) void tail_tri_diag_kernel(SpArgs a, int c0) {
     constexpr bool UNIT = (LOWER && !TRANS) || (!LOWER && TRANS);
     constexpr int NW = WG / 64;                  // right-hand sides per workgroup, one per wave
-    __shared__ double Tri[SB * SB];
+    constexpr int TP = SB + 1;                  // padded rows: the solve's column reads hit distinct banks
+    __shared__ double Tri[SB * TP];
     const int ld = a.ix.tail_ld, nrhs = a.nrhs, bs = min(SB, ld - c0);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int groups = (nrhs + NW - 1) / NW;     // workgroup b: system b / groups, waves' RHS from (b % groups) * NW
@@ -1086,7 +1087,7 @@ __global__ __launch_bounds__(WG) void tail_tri_diag_kernel(SpArgs a, int c0) {
             const int i = t % SB, j = t / SB;
             double v = 0.0;
             if (i < bs && j < bs) v = TRANS ? M[(int64_t)(c0 + i) * ld + c0 + j] : M[(int64_t)(c0 + j) * ld + c0 + i];
-            Tri[i * SB + j] = v;
+            Tri[i * TP + j] = v;
         }
         __syncthreads();
         for (int r = r0 + wave; r < min(nrhs, r0 + NW); r += NW) {
@@ -1095,16 +1096,16 @@ __global__ __launch_bounds__(WG) void tail_tri_diag_kernel(SpArgs a, int c0) {
             if (LOWER) {
                 for (int k = 0; k < bs; ++k) {
                     double xk = readlane_d(t, k);
-                    if (!UNIT) xk = xk / Tri[k * SB + k];
+                    if (!UNIT) xk = xk / Tri[k * TP + k];
                     if (lane == k) t = xk;
-                    if (lane > k) t = fmad(-Tri[lane * SB + k], xk, t);
+                    if (lane > k) t = fmad(-Tri[lane * TP + k], xk, t);
                 }
             } else {
                 for (int k = bs - 1; k >= 0; --k) {
                     double xk = readlane_d(t, k);
-                    if (!UNIT) xk = xk / Tri[k * SB + k];
+                    if (!UNIT) xk = xk / Tri[k * TP + k];
                     if (lane == k) t = xk;
-                    if (lane < k) t = fmad(-Tri[lane * SB + k], xk, t);
+                    if (lane < k) t = fmad(-Tri[lane * TP + k], xk, t);
                 }
             }
             if (lane < bs) tc[lane] = t;
@@ -1145,12 +1146,13 @@ __global__ void tail_tri_rest_kernel(SpArgs a, int c0) {
 // One workgroup per system (large batches): the block's whole LU with super-panels and MFMA
 // updates, or one triangular solve; the same operations in the same order as the per-panel and
 // per-block kernels above, so the same bits.
-__global__ __launch_bounds__(WG) void tail_lu_slot_kernel(SpArgs a) {
+// The LU takes the dense path's configuration: 256-lane workgroups, two per CU.
+__global__ __launch_bounds__(WGD, 2) void tail_lu_slot_kernel(SpArgs a) {
     extern __shared__ double lds[];
     const int ld = a.ix.tail_ld;
     for (int task = blockIdx.x; task < a.ntasks; task += gridDim.x) {
         double* T = a.dense + (int64_t)task * a.dstride;
-        const int bad = factor_slot(T, ld, ld, ld, lds);
+        const int bad = factor_slot<WGD, kFusedBuf, kFusedCT>(T, ld, ld, ld, lds);
         if (threadIdx.x == 0 && bad) atomicMin(&a.info[task], a.ix.tail_b0 + bad);
         __syncthreads();
     }
@@ -1675,7 +1677,7 @@ hipError_t tail_dense_factor(SpArgs a, const EpsSet& es, hipStream_t st, int col
                            dim3(kAsmThreads), (int)tail_asm_lds(a.ix.tail_b0), st, a, cols);
     }
     if (slot) {
-        hipLaunchKernelGGL(tail_lu_slot_kernel, dim3(std::min(a.ntasks, 65535)), dim3(WG), kLdsFactor, st, a);
+        hipLaunchKernelGGL(tail_lu_slot_kernel, dim3(std::min(a.ntasks, 65535)), dim3(WGD), kLdsFused, st, a);
         return hipGetLastError();
     }
     for (int p0 = 0; p0 < ld; p0 += NB) {
@@ -2055,7 +2057,7 @@ hipError_t sparse_kernel_attrs() {
                                     (int)tail_asm_lds(kTailAsmMaxB0));
         if (r == hipSuccess)
             r = hipFuncSetAttribute((const void*)tail_lu_slot_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    kLdsFactor);
+                                    kLdsFused);
         return r;
     }();
     return e;
