@@ -114,7 +114,7 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int KDMAX = 128;
 
 template <int KDM = KDMAX, int W = WG>
-__device__ __attribute__((noinline)) void gemm_mfma(double* M, int ld, int r_lo, int r_hi, int c_lo, int c_hi, int k_lo, int kd,
+__device__ __forceinline__ void gemm_mfma(double* M, int ld, int r_lo, int r_hi, int c_lo, int c_hi, int k_lo, int kd,
                                           double* Us) {
     constexpr int KS = KDM / 4;
     constexpr int NW = W / 64;                  // waves; each owns 16 rows of the 16*NW-row group
@@ -323,6 +323,14 @@ __device__ __forceinline__ void gemm_mfma_pipe(double* M, int ld, int r_lo, int 
     }
 }
 
+// A partial super-panel (kd other than NB or KDMAX; none occurs with rows to update): the
+// plain update, kept out of line so that it does not weigh on the callers' registers.
+template <int W>
+__device__ __attribute__((noinline)) void gemm_mfma_cold(double* M, int ld, int r_lo, int r_hi, int c_lo, int c_hi,
+                                                         int k_lo, int kd, double* Us) {
+    gemm_mfma<KDMAX, W>(M, ld, r_lo, r_hi, c_lo, c_hi, k_lo, kd, Us);
+}
+
 template <int W, int NBUF, int CT = 64>
 __device__ __forceinline__ void gemm_kd(int kd, double* M, int ld, int r_lo, int r_hi, int c_lo, int c_hi, int k_lo,
                                         double* Us) {
@@ -332,7 +340,7 @@ __device__ __forceinline__ void gemm_kd(int kd, double* M, int ld, int r_lo, int
     else if (kd == KDMAX)
         gemm_mfma_pipe<KDMAX, W, NBUF, CT>(M, ld, r_lo, r_hi, c_lo, c_hi, k_lo, Us);
     else
-        gemm_mfma<KDMAX, W>(M, ld, r_lo, r_hi, c_lo, c_hi, k_lo, kd, Us);
+        gemm_mfma_cold<W>(M, ld, r_lo, r_hi, c_lo, c_hi, k_lo, kd, Us);
 }
 
 // Right-looking factorisation with super-panels of SP = 4 NB columns:
