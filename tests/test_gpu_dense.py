@@ -43,7 +43,7 @@ def _check(xg, xo, info_g, info_o):
 
 
 @pytest.mark.parametrize("N,count,order", [(14, 3, "md"), (14, 2, "natural"), (30, 4, "md"), (118, 2, "md"),
-                                           (300, 2, "md"), (300, 1, "natural")])
+                                           (300, 2, "md"), (300, 1, "natural"), (500, 1, "md")])
 def test_fused_matches_oracle_bitwise(psp, O, W, dev, N, count, order):
     ip, ix, vals, bs = W.scenario_batch(N, count)
     n = len(ip) - 1
