@@ -14,7 +14,6 @@
 namespace psp {
 
 constexpr int NB = 32;        // panel width
-constexpr int TB = 64;        // trailing-update tile (TB x TB)
 constexpr int SB = 64;        // triangular-solve block
 constexpr int WG = 512;       // threads per workgroup (8 waves)
 
@@ -109,8 +108,8 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // column of the column-major matrix: lane l, register q holds
 // C[row0 + l%16][col0 + 4q + l/16].  Each wave keeps its 16 rows of L
 // (the b operand) in registers for the whole sweep; the U tile (KD x 64) is
-// staged in LDS and shared by the 8 waves; the workgroup covers 128 rows x 64
-// columns per step.
+// staged in LDS and shared by the workgroup's W/64 waves, which cover 16 W/64
+// rows x 64 columns per step.
 constexpr int KDMAX = 128;
 
 template <int KDM = KDMAX, int W = WG>
@@ -192,7 +191,7 @@ __device__ __forceinline__ void gemm_mfma(double* M, int ld, int r_lo, int r_hi,
 template <int KDM, int NBUF, int CT = 64>
 constexpr int gemm_pipe_lds_doubles() { return NBUF * CT * (KDM + 2); }
 
-// kd == KDM (a full panel or super-panel); ld * ncols * 8 < 2^32 bytes.
+// kd == KDM (a full panel or super-panel).
 template <int KDM, int W, int NBUF, int CT = 64>
 __device__ __forceinline__ void gemm_mfma_pipe(double* M, int ld, int r_lo, int r_hi, int c_lo, int c_hi, int k_lo,
                                                double* Us) {
