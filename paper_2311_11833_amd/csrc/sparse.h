@@ -41,6 +41,8 @@ struct SpIdx {
     int32_t tail_n, tail_b0, tail_ld, fac_lev_sp, nlev_sp[2];
     int64_t tail_off;
     const int32_t* tail_rcnt;       // tail_n: entries below tail_b0 in each row of the block
+    const int32_t* tail_long;       // tail_nlong: block rows with at least 2,048 such entries (long chains)
+    int32_t tail_nlong;
     const int32_t* tail_lastpos;    // tail_b0: position of (n-1, k) in column k of L, or -1
     const int32_t* tail_ccnt;       // tail_b0: entries of column k of L in rows before tail_b0
     const int32_t* lev_sp_ptr[2];   // L-solve / U-solve levels of the rows < tail_b0

@@ -946,6 +946,80 @@ __global__ __launch_bounds__(WG) void tail_update_kernel(SpArgs a, int p0, int t
 // division, which the dense solve applies after the block's own updates.
 constexpr int kExtThreads = 128;   // the block-row update kernel: room for 32 loads in flight per lane
 
+// A block row with this many terms from the sparse part (the slack row: 18,480 at n = 20,001)
+// is one long fma chain per system and right-hand side; one lane per chain keeps only ~32 terms'
+// loads in flight, so such rows get a wave per chain instead (tail_fwd_long_kernel).
+constexpr int kTailLongRow = 2048;
+
+// One wave per (long row, system, right-hand side), grid-stride: lane l fetches term 64 b + l of
+// batch b, its index three batches and its values (the L (U^T) entry and the solution entry) two
+// batches before the batch is applied; the index of batch b + 3 is waited for only once batch b's
+// values are due anyway (loads complete in order).  A batch's 64 pairs go through LDS and every
+// lane applies them in ascending order to the same accumulator with broadcast reads: the chain
+// and its rounding are those of one lane walking the row.  Terms past the row's end read a valid
+// entry and count as 0 x 0.
+template <int TRANS>
+__global__ __launch_bounds__(64) void tail_fwd_long_kernel(SpArgs a) {
+    constexpr int DV = 2, DI = 4;            // batches of values / of indices in flight
+    __shared__ __align__(16) double sp[64][2];
+    const SpIdx& ix = a.ix;
+    const int n = ix.n, nl = ix.nnzl, nrhs = a.nrhs, b0 = ix.tail_b0, lane = threadIdx.x;
+    const int64_t per_row = (int64_t)nrhs * a.ntasks, chains = (int64_t)ix.tail_nlong * per_row;
+    const bool il = a.vs != 1;
+    for (int64_t c = blockIdx.x; c < chains; c += gridDim.x) {
+        const int lr = (int)(c / per_row);
+        const int q = (int)(c % per_row);
+        const int task = il ? q % a.ntasks : q / nrhs;
+        const int r = il ? q / a.ntasks : q % nrhs;
+        if (a.info[task]) continue;                       // uniform per wave
+        const int i = b0 + ix.tail_long[lr];
+        const int64_t vs = a.vs, ys = a.yv;
+        const double* m = a.fac + (int64_t)task * a.ts + (int64_t)(TRANS ? n + nl : n) * vs;
+        double* y = a.y + (int64_t)task * a.yt + (int64_t)r * ys;
+        const int p0 = ix.r_ptr[i], len = ix.tail_rcnt[i - b0], pl = p0 + len - 1;
+        const int nb = (len + 63) / 64;
+        double acc = y[(int64_t)i * nrhs * ys];
+        int ip[DI], iy[DI];
+        double mv[DV], yw[DV];
+        auto load_idx = [&](int b, int& ipo, int& iyo) {
+            const int p = min(p0 + 64 * b + lane, pl);
+            ipo = ix.r_pos[p];
+            iyo = ix.r_idx[p];
+        };
+        auto load_val = [&](int b, int ipi, int iyi, double& mo, double& yo) {
+            const bool ok = 64 * b + lane < len;
+            const double mm = m[(int64_t)ipi * vs], yy = y[(int64_t)iyi * nrhs * ys];
+            mo = ok ? mm : 0.0;
+            yo = ok ? yy : 0.0;
+        };
+#pragma unroll
+        for (int d = 0; d < DI; ++d) load_idx(d, ip[d], iy[d]);
+#pragma unroll
+        for (int d = 0; d < DV; ++d) load_val(d, ip[d], iy[d], mv[d], yw[d]);
+        for (int bb = 0; bb < nb; bb += DI) {
+#pragma unroll
+            for (int d = 0; d < DI; ++d) {
+                const int b = bb + d;
+                if (b >= nb) break;
+                const int dv = d % DV;
+                sp[lane][0] = mv[dv];
+                sp[lane][1] = yw[dv];
+                // batch b + DV's values from the indices fetched DI - DV batches ago, then the
+                // indices of batch b + DI into the slot batch b's indices used
+                load_val(b + DV, ip[(d + DV) % DI], iy[(d + DV) % DI], mv[dv], yw[dv]);
+                load_idx(b + DI, ip[d], iy[d]);
+                __builtin_amdgcn_wave_barrier();
+                // all 64 slots (past the row's end they hold 0 x 0, which leaves acc as it is), a
+                // fixed count so that the reads run ahead of the chain
+#pragma unroll 16
+                for (int j = 0; j < 64; ++j) acc = fmad(-sp[j][0], sp[j][1], acc);
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+        if (lane == 0) y[(int64_t)i * nrhs * ys] = acc;
+    }
+}
+
 template <int TRANS>
 __global__ __launch_bounds__(kExtThreads) void tail_fwd_ext_kernel(SpArgs a) {
     const SpIdx& ix = a.ix;
@@ -957,6 +1031,7 @@ __global__ __launch_bounds__(kExtThreads) void tail_fwd_ext_kernel(SpArgs a) {
         const int t = il ? (int)(g / a.ntasks) : (int)(g % per);
         if (a.info[task]) continue;
         const int i = b0 + t / nrhs, r = t % nrhs;
+        if (ix.tail_rcnt[i - b0] >= kTailLongRow) continue;   // tail_fwd_long_kernel's
         const int64_t vs = a.vs, ys = a.yv;
         const double* m = a.fac + (int64_t)task * a.ts + (int64_t)(TRANS ? n + nl : n) * vs;
         double* y = a.y + (int64_t)task * a.yt + (int64_t)r * ys;
@@ -1728,6 +1803,14 @@ hipError_t tail_dense_solve(SpArgs a, hipStream_t st, bool slot) {
         hipLaunchKernelGGL(tail_fwd_ext_kernel<1>, dim3(grid_for(trows, kExtThreads)), dim3(kExtThreads), 0, st, a);
     else
         hipLaunchKernelGGL(tail_fwd_ext_kernel<0>, dim3(grid_for(trows, kExtThreads)), dim3(kExtThreads), 0, st, a);
+    const int64_t lchains = (int64_t)a.ix.tail_nlong * a.nrhs * a.ntasks;
+    if (lchains > 0) {
+        const dim3 lg((unsigned)std::min<int64_t>(lchains, 1 << 20));
+        if (a.trans)
+            hipLaunchKernelGGL(tail_fwd_long_kernel<1>, lg, dim3(64), 0, st, a);
+        else
+            hipLaunchKernelGGL(tail_fwd_long_kernel<0>, lg, dim3(64), 0, st, a);
+    }
     hipLaunchKernelGGL(tail_rhs_in_kernel, dim3(grid_for(tpad, kThreads)), dim3(kThreads), 0, st, a);
     if (slot) {
         const dim3 g(std::min(a.ntasks, 65535));
@@ -2000,6 +2083,12 @@ void sparse_image(const Symbolic& s, PlanImage& img, SparseDevice& d) {
                                                s.tail_b0) - (s.lrow_idx.begin() + s.lrow_ptr[r]));
         }
         img.bind(&ix.tail_rcnt, img.put(rc));
+        std::vector<int32_t> lr;
+        for (int i = 0; i < s.tail_n; ++i)
+            if (rc[i] >= kTailLongRow) lr.push_back(i);
+        ix.tail_nlong = (int32_t)lr.size();
+        if (lr.empty()) lr.push_back(0);
+        img.bind(&ix.tail_long, img.put(lr));
         std::vector<int32_t> lp(std::max(s.tail_b0, 1), -1);
         for (int k = 0; k < s.tail_b0; ++k)
             if (s.l_ptr[k + 1] > s.l_ptr[k] && s.l_idx[s.l_ptr[k + 1] - 1] == n - 1) lp[k] = s.l_ptr[k + 1] - 1;
