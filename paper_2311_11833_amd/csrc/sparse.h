@@ -61,6 +61,8 @@ struct SpIdx {
     const int32_t* tail_kt_ptr;         // tiles + 1
     const int32_t* tail_mpos;           // 16 x panel columns
     const int32_t* tail_pp_ptr;         // tiles^2 + 1
+    const int32_t* tail_lpairs;         // tail_nlpairs: tile pairs of 512 or more steps (long chains)
+    int32_t tail_nlpairs;
     const int32_t* tail_pairs;
 };
 

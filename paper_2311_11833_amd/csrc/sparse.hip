@@ -748,8 +748,15 @@ int64_t tail_asm_lds(int32_t b0) {
 // ascending k), computed transposed like gemm_mfma: A = -U panel of u, B = L panel of t, so lane
 // l, register q holds the entry of slots (16t + l%16, 16u + 4q + l/16); the chains start from the
 // block's initial values, written beforehand.
-constexpr int kTpWaves = 4;
+constexpr int kTpWaves = 8;
 constexpr int kTpUnroll = 8;
+constexpr int kTileLongSteps = 512;   // tile pairs with this many steps take the staged path
+// Staged path of the long tile pairs: chunks of kLcSteps MFMA steps, kLcDepth chunks in flight,
+// a ring of kLcDepth + 1 chunk slots in LDS (A columns then B columns, 16 doubles each), and per
+// wave two blocks of 8 chunks' pair words (68 KB in all: the two workgroups per CU that the
+// registers allow still fit).
+constexpr int kLcSteps = 16, kLcDepth = 3, kLcSlots = kLcDepth + 1;
+constexpr int kLcSlot = 2 * 4 * kLcSteps * 16;
 
 __device__ __forceinline__ double* tail_panels(const SpIdx& ix, double* T) {
     return T + (int64_t)ix.tail_ld * ix.tail_ld + (int64_t)ix.tail_ld * 64;
@@ -827,22 +834,181 @@ __global__ __launch_bounds__(256) void tail_panel_gather_il_kernel(SpArgs a, int
     }
 }
 
+// LDS byte address of a pointer into a __shared__ array.
+__device__ __forceinline__ uint32_t lds_addr(const void* p) {
+    return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void*)p;
+}
+
+// The staged path's LDS reads are written out with their wait in the same block: they follow
+// the wait and barrier that complete the copies they read, and left to the compiler each read
+// would also wait for every copy still in flight (it cannot tell the ring slots apart).
+// Eight steps of a chunk's operands at LDS address s (A: steps 64 doubles apart, B 8 KB on),
+// and the pair word at LDS address w, under one wait.
+__device__ __forceinline__ void read_half(uint32_t s, uint32_t w, double* av, double* bv, int& wd) {
+    static_assert(kLcSlot == 2048, "offsets below assume chunks of 16 steps of 4 x 16 doubles");
+    asm volatile(
+        "ds_read_b32 %16, %18\n\t"
+        "ds_read_b64 %0, %17\n\t"
+        "ds_read_b64 %1, %17 offset:512\n\t"
+        "ds_read_b64 %2, %17 offset:1024\n\t"
+        "ds_read_b64 %3, %17 offset:1536\n\t"
+        "ds_read_b64 %4, %17 offset:2048\n\t"
+        "ds_read_b64 %5, %17 offset:2560\n\t"
+        "ds_read_b64 %6, %17 offset:3072\n\t"
+        "ds_read_b64 %7, %17 offset:3584\n\t"
+        "ds_read_b64 %8, %17 offset:8192\n\t"
+        "ds_read_b64 %9, %17 offset:8704\n\t"
+        "ds_read_b64 %10, %17 offset:9216\n\t"
+        "ds_read_b64 %11, %17 offset:9728\n\t"
+        "ds_read_b64 %12, %17 offset:10240\n\t"
+        "ds_read_b64 %13, %17 offset:10752\n\t"
+        "ds_read_b64 %14, %17 offset:11264\n\t"
+        "ds_read_b64 %15, %17 offset:11776\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(av[0]), "=&v"(av[1]), "=&v"(av[2]), "=&v"(av[3]), "=&v"(av[4]), "=&v"(av[5]), "=&v"(av[6]),
+          "=&v"(av[7]), "=&v"(bv[0]), "=&v"(bv[1]), "=&v"(bv[2]), "=&v"(bv[3]), "=&v"(bv[4]), "=&v"(bv[5]),
+          "=&v"(bv[6]), "=&v"(bv[7]), "=&v"(wd)
+        : "v"(s), "v"(w)
+        : "memory");
+}
+
+// The pair word at LDS address w alone.
+__device__ __forceinline__ int read_word(uint32_t w) {
+    int wd;
+    asm volatile("ds_read_b32 %0, %1\n\ts_waitcnt lgkmcnt(0)" : "=v"(wd) : "v"(w) : "memory");
+    return wd;
+}
+
+// One long tile pair per workgroup at a time (see tail_tile_kernel): the eight waves copy the
+// panel columns of chunk c + kLcDepth while wave 0 runs the MFMAs of chunk c.
+__device__ __forceinline__ void tail_tile_long(const SpArgs& a, int lwgs, double* ring, int32_t* words) {
+    const SpIdx& ix = a.ix;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+    constexpr int CW = 4 * kLcSteps;   // pair words (columns of A, and of B) per chunk
+    // this lane's share of a chunk's copies: column q of A and of B, rows r0 and r0 + 1
+    const int q = 8 * wave + (lane >> 3), r0 = 2 * (lane & 7);
+    static_assert(kTpWaves == 8 && CW == 64, "eight waves copy a chunk's 64 + 64 columns, 8 + 8 each");
+    int32_t* Wd = words + wave * 128;   // this wave's words: two blocks of 8 chunks x its 8 columns
+    const int64_t items = (int64_t)ix.tail_nlpairs * a.ntasks;
+    for (int64_t it = blockIdx.x; it < items; it += lwgs) {
+        const int task = (int)(it / ix.tail_nlpairs), pi = ix.tail_lpairs[it % ix.tail_nlpairs];
+        const int TT = ix.tail_tiles, t = pi / TT, u = pi % TT;
+        double* T = a.dense + (int64_t)task * a.dstride;
+        const double* PL = tail_panels(ix, T);
+        const double* Lt = PL + 16 * (int64_t)ix.tail_kt_ptr[t] + r0;
+        const double* Uu = PL + ix.tail_panel + 16 * (int64_t)ix.tail_kt_ptr[u] + r0;
+        // past the end: the zero column of each panel (the pair lists' own padding), so that the
+        // last chunk's extra steps leave the sums unchanged
+        const int zw = (ix.tail_kt_ptr[t + 1] - ix.tail_kt_ptr[t] - 1) | (ix.tail_kt_ptr[u + 1] - ix.tail_kt_ptr[u] - 1) << 16;
+        const int p0 = ix.tail_pp_ptr[pi], p1 = ix.tail_pp_ptr[pi + 1];
+        const int len = p1 - p0, nch = (len + CW - 1) / CW;
+        // Word block m (chunks 8m .. 8m + 7) into block slot m % 2: lane l takes the word of chunk
+        // 8m + l / 8, column 8 wave + l % 8 (clamped in bounds).
+        const int wcol = 8 * wave + (lane & 7), wch = lane >> 3;
+        auto load_words = [&](int m) {
+            __builtin_amdgcn_global_load_lds(ix.tail_pairs + p0 + min(CW * (8 * m + wch) + wcol, len - 1),
+                                             Wd + (m % 2) * 64, 4, 0, 0);
+        };
+        auto word_addr = [&](int j) { return lds_addr(Wd + ((j >> 3) % 2) * 64 + (j & 7) * 8 + (lane >> 3)); };
+        // Columns of chunk j into ring slot j % kLcSlots.
+        auto copy = [&](int j, int wd) {
+            wd = CW * j + q < len ? wd : zw;
+            double* S = ring + (j % kLcSlots) * kLcSlot + 128 * wave;
+            __builtin_amdgcn_global_load_lds(Uu + 16 * (int)((uint32_t)wd >> 16), S, 16, 0, 0);
+            __builtin_amdgcn_global_load_lds(Lt + 16 * (wd & 0xFFFF), S + kLcSlot / 2, 16, 0, 0);
+        };
+        v4d acc = {0.0, 0.0, 0.0, 0.0};
+        int gi = -1, gj[4] = {-1, -1, -1, -1};
+        if (wave == 0) {
+            gi = ix.tail_rord[16 * t + li];
+#pragma unroll
+            for (int x = 0; x < 4; ++x) {
+                gj[x] = ix.tail_rord[16 * u + 4 * x + lk];
+                acc[x] = (gi >= 0 && gj[x] >= 0) ? T[(int64_t)gj[x] * ix.tail_ld + gi] : 0.0;
+            }
+        }
+        static_assert(kLcDepth < 8, "the first kLcDepth copies take their words from block 0");
+        load_words(0);
+        load_words(1);
+        __builtin_amdgcn_s_waitcnt(0);
+        for (int j = 0; j < kLcDepth; ++j) copy(j, read_word(word_addr(j)));
+        __builtin_amdgcn_s_waitcnt(0);
+        for (int c = 0; c < nch; ++c) {
+            // Each iteration issues two copies per wave (and every eighth one word load as well).
+            // Waiting until 2 (kLcDepth - 1) loads remain completes the copies of chunk c, issued
+            // kLcDepth iterations back, and the word block that chunk c + kLcDepth reads, issued
+            // eight iterations before its first use; the barrier then makes chunk c visible and
+            // tells that wave 0 is done with chunk c - 1, whose slot is refilled next.
+            static_assert(2 * (kLcDepth - 1) < 16, "the wait below encodes vmcnt in its low four bits");
+            __builtin_amdgcn_s_waitcnt(0x0070 | (2 * (kLcDepth - 1)));   // vmcnt(2 (kLcDepth - 1)) lgkmcnt(0)
+            asm volatile("" ::: "memory");
+            __builtin_amdgcn_s_barrier();
+            asm volatile("" ::: "memory");
+            const uint32_t S = lds_addr(ring + (c % kLcSlots) * kLcSlot + 16 * lk + li);
+            double av[8], bv[8];
+            int wd;
+            if (wave == 0)
+                read_half(S, word_addr(c + kLcDepth), av, bv, wd);
+            else
+                wd = read_word(word_addr(c + kLcDepth));
+            copy(c + kLcDepth, wd);
+            // block m is first read by the copy of chunk 8 m, at iteration 8 m - kLcDepth; it
+            // is loaded eight iterations before, after the last read of block m - 2
+            if (((c + 8 + kLcDepth) & 7) == 0) load_words((c + 8 + kLcDepth) >> 3);
+            if (wave == 0) {
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    if (h == 1) read_half(S + 4096, word_addr(c + kLcDepth), av, bv, wd);
+#pragma unroll
+                    for (int x = 0; x < 8; ++x)
+                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[x], bv[x], acc, 0, 0, 0);
+                }
+            }
+        }
+        if (wave == 0) {
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+                if (gi >= 0 && gj[x] >= 0) T[(int64_t)gj[x] * ix.tail_ld + gi] = acc[x];
+        }
+        // the loads past the end land before the ring is used again
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+    }
+}
+
 // Logical workgroup l of a launch of G = 8 m workgroups runs as hardware workgroup
 // (l % m) * 8 + l / m, so consecutive logical workgroups (the tile pairs of one system, which
 // share its panels) are dispatched to the same XCD and its L2.  Wave w of logical workgroup l
 // takes tile pair l * kTpWaves + w (item = system * tiles^2 + t * tiles + u).  The panel loads
 // of the next kTpUnroll steps are issued before the MFMAs of the current ones (the chain of a
 // long pair, the slack row's tile with itself, is otherwise one memory latency per step).
-__global__ __launch_bounds__(64 * kTpWaves) void tail_tile_kernel(SpArgs a, int64_t items) {
+//
+// The long pairs (the slack row's tile with itself: 4,620 steps at n = 20,001) are not left to
+// one wave's register prefetch: the first lwgs workgroups of the launch (a multiple of 8, so the
+// XCD mapping of the others is unchanged) take one long pair each, and all four waves stage its
+// panel columns through an LDS ring (global_load_lds, kLcDepth chunks of kLcSteps steps in
+// flight) while wave 0 runs the chain from LDS in the same step order.  They run beside the
+// regular pairs instead of after them.
+__global__ __launch_bounds__(64 * kTpWaves) void tail_tile_kernel(SpArgs a, int64_t items, int lwgs) {
+    __shared__ __align__(16) double ring[kLcSlots * kLcSlot];
+    __shared__ __align__(16) int32_t words[kTpWaves * 128];
+    if ((int)blockIdx.x < lwgs) {   // uniform per workgroup
+        tail_tile_long(a, lwgs, ring, words);
+        return;
+    }
     const SpIdx& ix = a.ix;
-    const int64_t m = gridDim.x / 8;
-    const int64_t lw = (int64_t)(blockIdx.x % 8) * m + blockIdx.x / 8;
+    const int64_t bid = blockIdx.x - lwgs;
+    const int64_t m = (gridDim.x - lwgs) / 8;
+    const int64_t lw = (bid % 8) * m + bid / 8;
     const int64_t it = lw * kTpWaves + (threadIdx.x >> 6);
     if (it >= items) return;                     // uniform per wave; the kernel has no barrier
     const int TT = ix.tail_tiles;
     const int64_t pairs_per = (int64_t)TT * TT;
     const int task = (int)(it / pairs_per), pi = (int)(it % pairs_per);
     const int t = pi / TT, u = pi % TT;
+    const int p0 = ix.tail_pp_ptr[pi], p1 = ix.tail_pp_ptr[pi + 1];
+    if (lwgs > 0 && (p1 - p0) / 4 >= kTileLongSteps) return;   // a long pair: the staged path's
     const int ld = ix.tail_ld;
     const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
     double* T = a.dense + (int64_t)task * a.dstride;
@@ -857,7 +1023,6 @@ __global__ __launch_bounds__(64 * kTpWaves) void tail_tile_kernel(SpArgs a, int6
         gj[q] = ix.tail_rord[16 * u + 4 * q + lk];
         acc[q] = (gi >= 0 && gj[q] >= 0) ? T[(int64_t)gj[q] * ld + gi] : 0.0;
     }
-    const int p0 = ix.tail_pp_ptr[pi], p1 = ix.tail_pp_ptr[pi + 1];
     const int32_t* pr = ix.tail_pairs + lk;
     constexpr int UN = kTpUnroll;
     // pair words: a | b << 16 (past the end: column 0 of both panels, never used)
@@ -1744,7 +1909,10 @@ hipError_t tail_dense_factor(SpArgs a, const EpsSet& es, hipStream_t st, int col
         const int64_t items = (int64_t)a.ix.tail_tiles * a.ix.tail_tiles * a.ntasks;
         const int64_t wgs = (items + kTpWaves - 1) / kTpWaves;
         if ((wgs + 7) / 8 * 8 > INT32_MAX) return hipErrorInvalidValue;
-        hipLaunchKernelGGL(tail_tile_kernel, dim3((unsigned)((wgs + 7) / 8 * 8)), dim3(64 * kTpWaves), 0, st, a, items);
+        const int64_t litems = (int64_t)a.ix.tail_nlpairs * a.ntasks;
+        const int lwgs = (int)((std::min<int64_t>(litems, 1 << 16) + 7) / 8 * 8);
+        hipLaunchKernelGGL(tail_tile_kernel, dim3((unsigned)((wgs + 7) / 8 * 8 + lwgs)), dim3(64 * kTpWaves), 0, st, a,
+                           items, lwgs);
     } else {
         if (a.vs != 1) return hipErrorInvalidValue;
         cols = cols == 1 ? 1 : kAsmCols;
@@ -2126,6 +2294,12 @@ void sparse_image(const Symbolic& s, PlanImage& img, SparseDevice& d) {
         img.bind(&ix.tail_mpos, img.put(mpos));
         img.bind(&ix.tail_pp_ptr, img.put(ppp));
         img.bind(&ix.tail_pairs, img.put(prs));
+        std::vector<int32_t> lpr;
+        for (int64_t pi = 0; pi + 1 < (int64_t)ppp.size(); ++pi)
+            if ((ppp[pi + 1] - ppp[pi]) / 4 >= kTileLongSteps) lpr.push_back((int32_t)pi);
+        ix.tail_nlpairs = TT ? (int32_t)lpr.size() : 0;
+        if (lpr.empty()) lpr.push_back(0);
+        img.bind(&ix.tail_lpairs, img.put(lpr));
     }
     for (int w = 0; w < 2; ++w) {
         ix.nlev_sp[w] = s.tail_n ? (int32_t)s.lev_sp_ptr[w].size() - 1 : 0;
