@@ -1354,32 +1354,60 @@ __global__ __launch_bounds__(WG) void tail_tri_diag_kernel(SpArgs a, int c0) {
     }
 }
 
+// The rows outside the solved 64-row block, each (row, right-hand side) updated by the block's
+// bs terms in the order of the solve.  A workgroup takes one system, 64 rows and up to 32
+// right-hand sides: it stages the 64 x bs multipliers (transposed when TRANS, so that both
+// orientations are read along a row index) and the bs x 32 solved values in LDS, and wave w
+// runs eight right-hand sides' chains, lane = row.  Each chain is the same sequence of fmas as
+// one thread per (row, right-hand side) would run.
+constexpr int kRestRows = 64, kRestRhs = 32, kRestMP = SB + 1, kRestXP = kRestRhs + 2;
 template <int LOWER, int TRANS>
-__global__ void tail_tri_rest_kernel(SpArgs a, int c0) {
+__global__ __launch_bounds__(256) void tail_tri_rest_kernel(SpArgs a, int c0) {
+    __shared__ double Ms[SB * kRestMP];       // Ms[k * kRestMP + row]
+    __shared__ double Xs[SB * kRestXP];       // Xs[k * kRestXP + rhs]
     const int ld = a.ix.tail_ld, nrhs = a.nrhs, bs = min(SB, ld - c0);
     const int lo = LOWER ? c0 + bs : 0, hi = LOWER ? ld : c0;
     if (hi <= lo) return;
-    const int64_t per = (int64_t)(hi - lo) * nrhs, total = per * a.ntasks;
-    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
-        const int task = (int)(g / per), t = (int)(g % per);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int row_tiles = (hi - lo + kRestRows - 1) / kRestRows, rhs_chunks = (nrhs + kRestRhs - 1) / kRestRhs;
+    const int64_t per = (int64_t)row_tiles * rhs_chunks;
+    for (int64_t b = blockIdx.x; b < per * a.ntasks; b += gridDim.x) {   // uniform per workgroup
+        const int task = (int)(b / per), rt = (int)(b % per) / rhs_chunks, rc = (int)(b % per) % rhs_chunks;
         if (a.info[task]) continue;
-        const int i = lo + t % (hi - lo), r = t / (hi - lo);
+        const int i0 = lo + rt * kRestRows, rows = min(kRestRows, hi - i0);
+        const int r0 = rc * kRestRhs, nr = min(kRestRhs, nrhs - r0);
         const double* M = a.dense + (int64_t)task * a.dstride;
         double* R = const_cast<double*>(M) + (int64_t)ld * ld;
-        const double* xb = R + (int64_t)r * ld + c0;
-        double v = R[(int64_t)r * ld + i];
-        if (LOWER) {
-            for (int k = 0; k < bs; ++k) {
-                const double m = TRANS ? M[(int64_t)i * ld + c0 + k] : M[(int64_t)(c0 + k) * ld + i];
-                v = fmad(-m, xb[k], v);
-            }
-        } else {
-            for (int k = bs - 1; k >= 0; --k) {
-                const double m = TRANS ? M[(int64_t)i * ld + c0 + k] : M[(int64_t)(c0 + k) * ld + i];
-                v = fmad(-m, xb[k], v);
-            }
+        __syncthreads();                          // the previous item's reads are done
+        for (int t = tid; t < SB * kRestRows; t += 256) {
+            // coalesced along the row index (not TRANS) or along k (TRANS)
+            const int k = TRANS ? t % SB : t / kRestRows, ii = TRANS ? t / SB : t % kRestRows;
+            double v = 0.0;
+            if (k < bs && ii < rows)
+                v = TRANS ? M[(int64_t)(i0 + ii) * ld + c0 + k] : M[(int64_t)(c0 + k) * ld + i0 + ii];
+            Ms[k * kRestMP + ii] = v;
         }
-        R[(int64_t)r * ld + i] = v;
+        for (int t = tid; t < SB * kRestRhs; t += 256) {
+            const int k = t % SB, rr = t / SB;
+            Xs[k * kRestXP + rr] = (k < bs && rr < nr) ? R[(int64_t)(r0 + rr) * ld + c0 + k] : 0.0;
+        }
+        __syncthreads();
+        const int rw = 8 * wave;                  // this wave's right-hand sides: r0 + rw .. + 7
+        if (rw < nr && lane < rows) {              // uniform in the first, per lane in the second
+            double acc[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) acc[j] = rw + j < nr ? R[(int64_t)(r0 + rw + j) * ld + i0 + lane] : 0.0;
+            for (int kk = 0; kk < bs; ++kk) {
+                const int k = LOWER ? kk : bs - 1 - kk;
+                const double m = Ms[k * kRestMP + lane];
+                const double* x = Xs + k * kRestXP + rw;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) acc[j] = fmad(-m, x[j], acc[j]);
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                if (rw + j < nr) R[(int64_t)(r0 + rw + j) * ld + i0 + lane] = acc[j];
+        }
     }
 }
 
@@ -1419,9 +1447,11 @@ hipError_t tail_tri(SpArgs a, hipStream_t st) {
         const int blk = LOWER ? bb : nblk - 1 - bb, c0 = blk * SB, bs = std::min(SB, ld - c0);
         hipLaunchKernelGGL((tail_tri_diag_kernel<LOWER, TRANS>), dim3(tgrid), dim3(WG), 0, st, a, c0);
         const int rows = LOWER ? ld - c0 - bs : c0;
-        if (rows > 0)
-            hipLaunchKernelGGL((tail_tri_rest_kernel<LOWER, TRANS>),
-                               dim3(grid_for((int64_t)rows * a.nrhs * a.ntasks, kThreads)), dim3(kThreads), 0, st, a, c0);
+        if (rows > 0) {
+            const int64_t wgs = (int64_t)a.ntasks * ((rows + kRestRows - 1) / kRestRows) * ((a.nrhs + kRestRhs - 1) / kRestRhs);
+            hipLaunchKernelGGL((tail_tri_rest_kernel<LOWER, TRANS>), dim3((unsigned)std::min<int64_t>(wgs, 1 << 20)),
+                               dim3(256), 0, st, a, c0);
+        }
     }
     return hipGetLastError();
 }
