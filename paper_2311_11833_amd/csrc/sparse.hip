@@ -1323,11 +1323,18 @@ __global__ __launch_bounds__(WG) void tail_tri_diag_kernel(SpArgs a, int c0) {
         if (a.info[task]) continue;
         const double* M = a.dense + (int64_t)task * a.dstride;
         double* R = const_cast<double*>(M) + (int64_t)ld * ld;
-        for (int t = tid; t < SB * SB; t += WG) {
-            const int i = t % SB, j = t / SB;
-            double v = 0.0;
-            if (i < bs && j < bs) v = TRANS ? M[(int64_t)(c0 + i) * ld + c0 + j] : M[(int64_t)(c0 + j) * ld + c0 + i];
-            Tri[i * TP + j] = v;
+        constexpr int QT = SB * SB / WG;          // all of the block's loads in flight first
+        double vt[QT];
+#pragma unroll
+        for (int q = 0; q < QT; ++q) {
+            const int t = tid + WG * q, i = t % SB, j = t / SB;
+            vt[q] = (i < bs && j < bs) ? (TRANS ? M[(int64_t)(c0 + i) * ld + c0 + j] : M[(int64_t)(c0 + j) * ld + c0 + i])
+                                       : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < QT; ++q) {
+            const int t = tid + WG * q;
+            Tri[(t % SB) * TP + t / SB] = vt[q];
         }
         __syncthreads();
         for (int r = r0 + wave; r < min(nrhs, r0 + NW); r += NW) {
@@ -1378,18 +1385,33 @@ __global__ __launch_bounds__(256) void tail_tri_rest_kernel(SpArgs a, int c0) {
         const int r0 = rc * kRestRhs, nr = min(kRestRhs, nrhs - r0);
         const double* M = a.dense + (int64_t)task * a.dstride;
         double* R = const_cast<double*>(M) + (int64_t)ld * ld;
-        __syncthreads();                          // the previous item's reads are done
-        for (int t = tid; t < SB * kRestRows; t += 256) {
+        // all of the tile's loads in flight before the first LDS store
+        constexpr int QM = SB * kRestRows / 256, QX = SB * kRestRhs / 256;
+        double vm[QM], vx[QX];
+#pragma unroll
+        for (int q = 0; q < QM; ++q) {
             // coalesced along the row index (not TRANS) or along k (TRANS)
+            const int t = tid + 256 * q;
             const int k = TRANS ? t % SB : t / kRestRows, ii = TRANS ? t / SB : t % kRestRows;
-            double v = 0.0;
-            if (k < bs && ii < rows)
-                v = TRANS ? M[(int64_t)(i0 + ii) * ld + c0 + k] : M[(int64_t)(c0 + k) * ld + i0 + ii];
-            Ms[k * kRestMP + ii] = v;
+            vm[q] = (k < bs && ii < rows) ? (TRANS ? M[(int64_t)(i0 + ii) * ld + c0 + k] : M[(int64_t)(c0 + k) * ld + i0 + ii])
+                                          : 0.0;
         }
-        for (int t = tid; t < SB * kRestRhs; t += 256) {
-            const int k = t % SB, rr = t / SB;
-            Xs[k * kRestXP + rr] = (k < bs && rr < nr) ? R[(int64_t)(r0 + rr) * ld + c0 + k] : 0.0;
+#pragma unroll
+        for (int q = 0; q < QX; ++q) {
+            const int t = tid + 256 * q, k = t % SB, rr = t / SB;
+            vx[q] = (k < bs && rr < nr) ? R[(int64_t)(r0 + rr) * ld + c0 + k] : 0.0;
+        }
+        __syncthreads();                          // the previous item's reads are done
+#pragma unroll
+        for (int q = 0; q < QM; ++q) {
+            const int t = tid + 256 * q;
+            const int k = TRANS ? t % SB : t / kRestRows, ii = TRANS ? t / SB : t % kRestRows;
+            Ms[k * kRestMP + ii] = vm[q];
+        }
+#pragma unroll
+        for (int q = 0; q < QX; ++q) {
+            const int t = tid + 256 * q;
+            Xs[(t % SB) * kRestXP + t / SB] = vx[q];
         }
         __syncthreads();
         const int rw = 8 * wave;                  // this wave's right-hand sides: r0 + rw .. + 7
