@@ -763,29 +763,32 @@ __device__ __forceinline__ double* tail_panels(const SpIdx& ix, double* T) {
 }
 
 // Every block entry's initial value a_ij (+ eps d on the diagonal) straight from the Jacobian's
-// values, the identity on the padding rows and columns: one thread per entry, down the columns.
-__global__ void tail_block_init_kernel(SpArgs a, EpsSet es) {
+// values, the identity on the padding rows and columns: a workgroup per (column, system), one
+// thread per row, so that the per-system values and the column's L positions are uniform and no
+// index needs a division.
+__global__ __launch_bounds__(256) void tail_block_init_kernel(SpArgs a, EpsSet es) {
     const SpIdx& ix = a.ix;
     const int ld = ix.tail_ld, nt = ix.tail_n, b0 = ix.tail_b0;
-    const int64_t per = (int64_t)ld * ld, total = per * a.ntasks;
-    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
-        const int task = (int)(g / per);
-        const int64_t e = g % per;
-        const int i = (int)(e % ld), j = (int)(e / ld);
-        double v;
-        if (i >= nt || j >= nt) v = i == j ? 1.0 : 0.0;
-        else {
-            const double* vals = a.values + (int64_t)(task / es.K) * a.nnz;
-            const int gi = b0 + i, gj = b0 + j;
-            const double e = a.scale ? __dmul_rn(eps_at(es, task % es.K), a.scale[task / es.K])
-                                     : eps_at(es, task % es.K);
-            if (i == j) v = gather_diag(ix, gj, vals, e, a.dvec);
-            else {
-                const int src = i > j ? ix.src_l[ix.l_ptr[gj] + (gi - gj - 1)] : ix.src_u[ix.l_ptr[gi] + (gj - gi - 1)];
-                v = src >= 0 ? vals[src] : 0.0;
+    for (int task = blockIdx.y; task < a.ntasks; task += gridDim.y) {
+        const double* vals = a.values + (int64_t)(task / es.K) * a.nnz;
+        const double e = a.scale ? __dmul_rn(eps_at(es, task % es.K), a.scale[task / es.K]) : eps_at(es, task % es.K);
+        double* out = a.dense + (int64_t)task * a.dstride;
+        for (int j = blockIdx.x; j < ld; j += gridDim.x) {
+            const int gj = b0 + j;
+            for (int i = threadIdx.x; i < ld; i += 256) {
+                double v;
+                if (i >= nt || j >= nt) v = i == j ? 1.0 : 0.0;
+                else {
+                    const int gi = b0 + i;
+                    if (i == j) v = gather_diag(ix, gj, vals, e, a.dvec);
+                    else {
+                        const int src = i > j ? ix.src_l[ix.l_ptr[gj] + (gi - gj - 1)] : ix.src_u[ix.l_ptr[gi] + (gj - gi - 1)];
+                        v = src >= 0 ? vals[src] : 0.0;
+                    }
+                }
+                out[(int64_t)j * ld + i] = v;
             }
         }
-        a.dense[(int64_t)task * a.dstride + e] = v;
     }
 }
 
@@ -1948,7 +1951,7 @@ hipError_t tail_dense_factor(SpArgs a, const EpsSet& es, hipStream_t st, int col
     const int ld = a.ix.tail_ld;
     if (cols == 16 && a.ix.tail_tiles > 0) {
         if (!a.values) return hipErrorInvalidValue;   // the block's initial values come from the Jacobians
-        hipLaunchKernelGGL(tail_block_init_kernel, dim3(grid_for((int64_t)ld * ld * a.ntasks, kThreads)), dim3(kThreads),
+        hipLaunchKernelGGL(tail_block_init_kernel, dim3((unsigned)std::min(ld, 65535), (unsigned)std::min(a.ntasks, 65535)), dim3(256),
                            0, st, a, es);
         if (a.vs == 1) {
             hipLaunchKernelGGL(tail_panel_gather_kernel, dim3(grid_for(a.ix.tail_panel * a.ntasks, kThreads)),
