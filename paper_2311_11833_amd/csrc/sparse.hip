@@ -989,7 +989,7 @@ __device__ __forceinline__ void tail_tile_long(const SpArgs& a, int lwgs, double
 //
 // The long pairs (the slack row's tile with itself: 4,620 steps at n = 20,001) are not left to
 // one wave's register prefetch: the first lwgs workgroups of the launch (a multiple of 8, so the
-// XCD mapping of the others is unchanged) take one long pair each, and all four waves stage its
+// XCD mapping of the others is unchanged) take one long pair each, and all eight waves stage its
 // panel columns through an LDS ring (global_load_lds, kLcDepth chunks of kLcSteps steps in
 // flight) while wave 0 runs the chain from LDS in the same step order.  They run beside the
 // regular pairs instead of after them.
